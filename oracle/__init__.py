@@ -1,0 +1,195 @@
+"""CPU oracle for the FM-index hot path -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct reference computations written from "Vectorized
+Character Counting for Faster Pattern Matching" (Snytsar); the arithmetic lives in
+fm_oracle.c (compiled with gcc, loaded with ctypes). Only the test suite, the smoke
+check and the benchmark's CPU-baseline leg may import this package. It shares no code
+with the GPU library and the GPU library never imports it.
+
+What each function follows:
+  OracleIndex          suffix array by direct comparison (Background, Eq. 1), BWT from
+                       the SA (Eq. 2), Occ by linear scan and C (Background, Fig. 1)
+  occ8                 Occ(c, k-1) and Occ(c, l) for all four bases (the eight values of
+                       one inexact step, Background)
+  exact                SA interval by its definition (method="definition") or by the
+                       backward exact match (Listing 1, method="listing1")
+  darray               BWA's D lower bound over the index of reverse(R)
+  inexact              hit set by Hamming-ball enumeration (method="definition") or by the
+                       inexact match restricted to substitutions (Listing 2,
+                       method="listing2", optionally with the D bound)
+Every function is pinned by tests/test_oracle_*.py (Fig. 1 values, invariants,
+brute force on tiny inputs); none is "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fm_oracle.c")
+_LIB = os.path.join(_HERE, "_build", "liboracle.so")
+
+FWD, REVCOMP, BOTH = 1, 2, 3
+
+HIT_DTYPE = np.dtype([("read", "<u4"), ("k", "<u4"), ("l", "<u4"), ("strand", "u1"),
+                      ("d", "u1"), ("pad", "<u2")])
+
+
+def build(src: str = _SRC, out: str = _LIB, extra: tuple = ()) -> str:
+    """Compile the oracle with gcc into a shared object."""
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", *extra, "-o", tmp, src])
+    os.replace(tmp, out)
+    return out
+
+
+_lib_cache: dict = {}
+
+
+def load(path: str = _LIB) -> C.CDLL:
+    if path in _lib_cache:
+        return _lib_cache[path]
+    if not os.path.exists(path):
+        if path != _LIB:
+            raise FileNotFoundError(path)
+        build()
+    lib = C.CDLL(path)
+    p, i64, u8p, u32p, u64p = C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p
+    lib.oracle_index_new.restype = p
+    lib.oracle_index_new.argtypes = [u8p, i64]
+    lib.oracle_index_free.argtypes = [p]
+    lib.oracle_index_n.restype = i64
+    lib.oracle_index_n.argtypes = [p]
+    lib.oracle_index_dollar_row.restype = i64
+    lib.oracle_index_dollar_row.argtypes = [p]
+    lib.oracle_index_sa.restype = p
+    lib.oracle_index_sa.argtypes = [p]
+    lib.oracle_index_bwt.restype = p
+    lib.oracle_index_bwt.argtypes = [p]
+    lib.oracle_index_occ.restype = p
+    lib.oracle_index_occ.argtypes = [p]
+    lib.oracle_index_c.argtypes = [p, u64p]
+    lib.oracle_occ8.argtypes = [p, u32p, i64, u32p]
+    lib.oracle_exact.argtypes = [p, u8p, u64p, i64, C.c_int, C.c_int, u32p]
+    lib.oracle_darray.argtypes = [p, u8p, u64p, i64, C.c_int, u8p]
+    lib.oracle_inexact.restype = i64
+    lib.oracle_inexact.argtypes = [p, p, u8p, u64p, u8p, i64, C.c_int, C.c_int, p, i64, u64p, u64p]
+    _lib_cache[path] = lib
+    return lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+class OracleIndex:
+    """SA, BWT, Occ table and C of the text R (codes 0..3), built on the host."""
+
+    def __init__(self, R: np.ndarray, lib_path: str = _LIB):
+        self._lib = load(lib_path)
+        R = np.ascontiguousarray(R, dtype=np.uint8)
+        if R.size and R.max() > 3:
+            raise ValueError("text codes must be 0..3")
+        self._R = R
+        self.n = int(R.size)
+        h = self._lib.oracle_index_new(_ptr(R) if R.size else None, self.n)
+        if not h:
+            raise MemoryError("oracle index")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.oracle_index_free(h)
+            self._h = None
+
+    def _view(self, addr, dtype, count) -> np.ndarray:
+        buf = (C.c_char * (np.dtype(dtype).itemsize * count)).from_address(addr)
+        return np.frombuffer(buf, dtype=dtype, count=count).copy()
+
+    @property
+    def sa(self) -> np.ndarray:
+        return self._view(self._lib.oracle_index_sa(self._h), np.uint32, self.n + 1)
+
+    @property
+    def bwt(self) -> np.ndarray:
+        """n+1 codes: 0..3, and 4 at the '$' row."""
+        return self._view(self._lib.oracle_index_bwt(self._h), np.uint8, self.n + 1)
+
+    @property
+    def occ(self) -> np.ndarray:
+        """(n+1, 4) table: occ[k, c] = Occ(c, k)."""
+        return self._view(self._lib.oracle_index_occ(self._h), np.uint32, 4 * (self.n + 1)).reshape(-1, 4)
+
+    @property
+    def dollar_row(self) -> int:
+        return int(self._lib.oracle_index_dollar_row(self._h))
+
+    @property
+    def C(self) -> np.ndarray:
+        out = np.zeros(5, dtype=np.uint64)
+        self._lib.oracle_index_c(self._h, _ptr(out))
+        return out
+
+    def occ8(self, q: np.ndarray) -> np.ndarray:
+        q = np.ascontiguousarray(q, dtype=np.uint32).reshape(-1, 2)
+        out = np.zeros((q.shape[0], 8), dtype=np.uint32)
+        self._lib.oracle_occ8(self._h, _ptr(q), q.shape[0], _ptr(out))
+        return out
+
+    def exact(self, codes, offs, strands: int = FWD, method: str = "definition") -> np.ndarray:
+        codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        offs = np.ascontiguousarray(offs, dtype=np.uint64)
+        nreads = offs.size - 1
+        ns = bin(strands & 3).count("1")
+        out = np.zeros((nreads * ns, 2), dtype=np.uint32)
+        m = {"definition": 0, "listing1": 1}[method]
+        self._lib.oracle_exact(self._h, _ptr(codes) if codes.size else None, _ptr(offs), nreads,
+                               strands, m, _ptr(out))
+        return out
+
+    def darray(self, codes, offs, strands: int = FWD) -> np.ndarray:
+        """D for each requested strand: an array (strands, total_len) of uint8."""
+        codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        offs = np.ascontiguousarray(offs, dtype=np.uint64)
+        ns = bin(strands & 3).count("1")
+        out = np.zeros((ns, codes.size), dtype=np.uint8)
+        self._lib.oracle_darray(self._h, _ptr(codes) if codes.size else None, _ptr(offs),
+                                offs.size - 1, strands, _ptr(out) if out.size else None)
+        return out
+
+    def inexact(self, codes, offs, z, strands: int = BOTH, method: str = "listing2",
+                rev: "OracleIndex | None" = None, return_nodes: bool = False):
+        """Hits sorted by (read, strand, k) as a HIT_DTYPE array plus CSR offsets."""
+        codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        offs = np.ascontiguousarray(offs, dtype=np.uint64)
+        nreads = offs.size - 1
+        z = np.ascontiguousarray(np.broadcast_to(np.asarray(z, dtype=np.uint8), (nreads,)))
+        m = {"definition": 0, "listing2": 1, "listing2_darray": 2}[method]
+        if m == 2 and rev is None:
+            raise ValueError("the D bound needs the index of reverse(R)")
+        hit_offs = np.zeros(nreads + 1, dtype=np.uint64)
+        nodes = np.zeros(max(nreads, 1), dtype=np.uint64)
+        cap = max(16, 4 * nreads)
+        while True:
+            out = np.zeros(cap, dtype=HIT_DTYPE)
+            total = self._lib.oracle_inexact(self._h, rev._h if rev is not None else None,
+                                             _ptr(codes) if codes.size else None, _ptr(offs),
+                                             _ptr(z) if z.size else None, nreads, strands, m,
+                                             _ptr(out), cap, _ptr(hit_offs), _ptr(nodes))
+            if total <= cap:
+                break
+            cap = int(total)
+        hits = out[:total].copy()
+        if return_nodes:
+            return hits, hit_offs, nodes[:nreads].copy()
+        return hits, hit_offs
+
+
+def reverse_text(R: np.ndarray) -> np.ndarray:
+    """reverse(R): the text whose index gives the D-array bound (BWA)."""
+    return np.ascontiguousarray(np.asarray(R, dtype=np.uint8)[::-1])
