@@ -1,0 +1,271 @@
+/*
+ * fm.h -- C ABI of libfmocc, an MI355X (gfx950) FM-index engine: the Occ computation
+ * over an interleaved 2-bit BWT with checkpoint counts, and the exact and z-mismatch
+ * backward searches built on it.
+ *
+ * Definitions follow "Vectorized Character Counting for Faster Pattern Matching"
+ * (Snytsar): the suffix array of R$ (Background, Eq. 1), the BWT derived from it
+ * (Eq. 2), Occ(c, k) = number of c in BWT[0..k] and C[c] = number of characters
+ * smaller than c (Background, Fig. 1), the backward exact match (Listing 1) and the
+ * inexact match (Listing 2, substitution branches).
+ *
+ * Conventions used by every call:
+ *   - Symbol codes: A=0, C=1, G=2, T=3. In reads, any other value (4 is used for N)
+ *     occurs nowhere in R and never equals a base.
+ *   - R has length n; the index has n+1 rows 0..n; row 0 holds the suffix "$".
+ *     n + 1 must be below 2^32.
+ *   - An interval (k, l) names rows k..l (inclusive) whose suffix starts with the
+ *     pattern; the empty pattern has (0, n). A pattern that does not occur is
+ *     reported as the canonical miss (1, 0). Listing 1's update is
+ *       k <- C[b] + Occ(b, k-1) + 1,   l <- C[b] + Occ(b, l),   Occ(b, -1) = 0.
+ *   - Strand 0 searches the read W; strand 1 searches its reverse complement (W
+ *     reversed, c -> 3 - c for c < 4).
+ *   - Device pointers are HIP device memory (for example torch tensors' data_ptr());
+ *     host pointers are ordinary process memory. The library never keeps a pointer
+ *     it is passed beyond the call, except an index that owns its own memory.
+ *   - `stream` is a hipStream_t (NULL = the null stream). Calls that take a stream
+ *     only enqueue work and return; results are valid once the stream reaches them.
+ *   - Return values are FM_OK or an fm_status code; argument errors are detected on
+ *     the host before anything is enqueued. Per-read problems are reported per read
+ *     in device status words and never fail the whole call.
+ */
+#ifndef FM_H
+#define FM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fm_index fm_index;   /* opaque, immutable after construction except for
+                                       its launch tuning; one device */
+
+typedef struct {
+    uint32_t k, l;                  /* inclusive row range; miss = (1, 0) */
+} fm_interval;
+
+typedef struct {
+    uint32_t read;                  /* read number in the batch */
+    uint32_t k, l;                  /* interval of one distinct W' */
+    uint8_t strand;                 /* 0 = W, 1 = reverse complement */
+    uint8_t nmm;                    /* substitutions in W' relative to the strand */
+    uint16_t pad;
+} fm_hit;                           /* 16 bytes */
+
+enum fm_status {
+    FM_OK = 0,
+    FM_EINVAL = 1,                  /* bad argument (or, per read, a budget above zmax) */
+    FM_EIO = 2,                     /* file could not be read or written */
+    FM_EFORMAT = 3,                 /* index file or BWT is malformed */
+    FM_ENOMEM = 4,                  /* host or device allocation failed */
+    FM_EDEVICE = 5,                 /* a HIP call failed */
+    FM_EOVERFLOW = 6,               /* per read: its hits did not fit in hit_cap */
+    FM_EBUDGET = 7,                 /* per read: node budget exhausted */
+    FM_ERANGE = 8                   /* size beyond what the index or ABI supports */
+};
+
+/* Search flags. */
+enum {
+    FM_FWD = 1,                     /* search strand 0 */
+    FM_REVCOMP = 2,                 /* search strand 1 */
+    FM_BOTH = 3,
+    FM_DARRAY = 4,                  /* prune with the D lower bound (needs the reverse index) */
+    FM_PLAIN = 16,                  /* use the plain one-thread-per-read-strand kernels */
+    FM_STATS = 32                   /* count Occ queries and bucket fetches into the workspace */
+};
+
+/* Load flags. */
+enum {
+    FM_LOAD_REVERSE = 1,            /* also build/keep the index of reverse(R) */
+    FM_LOAD_ALL_LAYOUTS = 2         /* build the layouts for all of I = 64, 128, 256 */
+};
+
+#define FM_ZMAX 4                   /* largest per-read mismatch budget */
+
+typedef struct {
+    int device;                     /* HIP device ordinal */
+    uint32_t occ_interval;          /* checkpoint interval I: 64, 128, 256, or 0 for 128 */
+    uint32_t flags;                 /* FM_LOAD_* */
+} fm_load_opts;
+
+typedef struct {
+    uint64_t n;                     /* |R|; rows 0..n */
+    uint64_t dollar_row;            /* row whose BWT symbol is '$' */
+    uint64_t C[5];                  /* C[4] = n */
+    uint64_t rev_dollar_row;        /* same for reverse(R), if present */
+    uint64_t rev_C[5];
+    uint32_t occ_interval;          /* layout used by the searches */
+    uint32_t layouts;               /* built layouts: bit 0 = 64, bit 1 = 128, bit 2 = 256 */
+    uint32_t has_reverse;
+    uint32_t pad;
+    uint64_t device_bytes;          /* device memory owned by the index */
+} fm_info;
+
+/* Launch configuration of one operation (see fm_get_tuning). */
+typedef struct {
+    uint32_t occ_interval;          /* 64, 128 or 256; must be one of the index's layouts */
+    uint32_t lanes;                 /* lanes cooperating on one read-strand: 1, 2, 4 or 8 */
+    uint32_t depth;                 /* read-strands in flight per lane group: 1 or 2 */
+    uint32_t block;                 /* threads per workgroup: 64, 128, 192 or 256 */
+    uint32_t waves_per_cu;          /* persistent grid = CUs * waves_per_cu * 64 / block */
+    uint32_t node_budget;           /* inexact: DFS nodes per read-strand before FM_EBUDGET */
+} fm_tuning;
+
+enum { FM_OP_EXACT = 0, FM_OP_DARRAY = 1, FM_OP_INEXACT = 2 };
+
+/* ----------------------------------------------------------------- general */
+
+/* Text for a status code; never NULL. */
+const char *fm_strerror(int status);
+
+/* ABI version (increases when signatures change). */
+int fm_version(void);
+
+/* ----------------------------------------------------------------- construction (host) */
+
+/* BWT of R$ computed by the library's host builder (suffix array by induced sorting,
+ * then Eq. 2). text: host, n codes 0..3. bwt: host, n+1 bytes, receives codes 0..3
+ * and 4 at the '$' row, which is stored in *dollar_row. FM_EINVAL on a code above 3
+ * or n + 1 >= 2^32; FM_ENOMEM when the builder's memory cannot be allocated. */
+int fm_bwt_host(const uint8_t *text, uint64_t n, uint8_t *bwt, uint64_t *dollar_row);
+
+/* The library's 2-bit packing (host): code j of `codes` goes to bits 2(j mod 16) and
+ * 2(j mod 16)+1 of words[j / 16], least significant first -- the ordering of the
+ * 32-character register in Fig. 2. words: ceil(count/16) entries, fully written (the
+ * unused high bits of the last word are 0). Codes above 3 give FM_EINVAL. */
+int fm_pack_host(const uint8_t *codes, uint64_t count, uint32_t *words);
+
+/* Writes an index file for text (host, n codes 0..3): header, C, '$' row and the
+ * packed BWT of R$ (and of reverse(R)$ when flags has FM_LOAD_REVERSE). */
+int fm_index_build_file(const uint8_t *text, uint64_t n, const char *path, uint32_t flags);
+
+/* Builds the index of text (host) in memory and moves it to the device. */
+int fm_index_from_text(const uint8_t *text, uint64_t n, const fm_load_opts *opts, fm_index **out);
+
+/* Index from a BWT given directly (host): rows = n+1 codes 0..3 with exactly one 4 for
+ * '$'. rev_bwt (nullable) is the BWT of reverse(R)$ with the same number of rows.
+ * FM_EFORMAT when a BWT does not hold exactly one '$' or the two disagree in size. */
+int fm_index_from_codes(const uint8_t *bwt, uint64_t rows, const uint8_t *rev_bwt,
+                        const fm_load_opts *opts, fm_index **out);
+
+/* Loads an index file written by fm_index_build_file. FM_EIO, FM_EFORMAT (bad magic,
+ * sizes, C or checksum), FM_EINVAL (FM_LOAD_REVERSE asked of a file without one). */
+int fm_index_load(const char *path, const fm_load_opts *opts, fm_index **out);
+
+int fm_index_info(const fm_index *idx, fm_info *out);
+
+/* Frees the index's device memory; safe on NULL. No call may be in flight on it. */
+void fm_index_free(fm_index *idx);
+
+/* ----------------------------------------------------------------- tuning */
+
+/* Current launch configuration of op (FM_OP_*). Defaults are chosen at load time. */
+int fm_get_tuning(const fm_index *idx, int op, fm_tuning *out);
+
+/* Sets the launch configuration of op. FM_EINVAL when a value is outside the listed
+ * ones or the layout was not built. Not safe concurrently with searches on idx. */
+int fm_set_tuning(fm_index *idx, int op, const fm_tuning *t);
+
+/* Times every compiled launch configuration of op on a sample batch (same arguments
+ * as the corresponding search, device buffers owned by the caller, ws sized with
+ * the op's workspace call for the sample and hit_cap) and keeps the fastest that
+ * reproduces the plain kernel's output bit for bit. Synchronises `stream`. If
+ * cache_path is non-NULL the choice is looked up there first (key: device
+ * architecture, n, read count, total length, zmax, flags) and stored after tuning.
+ * best (nullable) receives the choice; ms (nullable) its time per call. */
+int fm_autotune(fm_index *idx, int op, const uint8_t *codes, const uint64_t *offs,
+                const uint8_t *z, uint64_t nreads, uint32_t flags, uint32_t zmax,
+                void *out_buf, uint64_t hit_cap, uint64_t *hit_offs, uint32_t *status,
+                void *ws, size_t ws_bytes, const char *cache_path, void *stream,
+                fm_tuning *best, float *ms);
+
+/* ----------------------------------------------------------------- Occ8 */
+
+/* For each query (k, l), 0 <= k <= n+1 and 0 <= l <= n, writes the eight values
+ *   Occ(A,k-1) Occ(C,k-1) Occ(G,k-1) Occ(T,k-1) Occ(A,l) Occ(C,l) Occ(G,l) Occ(T,l)
+ * -- everything one step of the inexact match consumes (Background). q: device, nq
+ * pairs. out: device, 8*nq uint32. A query outside the ranges gets eight 0xFFFFFFFF
+ * (no Occ value can be that large). */
+int fm_occ8(const fm_index *idx, const fm_interval *q, uint64_t nq, uint32_t *out, void *stream);
+
+/* ----------------------------------------------------------------- exact search */
+
+/* Workspace bytes fm_search_exact needs (a few hundred bytes; 0 with FM_PLAIN). */
+int fm_search_exact_workspace(const fm_index *idx, uint64_t nreads, uint32_t flags, size_t *bytes);
+
+/* Backward exact match (Listing 1) of every read on the strands in flags.
+ * codes: device, offs[nreads] bytes (reads concatenated). offs: device, nreads+1
+ * uint64 CSR offsets, offs[0] = 0. out: device, one fm_interval per read and strand,
+ * out[s_count * r + j] for the j-th requested strand. ws: device workspace (may be
+ * NULL with FM_PLAIN). An empty read gives (0, n); a miss or a non-ACGT symbol gives
+ * (1, 0). Reads may have any length below 2^32. */
+int fm_search_exact(const fm_index *idx, const uint8_t *codes, const uint64_t *offs,
+                    uint64_t nreads, uint32_t flags, fm_interval *out, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* ----------------------------------------------------------------- D-array */
+
+/* BWA's lower bound D (used by FM_DARRAY): for each read and requested strand, D[i] is
+ * the number of disjoint segments of the strand's pattern W[0..i] that do not occur in
+ * R, found by a left-to-right walk over the index of reverse(R) that restarts after
+ * each failure (values saturate at 255). total_len: host copy of offs[nreads].
+ * D: device, s_count * total_len bytes, the strand-0 block first, each laid out like
+ * `codes`. Needs FM_LOAD_REVERSE. Runs the plain (one thread per read-strand) walk. */
+int fm_darray(const fm_index *idx, const uint8_t *codes, const uint64_t *offs,
+              uint64_t nreads, uint64_t total_len, uint32_t flags, uint8_t *D, void *stream);
+
+/* ----------------------------------------------------------------- inexact search */
+
+/* Workspace bytes fm_search_inexact needs for this batch shape. */
+int fm_search_inexact_workspace(const fm_index *idx, uint64_t nreads, uint64_t total_len,
+                                uint32_t flags, uint32_t zmax, uint64_t hit_cap, size_t *bytes);
+
+/* Inexact match restricted to substitutions (Listing 2): for every read r and
+ * requested strand, every W' over ACGT of the read's length with at most z[r]
+ * substitutions (non-ACGT positions always count) that occurs in R, reported once
+ * as (read, k, l, strand, nmm). With FM_DARRAY the search is pruned with the D bound,
+ * which never changes the result.
+ *   z: device, nreads uint8 budgets; zmax: host, an upper bound on them (<= FM_ZMAX);
+ *      a read with z[r] > zmax gets status FM_EINVAL and no hits.
+ *   hits: device, hit_cap entries; hit_offs: device, nreads+1 uint64: the hits of
+ *      read r are hits[hit_offs[r] .. hit_offs[r+1]) sorted by (strand, k).
+ *   status: device, nreads uint32: FM_OK, FM_EINVAL, FM_ERANGE (read longer than
+ *      65535), FM_EOVERFLOW (hits did not fit in hit_cap; the read has no hits
+ *      listed) or FM_EBUDGET (node budget reached; no hits listed).
+ *   ws: device workspace of at least fm_search_inexact_workspace bytes. After the
+ *      call, the uint64 at byte offset 8 of ws holds the total hit count every read
+ *      would need (for a retry with a larger hit_cap); with FM_STATS the uint64s at
+ *      offsets 64 (expanded DFS nodes, each one Occ8 step), 72 (buckets fetched by
+ *      them; a node whose interval is still (0, n) takes its children from C and
+ *      fetches none) and 80 (D-walk steps that fetched) count the work done.
+ * Output is deterministic: independent of scheduling, batch order and launch tuning. */
+int fm_search_inexact(const fm_index *idx, const uint8_t *codes, const uint64_t *offs,
+                      const uint8_t *z, uint64_t nreads, uint32_t flags, uint32_t zmax,
+                      fm_hit *hits, uint64_t hit_cap, uint64_t *hit_offs, uint32_t *status,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* ----------------------------------------------------------------- launch graphs */
+
+typedef struct fm_plan fm_plan;
+
+/* Captures one call of an operation into a HIP graph for a fixed batch shape and fixed
+ * buffers (all pointers as in the search calls, op = FM_OP_EXACT or FM_OP_INEXACT).
+ * Replaying it searches whatever the buffers hold at replay time. Capture runs on an
+ * internal stream; nothing is executed. */
+int fm_plan_create(const fm_index *idx, int op, const uint8_t *codes, const uint64_t *offs,
+                   const uint8_t *z, uint64_t nreads, uint32_t flags, uint32_t zmax,
+                   void *out_buf, uint64_t hit_cap, uint64_t *hit_offs, uint32_t *status,
+                   void *ws, size_t ws_bytes, fm_plan **out);
+
+/* Enqueues one replay of the plan on stream. */
+int fm_plan_launch(fm_plan *plan, void *stream);
+
+void fm_plan_free(fm_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FM_H */

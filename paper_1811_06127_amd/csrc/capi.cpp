@@ -1,0 +1,348 @@
+// capi.cpp -- the C ABI (include/fm.h): argument checks on the host, index creation and
+// device memory, and dispatch to the kernels.
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "fm_build.hpp"
+#include "fm_internal.hpp"
+
+using namespace fm;
+
+namespace fm {
+
+DevLayout dev_layout(const fm_index *idx, uint32_t I, bool rev)
+{
+    DevLayout d;
+    const int li = ilog(I);
+    d.bk = (const uint4 *)(rev ? idx->rlay[li] : idx->lay[li]);
+    d.n = (uint32_t)idx->n;
+    d.dollar = (uint32_t)(rev ? idx->rev_dollar : idx->dollar);
+    const uint64_t *C = rev ? idx->rev_C : idx->C;
+    for (int c = 0; c < 5; ++c) d.C[c] = (uint32_t)C[c];
+    return d;
+}
+
+}  // namespace fm
+
+namespace {
+
+struct DeviceGuard {      // makes the index's device current for the duration of a call
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+    }
+};
+
+int hip_status(hipError_t e) { return e == hipSuccess ? FM_OK : (e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EDEVICE); }
+
+uint32_t nstrands(uint32_t flags) { return ((flags & FM_FWD) ? 1u : 0u) + ((flags & FM_REVCOMP) ? 1u : 0u); }
+
+bool valid_tuning(const fm_index *idx, const fm_tuning &t)
+{
+    const int li = ilog(t.occ_interval);
+    if (li < 0 || !idx->lay[li]) return false;
+    if (t.lanes != 1 && t.lanes != 2 && t.lanes != 4 && t.lanes != 8) return false;
+    if (t.depth != 1 && t.depth != 2) return false;
+    if (t.block < 64 || t.block > 256 || t.block % 64) return false;
+    return true;
+}
+
+void default_tunings(fm_index *idx, uint32_t I)
+{
+    fm_tuning ex = {I, 4, 2, 256, 0, 0};
+    fm_tuning dw = {I, 4, 2, 256, 0, 0};
+    fm_tuning in = {I, 1, 1, 256, 0, 1u << 22};
+    idx->tune[FM_OP_EXACT] = ex;
+    idx->tune[FM_OP_DARRAY] = dw;
+    idx->tune[FM_OP_INEXACT] = in;
+}
+
+// Moves packed BWTs to the device and builds the requested layouts.
+int create_index(const fm_load_opts *opts, uint64_t n, const HostSide &fwd, const HostSide *rev, fm_index **out)
+{
+    *out = nullptr;
+    const int dev = opts ? opts->device : 0;
+    uint32_t I = opts && opts->occ_interval ? opts->occ_interval : 128;
+    if (ilog(I) < 0) return FM_EINVAL;
+    const bool all = opts && (opts->flags & FM_LOAD_ALL_LAYOUTS);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || dev < 0 || dev >= ndev) return FM_EDEVICE;
+    DeviceGuard g(dev);
+    fm_index *idx = new (std::nothrow) fm_index();
+    if (!idx) return FM_ENOMEM;
+    idx->device = dev;
+    idx->n = n;
+    idx->dollar = fwd.dollar;
+    memcpy(idx->C, fwd.C, sizeof idx->C);
+    if (rev) {
+        idx->has_rev = true;
+        idx->rev_dollar = rev->dollar;
+        memcpy(idx->rev_C, rev->C, sizeof idx->rev_C);
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        delete idx;
+        return FM_EDEVICE;
+    }
+    idx->cu_count = prop.multiProcessorCount;
+    idx->arch = prop.gcnArchName;
+
+    const size_t pbytes = fwd.words.size() * 4;
+    size_t sbytes = 0;
+    for (uint32_t J : {64u, 128u, 256u}) sbytes = std::max(sbytes, build_layout_scratch(n, J));
+    void *packed = nullptr, *scratch = nullptr;
+    int st = FM_OK;
+    if (hipMalloc(&packed, pbytes ? pbytes : 16) != hipSuccess || hipMalloc(&scratch, sbytes) != hipSuccess) st = FM_ENOMEM;
+    for (int side = 0; side < (rev ? 2 : 1) && !st; ++side) {
+        const HostSide &h = side ? *rev : fwd;
+        if (hipMemcpy(packed, h.words.data(), pbytes, hipMemcpyHostToDevice) != hipSuccess) {
+            st = FM_EDEVICE;
+            break;
+        }
+        for (uint32_t J : {64u, 128u, 256u}) {
+            if (!all && J != I) continue;
+            void *buf = nullptr;
+            const size_t lb = layout_bytes(n, J);
+            if (hipMalloc(&buf, lb) != hipSuccess) {
+                st = FM_ENOMEM;
+                break;
+            }
+            (side ? idx->rlay : idx->lay)[ilog(J)] = buf;
+            idx->device_bytes += lb;
+            if (hipError_t e = build_layout((const uint32_t *)packed, n, J, buf, scratch, nullptr)) {
+                st = hip_status(e);
+                break;
+            }
+        }
+        if (!st && hipDeviceSynchronize() != hipSuccess) st = FM_EDEVICE;
+    }
+    if (packed) (void)hipFree(packed);
+    if (scratch) (void)hipFree(scratch);
+    if (st) {
+        fm_index_free(idx);
+        return st;
+    }
+    default_tunings(idx, I);
+    *out = idx;
+    return FM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fm_strerror(int s)
+{
+    switch (s) {
+    case FM_OK: return "ok";
+    case FM_EINVAL: return "invalid argument";
+    case FM_EIO: return "i/o error";
+    case FM_EFORMAT: return "malformed index or BWT";
+    case FM_ENOMEM: return "out of memory";
+    case FM_EDEVICE: return "HIP device error";
+    case FM_EOVERFLOW: return "hit capacity exceeded";
+    case FM_EBUDGET: return "node budget exhausted";
+    case FM_ERANGE: return "size out of range";
+    default: return "unknown status";
+    }
+}
+
+int fm_version(void) { return 1; }
+
+int fm_bwt_host(const uint8_t *text, uint64_t n, uint8_t *bwt, uint64_t *dollar_row)
+{
+    if ((!text && n) || !bwt || !dollar_row) return FM_EINVAL;
+    return build_bwt(text, n, bwt, dollar_row);
+}
+
+int fm_pack_host(const uint8_t *codes, uint64_t count, uint32_t *words)
+{
+    if ((!codes && count) || (!words && count)) return FM_EINVAL;
+    return pack_codes(codes, count, words, ~0ull);
+}
+
+int fm_index_build_file(const uint8_t *text, uint64_t n, const char *path, uint32_t flags)
+{
+    if ((!text && n) || !path) return FM_EINVAL;
+    HostSide fwd, rev;
+    int st = build_side(text, n, false, fwd);
+    if (!st && (flags & FM_LOAD_REVERSE)) st = build_side(text, n, true, rev);
+    if (st) return st;
+    return write_index_file(path, n, fwd, (flags & FM_LOAD_REVERSE) ? &rev : nullptr);
+}
+
+int fm_index_from_text(const uint8_t *text, uint64_t n, const fm_load_opts *opts, fm_index **out)
+{
+    if ((!text && n) || !out) return FM_EINVAL;
+    HostSide fwd, rev;
+    const bool want_rev = opts && (opts->flags & FM_LOAD_REVERSE);
+    int st = build_side(text, n, false, fwd);
+    if (!st && want_rev) st = build_side(text, n, true, rev);
+    if (st) return st;
+    return create_index(opts, n, fwd, want_rev ? &rev : nullptr, out);
+}
+
+int fm_index_from_codes(const uint8_t *bwt, uint64_t rows, const uint8_t *rev_bwt, const fm_load_opts *opts,
+                        fm_index **out)
+{
+    if (!bwt || !out || rows == 0) return FM_EINVAL;
+    if (rows >= (1ull << 32)) return FM_ERANGE;
+    HostSide fwd, rev;
+    try {
+        fwd.words.assign((rows + 15) / 16, 0u);
+        if (rev_bwt) rev.words.assign((rows + 15) / 16, 0u);
+    } catch (const std::bad_alloc &) {
+        return FM_ENOMEM;
+    }
+    int st = bwt_stats(bwt, rows, &fwd.dollar, fwd.C);
+    if (!st) st = pack_codes(bwt, rows, fwd.words.data(), fwd.dollar);
+    if (!st && rev_bwt) {
+        st = bwt_stats(rev_bwt, rows, &rev.dollar, rev.C);
+        if (!st) st = pack_codes(rev_bwt, rows, rev.words.data(), rev.dollar);
+        if (!st)
+            for (int c = 0; c < 5; ++c)
+                if (rev.C[c] != fwd.C[c]) st = FM_EFORMAT;   // reverse(R) has the same symbol counts
+    }
+    if (st) return st == FM_EINVAL ? FM_EFORMAT : st;
+    return create_index(opts, rows - 1, fwd, rev_bwt ? &rev : nullptr, out);
+}
+
+int fm_index_load(const char *path, const fm_load_opts *opts, fm_index **out)
+{
+    if (!path || !out) return FM_EINVAL;
+    HostSide fwd, rev;
+    uint64_t n = 0;
+    bool has_rev = false;
+    const bool want_rev = opts && (opts->flags & FM_LOAD_REVERSE);
+    int st = read_index_file(path, want_rev, &n, fwd, rev, &has_rev);
+    if (st) return st;
+    return create_index(opts, n, fwd, (want_rev && has_rev) ? &rev : nullptr, out);
+}
+
+int fm_index_info(const fm_index *idx, fm_info *out)
+{
+    if (!idx || !out) return FM_EINVAL;
+    memset(out, 0, sizeof *out);
+    out->n = idx->n;
+    out->dollar_row = idx->dollar;
+    memcpy(out->C, idx->C, sizeof out->C);
+    out->rev_dollar_row = idx->rev_dollar;
+    memcpy(out->rev_C, idx->rev_C, sizeof out->rev_C);
+    out->occ_interval = idx->tune[FM_OP_INEXACT].occ_interval;
+    for (int i = 0; i < 3; ++i)
+        if (idx->lay[i]) out->layouts |= 1u << i;
+    out->has_reverse = idx->has_rev ? 1u : 0u;
+    out->device_bytes = idx->device_bytes;
+    return FM_OK;
+}
+
+void fm_index_free(fm_index *idx)
+{
+    if (!idx) return;
+    DeviceGuard g(idx->device);
+    for (int i = 0; i < 3; ++i) {
+        if (idx->lay[i]) (void)hipFree(idx->lay[i]);
+        if (idx->rlay[i]) (void)hipFree(idx->rlay[i]);
+    }
+    delete idx;
+}
+
+int fm_get_tuning(const fm_index *idx, int op, fm_tuning *out)
+{
+    if (!idx || !out || op < 0 || op > 2) return FM_EINVAL;
+    *out = idx->tune[op];
+    return FM_OK;
+}
+
+int fm_set_tuning(fm_index *idx, int op, const fm_tuning *t)
+{
+    if (!idx || !t || op < 0 || op > 2 || !valid_tuning(idx, *t)) return FM_EINVAL;
+    if (op == FM_OP_DARRAY && (!idx->has_rev || !idx->rlay[ilog(t->occ_interval)])) return FM_EINVAL;
+    idx->tune[op] = *t;
+    return FM_OK;
+}
+
+int fm_occ8(const fm_index *idx, const fm_interval *q, uint64_t nq, uint32_t *out, void *stream)
+{
+    if (!idx || (nq && (!q || !out))) return FM_EINVAL;
+    DeviceGuard g(idx->device);
+    fm_tuning t = idx->tune[FM_OP_EXACT];
+    return hip_status(launch_occ8(idx, t, q, nq, out, (hipStream_t)stream));
+}
+
+int fm_search_exact_workspace(const fm_index *idx, uint64_t nreads, uint32_t flags, size_t *bytes)
+{
+    (void)nreads;
+    if (!idx || !bytes) return FM_EINVAL;
+    *bytes = (flags & FM_PLAIN) ? 0 : kWsHeader;
+    return FM_OK;
+}
+
+int fm_search_exact(const fm_index *idx, const uint8_t *codes, const uint64_t *offs, uint64_t nreads, uint32_t flags,
+                    fm_interval *out, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!idx || !nstrands(flags)) return FM_EINVAL;
+    if (nreads && (!codes || !offs || !out)) return FM_EINVAL;
+    if (nreads * nstrands(flags) >= 0xFFFFFFFFull) return FM_ERANGE;
+    const bool plain = (flags & FM_PLAIN) != 0;
+    if (!plain && (!ws || ws_bytes < kWsHeader)) return FM_EINVAL;
+    if (!nreads) return FM_OK;
+    DeviceGuard g(idx->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (!plain) {
+        if (hipError_t e = launch_fill(ws, 0, kWsHeader / 4, s)) return hip_status(e);
+    }
+    WalkCall c{codes, offs, nullptr, nreads, flags, 0, out, ws};
+    return hip_status(launch_walk(idx, idx->tune[FM_OP_EXACT], WALK_EXACT, plain, c, s));
+}
+
+int fm_darray(const fm_index *idx, const uint8_t *codes, const uint64_t *offs, uint64_t nreads, uint64_t total_len,
+              uint32_t flags, uint8_t *D, void *stream)
+{
+    if (!idx || !nstrands(flags) || !idx->has_rev) return FM_EINVAL;
+    if (nreads && (!codes || !offs || !D)) return FM_EINVAL;
+    if (nreads * nstrands(flags) >= 0xFFFFFFFFull) return FM_ERANGE;
+    if (!nreads) return FM_OK;
+    DeviceGuard g(idx->device);
+    WalkCall c{codes, offs, nullptr, nreads, flags, 0, D, nullptr};
+    return hip_status(launch_darray_full(idx, idx->tune[FM_OP_DARRAY], c, total_len, (hipStream_t)stream));
+}
+
+int fm_search_inexact_workspace(const fm_index *idx, uint64_t nreads, uint64_t total_len, uint32_t flags, uint32_t zmax,
+                                uint64_t hit_cap, size_t *bytes)
+{
+    (void)total_len;
+    if (!idx || !bytes || !nstrands(flags) || zmax > FM_ZMAX) return FM_EINVAL;
+    *bytes = inexact_ws_layout(nreads, nstrands(flags), zmax, hit_cap, (flags & FM_PLAIN) != 0).total;
+    return FM_OK;
+}
+
+int fm_search_inexact(const fm_index *idx, const uint8_t *codes, const uint64_t *offs, const uint8_t *z,
+                      uint64_t nreads, uint32_t flags, uint32_t zmax, fm_hit *hits, uint64_t hit_cap,
+                      uint64_t *hit_offs, uint32_t *status, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!idx || !nstrands(flags) || zmax > FM_ZMAX || !hit_offs || !ws) return FM_EINVAL;
+    if (nreads && (!codes || !offs || !z || !status || (hit_cap && !hits))) return FM_EINVAL;
+    if (nreads * nstrands(flags) >= 0xFFFFFFFFull) return FM_ERANGE;
+    if ((flags & FM_DARRAY) && (!idx->has_rev || !idx->rlay[ilog(idx->tune[FM_OP_DARRAY].occ_interval)]))
+        return FM_EINVAL;
+    const bool plain = (flags & FM_PLAIN) != 0;
+    if (ws_bytes < inexact_ws_layout(nreads, nstrands(flags), zmax, hit_cap, plain).total) return FM_EINVAL;
+    DeviceGuard g(idx->device);
+    DfsCall c{codes, offs, z, nreads, flags, zmax, hits, hit_cap, hit_offs, status, ws};
+    return hip_status(launch_inexact(idx, idx->tune[FM_OP_INEXACT], idx->tune[FM_OP_DARRAY], plain, c,
+                                     (hipStream_t)stream));
+}
+
+}  // extern "C"

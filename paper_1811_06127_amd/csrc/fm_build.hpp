@@ -1,0 +1,25 @@
+// fm_build.hpp -- host-side index construction and file I/O.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/fm.h"
+
+namespace fm {
+
+struct HostSide {                 // one text's packed BWT and its constants
+    std::vector<uint32_t> words;  // 2-bit codes, '$' stored as 0
+    uint64_t dollar = 0;
+    uint64_t C[5] = {0, 0, 0, 0, 0};
+};
+
+int build_bwt(const uint8_t *text, uint64_t n, uint8_t *bwt, uint64_t *dollar_row);
+int pack_codes(const uint8_t *codes, uint64_t count, uint32_t *words, uint64_t dollar_row);
+int bwt_stats(const uint8_t *bwt, uint64_t rows, uint64_t *dollar_row, uint64_t C[5]);
+int build_side(const uint8_t *text, uint64_t n, bool reverse, HostSide &out);
+int write_index_file(const char *path, uint64_t n, const HostSide &fwd, const HostSide *rev);
+int read_index_file(const char *path, bool want_rev, uint64_t *n, HostSide &fwd, HostSide &rev, bool *has_rev);
+
+}  // namespace fm

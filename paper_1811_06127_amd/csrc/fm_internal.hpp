@@ -1,0 +1,99 @@
+// fm_internal.hpp -- host-side structures shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/fm.h"
+#include "fm_device.hpp"
+
+struct fm_index {
+    int device = 0;
+    uint64_t n = 0;
+    uint64_t dollar = 0, rev_dollar = 0;
+    uint64_t C[5] = {0, 0, 0, 0, 0}, rev_C[5] = {0, 0, 0, 0, 0};
+    bool has_rev = false;
+    void *lay[3] = {nullptr, nullptr, nullptr};    // forward layouts for I = 64, 128, 256
+    void *rlay[3] = {nullptr, nullptr, nullptr};   // layouts of reverse(R)
+    uint64_t device_bytes = 0;
+    fm_tuning tune[3] = {};
+    int cu_count = 0;
+    std::string arch;
+};
+
+namespace fm {
+
+constexpr uint32_t kQueueChunk = 64;   // read-strands a wave takes from the work queue at once
+
+inline int ilog(uint32_t I) { return I == 64 ? 0 : (I == 128 ? 1 : (I == 256 ? 2 : -1)); }
+inline uint64_t num_buckets(uint64_t n, uint32_t I) { return n / I + 1; }
+inline uint64_t bucket_bytes(uint32_t I) { return I == 64 ? 32 : (I == 128 ? 64 : 128); }
+inline uint64_t layout_bytes(uint64_t n, uint32_t I) { return num_buckets(n, I) * bucket_bytes(I); }
+
+DevLayout dev_layout(const fm_index *idx, uint32_t I, bool rev);
+
+// Workspace header (byte offsets); the rest of the workspace follows at kWsHeader.
+enum : size_t {
+    kWsQueue = 0,        // uint32 work-queue counter (exact / D walk)
+    kWsRequired = 8,     // uint64 hits every read would need
+    kWsPool = 16,        // uint64 hits appended to the staging pool
+    kWsQueue2 = 24,      // uint32 work-queue counter (DFS)
+    kWsStatOcc = 64,     // uint64 Occ8 queries
+    kWsStatBuckets = 72, // uint64 distinct buckets fetched
+    kWsStatWalk = 80,    // uint64 D-walk steps
+    kWsHeader = 256
+};
+
+struct InexactWs {       // sub-buffers of the inexact workspace
+    size_t bp, rs_count, rs_status, cursor, cnt, part, pool, stack, total;
+};
+InexactWs inexact_ws_layout(uint64_t nreads, uint32_t nstr, uint32_t zmax, uint64_t hit_cap, bool plain);
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t build_layout(const uint32_t *packed_dev, uint64_t n, uint32_t I, void *out,
+                        void *scratch, hipStream_t s);
+size_t build_layout_scratch(uint64_t n, uint32_t I);
+
+hipError_t launch_fill(void *p, uint32_t value, size_t words, hipStream_t s);
+
+hipError_t launch_occ8(const fm_index *idx, const fm_tuning &t, const fm_interval *q, uint64_t nq,
+                       uint32_t *out, hipStream_t s);
+
+struct WalkCall {
+    const uint8_t *codes;
+    const uint64_t *offs;
+    const uint8_t *z;
+    uint64_t nreads;
+    uint32_t flags;
+    uint32_t zmax;
+    void *out;
+    void *ws;
+};
+enum { WALK_EXACT = 0, WALK_DBP = 1, WALK_DFULL = 2 };
+hipError_t launch_walk(const fm_index *idx, const fm_tuning &t, int mode, bool plain,
+                       const WalkCall &c, hipStream_t s);
+hipError_t launch_darray_full(const fm_index *idx, const fm_tuning &t, const WalkCall &c, uint64_t total_len,
+                              hipStream_t s);
+
+struct DfsCall {
+    const uint8_t *codes;
+    const uint64_t *offs;
+    const uint8_t *z;
+    uint64_t nreads;
+    uint32_t flags;
+    uint32_t zmax;
+    fm_hit *hits;
+    uint64_t hit_cap;
+    uint64_t *hit_offs;
+    uint32_t *status;
+    void *ws;
+};
+hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuning &tw, bool plain,
+                          const DfsCall &c, hipStream_t s);
+
+int max_blocks_per_cu(const void *kernel, int block, size_t lds);
+
+}  // namespace fm

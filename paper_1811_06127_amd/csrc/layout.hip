@@ -1,0 +1,255 @@
+// layout.hip -- interleaved checkpoint layout (built once at load time), the fill
+// kernel used instead of memsets, and the Occ8 kernel.
+#include "fm_internal.hpp"
+
+namespace fm {
+
+// ------------------------------------------------------------------ fill
+
+__global__ void fill_kernel(uint32_t *p, uint32_t value, size_t words)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+hipError_t launch_fill(void *p, uint32_t value, size_t words, hipStream_t s)
+{
+    if (!words) return hipSuccess;
+    size_t blocks = (words + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fill_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, (uint32_t *)p, value, words);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ layout build
+
+constexpr int kTile = 8;          // buckets per thread in the scan passes
+constexpr int kScanBlock = 256;
+
+// Symbol totals (A, C, G, T; '$' counted as A) of each full bucket j < nb - 1; the last
+// bucket's total is never needed (no checkpoint follows it) and is left at zero.
+template <int I>
+__global__ void bucket_totals(const uint32_t *packed, uint64_t nb, uint4 *tot)
+{
+    const uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (j >= nb) return;
+    if (j == nb - 1) {
+        tot[j] = make_uint4(0, 0, 0, 0);
+        return;
+    }
+    const uint4 *w = (const uint4 *)(packed + j * (I / 16));
+    uint32_t slo = 0, shi = 0, sb = 0;
+#pragma unroll
+    for (int i = 0; i < I / 64; ++i) {
+        const uint4 v = w[i];
+        const uint32_t x[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const uint32_t lo = x[t] & EVEN, hi = (x[t] >> 1) & EVEN;
+            slo += __popc(lo);
+            shi += __popc(hi);
+            sb += __popc(lo & hi);
+        }
+    }
+    tot[j] = make_uint4(I - slo - shi + sb, slo - sb, shi - sb, sb);
+}
+
+// Pass A: per-block sums of kScanBlock * kTile consecutive totals.
+__global__ void scan_reduce4(const uint4 *tot, uint64_t nb, uint4 *part)
+{
+    __shared__ uint32_t lds[32];
+    const uint64_t base = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) * kTile;
+    uint4 acc = make_uint4(0, 0, 0, 0);
+    for (int t = 0; t < kTile; ++t) {
+        if (base + t < nb) {
+            uint4 v = tot[base + t];
+            acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+        }
+    }
+    uint32_t sx, sy, sz, sw;
+    block_scan_u32(acc.x, lds, &sx);
+    block_scan_u32(acc.y, lds, &sy);
+    block_scan_u32(acc.z, lds, &sz);
+    block_scan_u32(acc.w, lds, &sw);
+    if (threadIdx.x == 0) part[blockIdx.x] = make_uint4(sx, sy, sz, sw);
+}
+
+// Pass B: exclusive scan of the per-block sums, in place, by one block.
+__global__ void scan_partials4(uint4 *part, uint64_t np)
+{
+    __shared__ uint32_t lds[32];
+    const uint64_t per = (np + blockDim.x - 1) / blockDim.x;
+    const uint64_t b0 = threadIdx.x * per;
+    uint4 acc = make_uint4(0, 0, 0, 0);
+    for (uint64_t i = b0; i < b0 + per && i < np; ++i) {
+        uint4 v = part[i];
+        acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+    }
+    uint32_t t;
+    uint4 off;
+    off.x = block_scan_u32(acc.x, lds, &t);
+    off.y = block_scan_u32(acc.y, lds, &t);
+    off.z = block_scan_u32(acc.z, lds, &t);
+    off.w = block_scan_u32(acc.w, lds, &t);
+    for (uint64_t i = b0; i < b0 + per && i < np; ++i) {
+        uint4 v = part[i];
+        part[i] = off;
+        off.x += v.x; off.y += v.y; off.z += v.z; off.w += v.w;
+    }
+}
+
+// Pass C: checkpoint of every bucket (exclusive prefix of the totals) and the bucket
+// itself: counts chunk, symbol chunks copied from the packed BWT, zero padding.
+template <int I>
+__global__ void write_buckets(const uint32_t *packed, uint64_t nwords, const uint4 *tot, uint64_t nb,
+                              const uint4 *part, uint4 *out)
+{
+    __shared__ uint32_t lds[32];
+    constexpr int CH = Geo<I>::CH, USED = Geo<I>::USED;
+    const uint64_t base = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) * kTile;
+    uint4 loc[kTile];
+    uint4 acc = make_uint4(0, 0, 0, 0);
+    for (int t = 0; t < kTile; ++t) {
+        loc[t] = acc;
+        if (base + t < nb) {
+            uint4 v = tot[base + t];
+            acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+        }
+    }
+    uint32_t dummy;
+    uint4 off = part[blockIdx.x];
+    off.x += block_scan_u32(acc.x, lds, &dummy);
+    off.y += block_scan_u32(acc.y, lds, &dummy);
+    off.z += block_scan_u32(acc.z, lds, &dummy);
+    off.w += block_scan_u32(acc.w, lds, &dummy);
+    for (int t = 0; t < kTile; ++t) {
+        const uint64_t j = base + t;
+        if (j >= nb) break;
+        uint4 *b = out + j * CH;
+        b[0] = make_uint4(off.x + loc[t].x, off.y + loc[t].y, off.z + loc[t].z, off.w + loc[t].w);
+        for (int c = 1; c < CH; ++c) {
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (c < USED) {
+                const uint64_t w0 = j * (I / 16) + (uint64_t)(c - 1) * 4;
+                if (w0 + 0 < nwords) v.x = packed[w0 + 0];
+                if (w0 + 1 < nwords) v.y = packed[w0 + 1];
+                if (w0 + 2 < nwords) v.z = packed[w0 + 2];
+                if (w0 + 3 < nwords) v.w = packed[w0 + 3];
+            }
+            b[c] = v;
+        }
+    }
+}
+
+size_t build_layout_scratch(uint64_t n, uint32_t I)
+{
+    const uint64_t nb = num_buckets(n, I);
+    const uint64_t nblk = (nb + kScanBlock * kTile - 1) / (kScanBlock * kTile);
+    return (size_t)(nb * 16 + nblk * 16 + 256);
+}
+
+template <int I>
+static hipError_t build_layout_t(const uint32_t *packed, uint64_t n, void *out, void *scratch, hipStream_t s)
+{
+    const uint64_t nb = num_buckets(n, I);
+    const uint64_t nwords = (n + 1 + 15) / 16;
+    const uint64_t nblk = (nb + kScanBlock * kTile - 1) / (kScanBlock * kTile);
+    uint4 *tot = (uint4 *)scratch;
+    uint4 *part = (uint4 *)((char *)scratch + nb * 16);
+    hipLaunchKernelGGL(bucket_totals<I>, dim3((uint32_t)((nb + 255) / 256)), dim3(256), 0, s, packed, nb, tot);
+    hipLaunchKernelGGL(scan_reduce4, dim3((uint32_t)nblk), dim3(kScanBlock), 0, s, tot, nb, part);
+    hipLaunchKernelGGL(scan_partials4, dim3(1), dim3(1024), 0, s, part, nblk);
+    hipLaunchKernelGGL(write_buckets<I>, dim3((uint32_t)nblk), dim3(kScanBlock), 0, s, packed, nwords, tot, nb,
+                       part, (uint4 *)out);
+    return hipGetLastError();
+}
+
+hipError_t build_layout(const uint32_t *packed_dev, uint64_t n, uint32_t I, void *out, void *scratch, hipStream_t s)
+{
+    switch (I) {
+    case 64: return build_layout_t<64>(packed_dev, n, out, scratch, s);
+    case 128: return build_layout_t<128>(packed_dev, n, out, scratch, s);
+    case 256: return build_layout_t<256>(packed_dev, n, out, scratch, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------ Occ8
+
+// One query per group of L lanes, grid-stride. Out-of-range queries are answered with
+// all-ones and fetch bucket 0 instead of their own.
+template <int I, int L>
+__global__ void __launch_bounds__(256) occ8_kernel(DevLayout lay, const uint2 *q, uint64_t nq, uint32_t *out)
+{
+    const uint32_t q_lane = L == 1 ? 0 : (__lane_id() & (L - 1));
+    const uint64_t groups = (uint64_t)gridDim.x * (blockDim.x / L);
+    for (uint64_t g = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / L; g < nq; g += groups) {
+        const uint2 kl = q[g];
+        const bool ok = kl.x <= lay.n + 1 && kl.y <= lay.n;
+        Occ4 a, b;
+        occ8<I, L>(lay, q_lane, ok ? kl.x : 0u, ok ? kl.y : 0u, a, b);
+        if (!ok) {
+            a = Occ4{~0u, ~0u, ~0u, ~0u};
+            b = a;
+        }
+        uint32_t *o = out + g * 8;
+        if (L == 1) {
+            ((uint4 *)o)[0] = make_uint4(a.a, a.c, a.g, a.t);
+            ((uint4 *)o)[1] = make_uint4(b.a, b.c, b.g, b.t);
+        } else if (L == 2) {
+            ((uint4 *)o)[q_lane] = q_lane ? make_uint4(b.a, b.c, b.g, b.t) : make_uint4(a.a, a.c, a.g, a.t);
+        } else if (q_lane < 4) {
+            const Occ4 s = q_lane < 2 ? a : b;
+            ((uint2 *)o)[q_lane] = (q_lane & 1) ? make_uint2(s.g, s.t) : make_uint2(s.a, s.c);
+        }
+    }
+}
+
+template <int I, int L>
+static hipError_t occ8_launch(DevLayout lay, const fm_tuning &t, int cus, const fm_interval *q, uint64_t nq,
+                              uint32_t *out, hipStream_t s)
+{
+    const int block = (int)t.block;
+    int per = max_blocks_per_cu((const void *)occ8_kernel<I, L>, block, 0);
+    uint64_t want = (nq * L + block - 1) / block;
+    uint64_t grid = (uint64_t)cus * (per > 0 ? per : 1);
+    if (want < grid) grid = want;
+    if (grid == 0) grid = 1;
+    hipLaunchKernelGGL((occ8_kernel<I, L>), dim3((uint32_t)grid), dim3(block), 0, s, lay, (const uint2 *)q, nq, out);
+    return hipGetLastError();
+}
+
+template <int I>
+static hipError_t occ8_by_lanes(DevLayout lay, const fm_tuning &t, int cus, const fm_interval *q, uint64_t nq,
+                                uint32_t *out, hipStream_t s)
+{
+    switch (t.lanes) {
+    case 1: return occ8_launch<I, 1>(lay, t, cus, q, nq, out, s);
+    case 2: return occ8_launch<I, 2>(lay, t, cus, q, nq, out, s);
+    case 4: return occ8_launch<I, 4>(lay, t, cus, q, nq, out, s);
+    case 8: return occ8_launch<I, 8>(lay, t, cus, q, nq, out, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_occ8(const fm_index *idx, const fm_tuning &t, const fm_interval *q, uint64_t nq, uint32_t *out,
+                       hipStream_t s)
+{
+    if (!nq) return hipSuccess;
+    DevLayout lay = dev_layout(idx, t.occ_interval, false);
+    switch (t.occ_interval) {
+    case 64: return occ8_by_lanes<64>(lay, t, idx->cu_count, q, nq, out, s);
+    case 128: return occ8_by_lanes<128>(lay, t, idx->cu_count, q, nq, out, s);
+    case 256: return occ8_by_lanes<256>(lay, t, idx->cu_count, q, nq, out, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int max_blocks_per_cu(const void *kernel, int block, size_t lds)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, lds) != hipSuccess) return 1;
+    return n > 0 ? n : 1;
+}
+
+}  // namespace fm

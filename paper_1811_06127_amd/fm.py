@@ -1,0 +1,400 @@
+"""ctypes binding of libfmocc (include/fm.h), with torch tensors for device memory and
+torch.cuda streams (HIP streams under ROCm).
+
+Argument marshalling only: every step of every search runs in the library's HIP
+kernels. There is no fallback: if the library is not built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmocc.so")
+
+FM_OK, FM_EINVAL, FM_EIO, FM_EFORMAT, FM_ENOMEM, FM_EDEVICE, FM_EOVERFLOW, FM_EBUDGET, FM_ERANGE = range(9)
+FM_FWD, FM_REVCOMP, FM_BOTH, FM_DARRAY, FM_PLAIN, FM_STATS = 1, 2, 3, 4, 16, 32
+FM_LOAD_REVERSE, FM_LOAD_ALL_LAYOUTS = 1, 2
+FM_OP_EXACT, FM_OP_DARRAY, FM_OP_INEXACT = 0, 1, 2
+FM_ZMAX = 4
+
+# byte offsets inside the inexact workspace (see fm_search_inexact in fm.h)
+WS_REQUIRED, WS_STAT_OCC, WS_STAT_BUCKETS, WS_STAT_WALK = 8, 64, 72, 80
+
+
+class FmError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__("%s: %s (status %d)" % (what, strerror(status), status))
+        self.status = status
+
+
+class Interval(C.Structure):
+    _fields_ = [("k", C.c_uint32), ("l", C.c_uint32)]
+
+
+class LoadOpts(C.Structure):
+    _fields_ = [("device", C.c_int), ("occ_interval", C.c_uint32), ("flags", C.c_uint32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("dollar_row", C.c_uint64), ("C", C.c_uint64 * 5),
+                ("rev_dollar_row", C.c_uint64), ("rev_C", C.c_uint64 * 5), ("occ_interval", C.c_uint32),
+                ("layouts", C.c_uint32), ("has_reverse", C.c_uint32), ("pad", C.c_uint32),
+                ("device_bytes", C.c_uint64)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("occ_interval", C.c_uint32), ("lanes", C.c_uint32), ("depth", C.c_uint32),
+                ("block", C.c_uint32), ("waves_per_cu", C.c_uint32), ("node_budget", C.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+HIT_DTYPE = np.dtype([("read", "<u4"), ("k", "<u4"), ("l", "<u4"), ("strand", "u1"), ("nmm", "u1"),
+                      ("pad", "<u2")])
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libfmocc.so is not built (run __graft_entry__.build()); "
+                           "the FM-index searches have no other implementation")
+    L = C.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
+    sig = {
+        "fm_strerror": (C.c_char_p, [i32]),
+        "fm_version": (i32, []),
+        "fm_bwt_host": (i32, [vp, u64, vp, C.POINTER(C.c_uint64)]),
+        "fm_pack_host": (i32, [vp, u64, vp]),
+        "fm_index_build_file": (i32, [vp, u64, C.c_char_p, u32]),
+        "fm_index_from_text": (i32, [vp, u64, C.POINTER(LoadOpts), C.POINTER(vp)]),
+        "fm_index_from_codes": (i32, [vp, u64, vp, C.POINTER(LoadOpts), C.POINTER(vp)]),
+        "fm_index_load": (i32, [C.c_char_p, C.POINTER(LoadOpts), C.POINTER(vp)]),
+        "fm_index_info": (i32, [vp, C.POINTER(Info)]),
+        "fm_index_free": (None, [vp]),
+        "fm_get_tuning": (i32, [vp, i32, C.POINTER(Tuning)]),
+        "fm_set_tuning": (i32, [vp, i32, C.POINTER(Tuning)]),
+        "fm_autotune": (i32, [vp, i32, vp, vp, vp, u64, u32, u32, vp, u64, vp, vp, vp, C.c_size_t, C.c_char_p,
+                              vp, C.POINTER(Tuning), C.POINTER(C.c_float)]),
+        "fm_occ8": (i32, [vp, vp, u64, vp, vp]),
+        "fm_search_exact_workspace": (i32, [vp, u64, u32, C.POINTER(C.c_size_t)]),
+        "fm_search_exact": (i32, [vp, vp, vp, u64, u32, vp, vp, C.c_size_t, vp]),
+        "fm_darray": (i32, [vp, vp, vp, u64, u64, u32, vp, vp]),
+        "fm_search_inexact_workspace": (i32, [vp, u64, u64, u32, u32, u64, C.POINTER(C.c_size_t)]),
+        "fm_search_inexact": (i32, [vp, vp, vp, vp, u64, u32, u32, vp, u64, vp, vp, vp, C.c_size_t, vp]),
+        "fm_plan_create": (i32, [vp, i32, vp, vp, vp, u64, u32, u32, vp, u64, vp, vp, vp, C.c_size_t,
+                                 C.POINTER(vp)]),
+        "fm_plan_launch": (i32, [vp, vp]),
+        "fm_plan_free": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    return lib().fm_strerror(status).decode()
+
+
+def _check(status: int, what: str):
+    if status != FM_OK:
+        raise FmError(status, what)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        return t.data_ptr() if t.numel() else None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data if t.size else None
+    raise TypeError(type(t))
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+def _dev(t: torch.Tensor, dtype, what: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % what)
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous %s tensor" % (what, dtype))
+
+
+def nstrands(flags: int) -> int:
+    return (1 if flags & FM_FWD else 0) + (1 if flags & FM_REVCOMP else 0)
+
+
+# ---------------------------------------------------------------- host helpers
+
+def fm_bwt_host(text: np.ndarray):
+    text = np.ascontiguousarray(text, dtype=np.uint8)
+    bwt = np.zeros(text.size + 1, np.uint8)
+    dr = C.c_uint64(0)
+    _check(lib().fm_bwt_host(_ptr(text), text.size, _ptr(bwt), C.byref(dr)), "fm_bwt_host")
+    return bwt, int(dr.value)
+
+
+def fm_pack_host(codes: np.ndarray) -> np.ndarray:
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    words = np.zeros((codes.size + 15) // 16, np.uint32)
+    _check(lib().fm_pack_host(_ptr(codes), codes.size, _ptr(words)), "fm_pack_host")
+    return words
+
+
+def fm_index_build_file(text: np.ndarray, path: str, flags: int = 0):
+    text = np.ascontiguousarray(text, dtype=np.uint8)
+    _check(lib().fm_index_build_file(_ptr(text), text.size, path.encode(), flags), "fm_index_build_file")
+
+
+# ---------------------------------------------------------------- index
+
+class Index:
+    """An FM-index resident in device memory (owner of an fm_index handle)."""
+
+    def __init__(self, handle: int):
+        self._h = C.c_void_p(handle)
+
+    @staticmethod
+    def _opts(device, occ_interval, flags):
+        return LoadOpts(device, occ_interval, flags)
+
+    @classmethod
+    def from_text(cls, text: np.ndarray, device: int = 0, occ_interval: int = 128, flags: int = 0) -> "Index":
+        text = np.ascontiguousarray(text, dtype=np.uint8)
+        h = C.c_void_p()
+        o = cls._opts(device, occ_interval, flags)
+        _check(lib().fm_index_from_text(_ptr(text), text.size, C.byref(o), C.byref(h)), "fm_index_from_text")
+        return cls(h.value)
+
+    @classmethod
+    def from_codes(cls, bwt: np.ndarray, rev_bwt: np.ndarray | None = None, device: int = 0,
+                   occ_interval: int = 128, flags: int = 0) -> "Index":
+        bwt = np.ascontiguousarray(bwt, dtype=np.uint8)
+        rb = None if rev_bwt is None else np.ascontiguousarray(rev_bwt, dtype=np.uint8)
+        h = C.c_void_p()
+        o = cls._opts(device, occ_interval, flags)
+        _check(lib().fm_index_from_codes(_ptr(bwt), bwt.size, _ptr(rb), C.byref(o), C.byref(h)),
+               "fm_index_from_codes")
+        return cls(h.value)
+
+    @classmethod
+    def load(cls, path: str, device: int = 0, occ_interval: int = 128, flags: int = 0) -> "Index":
+        h = C.c_void_p()
+        o = cls._opts(device, occ_interval, flags)
+        _check(lib().fm_index_load(path.encode(), C.byref(o), C.byref(h)), "fm_index_load")
+        return cls(h.value)
+
+    @property
+    def handle(self) -> C.c_void_p:
+        if not self._h:
+            raise RuntimeError("index was freed")
+        return self._h
+
+    def info(self) -> dict:
+        i = Info()
+        _check(lib().fm_index_info(self.handle, C.byref(i)), "fm_index_info")
+        return {"n": i.n, "dollar_row": i.dollar_row, "C": list(i.C), "rev_dollar_row": i.rev_dollar_row,
+                "rev_C": list(i.rev_C), "occ_interval": i.occ_interval, "layouts": i.layouts,
+                "has_reverse": bool(i.has_reverse), "device_bytes": i.device_bytes}
+
+    def get_tuning(self, op: int) -> dict:
+        t = Tuning()
+        _check(lib().fm_get_tuning(self.handle, op, C.byref(t)), "fm_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, op: int, **kw):
+        cur = self.get_tuning(op)
+        cur.update(kw)
+        t = Tuning(**cur)
+        _check(lib().fm_set_tuning(self.handle, op, C.byref(t)), "fm_set_tuning")
+
+    def free(self):
+        if self._h:
+            lib().fm_index_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- searches
+
+def fm_occ8(idx: Index, q: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """q: (nq, 2) int32 device tensor of (k, l); returns (nq, 8) int32 (bit pattern of uint32)."""
+    _dev(q, torch.int32, "q")
+    nq = q.numel() // 2
+    if out is None:
+        out = torch.empty((nq, 8), dtype=torch.int32, device=q.device)
+    _dev(out, torch.int32, "out")
+    _check(lib().fm_occ8(idx.handle, _ptr(q), nq, _ptr(out), _stream(stream)), "fm_occ8")
+    return out
+
+
+def fm_search_exact_workspace(idx: Index, nreads: int, flags: int) -> int:
+    b = C.c_size_t(0)
+    _check(lib().fm_search_exact_workspace(idx.handle, nreads, flags, C.byref(b)), "fm_search_exact_workspace")
+    return int(b.value)
+
+
+def fm_search_exact(idx: Index, codes: torch.Tensor, offs: torch.Tensor, flags: int = FM_FWD,
+                    out: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """codes: uint8 device tensor; offs: int64 device tensor (nreads+1). Returns
+    (nreads * strands, 2) int32 intervals (k, l), strand-major within a read."""
+    _dev(codes, torch.uint8, "codes")
+    _dev(offs, torch.int64, "offs")
+    nreads = offs.numel() - 1
+    if out is None:
+        out = torch.empty((nreads * nstrands(flags), 2), dtype=torch.int32, device=codes.device)
+    need = fm_search_exact_workspace(idx, nreads, flags)
+    if ws is None and need:
+        ws = torch.empty(need, dtype=torch.uint8, device=codes.device)
+    wsb = ws.numel() if ws is not None else 0
+    _check(lib().fm_search_exact(idx.handle, _ptr(codes), _ptr(offs), nreads, flags, _ptr(out), _ptr(ws), wsb,
+                                 _stream(stream)), "fm_search_exact")
+    return out
+
+
+def fm_darray(idx: Index, codes: torch.Tensor, offs: torch.Tensor, total_len: int, flags: int = FM_FWD,
+              out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """D for each requested strand: (strands, total_len) uint8."""
+    _dev(codes, torch.uint8, "codes")
+    _dev(offs, torch.int64, "offs")
+    nreads = offs.numel() - 1
+    if out is None:
+        out = torch.zeros((nstrands(flags), total_len), dtype=torch.uint8, device=codes.device)
+    _check(lib().fm_darray(idx.handle, _ptr(codes), _ptr(offs), nreads, total_len, flags, _ptr(out),
+                           _stream(stream)), "fm_darray")
+    return out
+
+
+def fm_search_inexact_workspace(idx: Index, nreads: int, total_len: int, flags: int, zmax: int, hit_cap: int) -> int:
+    b = C.c_size_t(0)
+    _check(lib().fm_search_inexact_workspace(idx.handle, nreads, total_len, flags, zmax, hit_cap, C.byref(b)),
+           "fm_search_inexact_workspace")
+    return int(b.value)
+
+
+class InexactBuffers:
+    """Device buffers of one inexact call shape."""
+
+    def __init__(self, idx: Index, nreads: int, total_len: int, flags: int, zmax: int, hit_cap: int, device):
+        self.hits = torch.empty((max(hit_cap, 1), 4), dtype=torch.int32, device=device)
+        self.hit_offs = torch.empty(nreads + 1, dtype=torch.int64, device=device)
+        self.status = torch.empty(max(nreads, 1), dtype=torch.int32, device=device)
+        n = fm_search_inexact_workspace(idx, nreads, total_len, flags, zmax, hit_cap)
+        self.ws = torch.empty(n, dtype=torch.uint8, device=device)
+        self.hit_cap = hit_cap
+
+    def required(self) -> int:
+        return int(self.ws[WS_REQUIRED:WS_REQUIRED + 8].cpu().numpy().view(np.uint64)[0])
+
+    def stats(self) -> dict:
+        v = self.ws[WS_STAT_OCC:WS_STAT_OCC + 24].cpu().numpy().view(np.uint64)
+        return {"occ8": int(v[0]), "buckets": int(v[1]), "walk_steps": int(v[2])}
+
+
+def fm_search_inexact(idx: Index, codes: torch.Tensor, offs: torch.Tensor, z: torch.Tensor, flags: int,
+                      zmax: int, hit_cap: int, bufs: InexactBuffers | None = None, stream=None) -> InexactBuffers:
+    _dev(codes, torch.uint8, "codes")
+    _dev(offs, torch.int64, "offs")
+    _dev(z, torch.uint8, "z")
+    nreads = offs.numel() - 1
+    if bufs is None:
+        total_len = codes.numel()
+        bufs = InexactBuffers(idx, nreads, total_len, flags, zmax, hit_cap, codes.device)
+    _check(lib().fm_search_inexact(idx.handle, _ptr(codes), _ptr(offs), _ptr(z), nreads, flags, zmax,
+                                   _ptr(bufs.hits), bufs.hit_cap, _ptr(bufs.hit_offs), _ptr(bufs.status),
+                                   _ptr(bufs.ws), bufs.ws.numel(), _stream(stream)), "fm_search_inexact")
+    return bufs
+
+
+def hits_to_numpy(bufs: InexactBuffers, nreads: int):
+    """(hits as HIT_DTYPE array, hit_offs uint64, status uint32) copied to the host."""
+    offs = bufs.hit_offs[:nreads + 1].cpu().numpy().view(np.uint64).copy()
+    total = int(offs[-1]) if nreads >= 0 else 0
+    raw = bufs.hits[:total].cpu().numpy()
+    hits = raw.view(np.uint32).reshape(-1, 4).copy().view(HIT_DTYPE).reshape(-1)
+    status = bufs.status[:nreads].cpu().numpy().view(np.uint32).copy()
+    return hits, offs, status
+
+
+def fm_autotune(idx: Index, op: int, codes, offs, z, flags: int, zmax: int = 0, out=None,
+                bufs: InexactBuffers | None = None, ws=None, cache_path: str | None = None, stream=None):
+    nreads = offs.numel() - 1
+    best = Tuning()
+    ms = C.c_float(0)
+    if op == FM_OP_EXACT:
+        if out is None:
+            out = torch.empty((nreads * nstrands(flags), 2), dtype=torch.int32, device=codes.device)
+        if ws is None:
+            ws = torch.empty(max(fm_search_exact_workspace(idx, nreads, flags), 1), dtype=torch.uint8,
+                             device=codes.device)
+        st = lib().fm_autotune(idx.handle, op, _ptr(codes), _ptr(offs), None, nreads, flags, 0, _ptr(out), 0,
+                               None, None, _ptr(ws), ws.numel(), cache_path.encode() if cache_path else None,
+                               _stream(stream), C.byref(best), C.byref(ms))
+    else:
+        st = lib().fm_autotune(idx.handle, op, _ptr(codes), _ptr(offs), _ptr(z), nreads, flags, zmax,
+                               _ptr(bufs.hits), bufs.hit_cap, _ptr(bufs.hit_offs), _ptr(bufs.status), _ptr(bufs.ws),
+                               bufs.ws.numel(), cache_path.encode() if cache_path else None, _stream(stream),
+                               C.byref(best), C.byref(ms))
+    _check(st, "fm_autotune")
+    return best.as_dict(), float(ms.value)
+
+
+class Plan:
+    """A captured launch graph for one batch shape (fm_plan_*)."""
+
+    def __init__(self, idx: Index, op: int, codes, offs, z, flags: int, zmax: int = 0, out=None,
+                 bufs: InexactBuffers | None = None, ws=None):
+        nreads = offs.numel() - 1
+        h = C.c_void_p()
+        self._keep = (idx, codes, offs, z, out, bufs, ws)
+        if op == FM_OP_EXACT:
+            st = lib().fm_plan_create(idx.handle, op, _ptr(codes), _ptr(offs), None, nreads, flags, 0, _ptr(out), 0,
+                                      None, None, _ptr(ws), ws.numel() if ws is not None else 0, C.byref(h))
+        else:
+            st = lib().fm_plan_create(idx.handle, op, _ptr(codes), _ptr(offs), _ptr(z), nreads, flags, zmax,
+                                      _ptr(bufs.hits), bufs.hit_cap, _ptr(bufs.hit_offs), _ptr(bufs.status),
+                                      _ptr(bufs.ws), bufs.ws.numel(), C.byref(h))
+        _check(st, "fm_plan_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().fm_plan_launch(self._h, _stream(stream)), "fm_plan_launch")
+
+    def free(self):
+        if self._h:
+            lib().fm_plan_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def reads_to_device(codes: np.ndarray, offs: np.ndarray, z: np.ndarray | None = None, device="cuda"):
+    c = torch.from_numpy(np.ascontiguousarray(codes, dtype=np.uint8)).to(device)
+    o = torch.from_numpy(np.ascontiguousarray(offs, dtype=np.uint64).view(np.int64)).to(device)
+    zz = None if z is None else torch.from_numpy(np.ascontiguousarray(z, dtype=np.uint8)).to(device)
+    return c, o, zz

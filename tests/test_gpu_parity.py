@@ -1,0 +1,293 @@
+"""Parity of the HIP kernels (through the C ABI) with the CPU oracle, element by element,
+on seeded inputs that span many buckets and end in ragged tails."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_1811_06127_amd import fm
+
+pytestmark = pytest.mark.gpu
+
+LAYOUTS = (64, 128, 256)
+LANES = {64: (1, 2), 128: (1, 2, 4), 256: (1, 2, 4, 8)}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def small():
+    """A 70,001-base text with repeats (ragged last bucket for every I), its oracle index
+    and the reverse-text oracle index, and a GPU index with every layout."""
+    R = synth.reference_with_repeats(70_001, 4242, copy_frac=0.08, copy_len=(300, 2000), copy_sub=0.02,
+                                     tandem_frac=0.02, tandem_unit=(2, 12), tandem_len=(100, 400))
+    x = oracle.OracleIndex(R)
+    xr = oracle.OracleIndex(oracle.reverse_text(R))
+    idx = fm.Index.from_text(R, occ_interval=128, flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_ALL_LAYOUTS)
+    say("small index built", idx.info())
+    return R, x, xr, idx
+
+
+def to_u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def test_index_constants(small):
+    R, x, xr, idx = small
+    info = idx.info()
+    assert info["n"] == R.size and info["dollar_row"] == x.dollar_row
+    assert info["C"] == x.C.tolist()
+    assert info["rev_dollar_row"] == xr.dollar_row and info["rev_C"] == xr.C.tolist()
+    assert info["layouts"] == 7 and info["has_reverse"]
+
+
+def occ8_queries(n, dollar):
+    q = [synth.occ8_queries(n, 20_000, 7, "uniform"), synth.occ8_queries(n, 20_000, 8, "narrow")]
+    edge = []
+    for I in LAYOUTS:
+        for b in range(0, n + 2, I * 37):
+            for d in (-2, -1, 0, 1, 2):
+                p = b + d
+                if 0 <= p <= n:
+                    edge += [(p, p), (p + 1, p), (0, p), (p, n), (max(p - 5, 0), p)]
+    for p in (dollar - 1, dollar, dollar + 1):
+        if 0 <= p <= n:
+            edge += [(p, p), (p + 1, p), (0, p), (p + 1, n)]
+    edge += [(0, 0), (0, n), (n + 1, n), (n, n), (1, 0), (n + 1, 0)]
+    bad = [(n + 2, 0), (0, n + 1), (0xFFFFFFFF, 5), (3, 0xFFFFFFFF)]
+    return np.concatenate(q + [np.array(edge + bad, np.uint32)])
+
+
+@pytest.mark.parametrize("I", LAYOUTS)
+def test_occ8_all_lanes(small, I):
+    R, x, xr, idx = small
+    q = occ8_queries(R.size, x.dollar_row)
+    want = x.occ8(q)
+    qd = torch.from_numpy(q.view(np.int32)).cuda()
+    for L in LANES[I]:
+        idx.set_tuning(fm.FM_OP_EXACT, occ_interval=I, lanes=L)
+        got = to_u32(fm.fm_occ8(idx, qd))
+        torch.cuda.synchronize()
+        bad = np.nonzero((got != want).any(axis=1))[0]
+        assert bad.size == 0, (I, L, q[bad[:5]], got[bad[:5]], want[bad[:5]])
+    idx.set_tuning(fm.FM_OP_EXACT, occ_interval=128, lanes=4)
+
+
+def test_occ8_fig2_block():
+    """The 32 symbols of Fig. 2 at the start of a BWT: Occ at row 31 counts them (G = 6,
+    the figure's final value), and every prefix count matches a direct count."""
+    s = "ccacttgcgaaatttacaaggtttattaggtt"
+    code = {"a": 0, "c": 1, "g": 2, "t": 3}
+    head = np.array([code[c] for c in s], np.uint8)
+    tail = synth.iid_reference(300, 5)
+    bwt = np.concatenate([head, tail, np.array([4], np.uint8)])
+    for I in LAYOUTS:
+        idx = fm.Index.from_codes(bwt, occ_interval=I)
+        q = np.array([[0, p] for p in range(bwt.size)], np.uint32)
+        got = to_u32(fm.fm_occ8(idx, torch.from_numpy(q.view(np.int32)).cuda()))[:, 4:]
+        assert got[31].tolist() == [9, 5, 6, 12]
+        want = np.zeros((bwt.size, 4), np.int64)
+        for p in range(bwt.size):
+            want[p] = [np.count_nonzero(bwt[:p + 1] == c) for c in range(4)]
+        assert np.array_equal(got, want)
+        idx.free()
+
+
+def exact_inputs(R):
+    rng = np.random.default_rng(99)
+    pats = []
+    for j in range(3000):
+        m = int(rng.integers(1, 120))
+        if j % 3 == 0:
+            w = rng.integers(0, 4, m).astype(np.uint8)
+        else:
+            p = int(rng.integers(0, R.size - m))
+            w = R[p:p + m].copy()
+            if j % 7 == 0:
+                w[int(rng.integers(0, m))] = (w[0] + 1) % 4
+        if j % 50 == 0:
+            w[int(rng.integers(0, m))] = 4
+        pats.append(w)
+    pats += [np.zeros(0, np.uint8), np.zeros(0, np.uint8), R[:40].copy(), R[-40:].copy(), np.array([4], np.uint8)]
+    offs = np.zeros(len(pats) + 1, np.uint64)
+    offs[1:] = np.cumsum([p.size for p in pats])
+    return np.concatenate(pats), offs
+
+
+@pytest.mark.parametrize("flags", [fm.FM_FWD, fm.FM_REVCOMP, fm.FM_BOTH])
+def test_exact_plain_and_batched(small, flags):
+    R, x, xr, idx = small
+    codes, offs = exact_inputs(R)
+    want = x.exact(codes, offs, flags, "definition")
+    cd, od, _ = fm.reads_to_device(codes, offs)
+    got = to_u32(fm.fm_search_exact(idx, cd, od, flags | fm.FM_PLAIN))
+    assert np.array_equal(got, want)
+    for I in LAYOUTS:
+        for L in LANES[I]:
+            for P in (1, 2):
+                idx.set_tuning(fm.FM_OP_EXACT, occ_interval=I, lanes=L, depth=P)
+                got = to_u32(fm.fm_search_exact(idx, cd, od, flags))
+                bad = np.nonzero((got != want).any(axis=1))[0]
+                assert bad.size == 0, (I, L, P, bad[:5], got[bad[:5]], want[bad[:5]])
+    idx.set_tuning(fm.FM_OP_EXACT, occ_interval=128, lanes=4, depth=2)
+
+
+def test_exact_cfg1_workload():
+    w = synth.cfg1_small()
+    x = oracle.OracleIndex(w.ref)
+    want = x.exact(w.reads.codes, w.reads.offs, oracle.FWD, "definition")
+    idx = fm.Index.from_text(w.ref, occ_interval=128)
+    cd, od, _ = fm.reads_to_device(w.reads.codes, w.reads.offs)
+    for flags in (fm.FM_FWD | fm.FM_PLAIN, fm.FM_FWD):
+        got = to_u32(fm.fm_search_exact(idx, cd, od, flags))
+        assert np.array_equal(got, want)
+    hits = np.count_nonzero(want[:5000, 0] <= want[:5000, 1])
+    assert hits == 5000          # the copied half always occurs
+    idx.free()
+
+
+@pytest.mark.parametrize("flags", [fm.FM_FWD, fm.FM_BOTH])
+def test_darray(small, flags):
+    R, x, xr, idx = small
+    codes, offs = exact_inputs(R)
+    want = xr.darray(codes, offs, flags)
+    cd, od, _ = fm.reads_to_device(codes, offs)
+    for I in LAYOUTS:
+        idx.set_tuning(fm.FM_OP_DARRAY, occ_interval=I)
+        got = fm.fm_darray(idx, cd, od, int(offs[-1]), flags).cpu().numpy()
+        assert np.array_equal(got, want), I
+    idx.set_tuning(fm.FM_OP_DARRAY, occ_interval=128)
+
+
+def inexact_inputs(R, count=1500, seed=3):
+    rd = synth.simulate_reads(R, count, seed, length=(20, 90), sub=(0.0, 0.06), z=(0, 2))
+    codes = rd.codes.copy()
+    codes[::997] = 4                                # sprinkle N
+    # an empty read and a read of N only
+    codes = np.concatenate([codes, np.array([4, 4, 4], np.uint8)])
+    offs = np.concatenate([rd.offs, [rd.offs[-1], rd.offs[-1] + 3]]).astype(np.uint64)
+    z = np.concatenate([rd.z, [1, 2]]).astype(np.uint8)
+    return codes, offs, z
+
+
+def run_inexact(idx, codes, offs, z, flags, zmax, cap=1 << 16):
+    cd, od, zd = fm.reads_to_device(codes, offs, z)
+    bufs = fm.fm_search_inexact(idx, cd, od, zd, flags, zmax, cap)
+    return fm.hits_to_numpy(bufs, offs.size - 1), bufs
+
+
+def assert_same_hits(got, want_hits, want_offs, tag):
+    hits, hoffs, status = got
+    assert (status == 0).all(), (tag, np.unique(status))
+    assert np.array_equal(hoffs, want_offs), tag
+    for f in ("read", "k", "l", "strand"):
+        assert np.array_equal(hits[f], want_hits[f]), (tag, f)
+    assert np.array_equal(hits["nmm"], want_hits["d"]), tag
+
+
+@pytest.mark.parametrize("use_d", [False, True])
+def test_inexact_plain_and_batched(small, use_d):
+    R, x, xr, idx = small
+    codes, offs, z = inexact_inputs(R)
+    method = "listing2_darray" if use_d else "listing2"
+    wh, wo = x.inexact(codes, offs, z, oracle.BOTH, method, rev=xr)
+    say("oracle hits", wh.size)
+    flags = fm.FM_BOTH | (fm.FM_DARRAY if use_d else 0)
+    assert_same_hits(run_inexact(idx, codes, offs, z, flags | fm.FM_PLAIN, 2)[0], wh, wo, "plain")
+    for I in LAYOUTS:
+        for L in LANES[I]:
+            idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=I, lanes=L)
+            idx.set_tuning(fm.FM_OP_DARRAY, occ_interval=I, lanes=min(L, 4))
+            assert_same_hits(run_inexact(idx, codes, offs, z, flags, 2)[0], wh, wo, (I, L))
+    idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=128, lanes=1)
+    idx.set_tuning(fm.FM_OP_DARRAY, occ_interval=128, lanes=4)
+
+
+def test_inexact_definition_and_node_count(small):
+    """Hits equal the Hamming-ball definition; expanded nodes equal the oracle's."""
+    R, x, xr, idx = small
+    codes, offs, z = inexact_inputs(R, count=300, seed=11)
+    z = np.minimum(z, 1)
+    wh, wo = x.inexact(codes, offs, z, oracle.BOTH, "definition")
+    lh, lo, nodes = x.inexact(codes, offs, z, oracle.BOTH, "listing2_darray", rev=xr, return_nodes=True)
+    assert np.array_equal(wh, lh) and np.array_equal(wo, lo)
+    for extra in (fm.FM_PLAIN, 0):
+        got, bufs = run_inexact(idx, codes, offs, z, fm.FM_BOTH | fm.FM_DARRAY | fm.FM_STATS | extra, 1)
+        assert_same_hits(got, wh, wo, "def")
+        assert bufs.stats()["occ8"] == int(nodes.sum())
+
+
+def test_inexact_zmax4_and_limits(small):
+    R, x, xr, idx = small
+    rd = synth.simulate_reads(R, 60, 21, length=(12, 18), sub=(0.0, 0.1), z=(0, 4))
+    wh, wo = x.inexact(rd.codes, rd.offs, rd.z, oracle.BOTH, "listing2_darray", rev=xr)
+    for extra in (fm.FM_PLAIN, 0):
+        got, _ = run_inexact(idx, rd.codes, rd.offs, rd.z, fm.FM_BOTH | fm.FM_DARRAY | extra, 4, cap=1 << 20)
+        assert_same_hits(got, wh, wo, "z4")
+    # budgets above zmax are rejected per read, others unaffected
+    got, _ = run_inexact(idx, rd.codes, rd.offs, rd.z, fm.FM_BOTH | fm.FM_DARRAY, 2, cap=1 << 20)
+    hits, hoffs, status = got
+    assert ((status == fm.FM_EINVAL) == (rd.z > 2)).all()
+    ok = np.nonzero(rd.z <= 2)[0]
+    for r in ok[:20]:
+        a = hits[int(hoffs[r]):int(hoffs[r + 1])]
+        b = wh[int(wo[r]):int(wo[r + 1])]
+        assert np.array_equal(a["k"], b["k"]) and np.array_equal(a["nmm"], b["d"])
+
+
+def test_inexact_overflow_and_retry(small):
+    R, x, xr, idx = small
+    codes, offs, z = inexact_inputs(R, count=400, seed=5)
+    wh, wo = x.inexact(codes, offs, z, oracle.BOTH, "listing2")
+    total = int(wo[-1])
+    cap = total // 3
+    (hits, hoffs, status), bufs = run_inexact(idx, codes, offs, z, fm.FM_BOTH, 2, cap=cap)
+    assert bufs.required() == total
+    assert (status == fm.FM_EOVERFLOW).any()
+    okr = np.nonzero(status == 0)[0]
+    for r in okr:
+        a = hits[int(hoffs[r]):int(hoffs[r + 1])]
+        b = wh[int(wo[r]):int(wo[r + 1])]
+        assert np.array_equal(a["k"], b["k"]) and np.array_equal(a["l"], b["l"])
+    for r in np.nonzero(status == fm.FM_EOVERFLOW)[0]:
+        assert hoffs[r] == hoffs[r + 1]
+    got, _ = run_inexact(idx, codes, offs, z, fm.FM_BOTH, 2, cap=bufs.required())
+    assert_same_hits(got, wh, wo, "retry")
+
+
+def test_inexact_node_budget(small):
+    R, x, xr, idx = small
+    codes, offs, z = inexact_inputs(R, count=200, seed=6)
+    idx.set_tuning(fm.FM_OP_INEXACT, node_budget=30)
+    try:
+        a = run_inexact(idx, codes, offs, z, fm.FM_BOTH | fm.FM_PLAIN, 2)[0]
+        b = run_inexact(idx, codes, offs, z, fm.FM_BOTH, 2)[0]
+    finally:
+        idx.set_tuning(fm.FM_OP_INEXACT, node_budget=1 << 22)
+    assert (a[2] == fm.FM_EBUDGET).any()
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[0], b[0])
+
+
+def test_determinism_and_batch_independence(small):
+    R, x, xr, idx = small
+    codes, offs, z = inexact_inputs(R, count=800, seed=8)
+    flags = fm.FM_BOTH | fm.FM_DARRAY
+    a = run_inexact(idx, codes, offs, z, flags, 2)[0]
+    b = run_inexact(idx, codes, offs, z, flags, 2)[0]
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    # a permuted batch gives each read the same hits
+    rng = np.random.default_rng(1)
+    perm = rng.permutation(offs.size - 1)
+    rd = synth.Reads(codes, offs, z, np.zeros(z.size, np.int64), np.zeros(z.size, np.uint8)).subset(perm)
+    c = run_inexact(idx, rd.codes, rd.offs, rd.z, flags, 2)[0]
+    for j, r in enumerate(perm):
+        ha = a[0][int(a[1][r]):int(a[1][r + 1])]
+        hc = c[0][int(c[1][j]):int(c[1][j + 1])]
+        assert np.array_equal(ha[["k", "l", "strand", "nmm"]], hc[["k", "l", "strand", "nmm"]])
