@@ -1,0 +1,290 @@
+#!/usr/bin/env python3
+"""Throughput of the FM-index hot path on one MI355X.
+
+Workload (one step): a 2^24-base reference (95% i.i.d. bases plus 500-5,000 bp copies
+with 2% substitutions), 1,000,000 reads of 100 bp sampled from either strand with 1%
+substitutions; the exact backward search of every read on both strands, then the
+z=1 substitution search on both strands pruned by the D lower bound. Inputs are
+resident in device memory before timing starts; the index is built once, untimed.
+
+Prints one JSON line: reads/s of the batched persistent kernels (value), the plain
+one-thread-per-read-strand kernels on the same step, Occ8 rates, the roofline of the
+dominant kernel and the CPU oracle's rate on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "reads/s & Occ8 queries/s, batched vs plain kernel, bit-exact; p99 latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--reads", type=int, default=1_000_000)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--occ8-queries", type=int, default=1 << 26)
+    ap.add_argument("--cpu-sample", type=int, default=100_000,
+                    help="reads the CPU oracle searches for the baseline (0 skips it)")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one plain device-to-device copy of this many MiB (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the search shards by replicating the index and splitting the "
+              "reads, and this build runs and reports the single-GPU share only (--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1811_06127_amd import fm
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d bytes read, %d bytes written" % (n, n))
+        del src, dst
+    t0 = time.time()
+    R = synth.cfg2_reference()
+    rd = synth.cfg2_reads(R, args.reads)
+    log("inputs generated in %.1fs: n=%d reads=%d" % (time.time() - t0, R.size, rd.count))
+    t0 = time.time()
+    idx = fm.Index.from_text(R, occ_interval=128, flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_ALL_LAYOUTS)
+    log("index built in %.1fs" % (time.time() - t0))
+
+    nreads = rd.count
+    total_len = int(rd.offs[-1])
+    codes, offs, z = fm.reads_to_device(rd.codes, rd.offs, rd.z, dev)
+    EXACT = fm.FM_BOTH
+    INEXACT = fm.FM_BOTH | fm.FM_DARRAY
+    ZMAX = 1
+    hit_cap = 4 * nreads
+    ex_out = torch.empty((2 * nreads, 2), dtype=torch.int32, device=dev)
+    ex_ws = torch.zeros(fm.fm_search_exact_workspace(idx, nreads, EXACT), dtype=torch.uint8, device=dev)
+    # workspace sized for the plain kernels too (they keep their DFS stacks in it)
+    bufs = fm.InexactBuffers(idx, nreads, total_len, INEXACT | fm.FM_PLAIN, ZMAX, hit_cap, dev)
+
+    tuning = {}
+    if not args.no_tune:
+        t0 = time.time()
+        tuning["exact"] = fm.fm_autotune(idx, fm.FM_OP_EXACT, codes, offs, None, EXACT, out=ex_out, ws=ex_ws,
+                                         cache_path=args.tune_cache)
+        tuning["inexact"] = fm.fm_autotune(idx, fm.FM_OP_INEXACT, codes, offs, z, INEXACT, ZMAX, bufs=bufs,
+                                           cache_path=args.tune_cache)
+        tuning["d_walk"] = fm.fm_autotune(idx, fm.FM_OP_DARRAY, codes, offs, z, INEXACT, ZMAX, bufs=bufs,
+                                          cache_path=args.tune_cache)
+        log("autotuned in %.1fs: %s" % (time.time() - t0, tuning))
+    for name, op in (("exact", fm.FM_OP_EXACT), ("d_walk", fm.FM_OP_DARRAY), ("inexact", fm.FM_OP_INEXACT)):
+        tuning.setdefault(name, (idx.get_tuning(op), None))
+        tuning[name] = {"config": idx.get_tuning(op), "ms": tuning[name][1]}
+
+    def step(extra=0):
+        fm.fm_search_exact(idx, codes, offs, EXACT | extra, out=ex_out, ws=ex_ws)
+        fm.fm_search_inexact(idx, codes, offs, z, INEXACT | extra, ZMAX, hit_cap, bufs=bufs)
+
+    # work counters of one step (untimed)
+    step(fm.FM_STATS)
+    torch.cuda.synchronize()
+    ex_stats = fm.exact_stats(ex_ws)
+    in_stats = bufs.stats()
+    log("stats:", ex_stats, in_stats)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    idx.phase_timing(2 * args.steps)          # two calls per step: exact, then inexact
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    phases, calls = idx.phase_times()
+    idx.phase_timing(0)
+    assert calls == 2 * args.steps, calls
+    phase_ms = {k: v / args.steps for k, v in phases.items()}
+    log("batched: %.3f ms/step, phases per step %s" % (ms_step, phase_ms))
+    ex_batched = ex_out.clone()
+    in_batched = fm.hits_to_numpy(bufs, nreads)
+
+    # the same step replayed from launch graphs captured for this batch shape
+    plans = [fm.Plan(idx, fm.FM_OP_EXACT, codes, offs, None, EXACT, out=ex_out, ws=ex_ws),
+             fm.Plan(idx, fm.FM_OP_INEXACT, codes, offs, z, INEXACT, ZMAX, bufs=bufs)]
+    for p in plans:
+        p.launch()
+    torch.cuda.synchronize()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record()
+    for _ in range(args.steps):
+        for p in plans:
+            p.launch()
+    g1.record()
+    torch.cuda.synchronize()
+    graph_ms = g0.elapsed_time(g1) / args.steps
+    graph_equal = bool(torch.equal(ex_out, ex_batched)) and all(
+        np.array_equal(a, b) for a, b in zip(fm.hits_to_numpy(bufs, nreads), in_batched))
+    for p in plans:
+        p.free()
+    log("graph replay: %.3f ms/step, identical: %s" % (graph_ms, graph_equal))
+
+    # the plain kernels on the same step, and their agreement with the batched ones
+    plain_ms = None
+    plain_equal = None
+    if args.plain_steps > 0:
+        step(fm.FM_PLAIN)
+        torch.cuda.synchronize()
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0.record()
+        for _ in range(args.plain_steps):
+            step(fm.FM_PLAIN)
+        p1.record()
+        torch.cuda.synchronize()
+        plain_ms = p0.elapsed_time(p1) / args.plain_steps
+        in_plain = fm.hits_to_numpy(bufs, nreads)
+        plain_equal = bool(torch.equal(ex_out, ex_batched)) and all(
+            np.array_equal(a, b) for a, b in zip(in_plain, in_batched))
+        log("plain: %.3f ms/step, identical to batched: %s" % (plain_ms, plain_equal))
+
+    # Occ8 micro-benchmark: independent uniform (k, l) pairs
+    occ8_rate = None
+    if args.occ8_queries:
+        q = torch.from_numpy(synth.occ8_queries(R.size, args.occ8_queries, 4242, "uniform").view(np.int32)).to(dev)
+        qo = torch.empty((args.occ8_queries, 8), dtype=torch.int32, device=dev)
+        fm.fm_occ8(idx, q, out=qo)
+        torch.cuda.synchronize()
+        q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        q0.record()
+        for _ in range(3):
+            fm.fm_occ8(idx, q, out=qo)
+        q1.record()
+        torch.cuda.synchronize()
+        occ8_rate = args.occ8_queries / (q0.elapsed_time(q1) / 3 / 1e3)
+        del q, qo
+
+    # roofline of the dominant kernel: algorithmic bytes per launch / its event-timed duration
+    I = tuning["inexact"]["config"]["occ_interval"]
+    Iw = tuning["d_walk"]["config"]["occ_interval"]
+    Ie = tuning["exact"]["config"]["occ_interval"]
+    nrs = 2 * nreads
+    n_hits = int(in_batched[1][-1])
+    alg = {
+        "exact_walk": ex_stats["buckets"] * (16 + Ie // 4) + 2 * total_len + 8 * nrs,
+        "d_walk": in_stats["walk_buckets"] * (16 + Iw // 4) + 2 * total_len + 16 * nrs,
+        "dfs": in_stats["buckets"] * (16 + I // 4) + 2 * total_len + 24 * nrs + 16 * n_hits,
+    }
+    dom = max(("exact_walk", "d_walk", "dfs"), key=lambda k: phase_ms[k])
+    achieved = alg[dom] / (phase_ms[dom] / 1e3) / 1e9
+    roofline = {"bound": "hbm", "kernel": {"exact_walk": "walk_batched<EXACT>", "d_walk": "walk_batched<DBP>",
+                                           "dfs": "dfs_batched"}[dom],
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": int(alg[dom]), "avg_launch_ms": round(phase_ms[dom], 4)}
+
+    cpu = None
+    parity = None
+    if args.cpu_sample > 0:
+        cpu, parity = cpu_baseline(R, rd, min(args.cpu_sample, nreads), ex_batched, in_batched)
+
+    reads_s = nreads / (ms_step / 1e3)
+    out = {
+        "metric": METRIC,
+        "value": round(reads_s, 1),
+        "unit": "reads/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded SplitMix64 reference and reads)",
+        "config": {"workload": "2^24-base reference with 5% copies (2% divergence); 1M reads x 100 bp, 1% "
+                               "substitutions, either strand; exact + z=1 substitution search, both strands, "
+                               "D-array pruning",
+                   "n": int(R.size), "reads": nreads, "read_len": 100, "z": ZMAX, "strands": 2,
+                   "hit_cap": hit_cap},
+        "plain_reads_per_s": round(nreads / (plain_ms / 1e3), 1) if plain_ms else None,
+        "batched_vs_plain": round(plain_ms / ms_step, 3) if plain_ms else None,
+        "batched_equals_plain": plain_equal,
+        "graph_ms_per_step": round(graph_ms, 4),
+        "graph_equals_eager": graph_equal,
+        "occ8_queries_per_s": {"fm_occ8_uniform": round(occ8_rate, 1) if occ8_rate else None,
+                               "dfs_in_step": round(in_stats["occ8"] / (phase_ms["dfs"] / 1e3), 1)},
+        "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
+        "work_per_step": {"exact_steps": ex_stats["steps"], "exact_buckets": ex_stats["buckets"],
+                          "d_walk_steps": in_stats["walk_steps"], "d_walk_buckets": in_stats["walk_buckets"],
+                          "dfs_nodes": in_stats["occ8"], "dfs_buckets": in_stats["buckets"], "hits": n_hits},
+        "tuning": tuning,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity_sample": parity,
+        "p99_latency_ms": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(R, rd, sample, ex_batched, in_batched):
+    """The CPU oracle (Listing 1 exact + Listing 2 with the D bound, one thread) on the
+    first `sample` reads of the same batch; also checks the GPU's outputs for them."""
+    import oracle
+    t0 = time.time()
+    x = oracle.OracleIndex(R)
+    xr = oracle.OracleIndex(oracle.reverse_text(R))
+    log("oracle indexes built in %.1fs" % (time.time() - t0))
+    s = rd.subset(np.arange(sample))
+    t0 = time.time()
+    ex = x.exact(s.codes, s.offs, oracle.BOTH, "listing1")
+    hits, hoffs = x.inexact(s.codes, s.offs, s.z, oracle.BOTH, "listing2_darray", rev=xr)
+    dt = time.time() - t0
+    log("oracle: %d reads in %.1fs" % (sample, dt))
+    gex = ex_batched[:2 * sample].cpu().numpy().view(np.uint32)
+    gh, go, gs = in_batched
+    n = int(go[sample])
+    g = gh[:n]
+    ok_ex = bool(np.array_equal(gex, ex))
+    ok_in = bool(np.array_equal(go[:sample + 1], hoffs) and (gs[:sample] == 0).all()
+                 and all(np.array_equal(g[f], hits[f]) for f in ("read", "k", "l", "strand"))
+                 and np.array_equal(g["nmm"], hits["d"]))
+    cpu = {"value": round(sample / dt, 1), "unit": "reads/s", "cores": 1, "kind": "oracle",
+           "sample": "first %d of the step's reads; exact (Listing 1) + z=1 inexact (Listing 2, D bound), "
+                     "both strands, single-threaded, index prebuilt" % sample}
+    parity = {"reads": sample, "exact_bit_exact": ok_ex, "inexact_bit_exact": ok_in}
+    return cpu, parity
+
+
+if __name__ == "__main__":
+    main()

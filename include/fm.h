@@ -192,14 +192,16 @@ int fm_occ8(const fm_index *idx, const fm_interval *q, uint64_t nq, uint32_t *ou
 
 /* ----------------------------------------------------------------- exact search */
 
-/* Workspace bytes fm_search_exact needs (a few hundred bytes; 0 with FM_PLAIN). */
+/* Workspace bytes fm_search_exact needs (256; also with FM_PLAIN, where ws may be NULL
+ * unless FM_STATS is set). With FM_STATS the uint64s at byte offsets 80 and 88 of ws
+ * count the search steps that fetched and the buckets they fetched. */
 int fm_search_exact_workspace(const fm_index *idx, uint64_t nreads, uint32_t flags, size_t *bytes);
 
 /* Backward exact match (Listing 1) of every read on the strands in flags.
  * codes: device, offs[nreads] bytes (reads concatenated). offs: device, nreads+1
  * uint64 CSR offsets, offs[0] = 0. out: device, one fm_interval per read and strand,
  * out[s_count * r + j] for the j-th requested strand. ws: device workspace (may be
- * NULL with FM_PLAIN). An empty read gives (0, n); a miss or a non-ACGT symbol gives
+ * NULL with FM_PLAIN and no FM_STATS). An empty read gives (0, n); a miss or a non-ACGT symbol gives
  * (1, 0). Reads may have any length below 2^32. */
 int fm_search_exact(const fm_index *idx, const uint8_t *codes, const uint64_t *offs,
                     uint64_t nreads, uint32_t flags, fm_interval *out, void *ws,
@@ -239,12 +241,25 @@ int fm_search_inexact_workspace(const fm_index *idx, uint64_t nreads, uint64_t t
  *      would need (for a retry with a larger hit_cap); with FM_STATS the uint64s at
  *      offsets 64 (expanded DFS nodes, each one Occ8 step), 72 (buckets fetched by
  *      them; a node whose interval is still (0, n) takes its children from C and
- *      fetches none) and 80 (D-walk steps that fetched) count the work done.
+ *      fetches none), 80 (D-walk steps that fetched) and 88 (buckets they fetched)
+ *      count the work done.
  * Output is deterministic: independent of scheduling, batch order and launch tuning. */
 int fm_search_inexact(const fm_index *idx, const uint8_t *codes, const uint64_t *offs,
                       const uint8_t *z, uint64_t nreads, uint32_t flags, uint32_t zmax,
                       fm_hit *hits, uint64_t hit_cap, uint64_t *hit_offs, uint32_t *status,
                       void *ws, size_t ws_bytes, void *stream);
+
+/* ----------------------------------------------------------------- phase timing */
+
+/* Diagnostics. With capacity > 0, every later search call on idx records HIP events on
+ * its stream at its phase boundaries (the first `capacity` calls are kept); capacity 0
+ * turns this off. Not for concurrent use, and off while a plan is captured. */
+int fm_phase_timing(fm_index *idx, uint32_t capacity);
+
+/* Waits for the recorded events and writes the milliseconds spent per phase, summed
+ * over the recorded calls: ms[0] exact walk, ms[1] D walk, ms[2] DFS kernel, ms[3]
+ * compaction; *calls (nullable) gets the number of calls. Clears the record. */
+int fm_phase_times(fm_index *idx, float ms[4], uint32_t *calls);
 
 /* ----------------------------------------------------------------- launch graphs */
 

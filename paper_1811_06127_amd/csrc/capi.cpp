@@ -46,6 +46,26 @@ struct DeviceGuard {      // makes the index's device current for the duration o
 
 int hip_status(hipError_t e) { return e == hipSuccess ? FM_OK : (e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EDEVICE); }
 
+// Events for one call's phase boundaries, or none when timing is off or full.
+PhaseEvents take_events(const fm_index *idx, int kind)
+{
+    PhaseEvents pe;
+    if (!idx->timing_cap || idx->ev_calls >= idx->timing_cap) return pe;
+    const uint32_t j = idx->ev_calls++;
+    for (int i = 0; i < 5; ++i) pe.ev[i] = idx->ev_pool[5 * j + i];
+    idx->ev_kind[j] = kind;
+    return pe;
+}
+
+void release_events(const fm_index *idx)
+{
+    for (hipEvent_t e : idx->ev_pool) (void)hipEventDestroy(e);
+    idx->ev_pool.clear();
+    idx->ev_kind.clear();
+    idx->timing_cap = 0;
+    idx->ev_calls = 0;
+}
+
 uint32_t nstrands(uint32_t flags) { return ((flags & FM_FWD) ? 1u : 0u) + ((flags & FM_REVCOMP) ? 1u : 0u); }
 
 bool valid_tuning(const fm_index *idx, const fm_tuning &t)
@@ -251,6 +271,7 @@ void fm_index_free(fm_index *idx)
 {
     if (!idx) return;
     DeviceGuard g(idx->device);
+    release_events(idx);
     for (int i = 0; i < 3; ++i) {
         if (idx->lay[i]) (void)hipFree(idx->lay[i]);
         if (idx->rlay[i]) (void)hipFree(idx->rlay[i]);
@@ -285,7 +306,7 @@ int fm_search_exact_workspace(const fm_index *idx, uint64_t nreads, uint32_t fla
 {
     (void)nreads;
     if (!idx || !bytes) return FM_EINVAL;
-    *bytes = (flags & FM_PLAIN) ? 0 : kWsHeader;
+    *bytes = kWsHeader;
     return FM_OK;
 }
 
@@ -303,8 +324,16 @@ int fm_search_exact(const fm_index *idx, const uint8_t *codes, const uint64_t *o
     if (!plain) {
         if (hipError_t e = launch_fill(ws, 0, kWsHeader / 4, s)) return hip_status(e);
     }
+    if ((flags & FM_STATS) && (!ws || ws_bytes < kWsHeader)) return FM_EINVAL;
+    if (plain && (flags & FM_STATS)) {
+        if (hipError_t e = launch_fill(ws, 0, kWsHeader / 4, s)) return hip_status(e);
+    }
     WalkCall c{codes, offs, nullptr, nreads, flags, 0, out, ws};
-    return hip_status(launch_walk(idx, idx->tune[FM_OP_EXACT], WALK_EXACT, plain, c, s));
+    const PhaseEvents pe = take_events(idx, 0);
+    pe.mark(0, s);
+    const hipError_t e = launch_walk(idx, idx->tune[FM_OP_EXACT], WALK_EXACT, plain, c, s);
+    pe.mark(1, s);
+    return hip_status(e);
 }
 
 int fm_darray(const fm_index *idx, const uint8_t *codes, const uint64_t *offs, uint64_t nreads, uint64_t total_len,
@@ -324,7 +353,7 @@ int fm_search_inexact_workspace(const fm_index *idx, uint64_t nreads, uint64_t t
 {
     (void)total_len;
     if (!idx || !bytes || !nstrands(flags) || zmax > FM_ZMAX) return FM_EINVAL;
-    *bytes = inexact_ws_layout(nreads, nstrands(flags), zmax, hit_cap, (flags & FM_PLAIN) != 0).total;
+    *bytes = inexact_ws_layout(nreads, nstrands(flags), zmax, hit_cap).total;
     return FM_OK;
 }
 
@@ -338,11 +367,60 @@ int fm_search_inexact(const fm_index *idx, const uint8_t *codes, const uint64_t 
     if ((flags & FM_DARRAY) && (!idx->has_rev || !idx->rlay[ilog(idx->tune[FM_OP_DARRAY].occ_interval)]))
         return FM_EINVAL;
     const bool plain = (flags & FM_PLAIN) != 0;
-    if (ws_bytes < inexact_ws_layout(nreads, nstrands(flags), zmax, hit_cap, plain).total) return FM_EINVAL;
+    if (ws_bytes < inexact_ws_layout(nreads, nstrands(flags), zmax, hit_cap).total) return FM_EINVAL;
     DeviceGuard g(idx->device);
     DfsCall c{codes, offs, z, nreads, flags, zmax, hits, hit_cap, hit_offs, status, ws};
+    const PhaseEvents pe = take_events(idx, 1);
     return hip_status(launch_inexact(idx, idx->tune[FM_OP_INEXACT], idx->tune[FM_OP_DARRAY], plain, c,
-                                     (hipStream_t)stream));
+                                     (hipStream_t)stream, &pe));
+}
+
+int fm_phase_timing(fm_index *idx, uint32_t capacity)
+{
+    if (!idx) return FM_EINVAL;
+    DeviceGuard g(idx->device);
+    release_events(idx);
+    if (!capacity) return FM_OK;
+    try {
+        idx->ev_pool.resize((size_t)capacity * 5, nullptr);
+        idx->ev_kind.assign(capacity, 0);
+    } catch (const std::bad_alloc &) {
+        return FM_ENOMEM;
+    }
+    for (auto &e : idx->ev_pool) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            release_events(idx);
+            return FM_EDEVICE;
+        }
+    }
+    idx->timing_cap = capacity;
+    return FM_OK;
+}
+
+int fm_phase_times(fm_index *idx, float ms[4], uint32_t *calls)
+{
+    if (!idx || !ms) return FM_EINVAL;
+    DeviceGuard g(idx->device);
+    for (int i = 0; i < 4; ++i) ms[i] = 0.f;
+    auto span = [&](hipEvent_t a, hipEvent_t b) {
+        float m = 0.f;
+        if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&m, a, b) != hipSuccess) return 0.f;
+        return m;
+    };
+    for (uint32_t j = 0; j < idx->ev_calls; ++j) {
+        hipEvent_t *e = &idx->ev_pool[5 * j];
+        if (idx->ev_kind[j] == 0) {
+            ms[0] += span(e[0], e[1]);
+        } else {
+            ms[1] += span(e[1], e[2]);
+            ms[2] += span(e[2], e[3]);
+            ms[3] += span(e[3], e[4]);
+        }
+    }
+    if (calls) *calls = idx->ev_calls;
+    idx->ev_calls = 0;
+    return FM_OK;
 }
 
 }  // extern "C"

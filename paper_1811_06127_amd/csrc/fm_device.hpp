@@ -13,8 +13,8 @@
 //             - [c == A and p >= dollar_row]
 // The '$' row stores code 0 (A) since two bits cannot hold a fifth symbol; the last
 // term removes it. The in-bucket count masks the symbols after p and takes population
-// counts of the two bit planes (Solution section: zero-masking past position k, then
-// counting; the half-byte lookup tables are replaced by the native popcount).
+// counts of bit planes (Solution section: zero-masking past position k, then counting;
+// the half-byte lookup tables are replaced by the native popcount).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,6 +36,20 @@ template <> struct Geo<256> { static constexpr int CH = 8, USED = 5, LOG = 8; };
 
 constexpr uint32_t EVEN = 0x55555555u;
 
+// One of four values by a runtime index 0..3 (selects, no indexed memory access).
+template <typename T>
+__device__ __forceinline__ T sel4(uint32_t i, T a0, T a1, T a2, T a3)
+{
+    const T lo = (i & 1) ? a1 : a0;
+    const T hi = (i & 1) ? a3 : a2;
+    return (i & 2) ? hi : lo;
+}
+
+__device__ __forceinline__ uint32_t c_of(const DevLayout &lay, uint32_t b)
+{
+    return sel4(b, lay.C[0], lay.C[1], lay.C[2], lay.C[3]);
+}
+
 // Chunks of one bucket held by one lane of an L-lane group: lane q holds chunks
 // q, q+L, q+2L, ... below Geo<I>::USED (padding is never fetched).
 template <int I, int L> struct Bucket {
@@ -55,50 +69,109 @@ __device__ __forceinline__ void fetch(const DevLayout &lay, uint32_t j, uint32_t
     }
 }
 
-// Mask of the symbols of one 16-symbol word that lie at or before the position:
-// rel = position - first row of the word.
-__device__ __forceinline__ uint32_t word_mask(int rel)
+// Offset of position r (0 <= r < I) relative to the first symbol of chunk c (chunk 0
+// holds counts; chunk c >= 1 holds symbols 64(c-1) .. 64c-1), clamped to [-1, 63]:
+// -1 = no symbol of the chunk is at or before r, 63 = all are.
+__device__ __forceinline__ int chunk_rel(uint32_t r, int c)
 {
-    uint32_t m = 0xFFFFFFFFu >> (30 - 2 * (rel < 0 ? 0 : (rel > 15 ? 15 : rel)));
-    return rel < 0 ? 0u : m;
+    if (c < 1) return -1;
+    const int rel = (int)r - 64 * (c - 1);
+    return rel < -1 ? -1 : (rel > 63 ? 63 : rel);
 }
 
-// Symbols equal to `b` (pat = b * 0x55555555) among the masked symbols of w.
-__device__ __forceinline__ uint32_t count_eq(uint32_t w, uint32_t pat, uint32_t m, uint32_t acc)
-{
-    const uint32_t x = w ^ pat;
-    const uint32_t eq = ~(x | (x >> 1)) & EVEN & m;
-    return __popc(eq) + acc;
-}
+// Symbols of one code among symbols 0..rel of a 64-symbol chunk: one bit per matching
+// symbol, with the per-word counts accumulated once so a prefix needs one masked word.
+struct Eq1 {
+    uint32_t e[4];      // bit 2s set when symbol s of the word matches
+    uint32_t cum[4];    // matching symbols in words 0..w-1
+};
 
-// This lane's share of Occ(b, p) for p at offset r of the bucket: its counts chunk
-// (if it holds chunk 0) plus its symbol chunks. The group sum is Occ(b, p), before the
-// '$' correction.
-template <int I, int L>
-__device__ __forceinline__ uint32_t part1(const Bucket<I, L> &bk, uint32_t q, uint32_t r, uint32_t b)
+__device__ __forceinline__ Eq1 eq_chunk(uint4 v, uint32_t pat)
 {
-    const uint32_t pat = b * EVEN;
+    Eq1 q;
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
     uint32_t acc = 0;
 #pragma unroll
-    for (int t = 0; t < Bucket<I, L>::NPL; ++t) {
-        const int c = (int)q + L * t;
-        const uint4 v = bk.v[t];
-        const uint32_t sel = b == 0 ? v.x : (b == 1 ? v.y : (b == 2 ? v.z : v.w));
-        acc += (c == 0) ? sel : 0u;
-        const int rel = (c >= 1 && c < Geo<I>::USED) ? (int)r - (c - 1) * 64 : -1;
-        acc = count_eq(v.x, pat, word_mask(rel), acc);
-        acc = count_eq(v.y, pat, word_mask(rel - 16), acc);
-        acc = count_eq(v.z, pat, word_mask(rel - 32), acc);
-        acc = count_eq(v.w, pat, word_mask(rel - 48), acc);
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t x = w[i] ^ pat;
+        q.e[i] = ~(x | (x >> 1)) & EVEN;
+        q.cum[i] = acc;
+        acc = __popc(q.e[i]) + acc;
     }
-    return acc;
+    return q;
+}
+
+__device__ __forceinline__ uint32_t eq_prefix(const Eq1 &q, int rel)
+{
+    const uint32_t rc = (uint32_t)(rel < 0 ? 0 : rel);
+    const uint32_t wr = rc >> 4;
+    const uint32_t pm = 0xFFFFFFFFu >> (30 - 2 * (rc & 15));
+    const uint32_t word = sel4(wr, q.e[0], q.e[1], q.e[2], q.e[3]);
+    const uint32_t base = sel4(wr, q.cum[0], q.cum[1], q.cum[2], q.cum[3]);
+    return rel < 0 ? 0u : __popc(word & pm) + base;
+}
+
+// Per-word masks of symbols 0..rel of a chunk (rel in [-1, 63]).
+__device__ __forceinline__ void word_masks(int rel, uint32_t m[4])
+{
+    const int wr = rel < 0 ? -1 : (rel >> 4);
+    const uint32_t pm = 0xFFFFFFFFu >> (30 - 2 * ((rel < 0 ? 0 : rel) & 15));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m[i] = i < wr ? 0xFFFFFFFFu : (i == wr ? pm : 0u);
 }
 
 struct Occ4 {
     uint32_t a, c, g, t;
 };
 
-// This lane's share of Occ(., p) for all four symbols (same conventions as part1).
+// Counts of A, C, G, T among symbols 0..rel of a chunk, from the two bit planes.
+__device__ __forceinline__ Occ4 count4_chunk(uint4 v, int rel)
+{
+    uint32_t m[4];
+    word_masks(rel, m);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    uint32_t slo = 0, shi = 0, sboth = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t lo = w[i] & EVEN & m[i];          // low bit of each symbol
+        const uint32_t hi = (w[i] >> 1) & EVEN & m[i];   // high bit of each symbol
+        slo = __popc(lo) + slo;
+        shi = __popc(hi) + shi;
+        sboth = __popc(lo & hi) + sboth;
+    }
+    const uint32_t npos = (uint32_t)(rel + 1);
+    return Occ4{npos - slo - shi + sboth, slo - sboth, shi - sboth, sboth};   // 00 01 10 11
+}
+
+// This lane's share of Occ(sym, p1) and Occ(sym, p2) for positions at offsets r1 (in
+// bucket a) and r2 (in bucket b2, or in bucket a when `same`). The group sums are the
+// two Occ values before the '$' correction.
+template <int I, int L>
+__device__ __forceinline__ void part2(const Bucket<I, L> &a, const Bucket<I, L> &b2, bool same, uint32_t q,
+                                      uint32_t r1, uint32_t r2, uint32_t sym, uint32_t &o1, uint32_t &o2)
+{
+    const uint32_t pat = sym * EVEN;
+    uint32_t s1 = 0, s2 = 0;
+#pragma unroll
+    for (int t = 0; t < Bucket<I, L>::NPL; ++t) {
+        const int c = (int)q + L * t;
+        const uint4 va = a.v[t];
+        const uint4 vb = same ? va : b2.v[t];
+        if (c == 0) {
+            s1 += sel4(sym, va.x, va.y, va.z, va.w);
+            s2 += sel4(sym, vb.x, vb.y, vb.z, vb.w);
+        } else if (c < Geo<I>::USED) {
+            const Eq1 ea = eq_chunk(va, pat);
+            const Eq1 eb = same ? ea : eq_chunk(vb, pat);
+            s1 += eq_prefix(ea, chunk_rel(r1, c));
+            s2 += eq_prefix(eb, chunk_rel(r2, c));
+        }
+    }
+    o1 = s1;
+    o2 = s2;
+}
+
+// This lane's share of Occ(., p) for all four symbols at offset r of a bucket.
 template <int I, int L>
 __device__ __forceinline__ Occ4 part4(const Bucket<I, L> &bk, uint32_t q, uint32_t r)
 {
@@ -107,28 +180,18 @@ __device__ __forceinline__ Occ4 part4(const Bucket<I, L> &bk, uint32_t q, uint32
     for (int t = 0; t < Bucket<I, L>::NPL; ++t) {
         const int c = (int)q + L * t;
         const uint4 v = bk.v[t];
-        const uint32_t keep = (c == 0) ? 0xFFFFFFFFu : 0u;
-        o.a += v.x & keep;
-        o.c += v.y & keep;
-        o.g += v.z & keep;
-        o.t += v.w & keep;
-        const int rel = (c >= 1 && c < Geo<I>::USED) ? (int)r - (c - 1) * 64 : -1;
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-        uint32_t slo = 0, shi = 0, sboth = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t m = word_mask(rel - 16 * i);
-            const uint32_t lo = w[i] & EVEN & m;          // low bit of each symbol
-            const uint32_t hi = (w[i] >> 1) & EVEN & m;   // high bit of each symbol
-            slo += __popc(lo);
-            shi += __popc(hi);
-            sboth += __popc(lo & hi);
+        if (c == 0) {
+            o.a += v.x;
+            o.c += v.y;
+            o.g += v.z;
+            o.t += v.w;
+        } else if (c < Geo<I>::USED) {
+            const Occ4 p = count4_chunk(v, chunk_rel(r, c));
+            o.a += p.a;
+            o.c += p.c;
+            o.g += p.g;
+            o.t += p.t;
         }
-        const int npos = rel < 0 ? 0 : (rel >= 63 ? 64 : rel + 1);
-        o.a += (uint32_t)npos - slo - shi + sboth;        // 00
-        o.c += slo - sboth;                               // 01
-        o.g += shi - sboth;                               // 10
-        o.t += sboth;                                     // 11
     }
     return o;
 }
@@ -153,48 +216,46 @@ __device__ __forceinline__ Occ4 group_sum4(Occ4 o)
     return o;
 }
 
-// Occ(b, k-1) and Occ(b, l) -- the two values one step of Listing 1 consumes.
-// Fetches one bucket, or two when k-1 and l fall in different buckets.
+// Buckets of one query (k, l): the bucket of k-1 and the bucket of l, both loads issued
+// before either is used; the second is skipped when both positions share a bucket.
+// Callers guarantee k >= 1.
 template <int I, int L>
-__device__ __forceinline__ void occ2(const DevLayout &lay, uint32_t q, uint32_t b, uint32_t k,
-                                     uint32_t l, uint32_t &ok, uint32_t &ol)
+struct Pair {
+    Bucket<I, L> a, b;
+    bool same;
+    __device__ __forceinline__ void load(const DevLayout &lay, uint32_t q, uint32_t k, uint32_t l)
+    {
+        constexpr int LOG = Geo<I>::LOG;
+        const uint32_t j1 = (k - 1) >> LOG, j2 = l >> LOG;
+        same = j1 == j2;
+        fetch<I, L>(lay, j1, q, a);
+        if (!same) fetch<I, L>(lay, j2, q, b);
+    }
+};
+
+// Occ(sym, k-1) and Occ(sym, l) -- the two values one step of Listing 1 consumes.
+template <int I, int L>
+__device__ __forceinline__ void occ2(const DevLayout &lay, const Pair<I, L> &pr, uint32_t q, uint32_t sym,
+                                     uint32_t k, uint32_t l, uint32_t &ok, uint32_t &ol)
 {
-    constexpr int LOG = Geo<I>::LOG;
-    const uint32_t j2 = l >> LOG;
-    const uint32_t j1 = k ? (k - 1) >> LOG : j2;
-    Bucket<I, L> b1, b2;
-    fetch<I, L>(lay, j1, q, b1);
-    if (j1 != j2) fetch<I, L>(lay, j2, q, b2);
-    else b2 = b1;
-    uint32_t c1 = part1<I, L>(b1, q, (k - 1) & (I - 1), b);
-    uint32_t c2 = part1<I, L>(b2, q, l & (I - 1), b);
+    uint32_t c1, c2;
+    part2<I, L>(pr.a, pr.b, pr.same, q, (k - 1) & (I - 1), l & (I - 1), sym, c1, c2);
     c1 = group_sum<L>(c1);
     c2 = group_sum<L>(c2);
-    if (b == 0) {
-        c1 -= (k - 1 >= lay.dollar) ? 1u : 0u;
-        c2 -= (l >= lay.dollar) ? 1u : 0u;
-    }
-    ok = k ? c1 : 0u;
-    ol = c2;
+    const bool a = sym == 0;
+    ok = c1 - ((a && k - 1 >= lay.dollar) ? 1u : 0u);
+    ol = c2 - ((a && l >= lay.dollar) ? 1u : 0u);
 }
 
 // The eight values of one inexact step: Occ(., k-1) and Occ(., l).
 template <int I, int L>
-__device__ __forceinline__ void occ8(const DevLayout &lay, uint32_t q, uint32_t k, uint32_t l,
+__device__ __forceinline__ void occ8(const DevLayout &lay, const Pair<I, L> &pr, uint32_t q, uint32_t k, uint32_t l,
                                      Occ4 &ok, Occ4 &ol)
 {
-    constexpr int LOG = Geo<I>::LOG;
-    const uint32_t j2 = l >> LOG;
-    const uint32_t j1 = k ? (k - 1) >> LOG : j2;
-    Bucket<I, L> b1, b2;
-    fetch<I, L>(lay, j1, q, b1);
-    if (j1 != j2) fetch<I, L>(lay, j2, q, b2);
-    else b2 = b1;
-    Occ4 o1 = group_sum4<L>(part4<I, L>(b1, q, (k - 1) & (I - 1)));
-    Occ4 o2 = group_sum4<L>(part4<I, L>(b2, q, l & (I - 1)));
+    Occ4 o1 = group_sum4<L>(part4<I, L>(pr.a, q, (k - 1) & (I - 1)));
+    Occ4 o2 = group_sum4<L>(pr.same ? part4<I, L>(pr.a, q, l & (I - 1)) : part4<I, L>(pr.b, q, l & (I - 1)));
     o1.a -= (k - 1 >= lay.dollar) ? 1u : 0u;
     o2.a -= (l >= lay.dollar) ? 1u : 0u;
-    if (!k) o1 = Occ4{0, 0, 0, 0};
     ok = o1;
     ol = o2;
 }
@@ -258,10 +319,6 @@ __device__ __forceinline__ uint64_t block_scan_u64(uint64_t v, uint64_t *lds, ui
 }
 
 // ------------------------------------------------------------------ wave helpers
-
-__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
-
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 // Bits of `mask` for lanes strictly below `lane`.
 __device__ __forceinline__ uint32_t rank_below(uint64_t mask, uint32_t lane)

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/fm.h"
 #include "fm_device.hpp"
@@ -21,11 +22,17 @@ struct fm_index {
     fm_tuning tune[3] = {};
     int cu_count = 0;
     std::string arch;
+    // phase timing (diagnostics): events recorded per call, 5 boundaries per call
+    mutable uint32_t timing_cap = 0;
+    mutable std::vector<hipEvent_t> ev_pool;
+    mutable std::vector<int> ev_kind;      // per recorded call: 0 exact, 1 inexact
+    mutable uint32_t ev_calls = 0;
 };
 
 namespace fm {
 
 constexpr uint32_t kQueueChunk = 64;   // read-strands a wave takes from the work queue at once
+constexpr uint32_t kHitSlots = 4;      // hits stored per read-strand without an atomic
 
 inline int ilog(uint32_t I) { return I == 64 ? 0 : (I == 128 ? 1 : (I == 256 ? 2 : -1)); }
 inline uint64_t num_buckets(uint64_t n, uint32_t I) { return n / I + 1; }
@@ -40,16 +47,18 @@ enum : size_t {
     kWsRequired = 8,     // uint64 hits every read would need
     kWsPool = 16,        // uint64 hits appended to the staging pool
     kWsQueue2 = 24,      // uint32 work-queue counter (DFS)
+    kWsCut = 32,         // uint64 hit offset where the listed reads end
     kWsStatOcc = 64,     // uint64 Occ8 queries
     kWsStatBuckets = 72, // uint64 distinct buckets fetched
-    kWsStatWalk = 80,    // uint64 D-walk steps
+    kWsStatWalk = 80,    // uint64 walk steps that fetched
+    kWsStatWalkBk = 88,  // uint64 buckets those steps fetched
     kWsHeader = 256
 };
 
 struct InexactWs {       // sub-buffers of the inexact workspace
-    size_t bp, rs_count, rs_status, cursor, cnt, part, pool, stack, total;
+    size_t bp, rs_count, rs_status, cursor, rd_status, cnt, offs, part, slots, opool, total;
 };
-InexactWs inexact_ws_layout(uint64_t nreads, uint32_t nstr, uint32_t zmax, uint64_t hit_cap, bool plain);
+InexactWs inexact_ws_layout(uint64_t nreads, uint32_t nstr, uint32_t zmax, uint64_t hit_cap);
 
 // ------------------------------------------------------------------ launchers
 
@@ -91,8 +100,16 @@ struct DfsCall {
     uint32_t *status;
     void *ws;
 };
+// Phase boundary events of one call (nullptr entries: not recorded).
+struct PhaseEvents {
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    void mark(int i, hipStream_t s) const
+    {
+        if (ev[i]) (void)hipEventRecord(ev[i], s);
+    }
+};
 hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuning &tw, bool plain,
-                          const DfsCall &c, hipStream_t s);
+                          const DfsCall &c, hipStream_t s, const PhaseEvents *pe);
 
 int max_blocks_per_cu(const void *kernel, int block, size_t lds);
 

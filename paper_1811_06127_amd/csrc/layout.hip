@@ -1,5 +1,8 @@
 // layout.hip -- interleaved checkpoint layout (built once at load time), the fill
 // kernel used instead of memsets, and the Occ8 kernel.
+#include <mutex>
+#include <unordered_map>
+
 #include "fm_internal.hpp"
 
 namespace fm {
@@ -186,8 +189,13 @@ __global__ void __launch_bounds__(256) occ8_kernel(DevLayout lay, const uint2 *q
     for (uint64_t g = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / L; g < nq; g += groups) {
         const uint2 kl = q[g];
         const bool ok = kl.x <= lay.n + 1 && kl.y <= lay.n;
+        // row k-1 = -1 has no bucket (its values are 0); row 0's stands in for it
+        const uint32_t k = ok && kl.x ? kl.x : 1u, l = ok ? kl.y : 0u;
+        Pair<I, L> pr;
+        pr.load(lay, q_lane, k, l);
         Occ4 a, b;
-        occ8<I, L>(lay, q_lane, ok ? kl.x : 0u, ok ? kl.y : 0u, a, b);
+        occ8<I, L>(lay, pr, q_lane, k, l, a, b);
+        if (!kl.x) a = Occ4{0, 0, 0, 0};
         if (!ok) {
             a = Occ4{~0u, ~0u, ~0u, ~0u};
             b = a;
@@ -245,11 +253,38 @@ hipError_t launch_occ8(const fm_index *idx, const fm_tuning &t, const fm_interva
     }
 }
 
+// Resident workgroups per CU for a kernel; the runtime query is slow, so each
+// (device, kernel, block, LDS) answer is computed once and kept.
 int max_blocks_per_cu(const void *kernel, int block, size_t lds)
 {
+    struct Key {
+        int dev;
+        const void *k;
+        int block;
+        size_t lds;
+        bool operator==(const Key &o) const { return dev == o.dev && k == o.k && block == o.block && lds == o.lds; }
+    };
+    struct Hash {
+        size_t operator()(const Key &x) const
+        {
+            return std::hash<const void *>()(x.k) ^ ((size_t)x.block << 20) ^ (x.lds << 32) ^ (size_t)x.dev;
+        }
+    };
+    static std::mutex mu;
+    static std::unordered_map<Key, int, Hash> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const Key key{dev, kernel, block, lds};
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, lds) != hipSuccess) return 1;
-    return n > 0 ? n : 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, lds) != hipSuccess || n < 1) n = 1;
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = n;
+    return n;
 }
 
 }  // namespace fm

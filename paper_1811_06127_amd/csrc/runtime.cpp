@@ -109,8 +109,11 @@ int fm_plan_create(const fm_index *idx, int op, const uint8_t *codes, const uint
     int st = hs(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     if (!st) st = hs(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
     if (!st) {
+        const uint32_t cap = idx->timing_cap;   // no phase events inside a graph
+        idx->timing_cap = 0;
         const int cs = run_op(idx, op, codes, offs, z, nreads, flags, zmax, out_buf, hit_cap, hit_offs, status, ws,
                               ws_bytes, s);
+        idx->timing_cap = cap;
         const int es = hs(hipStreamEndCapture(s, &p->graph));
         st = cs ? cs : es;
     }

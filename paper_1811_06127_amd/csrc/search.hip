@@ -21,9 +21,21 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
 // ------------------------------------------------------------------ work queue
 
+// Per-wave view of the global work queue: the current chunk [qb, qe) of read-strands and,
+// in lane 0, the start of the next chunk, claimed one chunk ahead so that taking work
+// never waits for the atomic.
 struct WaveQueue {
     uint32_t qb, qe;
+    uint32_t nxt;          // lane 0: start of the next claimed chunk
     bool exhausted;
+
+    __device__ void start(uint32_t *queue)
+    {
+        qb = qe = 0;
+        exhausted = false;
+        nxt = 0;
+        if (__lane_id() == 0) nxt = atomicAdd(queue, kQueueChunk);
+    }
 };
 
 // Gives one item to every group of this wave whose `need` is set (need is uniform within
@@ -37,15 +49,14 @@ __device__ uint32_t wave_take(WaveQueue &wq, bool need, uint32_t *queue, uint32_
     while (mask) {
         if (wq.qb >= wq.qe) {
             if (wq.exhausted) break;
-            uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(queue, kQueueChunk);
-            base = __shfl(base, 0);
+            const uint32_t base = (uint32_t)__builtin_amdgcn_readfirstlane((int)wq.nxt);
             if (base >= total) {
                 wq.exhausted = true;
                 break;
             }
             wq.qb = base;
             wq.qe = base + kQueueChunk < total ? base + kQueueChunk : total;
+            if (lane == 0) wq.nxt = atomicAdd(queue, kQueueChunk);
         }
         const uint32_t avail = wq.qe - wq.qb;
         const uint32_t r = rank_below(mask, lead);
@@ -80,7 +91,7 @@ struct WalkArgs {
     void *out;
     uint64_t dstride;      // DFULL: bytes per strand block
     uint32_t *queue;
-    unsigned long long *stat_steps;
+    unsigned long long *stat_steps, *stat_bk;
 };
 
 template <int MODE>
@@ -104,19 +115,39 @@ struct Walker {
             if (MODE == WALK_EXACT) {
                 ((uint2 *)a.out)[rs] = (k <= l) ? make_uint2(k, l) : make_uint2(1u, 0u);
             } else if (MODE == WALK_DBP) {
-                ((uint4 *)a.out)[rs] = make_uint4(cnt | (bp01 << 16), (bp01 >> 16) | (bp23 << 16), (bp23 >> 16) | (bp4 << 16), 0u);
+                ((uint4 *)a.out)[rs] = make_uint4(cnt | (bp01 << 16), (bp01 >> 16) | (bp23 << 16),
+                                                  (bp23 >> 16) | (bp4 << 16), 0u);
             }
         }
         rs = kEmpty;
     }
 
-    __device__ void init(const WalkArgs &a, uint32_t item, bool lead_lane)
+    // Header of a new read-strand: its offsets (and budget) are loaded here and used by
+    // begin() one iteration later, so fetching them never delays the other lanes' steps.
+    uint64_t h0, h1;
+    uint32_t hz;
+
+    __device__ void request(const WalkArgs &a, uint32_t item)
     {
         rs = item;
         const uint32_t read = a.nstr == 2 ? item >> 1 : item;
+        h0 = a.offs[read];
+        h1 = a.offs[read + 1];
+        hz = MODE == WALK_DBP ? a.z[read] : 0u;
+    }
+
+    __device__ void init(const WalkArgs &a, uint32_t item, bool lead_lane)
+    {
+        request(a, item);
+        begin(a, lead_lane);
+    }
+
+    __device__ void begin(const WalkArgs &a, bool lead_lane)
+    {
+        const uint32_t item = rs;
         const uint32_t strand = a.nstr == 2 ? (item & 1u) : a.strand0;
-        const uint64_t b0 = a.offs[read];
-        const uint32_t m = (uint32_t)(a.offs[read + 1] - b0);
+        const uint64_t b0 = h0;
+        const uint32_t m = (uint32_t)(h1 - b0);
         // Listing 1 consumes the pattern right to left; the D walk left to right. The
         // strand-1 pattern is the reverse complement, so its direction flips.
         const bool asc = (MODE == WALK_EXACT) ? strand == 1 : strand == 0;
@@ -129,24 +160,22 @@ struct Walker {
         i = 0;
         cnt = 0;
         bp01 = bp23 = bp4 = 0;
-        if (MODE == WALK_DBP) zr = a.z[read] < a.zmax ? a.z[read] : a.zmax;
+        if (MODE == WALK_DBP) zr = hz < a.zmax ? hz : a.zmax;
         if (MODE == WALK_DFULL) outp = (a.nstr == 2 ? strand : 0u) * a.dstride + b0;
         if (m == 0) finish(a, lead_lane);
     }
 
-    // One step with pattern symbol c; ok/ol are Occ(b, k-1), Occ(b, l) (unused when k == 0).
-    __device__ void step(const WalkArgs &a, uint32_t c, uint32_t ok, uint32_t ol, bool lead_lane)
+    // One step with pattern symbol c (already complemented for strand 1); ok/ol are
+    // Occ(b, k-1), Occ(b, l), unused while the interval is still (0, n).
+    __device__ void step(const WalkArgs &a, uint32_t b, uint32_t ok, uint32_t ol, bool lead_lane)
     {
-        const uint32_t b = (comp && c < 4) ? 3u - c : c;
-        uint32_t nk = 1, nl = 0;
-        if (b < 4) {
-            if (k == 0) {                 // from the empty-pattern interval (0, n)
-                nk = a.lay.C[b] + 1;
-                nl = a.lay.C[b + 1];
-            } else {
-                nk = a.lay.C[b] + ok + 1;
-                nl = a.lay.C[b] + ol;
-            }
+        const uint32_t cb = c_of(a.lay, b & 3);
+        const uint32_t c1 = sel4(b & 3, a.lay.C[1], a.lay.C[2], a.lay.C[3], a.lay.C[4]);
+        uint32_t nk = k ? cb + ok + 1 : cb + 1;          // from (0, n) the step is C alone
+        uint32_t nl = k ? cb + ol : c1;
+        if (b > 3) {                                     // a non-base occurs nowhere
+            nk = 1;
+            nl = 0;
         }
         addr += dir;
         rem -= 1;
@@ -156,25 +185,21 @@ struct Walker {
             if (nk > nl || rem == 0) finish(a, lead_lane);
             return;
         }
-        if (nk > nl) {                    // a difference is certain in this segment
-            cnt += 1;
-            const uint32_t pos = i & 0xFFFFu;
-            if (cnt == 1) bp01 |= pos;
-            else if (cnt == 2) bp01 |= pos << 16;
-            else if (cnt == 3) bp23 |= pos;
-            else if (cnt == 4) bp23 |= pos << 16;
-            else if (cnt == 5) bp4 |= pos;
-            k = 0;
-            l = a.lay.n;
-        } else {
-            k = nk;
-            l = nl;
-        }
+        const bool fail = nk > nl;                       // a difference is certain in this segment
+        cnt += fail ? 1u : 0u;
+        const uint32_t pos = fail ? (i & 0xFFFFu) : 0u;
+        bp01 |= cnt == 1 ? pos : (cnt == 2 ? pos << 16 : 0u);
+        bp23 |= cnt == 3 ? pos : (cnt == 4 ? pos << 16 : 0u);
+        bp4 |= cnt == 5 ? pos : 0u;
+        k = fail ? 0u : nk;
+        l = fail ? a.lay.n : nl;
         if (MODE == WALK_DFULL && lead_lane) ((uint8_t *)a.out)[outp + i] = (uint8_t)(cnt < 255 ? cnt : 255);
         i += 1;
         if (rem == 0 || (MODE == WALK_DBP && cnt > zr)) finish(a, lead_lane);
     }
 };
+
+__device__ __forceinline__ uint32_t strand_sym(uint32_t c, uint32_t comp) { return (comp && c < 4) ? 3u - c : c; }
 
 template <int I, int MODE>
 __global__ void __launch_bounds__(256) walk_plain(WalkArgs a)
@@ -183,83 +208,82 @@ __global__ void __launch_bounds__(256) walk_plain(WalkArgs a)
     if (item >= a.total) return;
     Walker<MODE> w;
     w.init(a, item, true);
-    uint64_t steps = 0;
+    uint64_t steps = 0, bks = 0;
     while (w.rs != kEmpty) {
         const uint32_t c = a.codes[w.addr];
-        const uint32_t b = (w.comp && c < 4) ? 3u - c : c;
-        uint32_t ok = 0, ol = 0;
-        if (b < 4 && w.k != 0) {
-            occ2<I, 1>(a.lay, 0, b, w.k, w.l, ok, ol);
+        Pair<I, 1> pr;
+        pr.load(a.lay, 0, w.k ? w.k : 1u, w.l);          // (0, n) needs no buckets; row 0's are harmless
+        const uint32_t b = strand_sym(c, w.comp);
+        uint32_t ok, ol;
+        occ2<I, 1>(a.lay, pr, 0, b & 3, w.k ? w.k : 1u, w.l, ok, ol);
+        if (w.k && b < 4) {
             ++steps;
+            bks += pr.same ? 1 : 2;
         }
-        w.step(a, c, ok, ol, true);
+        w.step(a, b, ok, ol, true);
     }
-    if (a.stat_steps && steps) atomicAdd(a.stat_steps, (unsigned long long)steps);
+    if (a.stat_steps && steps) {
+        atomicAdd(a.stat_steps, (unsigned long long)steps);
+        atomicAdd(a.stat_bk, (unsigned long long)bks);
+    }
 }
 
 template <int I, int L, int P, int MODE>
 __global__ void __launch_bounds__(256) walk_batched(WalkArgs a)
 {
-    constexpr int LOG = Geo<I>::LOG;
     const uint32_t q = L == 1 ? 0u : (__lane_id() & (L - 1));
     const bool lead = q == 0;
     Walker<MODE> w[P];
+    bool pending[P];
 #pragma unroll
-    for (int p = 0; p < P; ++p) w[p].rs = kEmpty;
-    WaveQueue wq = {0, 0, false};
-    uint64_t steps = 0;
+    for (int p = 0; p < P; ++p) {
+        w[p].rs = kEmpty;
+        pending[p] = false;
+    }
+    WaveQueue wq;
+    wq.start(a.queue);
+    uint64_t steps = 0, bks = 0;
     for (;;) {
+        // 1. the loads of every running slot
+        uint32_t c[P];
+        Pair<I, L> pr[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const bool act = w[p].rs != kEmpty;
+            c[p] = act ? a.codes[w[p].addr] : 0u;
+            pr[p].load(a.lay, q, act && w[p].k ? w[p].k : 1u, act ? w[p].l : 0u);
+        }
+        // 2. idle slots take a read-strand and request its header; it starts next round
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const uint32_t it = wave_take<L>(wq, w[p].rs == kEmpty, a.queue, a.total);
-            if (it != kEmpty) w[p].init(a, it, lead);
+            pending[p] = it != kEmpty;
+            if (pending[p]) w[p].request(a, it);
         }
         bool any = false;
 #pragma unroll
         for (int p = 0; p < P; ++p) any |= w[p].rs != kEmpty;
         if (!__any(any)) break;
-
-        // issue every load of every slot before using any of them
-        uint32_t c[P], j1[P], j2[P];
-        Bucket<I, L> b1[P], b2[P];
+        // 3. steps of the running slots; pending ones begin
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            if (w[p].rs != kEmpty) {
-                c[p] = a.codes[w[p].addr];
-                if (w[p].k != 0) {
-                    j2[p] = w[p].l >> LOG;
-                    j1[p] = (w[p].k - 1) >> LOG;
-                    fetch<I, L>(a.lay, j1[p], q, b1[p]);
-                    if (j1[p] != j2[p]) fetch<I, L>(a.lay, j2[p], q, b2[p]);
-                }
+            if (pending[p]) {
+                w[p].begin(a, lead);
+                continue;
             }
-        }
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            if (w[p].rs != kEmpty) {
-                const uint32_t cc = c[p];
-                const uint32_t b = (w[p].comp && cc < 4) ? 3u - cc : cc;
-                uint32_t ok = 0, ol = 0;
-                if (b < 4 && w[p].k != 0) {
-                    const bool same = j1[p] == j2[p];
-                    uint32_t c1 = part1<I, L>(b1[p], q, (w[p].k - 1) & (I - 1), b);
-                    uint32_t c2 = same ? part1<I, L>(b1[p], q, w[p].l & (I - 1), b)
-                                       : part1<I, L>(b2[p], q, w[p].l & (I - 1), b);
-                    c1 = group_sum<L>(c1);
-                    c2 = group_sum<L>(c2);
-                    if (b == 0) {
-                        c1 -= (w[p].k - 1 >= a.lay.dollar) ? 1u : 0u;
-                        c2 -= (w[p].l >= a.lay.dollar) ? 1u : 0u;
-                    }
-                    ok = c1;
-                    ol = c2;
-                    steps += lead ? 1 : 0;
-                }
-                w[p].step(a, cc, ok, ol, lead);
+            if (w[p].rs == kEmpty) continue;
+            const uint32_t b = strand_sym(c[p], w[p].comp);
+            uint32_t ok, ol;
+            occ2<I, L>(a.lay, pr[p], q, b & 3, w[p].k ? w[p].k : 1u, w[p].l, ok, ol);
+            if (lead && w[p].k && b < 4) {
+                ++steps;
+                bks += pr[p].same ? 1 : 2;
             }
+            w[p].step(a, b, ok, ol, lead);
         }
     }
     wave_add(a.stat_steps, steps);
+    wave_add(a.stat_bk, bks);
 }
 
 template <int I, int L, int P, int MODE>
@@ -339,21 +363,19 @@ hipError_t launch_walk(const fm_index *idx, const fm_tuning &t, int mode, bool p
     a.dstride = 0;
     a.queue = (uint32_t *)((char *)c.ws + kWsQueue);
     a.stat_steps = nullptr;
-    if (c.flags & FM_STATS) a.stat_steps = (unsigned long long *)((char *)c.ws + kWsStatWalk);
+    a.stat_bk = nullptr;
+    if ((c.flags & FM_STATS) && c.ws) {
+        a.stat_steps = (unsigned long long *)((char *)c.ws + kWsStatWalk);
+        a.stat_bk = (unsigned long long *)((char *)c.ws + kWsStatWalkBk);
+    }
     if (a.total == 0) return hipSuccess;
     switch (mode) {
     case WALK_EXACT: return walk_dispatch<WALK_EXACT>(idx, t, plain, a, s);
     case WALK_DBP: return walk_dispatch<WALK_DBP>(idx, t, plain, a, s);
-    case WALK_DFULL: {
-        // the full D array is a test and diagnostics output: plain kernel only
-        a.dstride = 0;
-        return hipErrorInvalidValue;
-    }
-    default: return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;   // the full D array has its own entry (plain walk)
     }
 }
 
-// D array entry: needs the total length for the strand blocks.
 hipError_t launch_darray_full(const fm_index *idx, const fm_tuning &t, const WalkCall &c, uint64_t total_len,
                               hipStream_t s)
 {
@@ -370,6 +392,7 @@ hipError_t launch_darray_full(const fm_index *idx, const fm_tuning &t, const Wal
     a.dstride = total_len;
     a.queue = nullptr;
     a.stat_steps = nullptr;
+    a.stat_bk = nullptr;
     if (a.total == 0) return hipSuccess;
     return walk_dispatch<WALK_DFULL>(idx, t, true, a, s);
 }
@@ -383,14 +406,14 @@ struct DfsArgs {
     const uint8_t *z;
     const uint4 *bp;       // D breakpoint records per read-strand, or nullptr
     uint32_t total, nstr, strand0, zmax;
-    uint32_t scap;         // stack entries per read-strand (3 * zmax)
+    uint32_t scap;         // stack entries per read-strand (3 * zmax) plus one spare
     uint32_t budget;       // expanded nodes per read-strand
-    fm_hit *pool;
-    uint64_t cap;
-    unsigned long long *pool_count;
+    fm_hit *slots;         // kHitSlots hits per read-strand
+    fm_hit *opool;         // hits beyond the slots
+    uint64_t ocap;
+    unsigned long long *ocount;
     uint32_t *rs_count, *rs_status;
     uint32_t *queue;
-    uint32_t *gstack;      // plain kernel: scap * 3 words per read-strand
     unsigned long long *stat_occ, *stat_bk;
 };
 
@@ -408,32 +431,52 @@ struct Dfs {
 
     __device__ uint32_t bp_at(uint32_t j) const
     {
-        const uint32_t w = j == 0 ? (bpw0 >> 16) : (j == 1 ? bpw1 : (j == 2 ? (bpw1 >> 16) : (j == 3 ? bpw2 : (bpw2 >> 16))));
-        return w & 0xFFFFu;
+        const uint32_t lo = sel4(j & 3, bpw0 >> 16, bpw1 & 0xFFFFu, bpw1 >> 16, bpw2 & 0xFFFFu);
+        return j >= 4 ? (bpw2 >> 16) : lo;
     }
 
-    // D(pos) > zc, i.e. a node needing zc more substitutions for pattern[0..pos] is pruned.
-    __device__ bool dprune(uint32_t zc, int pos, bool use_d) const
+    // D(pos) > zc, i.e. a node that may still spend zc substitutions on pattern[0..pos]
+    // cannot lead to a hit.
+    __device__ bool dprune(uint32_t zc, int pos) const
     {
-        if (!use_d || pos < 0) return false;
-        return zc < nbp && bp_at(zc) <= (uint32_t)pos;
+        return pos >= 0 && zc < nbp && bp_at(zc) <= (uint32_t)pos;
     }
 
     __device__ uint32_t sym(const DfsArgs &a, uint32_t pos) const
     {
-        if (strand == 0) return a.codes[base + pos];
-        const uint32_t c = a.codes[base + m - 1 - pos];
-        return c < 4 ? 3u - c : c;
+        const uint32_t c = a.codes[base + (strand ? m - 1 - pos : pos)];
+        return strand_sym(c, strand);
+    }
+
+    // Header of a new read-strand (offsets, budget, D record): loaded into registers of
+    // its own by request() and used by begin() after the round's loads have arrived.
+    uint64_t h0, h1;
+    uint32_t hz;
+    uint4 hbp;
+
+    __device__ void request(const DfsArgs &a, uint32_t item)
+    {
+        rs = item;
+        const uint32_t rd = a.nstr == 2 ? item >> 1 : item;
+        h0 = a.offs[rd];
+        h1 = a.offs[rd + 1];
+        hz = a.z[rd];
+        hbp = a.bp ? a.bp[item] : make_uint4(0, 0, 0, 0);
     }
 
     __device__ void init(const DfsArgs &a, uint32_t item)
     {
-        rs = item;
-        read = a.nstr == 2 ? item >> 1 : item;
-        strand = a.nstr == 2 ? (item & 1u) : a.strand0;
-        base = a.offs[read];
-        m = (uint32_t)(a.offs[read + 1] - base);
-        z0 = a.z[read];
+        request(a, item);
+        begin(a);
+    }
+
+    __device__ void begin(const DfsArgs &a)
+    {
+        read = a.nstr == 2 ? rs >> 1 : rs;
+        strand = a.nstr == 2 ? (rs & 1u) : a.strand0;
+        base = h0;
+        m = (uint32_t)(h1 - h0);
+        z0 = hz;
         sp = 0;
         hits = 0;
         status = FM_OK;
@@ -443,6 +486,10 @@ struct Dfs {
         pd = 0;
         nbp = 0;
         bpw0 = bpw1 = bpw2 = 0;
+        i = 0;
+        zr = 0;
+        k = 0;
+        l = a.lay.n;
         if (z0 > a.zmax) {
             status = FM_EINVAL;
             done = true;
@@ -454,7 +501,7 @@ struct Dfs {
             return;
         }
         if (a.bp) {
-            const uint4 r = a.bp[item];
+            const uint4 r = hbp;
             nbp = r.x & 0xFFFFu;
             bpw0 = r.x;
             bpw1 = r.y;
@@ -474,138 +521,154 @@ struct Dfs {
         }
         i = m - 1;
         zr = z0;
-        k = 0;
-        l = a.lay.n;
     }
 };
 
-// Stack of one read-strand: entries (k, l, i | zr << 16); LDS for the batched kernel,
-// global memory for the plain one.
-struct StackRef {
-    uint32_t *p;
-    __device__ void push(uint32_t sp, uint32_t k, uint32_t l, uint32_t iz, bool w) const
-    {
-        if (w) {
-            p[3 * sp] = k;
-            p[3 * sp + 1] = l;
-            p[3 * sp + 2] = iz;
-        }
-    }
-};
-
-// Expands the current node: one Occ8 at (k-1, l) yields the intervals of all four
+// Expands the current node: one Occ8 at (k-1, l) gives the intervals of all four
 // one-symbol extensions (Listing 2's loop over b, each computed from the parent's
-// interval and guarded by k_b <= l_b). Children needing more substitutions than left
-// (or than the D bound allows) are dropped. At i == 0 the surviving children are hits.
-// Otherwise one mismatch child (if any) is continued and the match child and the other
-// mismatch children are pushed, the match child deepest -- so the stack never holds
-// more than 3 entries per unit of budget spent on the current path (3 * zmax in all).
+// interval and kept only when k_b <= l_b). Children needing more substitutions than
+// remain, or than the D bound allows, are dropped. At i == 0 the survivors are hits.
+// Otherwise one mismatch child (if any) is continued while the match child and the
+// other mismatch children are pushed, the match child deepest: every pushed group
+// lies below a step that spent one substitution, so the stack never holds more than
+// 3 * zmax entries. Entry `scap - 1` of the stack is a spare that absorbs the writes of
+// children that are not pushed, which keeps the update free of branches.
 template <int I, int L>
-__device__ void dfs_expand(const DfsArgs &a, Dfs &d, uint32_t q, const Occ4 &ok, const Occ4 &ol,
-                           uint32_t wi, const StackRef &st, bool lead)
+__device__ __forceinline__ void dfs_node(const DfsArgs &a, Dfs &d, uint32_t q, uint32_t *st, bool lead,
+                                         uint64_t &n_occ, uint64_t &n_bk)
 {
+    // loads: the pattern symbol and the bucket(s) of (k-1, l), issued together
+    const uint32_t kk = d.k ? d.k : 1u;
+    const uint32_t wi = d.sym(a, d.i);
+    Pair<I, L> pr;
+    pr.load(a.lay, q, kk, d.l);
+    Occ4 o1, o2;
+    occ8<I, L>(a.lay, pr, q, kk, d.l, o1, o2);
+    const bool root = d.k == 0;                   // (0, n): children come from C alone
+    const uint32_t C0 = a.lay.C[0], C1 = a.lay.C[1], C2 = a.lay.C[2], C3 = a.lay.C[3], C4 = a.lay.C[4];
     uint32_t kb[4], lb[4];
-    if (d.k == 0) {
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            kb[b] = a.lay.C[b] + 1;
-            lb[b] = a.lay.C[b + 1];
-        }
-    } else {
-        const uint32_t o1[4] = {ok.a, ok.c, ok.g, ok.t}, o2[4] = {ol.a, ol.c, ol.g, ol.t};
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            kb[b] = a.lay.C[b] + o1[b] + 1;
-            lb[b] = a.lay.C[b] + o2[b];
-        }
+    kb[0] = C0 + 1 + (root ? 0u : o1.a);
+    kb[1] = C1 + 1 + (root ? 0u : o1.c);
+    kb[2] = C2 + 1 + (root ? 0u : o1.g);
+    kb[3] = C3 + 1 + (root ? 0u : o1.t);
+    lb[0] = root ? C1 : C0 + o2.a;
+    lb[1] = root ? C2 : C1 + o2.c;
+    lb[2] = root ? C3 : C2 + o2.g;
+    lb[3] = root ? C4 : C3 + o2.t;
+    if (lead) {
+        n_occ += 1;
+        n_bk += root ? 0 : (pr.same ? 1 : 2);
     }
-    const bool use_d = a.bp != nullptr;
-    const int child_pos = (int)d.i - 1;
+    // surviving children
+    const int cpos = (int)d.i - 1;
+    const bool keep_match = !(a.bp && d.dprune(d.zr, cpos));
+    const bool keep_mism = d.zr >= 1 && !(a.bp && d.dprune(d.zr - 1, cpos));
     uint32_t valid = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        const uint32_t cost = (uint32_t)b != wi ? 1u : 0u;
-        if (kb[b] <= lb[b] && d.zr >= cost && !d.dprune(d.zr - cost, child_pos, use_d)) valid |= 1u << b;
+        const bool m = (uint32_t)b == wi;
+        valid |= (kb[b] <= lb[b] && (m ? keep_match : keep_mism)) ? (1u << b) : 0u;
     }
-    if (d.i == 0) {
-        d.pend = valid;
+    const bool leaf = d.i == 0;
+    const uint32_t mbit = wi < 4 ? (1u << wi) : 0u;
+    const uint32_t match = valid & mbit;
+    const uint32_t mism = valid & ~mbit;
+    // hits
+    d.pend = leaf ? valid : 0u;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            d.pk[b] = kb[b];
-            d.pl[b] = lb[b];
-        }
-        d.pd = (d.z0 - d.zr) | (wi << 8);
-    } else {
-        const uint32_t match = wi < 4 ? (valid & (1u << wi)) : 0u;
-        uint32_t mism = valid & ~match;
-        if (mism) {
-            const uint32_t cont = (uint32_t)__builtin_ctz(mism);
-            mism &= ~(1u << cont);
-            const uint32_t ci = d.i - 1;
-            if (match) {
-                st.push(d.sp, kb[wi], lb[wi], ci | (d.zr << 16), lead);
-                d.sp += 1;
-            }
+    for (int b = 0; b < 4; ++b) {
+        d.pk[b] = kb[b];
+        d.pl[b] = lb[b];
+    }
+    d.pd = (d.z0 - d.zr) | (wi << 8);
+    // continue with a mismatch child if there is one, else with the match child
+    const bool has_mism = !leaf && mism != 0;
+    const uint32_t cont = has_mism ? (uint32_t)__builtin_ctz(mism) : (wi & 3);
+    const bool advance = !leaf && (mism | match) != 0;
+    const uint32_t push = has_mism ? ((mism & ~(1u << cont)) | match) : 0u;
+    const uint32_t ci = d.i - 1;
+    const uint32_t spare = a.scap - 1;
+    const uint32_t base_other = d.sp + (match & push ? 1u : 0u);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                if (mism & (1u << b)) {
-                    st.push(d.sp, kb[b], lb[b], ci | ((d.zr - 1) << 16), lead);
-                    d.sp += 1;
-                }
-            }
-            d.i = ci;
-            d.zr -= 1;
-            d.k = kb[cont];
-            d.l = lb[cont];
-            return;
-        }
-        if (match) {
-            d.i -= 1;
-            d.k = kb[wi];
-            d.l = lb[wi];
-            return;
+    for (int b = 0; b < 4; ++b) {
+        const bool pb = (push >> b) & 1u;
+        const bool is_match = (mbit >> b) & 1u;
+        const uint32_t slot = !pb ? spare : (is_match ? d.sp : base_other + __popc(push & ~mbit & ((1u << b) - 1u)));
+        const uint32_t zc = d.zr - (is_match ? 0u : 1u);
+        if (lead) {
+            uint32_t *e = st + 3 * slot;
+            e[0] = kb[b];
+            e[1] = lb[b];
+            e[2] = ci | (zc << 16);
         }
     }
-    // no child to continue: take the next pending node
-    if (d.sp == 0) {
+    const uint32_t nsp = d.sp + __popc(push);
+    // next node: the continued child, or the top of the stack
+    const bool pop = !advance && nsp > 0;
+    const uint32_t *top = st + 3 * (pop ? nsp - 1 : spare);
+    const uint32_t t0 = top[0], t1 = top[1], t2 = top[2];
+    const uint32_t kc = sel4(cont, kb[0], kb[1], kb[2], kb[3]);
+    const uint32_t lc = sel4(cont, lb[0], lb[1], lb[2], lb[3]);
+    d.k = advance ? kc : t0;
+    d.l = advance ? lc : t1;
+    d.i = advance ? ci : (t2 & 0xFFFFu);
+    d.zr = advance ? d.zr - (cont != wi ? 1u : 0u) : (t2 >> 16);
+    d.sp = pop ? nsp - 1 : nsp;
+    d.done = !advance && !pop;
+    d.nodes += 1;
+    if (!d.done && d.nodes >= a.budget) {
+        d.status = FM_EBUDGET;
         d.done = true;
-        return;
     }
-    d.sp -= 1;
-    const uint32_t *e = st.p + 3 * d.sp;
-    d.k = e[0];
-    d.l = e[1];
-    d.i = e[2] & 0xFFFFu;
-    d.zr = e[2] >> 16;
 }
 
-// Appends pending hits to the staging pool (one atomic per wave) and retires finished
-// read-strands. Must be called by the whole wave.
+// Stores the hits of the last expansion: the first kHitSlots hits of a read-strand go
+// to its own slots with plain stores; later ones are appended to the overflow pool
+// (one atomic per wave, rarely needed). Then retires finished read-strands. Must be
+// called by the whole wave.
 template <int L>
 __device__ void dfs_emit(const DfsArgs &a, Dfs &d, bool active, bool lead)
 {
-    const uint32_t lane = __lane_id(), leadlane = lane & ~(uint32_t)(L - 1);
     const uint32_t pend = active ? d.pend : 0u;
-    uint64_t mb[4];
-    uint32_t tot = 0;
+    const uint32_t wi = d.pd >> 8;
+    uint32_t over = 0;                        // children whose hit goes to the overflow pool
+    if (pend) {
+        uint32_t h = d.hits;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        mb[b] = __ballot(lead && ((pend >> b) & 1u));
-        tot += (uint32_t)__popcll(mb[b]);
+        for (int b = 0; b < 4; ++b) {
+            if ((pend >> b) & 1u) {
+                const uint32_t nmm = (d.pd & 0xFFu) + ((uint32_t)b != wi ? 1u : 0u);
+                if (h < kHitSlots) {
+                    if (lead)
+                        ((uint4 *)a.slots)[(size_t)d.rs * kHitSlots + h] =
+                            make_uint4(d.read, d.pk[b], d.pl[b], d.strand | (nmm << 8));
+                } else {
+                    over |= 1u << b;
+                }
+                ++h;
+            }
+        }
     }
-    if (tot) {
+    if (__ballot(over != 0)) {
+        const uint32_t lane = __lane_id(), leadlane = lane & ~(uint32_t)(L - 1);
+        uint64_t mb[4];
+        uint32_t tot = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            mb[b] = __ballot(lead && ((over >> b) & 1u));
+            tot += (uint32_t)__popcll(mb[b]);
+        }
         unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(a.pool_count, (unsigned long long)tot);
+        if (lane == 0) base = atomicAdd(a.ocount, (unsigned long long)tot);
         base = __shfl(base, 0);
         uint64_t off = base;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            if ((pend >> b) & 1u) {
+            if ((over >> b) & 1u) {
                 const uint64_t pos = off + rank_below(mb[b], leadlane);
-                const uint32_t wi = d.pd >> 8;
                 const uint32_t nmm = (d.pd & 0xFFu) + ((uint32_t)b != wi ? 1u : 0u);
-                if (pos < a.cap) {
-                    if (lead) ((uint4 *)a.pool)[pos] = make_uint4(d.read, d.pk[b], d.pl[b], d.strand | (nmm << 8));
+                if (pos < a.ocap) {
+                    if (lead) ((uint4 *)a.opool)[pos] = make_uint4(d.read, d.pk[b], d.pl[b], d.strand | (nmm << 8));
                 } else {
                     d.status = FM_EOVERFLOW;
                 }
@@ -626,47 +689,20 @@ __device__ void dfs_emit(const DfsArgs &a, Dfs &d, bool active, bool lead)
     }
 }
 
-template <int I, int L>
-__device__ __forceinline__ void dfs_fetch_expand(const DfsArgs &a, Dfs &d, uint32_t q, const StackRef &st, bool lead,
-                                                 uint64_t &n_occ, uint64_t &n_bk)
-{
-    constexpr int LOG = Geo<I>::LOG;
-    const uint32_t wi = d.sym(a, d.i);
-    Occ4 o1 = {0, 0, 0, 0}, o2 = {0, 0, 0, 0};
-    if (d.k != 0) {
-        const uint32_t j2 = d.l >> LOG, j1 = (d.k - 1) >> LOG;
-        Bucket<I, L> b1, b2;
-        fetch<I, L>(a.lay, j1, q, b1);
-        if (j1 != j2) fetch<I, L>(a.lay, j2, q, b2);
-        o1 = group_sum4<L>(part4<I, L>(b1, q, (d.k - 1) & (I - 1)));
-        o2 = group_sum4<L>(j1 != j2 ? part4<I, L>(b2, q, d.l & (I - 1)) : part4<I, L>(b1, q, d.l & (I - 1)));
-        o1.a -= (d.k - 1 >= a.lay.dollar) ? 1u : 0u;
-        o2.a -= (d.l >= a.lay.dollar) ? 1u : 0u;
-        n_bk += lead ? (j1 != j2 ? 2 : 1) : 0;
-    }
-    n_occ += lead ? 1 : 0;
-    dfs_expand<I, L>(a, d, q, o1, o2, wi, st, lead);
-    d.nodes += 1;
-    if (!d.done && d.nodes >= a.budget) {
-        d.status = FM_EBUDGET;
-        d.done = true;
-    }
-}
-
 template <int I>
 __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
 {
+    extern __shared__ uint32_t lds_stack[];
     const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = item < a.total;
+    uint32_t *st = lds_stack + (size_t)threadIdx.x * a.scap * 3;
     Dfs d;
     d.rs = kEmpty;
-    if (live) d.init(a, item);
-    StackRef st{a.gstack + (size_t)(live ? item : 0) * a.scap * 3};
+    if (item < a.total) d.init(a, item);
     uint64_t n_occ = 0, n_bk = 0;
     for (;;) {
         const bool active = d.rs != kEmpty;
         if (!__any(active)) break;
-        if (active && !d.done) dfs_fetch_expand<I, 1>(a, d, 0, st, true, n_occ, n_bk);
+        if (active && !d.done) dfs_node<I, 1>(a, d, 0, st, true, n_occ, n_bk);
         dfs_emit<1>(a, d, active, true);
     }
     wave_add(a.stat_occ, n_occ);
@@ -679,19 +715,24 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
     extern __shared__ uint32_t lds_stack[];
     const uint32_t q = L == 1 ? 0u : (__lane_id() & (L - 1));
     const bool lead = q == 0;
-    const uint32_t group = threadIdx.x / L;
-    StackRef st{lds_stack + (size_t)group * a.scap * 3};
+    uint32_t *st = lds_stack + (size_t)(threadIdx.x / L) * a.scap * 3;
     Dfs d;
     d.rs = kEmpty;
-    WaveQueue wq = {0, 0, false};
+    d.done = false;
+    WaveQueue wq;
+    wq.start(a.queue);
     uint64_t n_occ = 0, n_bk = 0;
     for (;;) {
+        // expand the current nodes (their loads go out first), then refill idle lanes,
+        // whose headers arrive with the same round of loads
+        const bool running = d.rs != kEmpty;
+        if (running && !d.done) dfs_node<I, L>(a, d, q, st, lead, n_occ, n_bk);
+        dfs_emit<L>(a, d, running, lead);
         const uint32_t it = wave_take<L>(wq, d.rs == kEmpty, a.queue, a.total);
-        if (it != kEmpty) d.init(a, it);
-        const bool active = d.rs != kEmpty;
-        if (!__any(active)) break;
-        if (active && !d.done) dfs_fetch_expand<I, L>(a, d, q, st, lead, n_occ, n_bk);
-        dfs_emit<L>(a, d, active, lead);
+        if (it != kEmpty) d.request(a, it);
+        if (!__any(d.rs != kEmpty)) break;
+        if (it != kEmpty) d.begin(a);
+        dfs_emit<L>(a, d, it != kEmpty, lead);   // read-strands decided at once (pruned root, empty read)
     }
     wave_add(a.stat_occ, n_occ);
     wave_add(a.stat_bk, n_bk);
@@ -728,10 +769,11 @@ static hipError_t dfs_by_lanes(const fm_index *idx, const fm_tuning &t, const Df
 
 // ------------------------------------------------------------------ compaction
 
-// Per read: the worst strand status, the hit count to list (0 unless FM_OK), the
-// cursor reset, and the count every read would need (for FM_OK and FM_EOVERFLOW reads).
+// Per read: the worst strand status, the number of hits to list (0 unless FM_OK), and
+// the number every read would need (FM_OK and FM_EOVERFLOW reads). Clears the
+// overflow cursors.
 __global__ void finalize_reads(uint32_t nreads, uint32_t nstr, const uint32_t *rs_count, const uint32_t *rs_status,
-                               uint32_t *status, uint32_t *cnt, uint32_t *cursor, unsigned long long *required)
+                               uint32_t *rd_status, uint32_t *cnt, uint32_t *cursor, unsigned long long *required)
 {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t need = 0;
@@ -741,10 +783,10 @@ __global__ void finalize_reads(uint32_t nreads, uint32_t nstr, const uint32_t *r
             const uint32_t v = rs_status[r * nstr + s];
             st = v > st ? v : st;
             c += rs_count[r * nstr + s];
+            cursor[r * nstr + s] = 0;
         }
-        status[r] = st;
+        rd_status[r] = st;
         cnt[r] = st == FM_OK ? c : 0u;
-        cursor[r] = 0;
         need = (st == FM_OK || st == FM_EOVERFLOW) ? c : 0u;
     }
     wave_add(required, need);
@@ -800,20 +842,58 @@ __global__ void scan_write_u64(const uint32_t *cnt, uint64_t n, const uint64_t *
     }
 }
 
-__global__ void scatter_hits(const fm_hit *pool, const unsigned long long *pool_count, uint64_t cap,
-                             const uint32_t *status, const uint64_t *hit_offs, uint32_t *cursor, fm_hit *hits)
+// The listed prefix of reads: reads are listed in order while their hits fit in cap.
+// cut = the largest offset <= cap; exactly one r in [0, n] satisfies the test.
+__global__ void find_cut(const uint64_t *offs, uint64_t n, uint64_t cap, uint64_t *cut)
 {
-    const uint64_t total = *pool_count < cap ? *pool_count : cap;
+    const uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (r > n) return;
+    if (offs[r] <= cap && (r == n || offs[r + 1] > cap)) *cut = offs[r];
+}
+
+// Final offsets and statuses, and the slot hits of every listed read (strand 0's hits,
+// then strand 1's; within a strand the slot hits precede its overflow-pool hits).
+__global__ void gather_hits(uint32_t nreads, uint32_t nstr, const uint32_t *rs_count, const uint32_t *rd_status,
+                            const uint64_t *offs, const uint64_t *cut, const fm_hit *slots, uint64_t *hit_offs,
+                            uint32_t *status, fm_hit *hits)
+{
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nreads) return;
+    const uint64_t c = *cut;
+    const uint64_t o0 = offs[r], o1 = offs[r + 1];
+    hit_offs[r] = o0 < c ? o0 : c;
+    if (r + 1 == nreads) hit_offs[nreads] = o1 < c ? o1 : c;
+    uint32_t st = rd_status[r];
+    if (st == FM_OK && o1 > c) st = FM_EOVERFLOW;    // beyond hit_cap: not listed
+    status[r] = st;
+    if (st != FM_OK) return;
+    uint64_t dst = o0;
+    for (uint32_t s = 0; s < nstr; ++s) {
+        const uint32_t rs = r * nstr + s;
+        const uint32_t n = rs_count[rs];
+        const uint32_t ns = n < kHitSlots ? n : kHitSlots;
+        for (uint32_t h = 0; h < ns; ++h) ((uint4 *)hits)[dst + h] = ((const uint4 *)slots)[(size_t)rs * kHitSlots + h];
+        dst += n;
+    }
+}
+
+// Overflow-pool hits of listed reads, after their read-strand's slot hits.
+__global__ void scatter_overflow(const fm_hit *opool, const unsigned long long *ocount, uint64_t ocap, uint32_t nstr,
+                                 const uint32_t *rs_count, const uint32_t *status, const uint64_t *hit_offs,
+                                 uint32_t *cursor, fm_hit *hits)
+{
+    const uint64_t total = *ocount < ocap ? *ocount : ocap;
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total; e += (uint64_t)gridDim.x * blockDim.x) {
-        const uint4 h = ((const uint4 *)pool)[e];
-        if (status[h.x] != FM_OK) continue;
-        const uint64_t pos = hit_offs[h.x] + atomicAdd(&cursor[h.x], 1u);
-        ((uint4 *)hits)[pos] = h;
+        const uint4 h = ((const uint4 *)opool)[e];
+        const uint32_t r = h.x, s = nstr == 2 ? (h.w & 0xFFu) : 0u;
+        if (status[r] != FM_OK) continue;
+        const uint64_t start = hit_offs[r] + (s ? rs_count[r * nstr] : 0u) + kHitSlots;
+        ((uint4 *)hits)[start + atomicAdd(&cursor[r * nstr + s], 1u)] = h;
     }
 }
 
 // Hits of one read sorted by (strand, k): in substitution mode every (strand, k) is
-// distinct, so the order is unique whatever order the pool received them in.
+// distinct, so the order is unique whatever order the hits were found in.
 __global__ void sort_read_hits(uint64_t nreads, const uint64_t *hit_offs, fm_hit *hits)
 {
     const uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
@@ -835,8 +915,9 @@ __global__ void sort_read_hits(uint64_t nreads, const uint64_t *hit_offs, fm_hit
     }
 }
 
-InexactWs inexact_ws_layout(uint64_t nreads, uint32_t nstr, uint32_t zmax, uint64_t hit_cap, bool plain)
+InexactWs inexact_ws_layout(uint64_t nreads, uint32_t nstr, uint32_t zmax, uint64_t hit_cap)
 {
+    (void)zmax;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     InexactWs w;
     size_t off = kWsHeader;
@@ -844,27 +925,31 @@ InexactWs inexact_ws_layout(uint64_t nreads, uint32_t nstr, uint32_t zmax, uint6
     w.bp = off;        off = al(off + nrs * 16);
     w.rs_count = off;  off = al(off + nrs * 4);
     w.rs_status = off; off = al(off + nrs * 4);
-    w.cursor = off;    off = al(off + nreads * 4);
+    w.cursor = off;    off = al(off + nrs * 4);
+    w.rd_status = off; off = al(off + nreads * 4);
     w.cnt = off;       off = al(off + nreads * 4);
+    w.offs = off;      off = al(off + (nreads + 1) * 8);
     const uint64_t nblk = (nreads + kScanBlock * kTile - 1) / (kScanBlock * kTile);
     w.part = off;      off = al(off + (nblk + 1) * 8);
-    w.pool = off;      off = al(off + hit_cap * 16);
-    w.stack = off;
-    if (plain) off = al(off + nrs * (3ull * (zmax ? zmax : 1)) * 12);
+    w.slots = off;     off = al(off + nrs * kHitSlots * 16);
+    w.opool = off;     off = al(off + hit_cap * 16);
     w.total = off;
     return w;
 }
 
 hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuning &tw, bool plain, const DfsCall &c,
-                          hipStream_t s)
+                          hipStream_t s, const PhaseEvents *pe)
 {
+    const PhaseEvents none;
+    if (!pe) pe = &none;
     char *ws = (char *)c.ws;
     const uint32_t nstr = strand_count(c.flags);
-    const InexactWs W = inexact_ws_layout(c.nreads, nstr, c.zmax, c.hit_cap, plain);
+    const InexactWs W = inexact_ws_layout(c.nreads, nstr, c.zmax, c.hit_cap);
     hipError_t e = launch_fill(ws, 0, kWsHeader / 4, s);
     if (e != hipSuccess) return e;
     if (c.nreads == 0) return launch_fill(c.hit_offs, 0, 2, s);
     const bool use_d = (c.flags & FM_DARRAY) != 0;
+    pe->mark(1, s);
     if (use_d) {
         WalkCall wc{c.codes, c.offs, c.z, c.nreads, c.flags, c.zmax, ws + W.bp, ws};
         e = launch_walk(idx, tw, WALK_DBP, plain, wc, s);
@@ -880,23 +965,25 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     a.strand0 = (c.flags & FM_FWD) ? 0u : 1u;
     a.total = (uint32_t)(c.nreads * nstr);
     a.zmax = c.zmax;
-    a.scap = 3 * (c.zmax ? c.zmax : 1);
+    a.scap = 3 * c.zmax + 1;
     a.budget = t.node_budget ? t.node_budget : 0xFFFFFFFFu;
-    a.pool = (fm_hit *)(ws + W.pool);
-    a.cap = c.hit_cap;
-    a.pool_count = (unsigned long long *)(ws + kWsPool);
+    a.slots = (fm_hit *)(ws + W.slots);
+    a.opool = (fm_hit *)(ws + W.opool);
+    a.ocap = c.hit_cap;
+    a.ocount = (unsigned long long *)(ws + kWsPool);
     a.rs_count = (uint32_t *)(ws + W.rs_count);
     a.rs_status = (uint32_t *)(ws + W.rs_status);
     a.queue = (uint32_t *)(ws + kWsQueue2);
-    a.gstack = (uint32_t *)(ws + W.stack);
     a.stat_occ = (c.flags & FM_STATS) ? (unsigned long long *)(ws + kWsStatOcc) : nullptr;
     a.stat_bk = (c.flags & FM_STATS) ? (unsigned long long *)(ws + kWsStatBuckets) : nullptr;
+    pe->mark(2, s);
     if (plain) {
         const uint32_t grid = (a.total + 255) / 256;
+        const size_t lds = (size_t)256 * a.scap * 3 * sizeof(uint32_t);
         switch (t.occ_interval) {
-        case 64: hipLaunchKernelGGL(dfs_plain<64>, dim3(grid), dim3(256), 0, s, a); break;
-        case 128: hipLaunchKernelGGL(dfs_plain<128>, dim3(grid), dim3(256), 0, s, a); break;
-        case 256: hipLaunchKernelGGL(dfs_plain<256>, dim3(grid), dim3(256), 0, s, a); break;
+        case 64: hipLaunchKernelGGL(dfs_plain<64>, dim3(grid), dim3(256), lds, s, a); break;
+        case 128: hipLaunchKernelGGL(dfs_plain<128>, dim3(grid), dim3(256), lds, s, a); break;
+        case 256: hipLaunchKernelGGL(dfs_plain<256>, dim3(grid), dim3(256), lds, s, a); break;
         default: return hipErrorInvalidValue;
         }
         e = hipGetLastError();
@@ -909,22 +996,30 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
         }
     }
     if (e != hipSuccess) return e;
+    pe->mark(3, s);
     // compaction
     uint32_t *cnt = (uint32_t *)(ws + W.cnt), *cursor = (uint32_t *)(ws + W.cursor);
+    uint32_t *rd_status = (uint32_t *)(ws + W.rd_status);
+    uint64_t *offs_tmp = (uint64_t *)(ws + W.offs);
+    uint64_t *cut = (uint64_t *)(ws + kWsCut);
     const uint32_t nr = (uint32_t)c.nreads;
     hipLaunchKernelGGL(finalize_reads, dim3((nr + 255) / 256), dim3(256), 0, s, nr, nstr, a.rs_count, a.rs_status,
-                       c.status, cnt, cursor, (unsigned long long *)(ws + kWsRequired));
+                       rd_status, cnt, cursor, (unsigned long long *)(ws + kWsRequired));
     const uint64_t nblk = (c.nreads + kScanBlock * kTile - 1) / (kScanBlock * kTile);
     uint64_t *part = (uint64_t *)(ws + W.part);
     hipLaunchKernelGGL(scan_reduce_u64, dim3((uint32_t)nblk), dim3(kScanBlock), 0, s, cnt, c.nreads, part);
     hipLaunchKernelGGL(scan_partials_u64, dim3(1), dim3(1024), 0, s, part, nblk);
-    hipLaunchKernelGGL(scan_write_u64, dim3((uint32_t)nblk), dim3(kScanBlock), 0, s, cnt, c.nreads, part, c.hit_offs);
+    hipLaunchKernelGGL(scan_write_u64, dim3((uint32_t)nblk), dim3(kScanBlock), 0, s, cnt, c.nreads, part, offs_tmp);
+    hipLaunchKernelGGL(find_cut, dim3((nr + 1 + 255) / 256), dim3(256), 0, s, offs_tmp, c.nreads, c.hit_cap, cut);
+    hipLaunchKernelGGL(gather_hits, dim3((nr + 255) / 256), dim3(256), 0, s, nr, nstr, a.rs_count, rd_status, offs_tmp,
+                       cut, a.slots, c.hit_offs, c.status, c.hits);
     uint64_t sgrid = (c.hit_cap + 255) / 256;
-    if (sgrid > (uint64_t)idx->cu_count * 8) sgrid = (uint64_t)idx->cu_count * 8;
+    if (sgrid > (uint64_t)idx->cu_count * 4) sgrid = (uint64_t)idx->cu_count * 4;
     if (sgrid == 0) sgrid = 1;
-    hipLaunchKernelGGL(scatter_hits, dim3((uint32_t)sgrid), dim3(256), 0, s, a.pool, a.pool_count, c.hit_cap, c.status,
-                       c.hit_offs, cursor, c.hits);
+    hipLaunchKernelGGL(scatter_overflow, dim3((uint32_t)sgrid), dim3(256), 0, s, a.opool, a.ocount, a.ocap, nstr,
+                       a.rs_count, c.status, c.hit_offs, cursor, c.hits);
     hipLaunchKernelGGL(sort_read_hits, dim3((nr + 255) / 256), dim3(256), 0, s, c.nreads, c.hit_offs, c.hits);
+    pe->mark(4, s);
     return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ FM_OP_EXACT, FM_OP_DARRAY, FM_OP_INEXACT = 0, 1, 2
 FM_ZMAX = 4
 
 # byte offsets inside the inexact workspace (see fm_search_inexact in fm.h)
-WS_REQUIRED, WS_STAT_OCC, WS_STAT_BUCKETS, WS_STAT_WALK = 8, 64, 72, 80
+WS_REQUIRED, WS_STAT_OCC, WS_STAT_BUCKETS, WS_STAT_WALK, WS_STAT_WALK_BK = 8, 64, 72, 80, 88
 
 
 class FmError(RuntimeError):
@@ -94,6 +94,8 @@ def lib() -> C.CDLL:
         "fm_plan_create": (i32, [vp, i32, vp, vp, vp, u64, u32, u32, vp, u64, vp, vp, vp, C.c_size_t,
                                  C.POINTER(vp)]),
         "fm_plan_launch": (i32, [vp, vp]),
+        "fm_phase_timing": (i32, [vp, u32]),
+        "fm_phase_times": (i32, [vp, C.POINTER(C.c_float), C.POINTER(C.c_uint32)]),
         "fm_plan_free": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -224,6 +226,15 @@ class Index:
         t = Tuning(**cur)
         _check(lib().fm_set_tuning(self.handle, op, C.byref(t)), "fm_set_tuning")
 
+    def phase_timing(self, capacity: int):
+        _check(lib().fm_phase_timing(self.handle, capacity), "fm_phase_timing")
+
+    def phase_times(self) -> tuple:
+        ms = (C.c_float * 4)()
+        calls = C.c_uint32(0)
+        _check(lib().fm_phase_times(self.handle, ms, C.byref(calls)), "fm_phase_times")
+        return {"exact_walk": ms[0], "d_walk": ms[1], "dfs": ms[2], "compaction": ms[3]}, int(calls.value)
+
     def free(self):
         if self._h:
             lib().fm_index_free(self._h)
@@ -255,6 +266,11 @@ def fm_search_exact_workspace(idx: Index, nreads: int, flags: int) -> int:
     return int(b.value)
 
 
+def exact_stats(ws: torch.Tensor) -> dict:
+    v = ws[WS_STAT_WALK:WS_STAT_WALK + 16].cpu().numpy().view(np.uint64)
+    return {"steps": int(v[0]), "buckets": int(v[1])}
+
+
 def fm_search_exact(idx: Index, codes: torch.Tensor, offs: torch.Tensor, flags: int = FM_FWD,
                     out: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """codes: uint8 device tensor; offs: int64 device tensor (nreads+1). Returns
@@ -264,7 +280,7 @@ def fm_search_exact(idx: Index, codes: torch.Tensor, offs: torch.Tensor, flags: 
     nreads = offs.numel() - 1
     if out is None:
         out = torch.empty((nreads * nstrands(flags), 2), dtype=torch.int32, device=codes.device)
-    need = fm_search_exact_workspace(idx, nreads, flags)
+    need = fm_search_exact_workspace(idx, nreads, flags) if not (flags & FM_PLAIN and not flags & FM_STATS) else 0
     if ws is None and need:
         ws = torch.empty(need, dtype=torch.uint8, device=codes.device)
     wsb = ws.numel() if ws is not None else 0
@@ -308,8 +324,8 @@ class InexactBuffers:
         return int(self.ws[WS_REQUIRED:WS_REQUIRED + 8].cpu().numpy().view(np.uint64)[0])
 
     def stats(self) -> dict:
-        v = self.ws[WS_STAT_OCC:WS_STAT_OCC + 24].cpu().numpy().view(np.uint64)
-        return {"occ8": int(v[0]), "buckets": int(v[1]), "walk_steps": int(v[2])}
+        v = self.ws[WS_STAT_OCC:WS_STAT_OCC + 32].cpu().numpy().view(np.uint64)
+        return {"occ8": int(v[0]), "buckets": int(v[1]), "walk_steps": int(v[2]), "walk_buckets": int(v[3])}
 
 
 def fm_search_inexact(idx: Index, codes: torch.Tensor, offs: torch.Tensor, z: torch.Tensor, flags: int,
