@@ -79,14 +79,15 @@ enum {
 /* Load flags. */
 enum {
     FM_LOAD_REVERSE = 1,            /* also build/keep the index of reverse(R) */
-    FM_LOAD_ALL_LAYOUTS = 2         /* build the layouts for all of I = 64, 128, 256 */
+    FM_LOAD_ALL_LAYOUTS = 2         /* build the layouts for every supported I */
 };
 
 #define FM_ZMAX 4                   /* largest per-read mismatch budget */
 
 typedef struct {
     int device;                     /* HIP device ordinal */
-    uint32_t occ_interval;          /* checkpoint interval I: 64, 128, 256, or 0 for 128 */
+    uint32_t occ_interval;          /* checkpoint interval I: 64, 96, 128, 192, 224, 256, 448;
+                                       0 for 128 */
     uint32_t flags;                 /* FM_LOAD_* */
 } fm_load_opts;
 
@@ -97,7 +98,8 @@ typedef struct {
     uint64_t rev_dollar_row;        /* same for reverse(R), if present */
     uint64_t rev_C[5];
     uint32_t occ_interval;          /* layout used by the searches */
-    uint32_t layouts;               /* built layouts: bit 0 = 64, bit 1 = 128, bit 2 = 256 */
+    uint32_t layouts;               /* built layouts: bits 0..6 = I of 64, 96, 128, 192, 224,
+                                       256, 448 */
     uint32_t has_reverse;
     uint32_t pad;
     uint64_t device_bytes;          /* device memory owned by the index */
@@ -105,11 +107,15 @@ typedef struct {
 
 /* Launch configuration of one operation (see fm_get_tuning). */
 typedef struct {
-    uint32_t occ_interval;          /* 64, 128 or 256; must be one of the index's layouts */
-    uint32_t lanes;                 /* lanes cooperating on one read-strand: 1, 2, 4 or 8 */
-    uint32_t depth;                 /* read-strands in flight per lane group: 1 or 2 */
+    uint32_t occ_interval;          /* one of the index's layouts (see fm_load_opts) */
+    uint32_t lanes;                 /* lanes per read-strand: 1, 2, 4 or 8, at most the bucket's
+                                       16-byte chunks (2 for I = 64/96, 4 for 128/192/224,
+                                       8 for 256/448) */
+    uint32_t depth;                 /* walks: read-strands in flight per lane group, 1 or 2
+                                       (the DFS keeps one) */
     uint32_t block;                 /* threads per workgroup: 64, 128, 192 or 256 */
-    uint32_t waves_per_cu;          /* persistent grid = CUs * waves_per_cu * 64 / block */
+    uint32_t waves_per_cu;          /* persistent grid = CUs * waves_per_cu * 64 / block;
+                                       0 = as many as fit */
     uint32_t node_budget;           /* inexact: DFS nodes per read-strand before FM_EBUDGET */
 } fm_tuning;
 

@@ -19,6 +19,7 @@ DevLayout dev_layout(const fm_index *idx, uint32_t I, bool rev)
     DevLayout d;
     const int li = ilog(I);
     d.bk = (const uint4 *)(rev ? idx->rlay[li] : idx->lay[li]);
+    d.sb = compact_layout(I) ? (const uint4 *)((const char *)d.bk + num_buckets(idx->n, I) * bucket_bytes(I)) : nullptr;
     d.n = (uint32_t)idx->n;
     d.dollar = (uint32_t)(rev ? idx->rev_dollar : idx->dollar);
     const uint64_t *C = rev ? idx->rev_C : idx->C;
@@ -73,16 +74,19 @@ bool valid_tuning(const fm_index *idx, const fm_tuning &t)
     const int li = ilog(t.occ_interval);
     if (li < 0 || !idx->lay[li]) return false;
     if (t.lanes != 1 && t.lanes != 2 && t.lanes != 4 && t.lanes != 8) return false;
+    if (t.lanes > max_lanes(t.occ_interval)) return false;
     if (t.depth != 1 && t.depth != 2) return false;
     if (t.block < 64 || t.block > 256 || t.block % 64) return false;
     return true;
 }
 
+// One lane per read-strand, one read-strand in flight per lane and 8 waves per CU: the
+// best setting measured on MI355X for all three searches; fm_autotune refines it.
 void default_tunings(fm_index *idx, uint32_t I)
 {
-    fm_tuning ex = {I, 4, 2, 256, 0, 0};
-    fm_tuning dw = {I, 4, 2, 256, 0, 0};
-    fm_tuning in = {I, 1, 1, 256, 0, 1u << 22};
+    fm_tuning ex = {I, 1, 1, 256, 8, 0};
+    fm_tuning dw = {I, 1, 1, 256, 8, 0};
+    fm_tuning in = {I, 1, 1, 256, 8, 1u << 22};
     idx->tune[FM_OP_EXACT] = ex;
     idx->tune[FM_OP_DARRAY] = dw;
     idx->tune[FM_OP_INEXACT] = in;
@@ -120,7 +124,7 @@ int create_index(const fm_load_opts *opts, uint64_t n, const HostSide &fwd, cons
 
     const size_t pbytes = fwd.words.size() * 4;
     size_t sbytes = 0;
-    for (uint32_t J : {64u, 128u, 256u}) sbytes = std::max(sbytes, build_layout_scratch(n, J));
+    for (uint32_t J : kIntervals) sbytes = std::max(sbytes, build_layout_scratch(n, J));
     void *packed = nullptr, *scratch = nullptr;
     int st = FM_OK;
     if (hipMalloc(&packed, pbytes ? pbytes : 16) != hipSuccess || hipMalloc(&scratch, sbytes) != hipSuccess) st = FM_ENOMEM;
@@ -130,7 +134,7 @@ int create_index(const fm_load_opts *opts, uint64_t n, const HostSide &fwd, cons
             st = FM_EDEVICE;
             break;
         }
-        for (uint32_t J : {64u, 128u, 256u}) {
+        for (uint32_t J : kIntervals) {
             if (!all && J != I) continue;
             void *buf = nullptr;
             const size_t lb = layout_bytes(n, J);
@@ -260,7 +264,7 @@ int fm_index_info(const fm_index *idx, fm_info *out)
     out->rev_dollar_row = idx->rev_dollar;
     memcpy(out->rev_C, idx->rev_C, sizeof out->rev_C);
     out->occ_interval = idx->tune[FM_OP_INEXACT].occ_interval;
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < kLayouts; ++i)
         if (idx->lay[i]) out->layouts |= 1u << i;
     out->has_reverse = idx->has_rev ? 1u : 0u;
     out->device_bytes = idx->device_bytes;
@@ -272,7 +276,7 @@ void fm_index_free(fm_index *idx)
     if (!idx) return;
     DeviceGuard g(idx->device);
     release_events(idx);
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < kLayouts; ++i) {
         if (idx->lay[i]) (void)hipFree(idx->lay[i]);
         if (idx->rlay[i]) (void)hipFree(idx->rlay[i]);
     }

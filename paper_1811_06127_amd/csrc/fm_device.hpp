@@ -5,7 +5,8 @@
 //   chunk 0        : uint32 counts of A, C, G, T over BWT rows [0, I*j)  ('$' counted as A)
 //   chunks 1..I/64 : the I BWT symbols of rows [I*j, I*(j+1)), 2 bits each, LSB first
 //                    (row I*j + 16*w + s at bits 2s, 2s+1 of word w, the order of Fig. 2)
-//   remaining      : padding up to the bucket size (32, 64, 128 bytes for I = 64, 128, 256).
+//   remaining      : padding up to the bucket size (32, 64, 64, 128, 128 bytes for
+//                    I = 64, 128, 192, 256, 448; the dense 192 and 448 have none).
 // This is the checkpoint-plus-block arrangement of the Background section (counters of
 // every I-th row followed by I 2-bit symbols), with 32-bit counters because n+1 < 2^32.
 //
@@ -24,15 +25,28 @@ namespace fm {
 
 struct DevLayout {
     const uint4 *bk;     // buckets, Geo<I>::CH chunks of 16 bytes each
+    const uint4 *sb;     // compact layouts: uint32 counts at each superblock start
     uint32_t n;          // text length: rows 0..n
     uint32_t dollar;     // row of '$'
     uint32_t C[5];       // C[4] = n
 };
 
+// Bucket geometry: CH 16-byte chunks per bucket, of which USED are fetched (counts and
+// symbols; the rest is padding). I = 192 and 448 fill their 64- and 128-byte lines.
+//
+// The compact layouts (I = 96 in 32 bytes, I = 224 in 64 bytes) keep 16-bit counts: the
+// bucket's chunk 0 holds the counts of A, C, G, T from the start of its superblock (SB
+// buckets, SB * I < 65536 rows) to the bucket, as 4 x uint16, then the bucket's first 32
+// symbols; later chunks hold 64 symbols each. A table of uint32 counts at every
+// superblock start completes them. Fewer bytes per row keep more of the index in L2.
 template <int I> struct Geo;
-template <> struct Geo<64> { static constexpr int CH = 2, USED = 2, LOG = 6; };
-template <> struct Geo<128> { static constexpr int CH = 4, USED = 3, LOG = 7; };
-template <> struct Geo<256> { static constexpr int CH = 8, USED = 5, LOG = 8; };
+template <> struct Geo<64> { static constexpr int CH = 2, USED = 2, SB = 0; static constexpr bool COMPACT = false; };
+template <> struct Geo<96> { static constexpr int CH = 2, USED = 2, SB = 682; static constexpr bool COMPACT = true; };
+template <> struct Geo<128> { static constexpr int CH = 4, USED = 3, SB = 0; static constexpr bool COMPACT = false; };
+template <> struct Geo<192> { static constexpr int CH = 4, USED = 4, SB = 0; static constexpr bool COMPACT = false; };
+template <> struct Geo<224> { static constexpr int CH = 4, USED = 4, SB = 292; static constexpr bool COMPACT = true; };
+template <> struct Geo<256> { static constexpr int CH = 8, USED = 5, SB = 0; static constexpr bool COMPACT = false; };
+template <> struct Geo<448> { static constexpr int CH = 8, USED = 8, SB = 0; static constexpr bool COMPACT = false; };
 
 constexpr uint32_t EVEN = 0x55555555u;
 
@@ -143,12 +157,37 @@ __device__ __forceinline__ Occ4 count4_chunk(uint4 v, int rel)
     return Occ4{npos - slo - shi + sboth, slo - sboth, shi - sboth, sboth};   // 00 01 10 11
 }
 
+// Mask of the symbols of global word gw (16 symbols) at or before offset r of a bucket.
+__device__ __forceinline__ uint32_t gword_mask(int gw, uint32_t r)
+{
+    const int wr = (int)(r >> 4);
+    const uint32_t pm = 0xFFFFFFFFu >> (30 - 2 * (r & 15));
+    return gw < wr ? 0xFFFFFFFFu : (gw == wr ? pm : 0u);
+}
+
+// Symbols of global word gw counted at offset r (0..16).
+__device__ __forceinline__ uint32_t gword_npos(int gw, uint32_t r)
+{
+    const int v = (int)r + 1 - 16 * gw;
+    return (uint32_t)(v < 0 ? 0 : (v > 16 ? 16 : v));
+}
+
+// Compact layouts: the global word index of word i (0..3) of chunk c, or -1 for the
+// counts half of chunk 0.
+__device__ __forceinline__ int compact_gw(int c, int i) { return c == 0 ? (i < 2 ? -1 : i - 2) : 4 * c - 2 + i; }
+
+__device__ __forceinline__ uint32_t u16_count(uint4 v, uint32_t sym)
+{
+    return sel4(sym, v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16);
+}
+
 // This lane's share of Occ(sym, p1) and Occ(sym, p2) for positions at offsets r1 (in
 // bucket a) and r2 (in bucket b2, or in bucket a when `same`). The group sums are the
 // two Occ values before the '$' correction.
 template <int I, int L>
 __device__ __forceinline__ void part2(const Bucket<I, L> &a, const Bucket<I, L> &b2, bool same, uint32_t q,
-                                      uint32_t r1, uint32_t r2, uint32_t sym, uint32_t &o1, uint32_t &o2)
+                                      uint32_t r1, uint32_t r2, uint32_t sym, uint4 sb1, uint4 sb2,
+                                      uint32_t &o1, uint32_t &o2)
 {
     const uint32_t pat = sym * EVEN;
     uint32_t s1 = 0, s2 = 0;
@@ -157,40 +196,86 @@ __device__ __forceinline__ void part2(const Bucket<I, L> &a, const Bucket<I, L> 
         const int c = (int)q + L * t;
         const uint4 va = a.v[t];
         const uint4 vb = same ? va : b2.v[t];
-        if (c == 0) {
-            s1 += sel4(sym, va.x, va.y, va.z, va.w);
-            s2 += sel4(sym, vb.x, vb.y, vb.z, vb.w);
-        } else if (c < Geo<I>::USED) {
-            const Eq1 ea = eq_chunk(va, pat);
-            const Eq1 eb = same ? ea : eq_chunk(vb, pat);
-            s1 += eq_prefix(ea, chunk_rel(r1, c));
-            s2 += eq_prefix(eb, chunk_rel(r2, c));
+        if constexpr (Geo<I>::COMPACT) {
+            if (c >= Geo<I>::USED) continue;
+            if (c == 0) {
+                s1 += u16_count(va, sym) + sel4(sym, sb1.x, sb1.y, sb1.z, sb1.w);
+                s2 += u16_count(vb, sym) + sel4(sym, sb2.x, sb2.y, sb2.z, sb2.w);
+            }
+            const uint32_t wa[4] = {va.x, va.y, va.z, va.w}, wb[4] = {vb.x, vb.y, vb.z, vb.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int gw = compact_gw(c, i);
+                if (gw < 0) continue;
+                const uint32_t xa = wa[i] ^ pat, xb = wb[i] ^ pat;
+                const uint32_t ea = ~(xa | (xa >> 1)) & EVEN, eb = ~(xb | (xb >> 1)) & EVEN;
+                s1 = __popc(ea & gword_mask(gw, r1)) + s1;
+                s2 = __popc(eb & gword_mask(gw, r2)) + s2;
+            }
+        } else {
+            if (c == 0) {
+                s1 += sel4(sym, va.x, va.y, va.z, va.w);
+                s2 += sel4(sym, vb.x, vb.y, vb.z, vb.w);
+            } else if (c < Geo<I>::USED) {
+                const Eq1 ea = eq_chunk(va, pat);
+                const Eq1 eb = same ? ea : eq_chunk(vb, pat);
+                s1 += eq_prefix(ea, chunk_rel(r1, c));
+                s2 += eq_prefix(eb, chunk_rel(r2, c));
+            }
         }
     }
     o1 = s1;
     o2 = s2;
 }
 
-// This lane's share of Occ(., p) for all four symbols at offset r of a bucket.
+// This lane's share of Occ(., p) for all four symbols at offset r of a bucket (sbc:
+// the superblock counts of compact layouts).
 template <int I, int L>
-__device__ __forceinline__ Occ4 part4(const Bucket<I, L> &bk, uint32_t q, uint32_t r)
+__device__ __forceinline__ Occ4 part4(const Bucket<I, L> &bk, uint32_t q, uint32_t r, uint4 sbc)
 {
     Occ4 o = {0, 0, 0, 0};
 #pragma unroll
     for (int t = 0; t < Bucket<I, L>::NPL; ++t) {
         const int c = (int)q + L * t;
         const uint4 v = bk.v[t];
-        if (c == 0) {
-            o.a += v.x;
-            o.c += v.y;
-            o.g += v.z;
-            o.t += v.w;
-        } else if (c < Geo<I>::USED) {
-            const Occ4 p = count4_chunk(v, chunk_rel(r, c));
-            o.a += p.a;
-            o.c += p.c;
-            o.g += p.g;
-            o.t += p.t;
+        if constexpr (Geo<I>::COMPACT) {
+            if (c >= Geo<I>::USED) continue;
+            if (c == 0) {
+                o.a += (v.x & 0xFFFFu) + sbc.x;
+                o.c += (v.x >> 16) + sbc.y;
+                o.g += (v.y & 0xFFFFu) + sbc.z;
+                o.t += (v.y >> 16) + sbc.w;
+            }
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+            uint32_t slo = 0, shi = 0, sboth = 0, npos = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int gw = compact_gw(c, i);
+                if (gw < 0) continue;
+                const uint32_t m = gword_mask(gw, r);
+                const uint32_t lo = w[i] & EVEN & m, hi = (w[i] >> 1) & EVEN & m;
+                slo = __popc(lo) + slo;
+                shi = __popc(hi) + shi;
+                sboth = __popc(lo & hi) + sboth;
+                npos += gword_npos(gw, r);
+            }
+            o.a += npos - slo - shi + sboth;
+            o.c += slo - sboth;
+            o.g += shi - sboth;
+            o.t += sboth;
+        } else {
+            if (c == 0) {
+                o.a += v.x;
+                o.c += v.y;
+                o.g += v.z;
+                o.t += v.w;
+            } else if (c < Geo<I>::USED) {
+                const Occ4 p = count4_chunk(v, chunk_rel(r, c));
+                o.a += p.a;
+                o.c += p.c;
+                o.g += p.g;
+                o.t += p.t;
+            }
         }
     }
     return o;
@@ -222,14 +307,20 @@ __device__ __forceinline__ Occ4 group_sum4(Occ4 o)
 template <int I, int L>
 struct Pair {
     Bucket<I, L> a, b;
+    uint4 sa, sbk;         // compact layouts: superblock counts of the two buckets
     bool same;
     __device__ __forceinline__ void load(const DevLayout &lay, uint32_t q, uint32_t k, uint32_t l)
     {
-        constexpr int LOG = Geo<I>::LOG;
-        const uint32_t j1 = (k - 1) >> LOG, j2 = l >> LOG;
+        const uint32_t j1 = (k - 1) / I, j2 = l / I;
         same = j1 == j2;
         fetch<I, L>(lay, j1, q, a);
         if (!same) fetch<I, L>(lay, j2, q, b);
+        if constexpr (Geo<I>::COMPACT) {
+            sa = lay.sb[j1 / Geo<I>::SB];
+            sbk = lay.sb[j2 / Geo<I>::SB];
+        } else {
+            sa = sbk = make_uint4(0, 0, 0, 0);
+        }
     }
 };
 
@@ -239,7 +330,7 @@ __device__ __forceinline__ void occ2(const DevLayout &lay, const Pair<I, L> &pr,
                                      uint32_t k, uint32_t l, uint32_t &ok, uint32_t &ol)
 {
     uint32_t c1, c2;
-    part2<I, L>(pr.a, pr.b, pr.same, q, (k - 1) & (I - 1), l & (I - 1), sym, c1, c2);
+    part2<I, L>(pr.a, pr.b, pr.same, q, (k - 1) % I, l % I, sym, pr.sa, pr.sbk, c1, c2);
     c1 = group_sum<L>(c1);
     c2 = group_sum<L>(c2);
     const bool a = sym == 0;
@@ -252,8 +343,8 @@ template <int I, int L>
 __device__ __forceinline__ void occ8(const DevLayout &lay, const Pair<I, L> &pr, uint32_t q, uint32_t k, uint32_t l,
                                      Occ4 &ok, Occ4 &ol)
 {
-    Occ4 o1 = group_sum4<L>(part4<I, L>(pr.a, q, (k - 1) & (I - 1)));
-    Occ4 o2 = group_sum4<L>(pr.same ? part4<I, L>(pr.a, q, l & (I - 1)) : part4<I, L>(pr.b, q, l & (I - 1)));
+    Occ4 o1 = group_sum4<L>(part4<I, L>(pr.a, q, (k - 1) % I, pr.sa));
+    Occ4 o2 = group_sum4<L>(pr.same ? part4<I, L>(pr.a, q, l % I, pr.sbk) : part4<I, L>(pr.b, q, l % I, pr.sbk));
     o1.a -= (k - 1 >= lay.dollar) ? 1u : 0u;
     o2.a -= (l >= lay.dollar) ? 1u : 0u;
     ok = o1;

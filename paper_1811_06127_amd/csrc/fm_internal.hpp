@@ -16,8 +16,8 @@ struct fm_index {
     uint64_t dollar = 0, rev_dollar = 0;
     uint64_t C[5] = {0, 0, 0, 0, 0}, rev_C[5] = {0, 0, 0, 0, 0};
     bool has_rev = false;
-    void *lay[3] = {nullptr, nullptr, nullptr};    // forward layouts for I = 64, 128, 256
-    void *rlay[3] = {nullptr, nullptr, nullptr};   // layouts of reverse(R)
+    void *lay[7] = {};     // forward layouts for I = 64, 96, 128, 192, 224, 256, 448
+    void *rlay[7] = {};    // layouts of reverse(R)
     uint64_t device_bytes = 0;
     fm_tuning tune[3] = {};
     int cu_count = 0;
@@ -34,10 +34,26 @@ namespace fm {
 constexpr uint32_t kQueueChunk = 64;   // read-strands a wave takes from the work queue at once
 constexpr uint32_t kHitSlots = 4;      // hits stored per read-strand without an atomic
 
-inline int ilog(uint32_t I) { return I == 64 ? 0 : (I == 128 ? 1 : (I == 256 ? 2 : -1)); }
+constexpr int kLayouts = 7;
+constexpr uint32_t kIntervals[kLayouts] = {64, 96, 128, 192, 224, 256, 448};
+// slot of a checkpoint interval in the index's layout arrays, -1 when unsupported
+inline int ilog(uint32_t I)
+{
+    for (int i = 0; i < kLayouts; ++i)
+        if (kIntervals[i] == I) return i;
+    return -1;
+}
+inline bool compact_layout(uint32_t I) { return I == 96 || I == 224; }
+inline uint64_t superblock_buckets(uint32_t I) { return I == 96 ? 682 : 292; }
 inline uint64_t num_buckets(uint64_t n, uint32_t I) { return n / I + 1; }
-inline uint64_t bucket_bytes(uint32_t I) { return I == 64 ? 32 : (I == 128 ? 64 : 128); }
-inline uint64_t layout_bytes(uint64_t n, uint32_t I) { return num_buckets(n, I) * bucket_bytes(I); }
+inline uint64_t bucket_bytes(uint32_t I) { return I <= 96 ? 32 : (I <= 224 ? 64 : 128); }
+inline uint32_t max_lanes(uint32_t I) { return I <= 96 ? 2 : (I <= 224 ? 4 : 8); }
+// buckets, then (compact layouts) one uint4 of counts per superblock
+inline uint64_t layout_bytes(uint64_t n, uint32_t I)
+{
+    const uint64_t nb = num_buckets(n, I);
+    return nb * bucket_bytes(I) + (compact_layout(I) ? ((nb + superblock_buckets(I) - 1) / superblock_buckets(I)) * 16 : 0);
+}
 
 DevLayout dev_layout(const fm_index *idx, uint32_t I, bool rev);
 

@@ -40,19 +40,14 @@ __global__ void bucket_totals(const uint32_t *packed, uint64_t nb, uint4 *tot)
         tot[j] = make_uint4(0, 0, 0, 0);
         return;
     }
-    const uint4 *w = (const uint4 *)(packed + j * (I / 16));
+    const uint32_t *w = packed + j * (I / 16);
     uint32_t slo = 0, shi = 0, sb = 0;
 #pragma unroll
-    for (int i = 0; i < I / 64; ++i) {
-        const uint4 v = w[i];
-        const uint32_t x[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const uint32_t lo = x[t] & EVEN, hi = (x[t] >> 1) & EVEN;
-            slo += __popc(lo);
-            shi += __popc(hi);
-            sb += __popc(lo & hi);
-        }
+    for (int i = 0; i < I / 16; ++i) {
+        const uint32_t lo = w[i] & EVEN, hi = (w[i] >> 1) & EVEN;
+        slo += __popc(lo);
+        shi += __popc(hi);
+        sb += __popc(lo & hi);
     }
     tot[j] = make_uint4(I - slo - shi + sb, slo - sb, shi - sb, sb);
 }
@@ -144,6 +139,57 @@ __global__ void write_buckets(const uint32_t *packed, uint64_t nwords, const uin
     }
 }
 
+// Compact layouts, pass C: the checkpoint of every bucket (exclusive prefix of the
+// totals) replaces its total in `tot`, and every superblock start is recorded in sb.
+template <int I>
+__global__ void compact_checkpoints(uint4 *tot, uint64_t nb, const uint4 *part, uint4 *sb)
+{
+    __shared__ uint32_t lds[32];
+    const uint64_t base = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) * kTile;
+    uint4 loc[kTile];
+    uint4 acc = make_uint4(0, 0, 0, 0);
+    for (int t = 0; t < kTile; ++t) {
+        loc[t] = acc;
+        if (base + t < nb) {
+            uint4 v = tot[base + t];
+            acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+        }
+    }
+    uint32_t dummy;
+    uint4 off = part[blockIdx.x];
+    off.x += block_scan_u32(acc.x, lds, &dummy);
+    off.y += block_scan_u32(acc.y, lds, &dummy);
+    off.z += block_scan_u32(acc.z, lds, &dummy);
+    off.w += block_scan_u32(acc.w, lds, &dummy);
+    for (int t = 0; t < kTile; ++t) {
+        const uint64_t j = base + t;
+        if (j >= nb) break;
+        const uint4 g = make_uint4(off.x + loc[t].x, off.y + loc[t].y, off.z + loc[t].z, off.w + loc[t].w);
+        tot[j] = g;
+        if (j % Geo<I>::SB == 0) sb[j / Geo<I>::SB] = g;
+    }
+}
+
+// Compact layouts, pass D: 16-bit counts relative to the bucket's superblock, then the
+// bucket's symbols (words 0-1 in chunk 0, then four words per chunk).
+template <int I>
+__global__ void compact_buckets(const uint32_t *packed, uint64_t nwords, const uint4 *gck, uint64_t nb,
+                                const uint4 *sb, uint4 *out)
+{
+    const uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (j >= nb) return;
+    constexpr int CH = Geo<I>::CH, NW = I / 16;
+    const uint4 g = gck[j], s0 = sb[j / Geo<I>::SB];
+    uint32_t w[4 * CH - 2];
+    for (int i = 0; i < 4 * CH - 2; ++i) {
+        const uint64_t wi = j * NW + i;
+        w[i] = (i < NW && wi < nwords) ? packed[wi] : 0u;
+    }
+    uint4 *b = out + j * CH;
+    b[0] = make_uint4((g.x - s0.x) | ((g.y - s0.y) << 16), (g.z - s0.z) | ((g.w - s0.w) << 16), w[0], w[1]);
+    for (int c = 1; c < CH; ++c) b[c] = make_uint4(w[4 * c - 2], w[4 * c - 1], w[4 * c], w[4 * c + 1]);
+}
+
 size_t build_layout_scratch(uint64_t n, uint32_t I)
 {
     const uint64_t nb = num_buckets(n, I);
@@ -162,8 +208,15 @@ static hipError_t build_layout_t(const uint32_t *packed, uint64_t n, void *out, 
     hipLaunchKernelGGL(bucket_totals<I>, dim3((uint32_t)((nb + 255) / 256)), dim3(256), 0, s, packed, nb, tot);
     hipLaunchKernelGGL(scan_reduce4, dim3((uint32_t)nblk), dim3(kScanBlock), 0, s, tot, nb, part);
     hipLaunchKernelGGL(scan_partials4, dim3(1), dim3(1024), 0, s, part, nblk);
-    hipLaunchKernelGGL(write_buckets<I>, dim3((uint32_t)nblk), dim3(kScanBlock), 0, s, packed, nwords, tot, nb,
-                       part, (uint4 *)out);
+    if constexpr (Geo<I>::COMPACT) {
+        uint4 *sb = (uint4 *)((char *)out + nb * bucket_bytes(I));
+        hipLaunchKernelGGL(compact_checkpoints<I>, dim3((uint32_t)nblk), dim3(kScanBlock), 0, s, tot, nb, part, sb);
+        hipLaunchKernelGGL(compact_buckets<I>, dim3((uint32_t)((nb + 255) / 256)), dim3(256), 0, s, packed, nwords,
+                           tot, nb, sb, (uint4 *)out);
+    } else {
+        hipLaunchKernelGGL(write_buckets<I>, dim3((uint32_t)nblk), dim3(kScanBlock), 0, s, packed, nwords, tot, nb,
+                           part, (uint4 *)out);
+    }
     return hipGetLastError();
 }
 
@@ -171,8 +224,12 @@ hipError_t build_layout(const uint32_t *packed_dev, uint64_t n, uint32_t I, void
 {
     switch (I) {
     case 64: return build_layout_t<64>(packed_dev, n, out, scratch, s);
+    case 96: return build_layout_t<96>(packed_dev, n, out, scratch, s);
     case 128: return build_layout_t<128>(packed_dev, n, out, scratch, s);
+    case 192: return build_layout_t<192>(packed_dev, n, out, scratch, s);
+    case 224: return build_layout_t<224>(packed_dev, n, out, scratch, s);
     case 256: return build_layout_t<256>(packed_dev, n, out, scratch, s);
+    case 448: return build_layout_t<448>(packed_dev, n, out, scratch, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -234,10 +291,11 @@ static hipError_t occ8_by_lanes(DevLayout lay, const fm_tuning &t, int cus, cons
     switch (t.lanes) {
     case 1: return occ8_launch<I, 1>(lay, t, cus, q, nq, out, s);
     case 2: return occ8_launch<I, 2>(lay, t, cus, q, nq, out, s);
-    case 4: return occ8_launch<I, 4>(lay, t, cus, q, nq, out, s);
-    case 8: return occ8_launch<I, 8>(lay, t, cus, q, nq, out, s);
-    default: return hipErrorInvalidValue;
+    case 4: if constexpr (Geo<I>::USED > 2) return occ8_launch<I, 4>(lay, t, cus, q, nq, out, s); break;
+    case 8: if constexpr (Geo<I>::USED > 4) return occ8_launch<I, 8>(lay, t, cus, q, nq, out, s); break;
+    default: break;
     }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_occ8(const fm_index *idx, const fm_tuning &t, const fm_interval *q, uint64_t nq, uint32_t *out,
@@ -247,8 +305,12 @@ hipError_t launch_occ8(const fm_index *idx, const fm_tuning &t, const fm_interva
     DevLayout lay = dev_layout(idx, t.occ_interval, false);
     switch (t.occ_interval) {
     case 64: return occ8_by_lanes<64>(lay, t, idx->cu_count, q, nq, out, s);
+    case 96: return occ8_by_lanes<96>(lay, t, idx->cu_count, q, nq, out, s);
     case 128: return occ8_by_lanes<128>(lay, t, idx->cu_count, q, nq, out, s);
+    case 192: return occ8_by_lanes<192>(lay, t, idx->cu_count, q, nq, out, s);
+    case 224: return occ8_by_lanes<224>(lay, t, idx->cu_count, q, nq, out, s);
     case 256: return occ8_by_lanes<256>(lay, t, idx->cu_count, q, nq, out, s);
+    case 448: return occ8_by_lanes<448>(lay, t, idx->cu_count, q, nq, out, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -186,37 +186,40 @@ int fm_autotune(fm_index *idx, int op, const uint8_t *codes, const uint64_t *off
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     const uint32_t run_flags = flags & ~(uint32_t)(FM_PLAIN | FM_STATS);
-    for (uint32_t I : {64u, 128u, 256u}) {
+    for (uint32_t I : kIntervals) {
         if (!idx->lay[ilog(I)]) continue;
         if (op == FM_OP_DARRAY && !idx->rlay[ilog(I)]) continue;
-        const uint32_t max_lanes = I == 64 ? 2 : (I == 128 ? 4 : 8);
-        for (uint32_t lanes = 1; lanes <= max_lanes; lanes *= 2) {
+        for (uint32_t lanes = 1; lanes <= max_lanes(I); lanes *= 2) {
             for (uint32_t depth = 1; depth <= (op == FM_OP_INEXACT ? 1u : 2u); ++depth) {
-                fm_tuning t = base;
-                t.occ_interval = I;
-                t.lanes = lanes;
-                t.depth = depth;
-                if (fm_set_tuning(idx, op, &t) != FM_OK) continue;
-                st = run_op(idx, call_op, codes, offs, z, nreads, run_flags, zmax, out_buf, hit_cap, hit_offs, status,
-                            ws, ws_bytes, s);
-                if (!st) st = snapshot(call_op, nreads, flags, out_buf, hit_offs, status, s, got);
+                for (uint32_t waves : {0u, 4u, 8u, 12u, 16u}) {
+                    fm_tuning t = base;
+                    t.occ_interval = I;
+                    t.lanes = lanes;
+                    t.depth = depth;
+                    t.waves_per_cu = waves;
+                    if (fm_set_tuning(idx, op, &t) != FM_OK) continue;
+                    st = run_op(idx, call_op, codes, offs, z, nreads, run_flags, zmax, out_buf, hit_cap, hit_offs,
+                                status, ws, ws_bytes, s);
+                    if (!st) st = snapshot(call_op, nreads, flags, out_buf, hit_offs, status, s, got);
+                    if (st) break;
+                    if (got != ref) continue;   // never pick a configuration that changes the output
+                    float best_t = 1e30f;
+                    for (int rep = 0; rep < 3; ++rep) {
+                        (void)hipEventRecord(e0, s);
+                        run_op(idx, call_op, codes, offs, z, nreads, run_flags, zmax, out_buf, hit_cap, hit_offs,
+                               status, ws, ws_bytes, s);
+                        (void)hipEventRecord(e1, s);
+                        (void)hipEventSynchronize(e1);
+                        float m = 0;
+                        (void)hipEventElapsedTime(&m, e0, e1);
+                        if (m < best_t) best_t = m;
+                    }
+                    if (best_t < win_ms) {
+                        win_ms = best_t;
+                        win = t;
+                    }
+                }
                 if (st) break;
-                if (got != ref) continue;   // never pick a configuration that changes the output
-                float best_t = 1e30f;
-                for (int rep = 0; rep < 3; ++rep) {
-                    (void)hipEventRecord(e0, s);
-                    run_op(idx, call_op, codes, offs, z, nreads, run_flags, zmax, out_buf, hit_cap, hit_offs, status,
-                           ws, ws_bytes, s);
-                    (void)hipEventRecord(e1, s);
-                    (void)hipEventSynchronize(e1);
-                    float m = 0;
-                    (void)hipEventElapsedTime(&m, e0, e1);
-                    if (m < best_t) best_t = m;
-                }
-                if (best_t < win_ms) {
-                    win_ms = best_t;
-                    win = t;
-                }
             }
             if (st) break;
         }

@@ -318,10 +318,11 @@ static hipError_t walk_by_lanes(const fm_index *idx, const fm_tuning &t, const W
     switch (t.lanes) {
     case 1: return walk_by_depth<I, 1, MODE>(idx, t, a, s);
     case 2: return walk_by_depth<I, 2, MODE>(idx, t, a, s);
-    case 4: return walk_by_depth<I, 4, MODE>(idx, t, a, s);
-    case 8: return walk_by_depth<I, 8, MODE>(idx, t, a, s);
-    default: return hipErrorInvalidValue;
+    case 4: if constexpr (Geo<I>::USED > 2) return walk_by_depth<I, 4, MODE>(idx, t, a, s); break;
+    case 8: if constexpr (Geo<I>::USED > 4) return walk_by_depth<I, 8, MODE>(idx, t, a, s); break;
+    default: break;
     }
+    return hipErrorInvalidValue;
 }
 
 template <int MODE>
@@ -331,16 +332,24 @@ static hipError_t walk_dispatch(const fm_index *idx, const fm_tuning &t, bool pl
         const uint32_t grid = (a.total + 255) / 256;
         switch (t.occ_interval) {
         case 64: hipLaunchKernelGGL((walk_plain<64, MODE>), dim3(grid), dim3(256), 0, s, a); break;
+        case 96: hipLaunchKernelGGL((walk_plain<96, MODE>), dim3(grid), dim3(256), 0, s, a); break;
         case 128: hipLaunchKernelGGL((walk_plain<128, MODE>), dim3(grid), dim3(256), 0, s, a); break;
+        case 192: hipLaunchKernelGGL((walk_plain<192, MODE>), dim3(grid), dim3(256), 0, s, a); break;
+        case 224: hipLaunchKernelGGL((walk_plain<224, MODE>), dim3(grid), dim3(256), 0, s, a); break;
         case 256: hipLaunchKernelGGL((walk_plain<256, MODE>), dim3(grid), dim3(256), 0, s, a); break;
+        case 448: hipLaunchKernelGGL((walk_plain<448, MODE>), dim3(grid), dim3(256), 0, s, a); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
     }
     switch (t.occ_interval) {
     case 64: return walk_by_lanes<64, MODE>(idx, t, a, s);
+    case 96: return walk_by_lanes<96, MODE>(idx, t, a, s);
     case 128: return walk_by_lanes<128, MODE>(idx, t, a, s);
+    case 192: return walk_by_lanes<192, MODE>(idx, t, a, s);
+    case 224: return walk_by_lanes<224, MODE>(idx, t, a, s);
     case 256: return walk_by_lanes<256, MODE>(idx, t, a, s);
+    case 448: return walk_by_lanes<448, MODE>(idx, t, a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -761,10 +770,11 @@ static hipError_t dfs_by_lanes(const fm_index *idx, const fm_tuning &t, const Df
     switch (t.lanes) {
     case 1: return dfs_launch_batched<I, 1>(idx, t, a, s);
     case 2: return dfs_launch_batched<I, 2>(idx, t, a, s);
-    case 4: return dfs_launch_batched<I, 4>(idx, t, a, s);
-    case 8: return dfs_launch_batched<I, 8>(idx, t, a, s);
-    default: return hipErrorInvalidValue;
+    case 4: if constexpr (Geo<I>::USED > 2) return dfs_launch_batched<I, 4>(idx, t, a, s); break;
+    case 8: if constexpr (Geo<I>::USED > 4) return dfs_launch_batched<I, 8>(idx, t, a, s); break;
+    default: break;
     }
+    return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------------ compaction
@@ -982,16 +992,24 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
         const size_t lds = (size_t)256 * a.scap * 3 * sizeof(uint32_t);
         switch (t.occ_interval) {
         case 64: hipLaunchKernelGGL(dfs_plain<64>, dim3(grid), dim3(256), lds, s, a); break;
+        case 96: hipLaunchKernelGGL(dfs_plain<96>, dim3(grid), dim3(256), lds, s, a); break;
         case 128: hipLaunchKernelGGL(dfs_plain<128>, dim3(grid), dim3(256), lds, s, a); break;
+        case 192: hipLaunchKernelGGL(dfs_plain<192>, dim3(grid), dim3(256), lds, s, a); break;
+        case 224: hipLaunchKernelGGL(dfs_plain<224>, dim3(grid), dim3(256), lds, s, a); break;
         case 256: hipLaunchKernelGGL(dfs_plain<256>, dim3(grid), dim3(256), lds, s, a); break;
+        case 448: hipLaunchKernelGGL(dfs_plain<448>, dim3(grid), dim3(256), lds, s, a); break;
         default: return hipErrorInvalidValue;
         }
         e = hipGetLastError();
     } else {
         switch (t.occ_interval) {
         case 64: e = dfs_by_lanes<64>(idx, t, a, s); break;
+        case 96: e = dfs_by_lanes<96>(idx, t, a, s); break;
         case 128: e = dfs_by_lanes<128>(idx, t, a, s); break;
+        case 192: e = dfs_by_lanes<192>(idx, t, a, s); break;
+        case 224: e = dfs_by_lanes<224>(idx, t, a, s); break;
         case 256: e = dfs_by_lanes<256>(idx, t, a, s); break;
+        case 448: e = dfs_by_lanes<448>(idx, t, a, s); break;
         default: return hipErrorInvalidValue;
         }
     }

@@ -12,8 +12,9 @@ from paper_1811_06127_amd import fm
 
 pytestmark = pytest.mark.gpu
 
-LAYOUTS = (64, 128, 256)
-LANES = {64: (1, 2), 128: (1, 2, 4), 256: (1, 2, 4, 8)}
+LAYOUTS = (64, 96, 128, 192, 224, 256, 448)
+LANES = {64: (1, 2), 96: (1, 2), 128: (1, 2, 4), 192: (1, 2, 4), 224: (1, 2, 4), 256: (1, 2, 4, 8),
+         448: (1, 2, 4, 8)}
 
 
 def say(*a):
@@ -43,7 +44,7 @@ def test_index_constants(small):
     assert info["n"] == R.size and info["dollar_row"] == x.dollar_row
     assert info["C"] == x.C.tolist()
     assert info["rev_dollar_row"] == xr.dollar_row and info["rev_C"] == xr.C.tolist()
-    assert info["layouts"] == 7 and info["has_reverse"]
+    assert info["layouts"] == 127 and info["has_reverse"]
 
 
 def occ8_queries(n, dollar):
@@ -75,7 +76,7 @@ def test_occ8_all_lanes(small, I):
         torch.cuda.synchronize()
         bad = np.nonzero((got != want).any(axis=1))[0]
         assert bad.size == 0, (I, L, q[bad[:5]], got[bad[:5]], want[bad[:5]])
-    idx.set_tuning(fm.FM_OP_EXACT, occ_interval=128, lanes=4)
+    idx.set_tuning(fm.FM_OP_EXACT, occ_interval=128, lanes=1)
 
 
 def test_occ8_fig2_block():
@@ -134,7 +135,7 @@ def test_exact_plain_and_batched(small, flags):
                 got = to_u32(fm.fm_search_exact(idx, cd, od, flags))
                 bad = np.nonzero((got != want).any(axis=1))[0]
                 assert bad.size == 0, (I, L, P, bad[:5], got[bad[:5]], want[bad[:5]])
-    idx.set_tuning(fm.FM_OP_EXACT, occ_interval=128, lanes=4, depth=2)
+    idx.set_tuning(fm.FM_OP_EXACT, occ_interval=128, lanes=1, depth=1)
 
 
 def test_exact_cfg1_workload():
@@ -158,7 +159,7 @@ def test_darray(small, flags):
     want = xr.darray(codes, offs, flags)
     cd, od, _ = fm.reads_to_device(codes, offs)
     for I in LAYOUTS:
-        idx.set_tuning(fm.FM_OP_DARRAY, occ_interval=I)
+        idx.set_tuning(fm.FM_OP_DARRAY, occ_interval=I, lanes=1)
         got = fm.fm_darray(idx, cd, od, int(offs[-1]), flags).cpu().numpy()
         assert np.array_equal(got, want), I
     idx.set_tuning(fm.FM_OP_DARRAY, occ_interval=128)
@@ -205,7 +206,7 @@ def test_inexact_plain_and_batched(small, use_d):
             idx.set_tuning(fm.FM_OP_DARRAY, occ_interval=I, lanes=min(L, 4))
             assert_same_hits(run_inexact(idx, codes, offs, z, flags, 2)[0], wh, wo, (I, L))
     idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=128, lanes=1)
-    idx.set_tuning(fm.FM_OP_DARRAY, occ_interval=128, lanes=4)
+    idx.set_tuning(fm.FM_OP_DARRAY, occ_interval=128, lanes=1)
 
 
 def test_inexact_definition_and_node_count(small):
