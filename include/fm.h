@@ -63,7 +63,8 @@ enum fm_status {
     FM_EDEVICE = 5,                 /* a HIP call failed */
     FM_EOVERFLOW = 6,               /* per read: its hits did not fit in hit_cap */
     FM_EBUDGET = 7,                 /* per read: node budget exhausted */
-    FM_ERANGE = 8                   /* size beyond what the index or ABI supports */
+    FM_ERANGE = 8,                  /* size beyond what the index or ABI supports */
+    FM_EAGAIN = 9                   /* not finished within the time allowed */
 };
 
 /* Search flags. */
@@ -284,6 +285,83 @@ int fm_plan_create(const fm_index *idx, int op, const uint8_t *codes, const uint
 int fm_plan_launch(fm_plan *plan, void *stream);
 
 void fm_plan_free(fm_plan *plan);
+
+/* ----------------------------------------------------------------- serving */
+
+/* A request server over fm_search_inexact with continuous batching. Submitted
+ * requests (reads with per-read budgets) wait in arrival order. A worker thread keeps
+ * up to `lanes` batches on the device at once, each on a stream of its own with an
+ * equal share of a device arena allocated at creation. Whenever a lane is idle it
+ * admits waiting requests, oldest first, while the batch's memory (fm_server_bytes)
+ * still fits the lane's share and the batch stays within max_batch_reads; requests
+ * that arrive while batches run therefore join the next batch of the first lane to
+ * free up, and their work overlaps with the batches already running. A batch whose
+ * hits exceed the reserve is searched again with room for all of them. Each read is
+ * searched independently of the rest of its batch, so a request gets the same bytes
+ * whatever it is batched with. The index must outlive the server, and its phase
+ * timing must stay off while the server runs. */
+typedef struct fm_server fm_server;
+
+typedef struct {
+    uint32_t lanes;                 /* batches in flight at once, 1..8 */
+    uint32_t flags;                 /* search flags for every request: strands, FM_DARRAY */
+    uint32_t zmax;                  /* largest budget a request may carry, <= FM_ZMAX */
+    uint32_t hit_reserve;           /* hits reserved per read-strand when admitting */
+    uint64_t arena_bytes;           /* device memory for batches in flight (split evenly
+                                       among lanes; the same again is pinned on the host) */
+    uint64_t max_batch_reads;       /* reads per batch; 0 = only memory limits a batch */
+} fm_server_opts;
+
+typedef struct {
+    uint64_t nreads;
+    const fm_hit *hits;             /* host; hits[i].read counts reads within the request */
+    uint64_t nhits;
+    const uint64_t *hit_offs;       /* host, nreads + 1, as in fm_search_inexact */
+    const uint32_t *status;         /* host, nreads, as in fm_search_inexact */
+    int error;                      /* FM_OK, or why the request as a whole failed */
+    double t_submit, t_launch, t_done;  /* seconds on the server clock: submitted, its batch
+                                       launched, results in host memory */
+    uint64_t batch;                 /* number of the batch that served it (from 1) */
+} fm_result;
+
+typedef struct {
+    uint64_t batches, retries, requests_done, reads_done, pending;
+    int error;                      /* first device error seen, FM_OK if none */
+} fm_server_counts;
+
+/* Device bytes a batch of nreads reads with total_len symbols takes under opts: the
+ * inputs, status, hit offsets, search workspace and hit_reserve hits per read-strand,
+ * each 256-byte aligned. This is the admission rule. Host only. */
+int fm_server_bytes(const fm_server_opts *opts, uint64_t nreads, uint64_t total_len, uint64_t *bytes);
+
+/* Creates the server and starts its worker. FM_EINVAL for options outside the listed
+ * ranges (or FM_DARRAY without a reverse index), FM_ENOMEM when the arena or its
+ * pinned mirror cannot be allocated. */
+int fm_server_create(const fm_index *idx, const fm_server_opts *opts, fm_server **out);
+
+/* Queues a request: codes (host) with nreads+1 nondecreasing offsets (host, codes of
+ * read r at offs[r] .. offs[r+1]) and nreads budgets z (host). The data are copied
+ * before the call returns. *ticket names the request. FM_ERANGE if the request alone
+ * does not fit a lane. Thread-safe. */
+int fm_server_submit(fm_server *s, const uint8_t *codes, const uint64_t *offs, const uint8_t *z,
+                     uint64_t nreads, uint64_t *ticket);
+
+/* Waits up to timeout_s seconds (negative: without limit) for the request to finish
+ * and describes its results; the pointers stay valid until fm_server_release.
+ * FM_EAGAIN if it is still running, FM_EINVAL for an unknown ticket. Thread-safe. */
+int fm_server_wait(fm_server *s, uint64_t ticket, double timeout_s, fm_result *out);
+
+/* Frees a finished request's results. */
+int fm_server_release(fm_server *s, uint64_t ticket);
+
+/* Seconds since the server was created (the clock of fm_result's times). */
+double fm_server_clock(const fm_server *s);
+
+int fm_server_stats(fm_server *s, fm_server_counts *out);
+
+/* Finishes every queued request, stops the worker and frees the arena; safe on NULL.
+ * Results not yet released are freed too. */
+void fm_server_free(fm_server *s);
 
 #ifdef __cplusplus
 }

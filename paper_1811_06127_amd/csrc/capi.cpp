@@ -178,6 +178,7 @@ const char *fm_strerror(int s)
     case FM_EOVERFLOW: return "hit capacity exceeded";
     case FM_EBUDGET: return "node budget exhausted";
     case FM_ERANGE: return "size out of range";
+    case FM_EAGAIN: return "not finished yet";
     default: return "unknown status";
     }
 }

@@ -93,68 +93,77 @@ __device__ __forceinline__ int chunk_rel(uint32_t r, int c)
     return rel < -1 ? -1 : (rel > 63 ? 63 : rel);
 }
 
-// Symbols of one code among symbols 0..rel of a 64-symbol chunk: one bit per matching
-// symbol, with the per-word counts accumulated once so a prefix needs one masked word.
-struct Eq1 {
-    uint32_t e[4];      // bit 2s set when symbol s of the word matches
-    uint32_t cum[4];    // matching symbols in words 0..w-1
+__device__ __forceinline__ uint64_t u64_of(uint32_t lo, uint32_t hi) { return ((uint64_t)hi << 32) | lo; }
+
+// Symbols 0..rel (rel in [-1, 63]) of a 64-symbol chunk given as two 64-bit halves (32
+// symbols each, 2 bits per symbol): the half holding symbol rel shifted left so that
+// only symbols up to rel remain (the bits shifted in are zero), and the earlier half
+// when it is counted whole (else zero). Shifts are by even amounts, so bit pairs stay
+// aligned to symbols.
+struct Prefix {
+    uint64_t part, full;
 };
 
-__device__ __forceinline__ Eq1 eq_chunk(uint4 v, uint32_t pat)
+__device__ __forceinline__ Prefix prefix_of(uint64_t h0, uint64_t h1, int rel)
 {
-    Eq1 q;
-    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-    uint32_t acc = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t x = w[i] ^ pat;
-        q.e[i] = ~(x | (x >> 1)) & EVEN;
-        q.cum[i] = acc;
-        acc = __popc(q.e[i]) + acc;
-    }
-    return q;
+    const bool upper = rel >= 32;
+    const uint32_t sh = 62u - 2u * ((uint32_t)rel & 31u);
+    Prefix p;
+    p.part = rel < 0 ? 0ull : ((upper ? h1 : h0) << sh);
+    p.full = upper ? h0 : 0ull;
+    return p;
 }
 
-__device__ __forceinline__ uint32_t eq_prefix(const Eq1 &q, int rel)
+// Bit 2s set when symbol s of word w equals the symbol whose code, repeated in every
+// pair of bits, is pat.
+__device__ __forceinline__ uint32_t eq_bits(uint32_t w, uint32_t pat)
 {
-    const uint32_t rc = (uint32_t)(rel < 0 ? 0 : rel);
-    const uint32_t wr = rc >> 4;
-    const uint32_t pm = 0xFFFFFFFFu >> (30 - 2 * (rc & 15));
-    const uint32_t word = sel4(wr, q.e[0], q.e[1], q.e[2], q.e[3]);
-    const uint32_t base = sel4(wr, q.cum[0], q.cum[1], q.cum[2], q.cum[3]);
-    return rel < 0 ? 0u : __popc(word & pm) + base;
+    const uint32_t x = w ^ pat;
+    return ~(x | (x >> 1)) & EVEN;
 }
 
-// Per-word masks of symbols 0..rel of a chunk (rel in [-1, 63]).
-__device__ __forceinline__ void word_masks(int rel, uint32_t m[4])
+// Population count of a 64-bit value whose set bits are all at even positions: the
+// high word moves onto the odd positions of the low one, so one count covers both.
+__device__ __forceinline__ uint32_t popc_even64(uint64_t v)
 {
-    const int wr = rel < 0 ? -1 : (rel >> 4);
-    const uint32_t pm = 0xFFFFFFFFu >> (30 - 2 * ((rel < 0 ? 0 : rel) & 15));
-#pragma unroll
-    for (int i = 0; i < 4; ++i) m[i] = i < wr ? 0xFFFFFFFFu : (i == wr ? pm : 0u);
+    return __popc((uint32_t)v | ((uint32_t)(v >> 32) << 1));
+}
+
+// Symbols equal to the symbol of `pat` among symbols 0..rel of a chunk.
+__device__ __forceinline__ uint32_t eq_count_chunk(uint4 v, uint32_t pat, int rel)
+{
+    const Prefix p = prefix_of(u64_of(eq_bits(v.x, pat), eq_bits(v.y, pat)),
+                               u64_of(eq_bits(v.z, pat), eq_bits(v.w, pat)), rel);
+    return popc_even64(p.part) + popc_even64(p.full);
+}
+
+// Adds the bit-plane counts of 32 symbols (low bits set, high bits set, both set). The
+// two 16-symbol words share one count per plane: the second word's plane bits take the
+// odd positions.
+__device__ __forceinline__ void add_planes(uint64_t v, uint32_t &slo, uint32_t &shi, uint32_t &sboth)
+{
+    const uint32_t u0 = (uint32_t)v, u1 = (uint32_t)(v >> 32);
+    const uint32_t lo = (u0 & EVEN) | ((u1 << 1) & ~EVEN);
+    const uint32_t hi = ((u0 >> 1) & EVEN) | (u1 & ~EVEN);
+    slo = __popc(lo) + slo;
+    shi = __popc(hi) + shi;
+    sboth = __popc(lo & hi) + sboth;
 }
 
 struct Occ4 {
     uint32_t a, c, g, t;
 };
 
-// Counts of A, C, G, T among symbols 0..rel of a chunk, from the two bit planes.
+// Counts of A, C, G, T among symbols 0..rel of a chunk, from the two bit planes
+// (codes 00 01 10 11: T has both bits, C only the low, G only the high one).
 __device__ __forceinline__ Occ4 count4_chunk(uint4 v, int rel)
 {
-    uint32_t m[4];
-    word_masks(rel, m);
-    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    const Prefix p = prefix_of(u64_of(v.x, v.y), u64_of(v.z, v.w), rel);
     uint32_t slo = 0, shi = 0, sboth = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t lo = w[i] & EVEN & m[i];          // low bit of each symbol
-        const uint32_t hi = (w[i] >> 1) & EVEN & m[i];   // high bit of each symbol
-        slo = __popc(lo) + slo;
-        shi = __popc(hi) + shi;
-        sboth = __popc(lo & hi) + sboth;
-    }
+    add_planes(p.part, slo, shi, sboth);
+    add_planes(p.full, slo, shi, sboth);
     const uint32_t npos = (uint32_t)(rel + 1);
-    return Occ4{npos - slo - shi + sboth, slo - sboth, shi - sboth, sboth};   // 00 01 10 11
+    return Occ4{npos - slo - shi + sboth, slo - sboth, shi - sboth, sboth};
 }
 
 // Mask of the symbols of global word gw (16 symbols) at or before offset r of a bucket.
@@ -182,10 +191,10 @@ __device__ __forceinline__ uint32_t u16_count(uint4 v, uint32_t sym)
 }
 
 // This lane's share of Occ(sym, p1) and Occ(sym, p2) for positions at offsets r1 (in
-// bucket a) and r2 (in bucket b2, or in bucket a when `same`). The group sums are the
-// two Occ values before the '$' correction.
+// bucket a) and r2 (in bucket b2). The group sums are the two Occ values before the
+// '$' correction.
 template <int I, int L>
-__device__ __forceinline__ void part2(const Bucket<I, L> &a, const Bucket<I, L> &b2, bool same, uint32_t q,
+__device__ __forceinline__ void part2(const Bucket<I, L> &a, const Bucket<I, L> &b2, uint32_t q,
                                       uint32_t r1, uint32_t r2, uint32_t sym, uint4 sb1, uint4 sb2,
                                       uint32_t &o1, uint32_t &o2)
 {
@@ -195,7 +204,7 @@ __device__ __forceinline__ void part2(const Bucket<I, L> &a, const Bucket<I, L> 
     for (int t = 0; t < Bucket<I, L>::NPL; ++t) {
         const int c = (int)q + L * t;
         const uint4 va = a.v[t];
-        const uint4 vb = same ? va : b2.v[t];
+        const uint4 vb = b2.v[t];
         if constexpr (Geo<I>::COMPACT) {
             if (c >= Geo<I>::USED) continue;
             if (c == 0) {
@@ -217,10 +226,8 @@ __device__ __forceinline__ void part2(const Bucket<I, L> &a, const Bucket<I, L> 
                 s1 += sel4(sym, va.x, va.y, va.z, va.w);
                 s2 += sel4(sym, vb.x, vb.y, vb.z, vb.w);
             } else if (c < Geo<I>::USED) {
-                const Eq1 ea = eq_chunk(va, pat);
-                const Eq1 eb = same ? ea : eq_chunk(vb, pat);
-                s1 += eq_prefix(ea, chunk_rel(r1, c));
-                s2 += eq_prefix(eb, chunk_rel(r2, c));
+                s1 += eq_count_chunk(va, pat, chunk_rel(r1, c));
+                s2 += eq_count_chunk(vb, pat, chunk_rel(r2, c));
             }
         }
     }
@@ -302,8 +309,10 @@ __device__ __forceinline__ Occ4 group_sum4(Occ4 o)
 }
 
 // Buckets of one query (k, l): the bucket of k-1 and the bucket of l, both loads issued
-// before either is used; the second is skipped when both positions share a bucket.
-// Callers guarantee k >= 1.
+// before either is used. The second is loaded even when both positions share a bucket:
+// the line is then already on its way, and a conditional load would let the compiler
+// fill the second bucket from the first, which waits for the first load before issuing
+// the second. Callers guarantee k >= 1.
 template <int I, int L>
 struct Pair {
     Bucket<I, L> a, b;
@@ -314,7 +323,7 @@ struct Pair {
         const uint32_t j1 = (k - 1) / I, j2 = l / I;
         same = j1 == j2;
         fetch<I, L>(lay, j1, q, a);
-        if (!same) fetch<I, L>(lay, j2, q, b);
+        fetch<I, L>(lay, j2, q, b);
         if constexpr (Geo<I>::COMPACT) {
             sa = lay.sb[j1 / Geo<I>::SB];
             sbk = lay.sb[j2 / Geo<I>::SB];
@@ -330,7 +339,7 @@ __device__ __forceinline__ void occ2(const DevLayout &lay, const Pair<I, L> &pr,
                                      uint32_t k, uint32_t l, uint32_t &ok, uint32_t &ol)
 {
     uint32_t c1, c2;
-    part2<I, L>(pr.a, pr.b, pr.same, q, (k - 1) % I, l % I, sym, pr.sa, pr.sbk, c1, c2);
+    part2<I, L>(pr.a, pr.b, q, (k - 1) % I, l % I, sym, pr.sa, pr.sbk, c1, c2);
     c1 = group_sum<L>(c1);
     c2 = group_sum<L>(c2);
     const bool a = sym == 0;
@@ -344,7 +353,7 @@ __device__ __forceinline__ void occ8(const DevLayout &lay, const Pair<I, L> &pr,
                                      Occ4 &ok, Occ4 &ol)
 {
     Occ4 o1 = group_sum4<L>(part4<I, L>(pr.a, q, (k - 1) % I, pr.sa));
-    Occ4 o2 = group_sum4<L>(pr.same ? part4<I, L>(pr.a, q, l % I, pr.sbk) : part4<I, L>(pr.b, q, l % I, pr.sbk));
+    Occ4 o2 = group_sum4<L>(part4<I, L>(pr.b, q, l % I, pr.sbk));
     o1.a -= (k - 1 >= lay.dollar) ? 1u : 0u;
     o2.a -= (l >= lay.dollar) ? 1u : 0u;
     ok = o1;
@@ -410,6 +419,12 @@ __device__ __forceinline__ uint64_t block_scan_u64(uint64_t v, uint64_t *lds, ui
 }
 
 // ------------------------------------------------------------------ wave helpers
+
+// Bits of `mask` for lanes strictly below the calling lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
 
 // Bits of `mask` for lanes strictly below `lane`.
 __device__ __forceinline__ uint32_t rank_below(uint64_t mask, uint32_t lane)

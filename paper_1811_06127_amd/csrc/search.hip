@@ -59,7 +59,7 @@ __device__ uint32_t wave_take(WaveQueue &wq, bool need, uint32_t *queue, uint32_
             if (lane == 0) wq.nxt = atomicAdd(queue, kQueueChunk);
         }
         const uint32_t avail = wq.qe - wq.qb;
-        const uint32_t r = rank_below(mask, lead);
+        const uint32_t r = lanes_below(mask) - ((lane != lead && ((mask >> lead) & 1ull)) ? 1u : 0u);
         const bool mine = need && ((mask >> lead) & 1ull) && r < avail;
         if (mine) got = wq.qb + r;
         const uint32_t cnt = (uint32_t)__popcll(mask);
@@ -68,6 +68,24 @@ __device__ uint32_t wave_take(WaveQueue &wq, bool need, uint32_t *queue, uint32_
         mask = __ballot(need && (lane & (L - 1)) == 0);
     }
     return got;
+}
+
+// Lanes of a wave that lead a group of L lanes.
+template <int L>
+__device__ constexpr uint64_t group_leads()
+{
+    return L == 1 ? ~0ull : (L == 2 ? 0x5555555555555555ull : (L == 4 ? 0x1111111111111111ull : 0x0101010101010101ull));
+}
+
+// Idle groups are refilled together once an eighth of the wave's groups is idle (or all
+// are): the take and the header loads then run for many groups at once instead of in
+// nearly every round, at the price of a few groups idling for a few rounds.
+template <int L>
+__device__ __forceinline__ bool refill_now(bool idle_lead)
+{
+    constexpr uint32_t th = (64 / L) / 8 ? (64 / L) / 8 : 1;
+    const uint64_t idle = __ballot(idle_lead);
+    return (uint32_t)__popcll(idle) >= th || idle == group_leads<L>();
 }
 
 __device__ __forceinline__ void wave_add(unsigned long long *dst, uint64_t v)
@@ -106,20 +124,22 @@ struct Walker {
     uint32_t cnt;          // D modes: failed segments so far
     uint32_t zr;           // DBP: the read's budget
     uint64_t outp;         // DFULL: output byte of position 0
-    uint32_t bp01, bp23;   // DBP: breakpoints 0..3 (16 bits each)
-    uint32_t bp4;
+    uint64_t bp03;         // DBP: positions of failures 1..4 (16 bits each, 0xFFFF: none)
+    uint32_t bp4;          // DBP: position of failure 5
+    bool fin;              // finished; the result is stored by retire()
 
-    __device__ void finish(const WalkArgs &a, bool lead_lane)
+    __device__ void retire(const WalkArgs &a, bool lead_lane)
     {
         if (lead_lane) {
             if (MODE == WALK_EXACT) {
                 ((uint2 *)a.out)[rs] = (k <= l) ? make_uint2(k, l) : make_uint2(1u, 0u);
             } else if (MODE == WALK_DBP) {
-                ((uint4 *)a.out)[rs] = make_uint4(cnt | (bp01 << 16), (bp01 >> 16) | (bp23 << 16),
-                                                  (bp23 >> 16) | (bp4 << 16), 0u);
+                const uint32_t lo = (uint32_t)bp03, hi = (uint32_t)(bp03 >> 32);
+                ((uint4 *)a.out)[rs] = make_uint4(cnt | (lo << 16), (lo >> 16) | (hi << 16), (hi >> 16) | (bp4 << 16), 0u);
             }
         }
         rs = kEmpty;
+        fin = false;
     }
 
     // Header of a new read-strand: its offsets (and budget) are loaded here and used by
@@ -159,10 +179,11 @@ struct Walker {
         l = a.lay.n;
         i = 0;
         cnt = 0;
-        bp01 = bp23 = bp4 = 0;
+        bp03 = ~0ull;
+        bp4 = 0xFFFFu;
         if (MODE == WALK_DBP) zr = hz < a.zmax ? hz : a.zmax;
         if (MODE == WALK_DFULL) outp = (a.nstr == 2 ? strand : 0u) * a.dstride + b0;
-        if (m == 0) finish(a, lead_lane);
+        fin = m == 0;
     }
 
     // One step with pattern symbol c (already complemented for strand 1); ok/ol are
@@ -182,20 +203,20 @@ struct Walker {
         if (MODE == WALK_EXACT) {
             k = nk;
             l = nl;
-            if (nk > nl || rem == 0) finish(a, lead_lane);
+            fin = nk > nl || rem == 0;
             return;
         }
         const bool fail = nk > nl;                       // a difference is certain in this segment
+        const uint32_t sh = 16u * (cnt & 3u);            // field of this failure (the cnt-th, 0-based)
+        const uint64_t fm = (fail && cnt < 4) ? (0xFFFFull << sh) : 0ull;
+        bp03 = (bp03 & ~fm) | (((uint64_t)(i & 0xFFFFu) << sh) & fm);
+        bp4 = (fail && cnt == 4) ? (i & 0xFFFFu) : bp4;
         cnt += fail ? 1u : 0u;
-        const uint32_t pos = fail ? (i & 0xFFFFu) : 0u;
-        bp01 |= cnt == 1 ? pos : (cnt == 2 ? pos << 16 : 0u);
-        bp23 |= cnt == 3 ? pos : (cnt == 4 ? pos << 16 : 0u);
-        bp4 |= cnt == 5 ? pos : 0u;
         k = fail ? 0u : nk;
         l = fail ? a.lay.n : nl;
         if (MODE == WALK_DFULL && lead_lane) ((uint8_t *)a.out)[outp + i] = (uint8_t)(cnt < 255 ? cnt : 255);
         i += 1;
-        if (rem == 0 || (MODE == WALK_DBP && cnt > zr)) finish(a, lead_lane);
+        fin = rem == 0 || (MODE == WALK_DBP && cnt > zr);
     }
 };
 
@@ -208,6 +229,7 @@ __global__ void __launch_bounds__(256) walk_plain(WalkArgs a)
     if (item >= a.total) return;
     Walker<MODE> w;
     w.init(a, item, true);
+    if (w.fin) w.retire(a, true);
     uint64_t steps = 0, bks = 0;
     while (w.rs != kEmpty) {
         const uint32_t c = a.codes[w.addr];
@@ -221,6 +243,7 @@ __global__ void __launch_bounds__(256) walk_plain(WalkArgs a)
             bks += pr.same ? 1 : 2;
         }
         w.step(a, b, ok, ol, true);
+        if (w.fin) w.retire(a, true);
     }
     if (a.stat_steps && steps) {
         atomicAdd(a.stat_steps, (unsigned long long)steps);
@@ -238,6 +261,7 @@ __global__ void __launch_bounds__(256) walk_batched(WalkArgs a)
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         w[p].rs = kEmpty;
+        w[p].fin = false;
         pending[p] = false;
     }
     WaveQueue wq;
@@ -253,12 +277,16 @@ __global__ void __launch_bounds__(256) walk_batched(WalkArgs a)
             c[p] = act ? a.codes[w[p].addr] : 0u;
             pr[p].load(a.lay, q, act && w[p].k ? w[p].k : 1u, act ? w[p].l : 0u);
         }
-        // 2. idle slots take a read-strand and request its header; it starts next round
+        // 2. idle slots take a read-strand and request its header, which arrives with the
+        //    round's bucket loads; it begins in step 3 and steps from the next round
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const uint32_t it = wave_take<L>(wq, w[p].rs == kEmpty, a.queue, a.total);
-            pending[p] = it != kEmpty;
-            if (pending[p]) w[p].request(a, it);
+            pending[p] = false;
+            if (refill_now<L>(lead && w[p].rs == kEmpty)) {
+                const uint32_t it = wave_take<L>(wq, w[p].rs == kEmpty, a.queue, a.total);
+                pending[p] = it != kEmpty;
+                if (pending[p]) w[p].request(a, it);
+            }
         }
         bool any = false;
 #pragma unroll
@@ -280,6 +308,19 @@ __global__ void __launch_bounds__(256) walk_batched(WalkArgs a)
                 bks += pr[p].same ? 1 : 2;
             }
             w[p].step(a, b, ok, ol, lead);
+        }
+        // The round's loads are issued and read under different conditions; reading
+        // their registers here on every path lets the compiler retire them now rather
+        // than wait on every memory operation, stores included, where the registers are
+        // next written. Results are stored only after this point.
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            asm volatile("" ::"v"(w[p].h0), "v"(w[p].h1), "v"(w[p].hz), "v"(c[p]));
+#pragma unroll
+            for (int t = 0; t < Bucket<I, L>::NPL; ++t)
+                asm volatile("" ::"v"(pr[p].a.v[t].x), "v"(pr[p].a.v[t].y), "v"(pr[p].a.v[t].z), "v"(pr[p].a.v[t].w),
+                             "v"(pr[p].b.v[t].x), "v"(pr[p].b.v[t].y), "v"(pr[p].b.v[t].z), "v"(pr[p].b.v[t].w));
+            if (w[p].fin) w[p].retire(a, lead);
         }
     }
     wave_add(a.stat_steps, steps);
@@ -415,7 +456,7 @@ struct DfsArgs {
     const uint8_t *z;
     const uint4 *bp;       // D breakpoint records per read-strand, or nullptr
     uint32_t total, nstr, strand0, zmax;
-    uint32_t scap;         // stack entries per read-strand (3 * zmax) plus one spare
+    uint32_t fcap;         // stack frames per read-strand: zmax, plus one spare
     uint32_t budget;       // expanded nodes per read-strand
     fm_hit *slots;         // kHitSlots hits per read-strand
     fm_hit *opool;         // hits beyond the slots
@@ -426,30 +467,37 @@ struct DfsArgs {
     unsigned long long *stat_occ, *stat_bk;
 };
 
+// Stack frame (48 bytes in LDS): the intervals of a node's four children and, in
+// meta, the node's pattern position less one (bits 0-15), its remaining budget (16-19),
+// its pattern symbol (20-23) and the children still to visit (24-27).
+struct Frame {
+    uint4 k, l;
+    uint4 meta;
+};
+
 struct Dfs {
     uint32_t rs;                    // kEmpty when idle
     uint32_t read, strand, m, z0;
     uint64_t base;
-    uint32_t nbp, bpw0, bpw1, bpw2; // D breakpoints: nbp, then 16-bit positions
+    uint64_t bp03;                  // D breakpoints 0..3, 16 bits each (0xFFFF: none)
+    uint32_t bp4;                   // D breakpoint 4
     uint32_t i, zr, k, l;           // current node: pattern symbol i (>= 0) still to match
-    uint32_t sp;
+    uint32_t sp;                    // frames on the stack
     uint32_t hits, status, nodes;
     bool done;
     // hits produced by the last expansion (children of a node with i == 0)
     uint32_t pend, pk[4], pl[4], pd;
 
-    __device__ uint32_t bp_at(uint32_t j) const
+    // First pattern position at which the D bound exceeds zc (0xFFFF: none).
+    __device__ uint32_t bp_at(uint32_t zc) const
     {
-        const uint32_t lo = sel4(j & 3, bpw0 >> 16, bpw1 & 0xFFFFu, bpw1 >> 16, bpw2 & 0xFFFFu);
-        return j >= 4 ? (bpw2 >> 16) : lo;
+        const uint32_t f = (uint32_t)(bp03 >> (16u * (zc & 3u))) & 0xFFFFu;
+        return zc >= 4 ? bp4 : f;
     }
 
     // D(pos) > zc, i.e. a node that may still spend zc substitutions on pattern[0..pos]
-    // cannot lead to a hit.
-    __device__ bool dprune(uint32_t zc, int pos) const
-    {
-        return pos >= 0 && zc < nbp && bp_at(zc) <= (uint32_t)pos;
-    }
+    // cannot lead to a hit (pos = -1: nothing is left to match, never pruned).
+    __device__ bool dprune(uint32_t zc, int pos) const { return (int)bp_at(zc) <= pos; }
 
     __device__ uint32_t sym(const DfsArgs &a, uint32_t pos) const
     {
@@ -473,12 +521,6 @@ struct Dfs {
         hbp = a.bp ? a.bp[item] : make_uint4(0, 0, 0, 0);
     }
 
-    __device__ void init(const DfsArgs &a, uint32_t item)
-    {
-        request(a, item);
-        begin(a);
-    }
-
     __device__ void begin(const DfsArgs &a)
     {
         read = a.nstr == 2 ? rs >> 1 : rs;
@@ -488,100 +530,91 @@ struct Dfs {
         z0 = hz;
         sp = 0;
         hits = 0;
-        status = FM_OK;
         nodes = 0;
-        done = false;
-        pend = 0;
         pd = 0;
-        nbp = 0;
-        bpw0 = bpw1 = bpw2 = 0;
-        i = 0;
-        zr = 0;
         k = 0;
         l = a.lay.n;
-        if (z0 > a.zmax) {
-            status = FM_EINVAL;
-            done = true;
-            return;
-        }
-        if (m > 65535u) {
-            status = FM_ERANGE;
-            done = true;
-            return;
-        }
+        i = m - 1;
+        zr = z0;
+        uint32_t nbp = 0;
+        bp03 = ~0ull;
+        bp4 = 0xFFFFu;
         if (a.bp) {
             const uint4 r = hbp;
             nbp = r.x & 0xFFFFu;
-            bpw0 = r.x;
-            bpw1 = r.y;
-            bpw2 = r.z;
-            if (nbp > z0) {               // root pruned: D(m-1) > z
-                done = true;
-                return;
-            }
+            bp03 = u64_of((r.x >> 16) | (r.y << 16), (r.y >> 16) | (r.z << 16));
+            bp4 = r.z >> 16;
         }
-        if (m == 0) {                     // the empty pattern matches every row
-            pend = 1;
-            pk[0] = 0;
-            pl[0] = a.lay.n;
-            pd = 0;
-            done = true;
-            return;
-        }
-        i = m - 1;
-        zr = z0;
+        const bool bad_z = z0 > a.zmax, bad_m = m > 65535u;
+        status = bad_z ? FM_EINVAL : (bad_m ? FM_ERANGE : FM_OK);
+        // decided at once: invalid budget or length, root pruned (D(m-1) > z), or the
+        // empty pattern, which matches every row with no substitution
+        const bool ok = !bad_z && !bad_m && nbp <= z0;
+        done = !ok || m == 0;
+        pend = (ok && m == 0) ? 1u : 0u;
+        pk[0] = 0;
+        pl[0] = a.lay.n;
     }
 };
+
+// Loads of one expansion, issued before anything waits on them.
+template <int I, int L>
+struct NodeLoads {
+    uint32_t code;
+    Pair<I, L> pr;
+};
+
+template <int I, int L>
+__device__ __forceinline__ void dfs_load(const DfsArgs &a, const Dfs &d, uint32_t q, NodeLoads<I, L> &nl)
+{
+    nl.code = a.codes[d.base + (d.strand ? d.m - 1 - d.i : d.i)];
+    nl.pr.load(a.lay, q, d.k ? d.k : 1u, d.l);
+}
 
 // Expands the current node: one Occ8 at (k-1, l) gives the intervals of all four
 // one-symbol extensions (Listing 2's loop over b, each computed from the parent's
 // interval and kept only when k_b <= l_b). Children needing more substitutions than
 // remain, or than the D bound allows, are dropped. At i == 0 the survivors are hits.
-// Otherwise one mismatch child (if any) is continued while the match child and the
-// other mismatch children are pushed, the match child deepest: every pushed group
-// lies below a step that spent one substitution, so the stack never holds more than
-// 3 * zmax entries. Entry `scap - 1` of the stack is a spare that absorbs the writes of
-// children that are not pushed, which keeps the update free of branches.
+// Otherwise a mismatch child, if any, is continued and the node's other survivors are
+// pushed as one frame; frames hand out their mismatch children first and the match
+// child last, so the current node descends from a mismatch child of every node with a
+// frame on the stack, and at most z frames are ever stacked. Frame `fcap - 1` is a spare
+// that absorbs the writes and reads of lanes that neither push nor pop, which keeps the
+// update free of branches.
 template <int I, int L>
-__device__ __forceinline__ void dfs_node(const DfsArgs &a, Dfs &d, uint32_t q, uint32_t *st, bool lead,
-                                         uint64_t &n_occ, uint64_t &n_bk)
+__device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeLoads<I, L> &nl, uint32_t q,
+                                           Frame *fr, bool lead, uint64_t &n_occ, uint64_t &n_bk)
 {
-    // loads: the pattern symbol and the bucket(s) of (k-1, l), issued together
     const uint32_t kk = d.k ? d.k : 1u;
-    const uint32_t wi = d.sym(a, d.i);
-    Pair<I, L> pr;
-    pr.load(a.lay, q, kk, d.l);
+    const uint32_t wi = strand_sym(nl.code, d.strand);
     Occ4 o1, o2;
-    occ8<I, L>(a.lay, pr, q, kk, d.l, o1, o2);
-    const bool root = d.k == 0;                   // (0, n): children come from C alone
-    const uint32_t C0 = a.lay.C[0], C1 = a.lay.C[1], C2 = a.lay.C[2], C3 = a.lay.C[3], C4 = a.lay.C[4];
+    occ8<I, L>(a.lay, nl.pr, q, kk, d.l, o1, o2);
+    // children; at the root (0, n) Occ(., -1) is zero and Occ(., n) is every symbol's total
+    const bool root = d.k == 0;
+    const uint32_t C0 = a.lay.C[0], C1 = a.lay.C[1], C2 = a.lay.C[2], C3 = a.lay.C[3];
     uint32_t kb[4], lb[4];
     kb[0] = C0 + 1 + (root ? 0u : o1.a);
     kb[1] = C1 + 1 + (root ? 0u : o1.c);
     kb[2] = C2 + 1 + (root ? 0u : o1.g);
     kb[3] = C3 + 1 + (root ? 0u : o1.t);
-    lb[0] = root ? C1 : C0 + o2.a;
-    lb[1] = root ? C2 : C1 + o2.c;
-    lb[2] = root ? C3 : C2 + o2.g;
-    lb[3] = root ? C4 : C3 + o2.t;
+    lb[0] = C0 + o2.a;
+    lb[1] = C1 + o2.c;
+    lb[2] = C2 + o2.g;
+    lb[3] = C3 + o2.t;
     if (lead) {
         n_occ += 1;
-        n_bk += root ? 0 : (pr.same ? 1 : 2);
+        n_bk += root ? 0 : (nl.pr.same ? 1 : 2);
     }
     // surviving children
     const int cpos = (int)d.i - 1;
-    const bool keep_match = !(a.bp && d.dprune(d.zr, cpos));
-    const bool keep_mism = d.zr >= 1 && !(a.bp && d.dprune(d.zr - 1, cpos));
-    uint32_t valid = 0;
+    const bool keep_match = !d.dprune(d.zr, cpos);
+    const bool keep_mism = d.zr >= 1 && !d.dprune(d.zr - 1, cpos);
+    const uint32_t mbit = wi < 4 ? 1u << wi : 0u;
+    uint32_t le = 0;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const bool m = (uint32_t)b == wi;
-        valid |= (kb[b] <= lb[b] && (m ? keep_match : keep_mism)) ? (1u << b) : 0u;
-    }
+    for (int b = 0; b < 4; ++b) le |= kb[b] <= lb[b] ? (1u << b) : 0u;
+    const uint32_t valid = le & ((keep_match ? mbit : 0u) | (keep_mism ? (0xFu & ~mbit) : 0u));
     const bool leaf = d.i == 0;
-    const uint32_t mbit = wi < 4 ? (1u << wi) : 0u;
-    const uint32_t match = valid & mbit;
-    const uint32_t mism = valid & ~mbit;
     // hits
     d.pend = leaf ? valid : 0u;
 #pragma unroll
@@ -590,39 +623,38 @@ __device__ __forceinline__ void dfs_node(const DfsArgs &a, Dfs &d, uint32_t q, u
         d.pl[b] = lb[b];
     }
     d.pd = (d.z0 - d.zr) | (wi << 8);
-    // continue with a mismatch child if there is one, else with the match child
-    const bool has_mism = !leaf && mism != 0;
-    const uint32_t cont = has_mism ? (uint32_t)__builtin_ctz(mism) : (wi & 3);
-    const bool advance = !leaf && (mism | match) != 0;
-    const uint32_t push = has_mism ? ((mism & ~(1u << cont)) | match) : 0u;
+    // continue with a mismatch child if there is one, else with the match child; the
+    // other survivors of a node that continues with a mismatch go into a frame
+    const uint32_t go = leaf ? 0u : valid;
+    const uint32_t mism = go & ~mbit;
+    const bool advance = go != 0;
+    const uint32_t cont = mism ? (uint32_t)__builtin_ctz(mism) : (wi & 3u);
+    const uint32_t rest = mism ? (go & ~(1u << cont)) : 0u;
     const uint32_t ci = d.i - 1;
-    const uint32_t spare = a.scap - 1;
-    const uint32_t base_other = d.sp + (match & push ? 1u : 0u);
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const bool pb = (push >> b) & 1u;
-        const bool is_match = (mbit >> b) & 1u;
-        const uint32_t slot = !pb ? spare : (is_match ? d.sp : base_other + __popc(push & ~mbit & ((1u << b) - 1u)));
-        const uint32_t zc = d.zr - (is_match ? 0u : 1u);
-        if (lead) {
-            uint32_t *e = st + 3 * slot;
-            e[0] = kb[b];
-            e[1] = lb[b];
-            e[2] = ci | (zc << 16);
-        }
+    const uint32_t spare = a.fcap - 1;
+    Frame *fw = fr + (rest ? d.sp : spare);
+    if (lead) {
+        fw->k = make_uint4(kb[0], kb[1], kb[2], kb[3]);
+        fw->l = make_uint4(lb[0], lb[1], lb[2], lb[3]);
+        fw->meta.x = (ci & 0xFFFFu) | (d.zr << 16) | (wi << 20) | (rest << 24);
     }
-    const uint32_t nsp = d.sp + __popc(push);
-    // next node: the continued child, or the top of the stack
+    const uint32_t nsp = d.sp + (rest ? 1u : 0u);
+    // otherwise the next node comes from the top frame: a mismatch child while there is
+    // one, then the match child, which retires the frame
     const bool pop = !advance && nsp > 0;
-    const uint32_t *top = st + 3 * (pop ? nsp - 1 : spare);
-    const uint32_t t0 = top[0], t1 = top[1], t2 = top[2];
-    const uint32_t kc = sel4(cont, kb[0], kb[1], kb[2], kb[3]);
-    const uint32_t lc = sel4(cont, lb[0], lb[1], lb[2], lb[3]);
-    d.k = advance ? kc : t0;
-    d.l = advance ? lc : t1;
-    d.i = advance ? ci : (t2 & 0xFFFFu);
-    d.zr = advance ? d.zr - (cont != wi ? 1u : 0u) : (t2 >> 16);
-    d.sp = pop ? nsp - 1 : nsp;
+    Frame *ft = fr + (pop ? nsp - 1 : spare);
+    const uint4 tk = ft->k, tl = ft->l;
+    const uint32_t meta = ft->meta.x;
+    const uint32_t trest = (meta >> 24) & 0xFu, twi = (meta >> 20) & 0xFu;
+    const uint32_t tmm = trest & ~(twi < 4 ? 1u << twi : 0u);
+    const uint32_t bt = (uint32_t)__builtin_ctz((tmm ? tmm : trest) | 0x10u) & 3u;
+    const uint32_t left = trest & ~(1u << bt);
+    if (lead) ft->meta.x = (meta & 0x00FFFFFFu) | (left << 24);
+    d.k = advance ? sel4(cont, kb[0], kb[1], kb[2], kb[3]) : sel4(bt, tk.x, tk.y, tk.z, tk.w);
+    d.l = advance ? sel4(cont, lb[0], lb[1], lb[2], lb[3]) : sel4(bt, tl.x, tl.y, tl.z, tl.w);
+    d.i = advance ? ci : (meta & 0xFFFFu);
+    d.zr = advance ? d.zr - (cont != wi ? 1u : 0u) : ((meta >> 16) & 0xFu) - (bt != twi ? 1u : 0u);
+    d.sp = pop && !left ? nsp - 1 : nsp;
     d.done = !advance && !pop;
     d.nodes += 1;
     if (!d.done && d.nodes >= a.budget) {
@@ -701,30 +733,42 @@ __device__ void dfs_emit(const DfsArgs &a, Dfs &d, bool active, bool lead)
 template <int I>
 __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
 {
-    extern __shared__ uint32_t lds_stack[];
+    extern __shared__ Frame lds_frames[];
     const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t *st = lds_stack + (size_t)threadIdx.x * a.scap * 3;
+    Frame *fr = lds_frames + (size_t)threadIdx.x * a.fcap;
     Dfs d;
     d.rs = kEmpty;
-    if (item < a.total) d.init(a, item);
+    d.done = false;
+    if (item < a.total) {
+        d.request(a, item);
+        d.begin(a);
+    }
     uint64_t n_occ = 0, n_bk = 0;
     for (;;) {
         const bool active = d.rs != kEmpty;
         if (!__any(active)) break;
-        if (active && !d.done) dfs_node<I, 1>(a, d, 0, st, true, n_occ, n_bk);
+        if (active && !d.done) {
+            NodeLoads<I, 1> nl;
+            dfs_load<I, 1>(a, d, 0, nl);
+            dfs_expand<I, 1>(a, d, nl, 0, fr, true, n_occ, n_bk);
+        }
         dfs_emit<1>(a, d, active, true);
     }
     wave_add(a.stat_occ, n_occ);
     wave_add(a.stat_bk, n_bk);
 }
 
+// Each round: idle groups (refilled in batches) take read-strands and issue their
+// header loads; running groups issue their node loads and expand their nodes, by which
+// time the older header loads have arrived too; new read-strands begin; hits are stored
+// and finished read-strands retired.
 template <int I, int L>
 __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
 {
-    extern __shared__ uint32_t lds_stack[];
+    extern __shared__ Frame lds_frames[];
     const uint32_t q = L == 1 ? 0u : (__lane_id() & (L - 1));
     const bool lead = q == 0;
-    uint32_t *st = lds_stack + (size_t)(threadIdx.x / L) * a.scap * 3;
+    Frame *fr = lds_frames + (size_t)(threadIdx.x / L) * a.fcap;
     Dfs d;
     d.rs = kEmpty;
     d.done = false;
@@ -732,16 +776,25 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
     wq.start(a.queue);
     uint64_t n_occ = 0, n_bk = 0;
     for (;;) {
-        // expand the current nodes (their loads go out first), then refill idle lanes,
-        // whose headers arrive with the same round of loads
         const bool running = d.rs != kEmpty;
-        if (running && !d.done) dfs_node<I, L>(a, d, q, st, lead, n_occ, n_bk);
-        dfs_emit<L>(a, d, running, lead);
-        const uint32_t it = wave_take<L>(wq, d.rs == kEmpty, a.queue, a.total);
-        if (it != kEmpty) d.request(a, it);
-        if (!__any(d.rs != kEmpty)) break;
-        if (it != kEmpty) d.begin(a);
-        dfs_emit<L>(a, d, it != kEmpty, lead);   // read-strands decided at once (pruned root, empty read)
+        bool fresh = false;
+        if (refill_now<L>(lead && !running)) {
+            const uint32_t it = wave_take<L>(wq, !running, a.queue, a.total);
+            fresh = it != kEmpty;
+            if (fresh) d.request(a, it);
+        }
+        if (running) {
+            NodeLoads<I, L> nl;
+            dfs_load<I, L>(a, d, q, nl);
+            dfs_expand<I, L>(a, d, nl, q, fr, lead, n_occ, n_bk);
+        }
+        if (fresh) d.begin(a);
+        // The header registers are loaded and read under two separate conditions; reading
+        // them here on every path lets the compiler retire those loads now instead of
+        // waiting on all memory operations where the registers are next written.
+        asm volatile("" ::"v"(d.h0), "v"(d.h1), "v"(d.hz), "v"(d.hbp.x), "v"(d.hbp.y), "v"(d.hbp.z), "v"(d.hbp.w));
+        dfs_emit<L>(a, d, running || fresh, lead);
+        if (!__any(d.rs != kEmpty) && wq.exhausted) break;
     }
     wave_add(a.stat_occ, n_occ);
     wave_add(a.stat_bk, n_bk);
@@ -751,7 +804,7 @@ template <int I, int L>
 static hipError_t dfs_launch_batched(const fm_index *idx, const fm_tuning &t, const DfsArgs &a, hipStream_t s)
 {
     const int block = (int)t.block;
-    const size_t lds = (size_t)(block / L) * a.scap * 3 * sizeof(uint32_t);
+    const size_t lds = (size_t)(block / L) * a.fcap * sizeof(Frame);
     int per = max_blocks_per_cu((const void *)dfs_batched<I, L>, block, lds);
     if (t.waves_per_cu) {
         int want = (int)(t.waves_per_cu * 64 / block);
@@ -975,7 +1028,7 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     a.strand0 = (c.flags & FM_FWD) ? 0u : 1u;
     a.total = (uint32_t)(c.nreads * nstr);
     a.zmax = c.zmax;
-    a.scap = 3 * c.zmax + 1;
+    a.fcap = c.zmax + 1;
     a.budget = t.node_budget ? t.node_budget : 0xFFFFFFFFu;
     a.slots = (fm_hit *)(ws + W.slots);
     a.opool = (fm_hit *)(ws + W.opool);
@@ -989,7 +1042,7 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     pe->mark(2, s);
     if (plain) {
         const uint32_t grid = (a.total + 255) / 256;
-        const size_t lds = (size_t)256 * a.scap * 3 * sizeof(uint32_t);
+        const size_t lds = (size_t)256 * a.fcap * sizeof(Frame);
         switch (t.occ_interval) {
         case 64: hipLaunchKernelGGL(dfs_plain<64>, dim3(grid), dim3(256), lds, s, a); break;
         case 96: hipLaunchKernelGGL(dfs_plain<96>, dim3(grid), dim3(256), lds, s, a); break;

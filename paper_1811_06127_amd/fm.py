@@ -15,7 +15,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfmocc.so")
 
-FM_OK, FM_EINVAL, FM_EIO, FM_EFORMAT, FM_ENOMEM, FM_EDEVICE, FM_EOVERFLOW, FM_EBUDGET, FM_ERANGE = range(9)
+FM_OK, FM_EINVAL, FM_EIO, FM_EFORMAT, FM_ENOMEM, FM_EDEVICE, FM_EOVERFLOW, FM_EBUDGET, FM_ERANGE, FM_EAGAIN = range(10)
 FM_FWD, FM_REVCOMP, FM_BOTH, FM_DARRAY, FM_PLAIN, FM_STATS = 1, 2, 3, 4, 16, 32
 FM_LOAD_REVERSE, FM_LOAD_ALL_LAYOUTS = 1, 2
 FM_OP_EXACT, FM_OP_DARRAY, FM_OP_INEXACT = 0, 1, 2
@@ -52,6 +52,22 @@ class Tuning(C.Structure):
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("lanes", C.c_uint32), ("flags", C.c_uint32), ("zmax", C.c_uint32), ("hit_reserve", C.c_uint32),
+                ("arena_bytes", C.c_uint64), ("max_batch_reads", C.c_uint64)]
+
+
+class ServerResult(C.Structure):
+    _fields_ = [("nreads", C.c_uint64), ("hits", C.c_void_p), ("nhits", C.c_uint64), ("hit_offs", C.c_void_p),
+                ("status", C.c_void_p), ("error", C.c_int), ("t_submit", C.c_double), ("t_launch", C.c_double),
+                ("t_done", C.c_double), ("batch", C.c_uint64)]
+
+
+class ServerCounts(C.Structure):
+    _fields_ = [("batches", C.c_uint64), ("retries", C.c_uint64), ("requests_done", C.c_uint64),
+                ("reads_done", C.c_uint64), ("pending", C.c_uint64), ("error", C.c_int)]
 
 
 HIT_DTYPE = np.dtype([("read", "<u4"), ("k", "<u4"), ("l", "<u4"), ("strand", "u1"), ("nmm", "u1"),
@@ -97,6 +113,14 @@ def lib() -> C.CDLL:
         "fm_phase_timing": (i32, [vp, u32]),
         "fm_phase_times": (i32, [vp, C.POINTER(C.c_float), C.POINTER(C.c_uint32)]),
         "fm_plan_free": (None, [vp]),
+        "fm_server_bytes": (i32, [C.POINTER(ServerOpts), u64, u64, C.POINTER(C.c_uint64)]),
+        "fm_server_create": (i32, [vp, C.POINTER(ServerOpts), C.POINTER(vp)]),
+        "fm_server_submit": (i32, [vp, vp, vp, vp, u64, C.POINTER(C.c_uint64)]),
+        "fm_server_wait": (i32, [vp, u64, C.c_double, C.POINTER(ServerResult)]),
+        "fm_server_release": (i32, [vp, u64]),
+        "fm_server_clock": (C.c_double, [vp]),
+        "fm_server_stats": (i32, [vp, C.POINTER(ServerCounts)]),
+        "fm_server_free": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -414,3 +438,98 @@ def reads_to_device(codes: np.ndarray, offs: np.ndarray, z: np.ndarray | None = 
     o = torch.from_numpy(np.ascontiguousarray(offs, dtype=np.uint64).view(np.int64)).to(device)
     zz = None if z is None else torch.from_numpy(np.ascontiguousarray(z, dtype=np.uint8)).to(device)
     return c, o, zz
+
+
+# ---------------------------------------------------------------- serving
+
+def server_opts(lanes: int = 2, flags: int = FM_BOTH | FM_DARRAY, zmax: int = 2, hit_reserve: int = 4,
+                arena_bytes: int = 1 << 30, max_batch_reads: int = 0) -> ServerOpts:
+    return ServerOpts(lanes, flags, zmax, hit_reserve, arena_bytes, max_batch_reads)
+
+
+def fm_server_bytes(opts: ServerOpts, nreads: int, total_len: int) -> int:
+    """Device bytes a batch of this shape takes under opts (the admission rule)."""
+    out = C.c_uint64()
+    _check(lib().fm_server_bytes(C.byref(opts), nreads, total_len, C.byref(out)), "fm_server_bytes")
+    return int(out.value)
+
+
+class Served:
+    """One finished request: hits (HIT_DTYPE, read numbers local to the request),
+    hit_offs, status and the server-clock times."""
+
+    def __init__(self, r: ServerResult):
+        n = int(r.nreads)
+        self.error = int(r.error)
+        self.hits = np.empty(int(r.nhits), dtype=HIT_DTYPE)
+        if r.nhits:
+            C.memmove(self.hits.ctypes.data, r.hits, 16 * int(r.nhits))
+        self.hit_offs = np.zeros(n + 1, dtype=np.uint64)
+        if r.hit_offs:
+            C.memmove(self.hit_offs.ctypes.data, r.hit_offs, 8 * (n + 1))
+        self.status = np.zeros(n, dtype=np.uint32)
+        if n and r.status:
+            C.memmove(self.status.ctypes.data, r.status, 4 * n)
+        self.t_submit, self.t_launch, self.t_done = float(r.t_submit), float(r.t_launch), float(r.t_done)
+        self.batch = int(r.batch)
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_submit
+
+
+class Server:
+    """fm_server_*: continuous batching of inexact-search requests on one index."""
+
+    def __init__(self, index: "Index", **kw):
+        self.index = index                    # kept alive while the server runs
+        self.opts = server_opts(**kw)
+        h = C.c_void_p()
+        _check(lib().fm_server_create(index.handle, C.byref(self.opts), C.byref(h)), "fm_server_create")
+        self.handle = h
+
+    def submit(self, codes: np.ndarray, offs: np.ndarray, z: np.ndarray) -> int:
+        codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        offs = np.ascontiguousarray(offs, dtype=np.uint64)
+        z = np.ascontiguousarray(z, dtype=np.uint8)
+        t = C.c_uint64()
+        _check(lib().fm_server_submit(self.handle, _ptr(codes), _ptr(offs), _ptr(z), offs.size - 1, C.byref(t)),
+               "fm_server_submit")
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout: float | None = None) -> Served | None:
+        """The finished request, or None if it is still running after `timeout` s."""
+        r = ServerResult()
+        st = lib().fm_server_wait(self.handle, ticket, -1.0 if timeout is None else float(timeout), C.byref(r))
+        if st == FM_EAGAIN:
+            return None
+        _check(st, "fm_server_wait")
+        return Served(r)
+
+    def release(self, ticket: int):
+        _check(lib().fm_server_release(self.handle, ticket), "fm_server_release")
+
+    def clock(self) -> float:
+        return float(lib().fm_server_clock(self.handle))
+
+    def stats(self) -> dict:
+        c = ServerCounts()
+        _check(lib().fm_server_stats(self.handle, C.byref(c)), "fm_server_stats")
+        return {f: int(getattr(c, f)) for f, _ in c._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().fm_server_free(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

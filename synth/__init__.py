@@ -24,10 +24,18 @@ _M2 = np.uint64(0x94D049BB133111EB)
 def splitmix64(seed: int, counters: np.ndarray) -> np.ndarray:
     """SplitMix64 outputs for the given counters of the stream `seed` (uint64 array)."""
     with np.errstate(over="ignore"):
-        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + (counters.astype(np.uint64) + np.uint64(1)) * _GAMMA
-        z = (z ^ (z >> np.uint64(30))) * _M1
-        z = (z ^ (z >> np.uint64(27))) * _M2
-        return z ^ (z >> np.uint64(31))
+        z = counters.astype(np.uint64)          # a fresh array, updated in place below
+        t = np.empty_like(z)
+        z += np.uint64(1)
+        z *= _GAMMA
+        z += np.uint64(seed & 0xFFFFFFFFFFFFFFFF)
+        for sh, mul in ((30, _M1), (27, _M2)):
+            np.right_shift(z, np.uint64(sh), out=t)
+            z ^= t
+            z *= mul
+        np.right_shift(z, np.uint64(31), out=t)
+        z ^= t
+        return z
 
 
 class Rng:
@@ -64,12 +72,23 @@ class Rng:
 
 def substitute(codes: np.ndarray, rate, rng: Rng) -> np.ndarray:
     """I.i.d. substitutions: each position mutates with probability `rate` (scalar or
-    per-position array) to one of the three other bases, chosen uniformly."""
+    per-position array) to one of the three other bases, chosen uniformly.
+
+    One 64-bit draw per position: its high 32 bits decide the substitution (below
+    rate * 2^32), its low 32 bits pick the replacement (floor(3 * low / 2^32) + 1 added
+    to the code, mod 4). Positions holding code 4 (N) are left alone."""
     out = codes.copy()
-    hit = rng.uniform(codes.size) < rate
-    shift = rng.integers(1, 3, codes.size).astype(np.uint8)
-    m = hit & (out < 4)
-    out[m] = (out[m] + shift[m]) & 3
+    rate = np.broadcast_to(np.asarray(rate, dtype=np.float64), codes.shape)
+    step = 1 << 24
+    for a in range(0, codes.size, step):
+        b = min(codes.size, a + step)
+        u = rng.u64(b - a)
+        thr = (rate[a:b] * 4294967296.0).astype(np.uint64)
+        hit = (u >> np.uint64(32)) < thr
+        shift = (((u & np.uint64(0xFFFFFFFF)) * np.uint64(3)) >> np.uint64(32)).astype(np.uint8) + np.uint8(1)
+        seg = out[a:b]
+        m = hit & (seg < 4)
+        seg[m] = (seg[m] + shift[m]) & 3
     return out
 
 
@@ -200,17 +219,24 @@ class Reads:
 
 
 def _gather(ref: np.ndarray, starts: np.ndarray, lens: np.ndarray, minus: np.ndarray) -> np.ndarray:
+    """Concatenated fragments ref[start, start + len), reverse-complemented where minus
+    is set; built in chunks of reads to bound the temporaries."""
     offs = np.zeros(lens.size + 1, dtype=np.int64)
     np.cumsum(lens, out=offs[1:])
-    total = int(offs[-1])
-    rid = np.repeat(np.arange(lens.size), lens)
-    j = np.arange(total, dtype=np.int64) - offs[rid]
-    fwd_idx = starts[rid] + j
-    rev_idx = starts[rid] + (lens[rid] - 1 - j)
-    mrow = minus[rid].astype(bool)
-    idx = np.where(mrow, rev_idx, fwd_idx)
-    out = ref[idx].copy()
-    out[mrow] = 3 - out[mrow]
+    out = np.empty(int(offs[-1]), dtype=np.uint8)
+    step = 1 << 18
+    for a in range(0, lens.size, step):
+        b = min(lens.size, a + step)
+        ln = lens[a:b].astype(np.int64)
+        base = offs[a:b] - offs[a]
+        rid = np.repeat(np.arange(b - a, dtype=np.int32), ln)
+        j = np.arange(int(offs[b] - offs[a]), dtype=np.int64) - base[rid]
+        mrow = minus[a:b].astype(bool)[rid]
+        first = starts[a:b].astype(np.int64)[rid]
+        idx = np.where(mrow, first + (ln[rid] - 1 - j), first + j)
+        seg = ref[idx]
+        seg[mrow] = 3 - seg[mrow]
+        out[offs[a]:offs[b]] = seg
     return out
 
 
