@@ -45,6 +45,11 @@ def parse():
                     help="reads the CPU oracle searches for the baseline (0 skips it)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests in the serving run on the 2^28-base index (0 skips it)")
+    ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of capacity")
+    ap.add_argument("--serve-lanes", type=int, default=2)
+    ap.add_argument("--serve-pool", type=int, default=2_000_000, help="reads the requests are drawn from")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain device-to-device copy of this many MiB (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -218,6 +223,13 @@ def main():
     if args.cpu_sample > 0:
         cpu, parity = cpu_baseline(R, rd, min(args.cpu_sample, nreads), ex_batched, in_batched)
 
+    serve = None
+    if args.serve_requests > 0:
+        del codes, offs, z, ex_out, ex_ws, bufs
+        idx.free()
+        torch.cuda.empty_cache()
+        serve = serve_bench(args)
+
     reads_s = nreads / (ms_step / 1e3)
     out = {
         "metric": METRIC,
@@ -252,9 +264,120 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_sample": parity,
-        "p99_latency_ms": None,
+        "serving": serve,
+        "p99_latency_ms": serve["p99_ms"] if serve else None,
     }
     print(json.dumps(out), flush=True)
+
+
+def serve_bench(args):
+    """Serving on the 2^28-base index (95% i.i.d., 5% diverged copies, 1% tandem repeats):
+    requests of U{1..20,000} reads with lengths U[50, 250], 0.5-3% substitutions and
+    budgets z in {0, 1, 2}, both strands with the D bound, arriving as a Poisson stream
+    at `serve_load` times the capacity measured with every request queued at once.
+    Latency runs from submission to results in host memory (server clock)."""
+    import threading
+
+    import synth
+    from paper_1811_06127_amd import fm
+
+    t0 = time.time()
+    R = synth.cfg3_reference()
+    res = {}
+
+    def bwt(key, text):
+        res[key] = fm.fm_bwt_host(text)
+
+    th = [threading.Thread(target=bwt, args=("f", R)), threading.Thread(target=bwt, args=("r", R[::-1].copy()))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    idx = fm.Index.from_codes(res["f"][0], res["r"][0], occ_interval=64)
+    del res
+    log("serving index (n=%d) built in %.1fs" % (R.size, time.time() - t0))
+    t0 = time.time()
+    pool = synth.cfg3_reads(R, args.serve_pool, seed=3005)
+    rng = synth.Rng(3105)
+    nreq = args.serve_requests
+    sizes = rng.integers(1, 20_000, nreq)
+    starts = np.minimum((rng.uniform(nreq) * (pool.count - sizes + 1)).astype(np.int64), pool.count - sizes)
+    gaps = rng.exponential(1.0, nreq)                     # unit-rate gaps, scaled below
+    reqs = []
+    for s0, n in zip(starts, sizes):
+        lo, hi = int(pool.offs[s0]), int(pool.offs[s0 + n])
+        reqs.append((pool.codes[lo:hi], pool.offs[s0:s0 + n + 1] - np.uint64(lo), pool.z[s0:s0 + n]))
+    log("serving requests drawn in %.1fs: %d requests, %d reads" % (time.time() - t0, nreq, int(sizes.sum())))
+    opts = dict(lanes=args.serve_lanes, flags=fm.FM_BOTH | fm.FM_DARRAY, zmax=2, hit_reserve=4,
+                arena_bytes=2 << 30)
+    mean_size = float(sizes.mean())
+
+    # capacity: the first requests all queued at once
+    with fm.Server(idx, **opts) as srv:
+        warm = [srv.submit(*r) for r in reqs[:20]]
+        for t in warm:
+            srv.wait(t)
+            srv.release(t)
+        m = min(200, nreq)
+        c0 = srv.clock()
+        tick = [srv.submit(*r) for r in reqs[:m]]
+        last = 0.0
+        for t in tick:
+            last = max(last, srv.wait(t).t_done)
+            srv.release(t)
+        capacity = float(sizes[:m].sum()) / (last - c0)
+    rate = args.serve_load * capacity / mean_size            # requests per second
+    log("serving capacity %.3g reads/s; arrival rate %.1f requests/s" % (capacity, rate))
+
+    arrivals = np.cumsum(gaps / rate)
+    results = [None] * nreq
+    with fm.Server(idx, **opts) as srv:
+        tickets = [None] * nreq
+        ready = threading.Semaphore(0)
+
+        def producer():
+            base = time.perf_counter()
+            for i, r in enumerate(reqs):
+                d = base + arrivals[i] - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(*r)
+                ready.release()
+
+        th = threading.Thread(target=producer)
+        th.start()
+        for i in range(nreq):
+            ready.acquire()
+            results[i] = srv.wait(tickets[i])
+            srv.release(tickets[i])
+        th.join()
+        st = srv.stats()
+        # a few requests again, alone: their results must not depend on the batch
+        same = True
+        for i in range(0, nreq, max(1, nreq // 8)):
+            t = srv.submit(*reqs[i])
+            a = srv.wait(t)
+            srv.release(t)
+            b = results[i]
+            same &= bool(np.array_equal(a.status, b.status) and np.array_equal(a.hit_offs, b.hit_offs)
+                         and a.hits.tobytes() == b.hits.tobytes())
+    idx.free()
+    lat = np.array([r.latency for r in results]) * 1e3
+    t_first = min(r.t_submit for r in results)
+    t_last = max(r.t_done for r in results)
+    reads = int(sizes.sum())
+    ok = all(r.error == fm.FM_OK for r in results)
+    per_batch = nreq / max(1, len({r.batch for r in results}))
+    out = {"workload": "2^28-base reference (5%% copies, 1%% tandem repeats); Poisson arrivals at %.2f of "
+                       "capacity; requests of U{1..20000} reads, length U[50,250], 0.5-3%% substitutions, z in "
+                       "{0,1,2}; both strands, D bound" % args.serve_load,
+           "requests": nreq, "reads": reads, "lanes": args.serve_lanes,
+           "capacity_reads_per_s": round(capacity, 1), "reads_per_s": round(reads / (t_last - t_first), 1),
+           "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "mean_ms": round(float(lat.mean()), 3), "requests_per_batch": round(per_batch, 2),
+           "retries": st["retries"], "all_ok": ok, "alone_equals_mixed": same}
+    log("serving:", out)
+    return out
 
 
 def cpu_baseline(R, rd, sample, ex_batched, in_batched):
