@@ -28,6 +28,24 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "reads/s & Occ8 queries/s, batched vs plain kernel, bit-exact; p99 latency"
 
+# Bytes per launch of the dominant kernel measured with rocprofv3 (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by
+# the same counters on a plain 1 GiB copy kernel; profiles/search_kernels_2e24_counters.md). They hold only for the
+# kernel sources and launch settings they were measured with: the key is a hash of the kernel sources and the
+# tuning of the kernel; any other combination reports traffic as null.
+MEASURED_TRAFFIC = {
+    ("82259c7466b3c83d", "dfs_batched", (64, 1, 1, 256, 8)): (17_334_054_698, 97_079_408),
+}
+KERNEL_SOURCES = ("search.hip", "fm_device.hpp", "fm_internal.hpp")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1811_06127_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -212,11 +230,18 @@ def main():
     }
     dom = max(("exact_walk", "d_walk", "dfs"), key=lambda k: phase_ms[k])
     achieved = alg[dom] / (phase_ms[dom] / 1e3) / 1e9
-    roofline = {"bound": "hbm", "kernel": {"exact_walk": "walk_batched<EXACT>", "d_walk": "walk_batched<DBP>",
-                                           "dfs": "dfs_batched"}[dom],
+    kname = {"exact_walk": "walk_batched<EXACT>", "d_walk": "walk_batched<DBP>", "dfs": "dfs_batched"}[dom]
+    tcfg = tuning[{"exact_walk": "exact", "d_walk": "d_walk", "dfs": "inexact"}[dom]]["config"]
+    key = (kernel_source_hash(), kname, tuple(tcfg[f] for f in ("occ_interval", "lanes", "depth", "block",
+                                                                "waves_per_cu")))
+    traffic = MEASURED_TRAFFIC.get(key)
+    roofline = {"bound": "hbm", "kernel": kname,
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": int(alg[dom]), "avg_launch_ms": round(phase_ms[dom], 4)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": int(sum(traffic)) if traffic else None,
+                "traffic_gb_per_s": round(sum(traffic) / (phase_ms[dom] / 1e3) / 1e9, 1) if traffic else None,
+                "bytes_per_launch": int(alg[dom]), "avg_launch_ms": round(phase_ms[dom], 4),
+                "kernel_source_hash": key[0]}
 
     cpu = None
     parity = None
