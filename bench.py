@@ -99,8 +99,8 @@ def main():
         log("copy calibration: %d bytes read, %d bytes written" % (n, n))
         del src, dst
     t0 = time.time()
-    R = synth.cfg2_reference()
-    rd = synth.cfg2_reads(R, args.reads)
+    R = synth.repeats_2e24_reference()
+    rd = synth.reads_2e24(R, args.reads)
     log("inputs generated in %.1fs: n=%d reads=%d" % (time.time() - t0, R.size, rd.count))
     t0 = time.time()
     idx = fm.Index.from_text(R, occ_interval=64, flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_ALL_LAYOUTS)
@@ -307,7 +307,7 @@ def serve_bench(args):
     from paper_1811_06127_amd import fm
 
     t0 = time.time()
-    R = synth.cfg3_reference()
+    R = synth.repeats_2e28_reference()
     res = {}
 
     def bwt(key, text):
@@ -322,7 +322,7 @@ def serve_bench(args):
     del res
     log("serving index (n=%d) built in %.1fs" % (R.size, time.time() - t0))
     t0 = time.time()
-    pool = synth.cfg3_reads(R, args.serve_pool, seed=3005)
+    pool = synth.mixed_reads_2e28(R, args.serve_pool, seed=3005)
     rng = synth.Rng(3105)
     nreq = args.serve_requests
     sizes = rng.integers(1, 20_000, nreq)

@@ -17,6 +17,11 @@ What each function follows:
   inexact              hit set by Hamming-ball enumeration (method="definition") or by the
                        inexact match restricted to substitutions (Listing 2,
                        method="listing2", optionally with the D bound)
+  rank_interval,       text-only checkers for large texts (no SA, BWT, Occ or C): the SA
+  exact_by_rank_scan   interval of a pattern from the number of smaller suffixes and of
+                       occurrences, counted by one scan of the text
+  pigeonhole_hits      the substitution hit set from the windows of R that agree exactly
+                       with one of z+1 pieces of the pattern (pigeonhole principle)
 Every function is pinned by tests/test_oracle_*.py (Fig. 1 values, invariants,
 brute force on tiny inputs); none is "parity unpinned".
 """
@@ -78,6 +83,10 @@ def load(path: str = _LIB) -> C.CDLL:
     lib.oracle_darray.argtypes = [p, u8p, u64p, i64, C.c_int, u8p]
     lib.oracle_inexact.restype = i64
     lib.oracle_inexact.argtypes = [p, p, u8p, u64p, u8p, i64, C.c_int, C.c_int, p, i64, u64p, u64p]
+    lib.oracle_rank_scan.argtypes = [u8p, i64, u8p, i64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.oracle_rank_scan.restype = None
+    lib.oracle_hits_pigeonhole.argtypes = [u8p, i64, u8p, i64, C.c_int, u32p, i64]
+    lib.oracle_hits_pigeonhole.restype = i64
     _lib_cache[path] = lib
     return lib
 
@@ -193,3 +202,69 @@ class OracleIndex:
 def reverse_text(R: np.ndarray) -> np.ndarray:
     """reverse(R): the text whose index gives the D-array bound (BWA)."""
     return np.ascontiguousarray(np.asarray(R, dtype=np.uint8)[::-1])
+
+
+# ---------------------------------------------------------------- text-only checkers
+
+def strand_pattern(W: np.ndarray, strand: int) -> np.ndarray:
+    """Strand 0: W itself; strand 1: W reversed with c -> 3 - c for the bases (4 stays 4)."""
+    W = np.asarray(W, dtype=np.uint8)
+    if strand == 0:
+        return np.ascontiguousarray(W)
+    r = W[::-1].copy()
+    b = r < 4
+    r[b] = 3 - r[b]
+    return r
+
+
+def rank_interval(R: np.ndarray, P: np.ndarray, lib_path: str = _LIB) -> tuple:
+    """(k, l) of P from one scan of R$ (k = smaller suffixes, l = k + occurrences - 1);
+    the canonical miss (1, 0) when P does not occur."""
+    lib = load(lib_path)
+    R = np.ascontiguousarray(R, dtype=np.uint8)
+    P = np.ascontiguousarray(P, dtype=np.uint8)
+    k, occ = C.c_int64(), C.c_int64()
+    lib.oracle_rank_scan(_ptr(R), R.size, _ptr(P) if P.size else None, P.size, C.byref(k), C.byref(occ))
+    return (int(k.value), int(k.value + occ.value - 1)) if occ.value else (1, 0)
+
+
+def exact_by_rank_scan(R: np.ndarray, codes, offs, strands: int = FWD, lib_path: str = _LIB) -> np.ndarray:
+    """Exact intervals like OracleIndex.exact, computed by rank scans of the text."""
+    offs = np.asarray(offs, dtype=np.uint64)
+    out = []
+    for r in range(offs.size - 1):
+        W = np.asarray(codes[int(offs[r]):int(offs[r + 1])], dtype=np.uint8)
+        for s in (0, 1):
+            if strands & (1 << s):
+                out.append(rank_interval(R, strand_pattern(W, s), lib_path))
+    return np.array(out, dtype=np.uint32).reshape(-1, 2)
+
+
+def pigeonhole_hits(R: np.ndarray, codes, offs, z, strands: int = BOTH, lib_path: str = _LIB):
+    """Substitution hit sets like OracleIndex.inexact (HIT_DTYPE sorted by (read, strand,
+    k), plus CSR offsets), computed from the text alone by the pigeonhole principle."""
+    lib = load(lib_path)
+    R = np.ascontiguousarray(R, dtype=np.uint8)
+    offs = np.asarray(offs, dtype=np.uint64)
+    nreads = offs.size - 1
+    z = np.broadcast_to(np.asarray(z, dtype=np.uint8), (nreads,))
+    rows = []
+    hit_offs = np.zeros(nreads + 1, dtype=np.uint64)
+    for r in range(nreads):
+        W = np.asarray(codes[int(offs[r]):int(offs[r + 1])], dtype=np.uint8)
+        for s in (0, 1):
+            if not strands & (1 << s):
+                continue
+            P = strand_pattern(W, s)
+            cap = 64
+            while True:
+                buf = np.zeros(3 * cap, dtype=np.uint32)
+                nh = int(lib.oracle_hits_pigeonhole(_ptr(R), R.size, _ptr(P) if P.size else None, P.size,
+                                                    int(z[r]), _ptr(buf), cap))
+                if nh <= cap:
+                    break
+                cap = nh
+            for h in buf[:3 * nh].reshape(-1, 3):
+                rows.append((r, int(h[0]), int(h[1]), s, int(h[2]), 0))
+        hit_offs[r + 1] = len(rows)
+    return np.array(rows, dtype=HIT_DTYPE), hit_offs

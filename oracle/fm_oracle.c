@@ -483,3 +483,99 @@ int64_t oracle_inexact(const oracle_index *x, const oracle_index *rev, const uin
     free(h.buf);
     return h.len;
 }
+
+/* ------------------------------------------------------------------ text-only checkers
+ * Two computations from the text alone, with no suffix array, BWT, Occ or C, for checks
+ * at sizes where the full index above is too large to build. */
+
+/* Rank scan over T = R$: *k = number of suffixes of T smaller than P and *occ = number of
+ * positions where P occurs in R. A suffix that reaches '$' while still equal to a prefix
+ * of P is smaller than P ('$' sorts first). The interval of P is (k, k + occ - 1). */
+void oracle_rank_scan(const uint8_t *R, int64_t n, const uint8_t *P, int64_t m, int64_t *k, int64_t *occ)
+{
+    int64_t less = 0, eq = 0;
+    for (int64_t j = 0; j <= n; j++) {
+        const int64_t avail = n - j;
+        const int64_t t = avail < m ? avail : m;
+        const int r = t ? memcmp(R + j, P, (size_t)t) : 0;
+        if (r < 0 || (r == 0 && avail < m)) less++;
+        else if (r == 0) eq++;
+    }
+    *k = less;
+    *occ = eq;
+}
+
+static int64_t hamming(const uint8_t *a, const uint8_t *b, int64_t m)
+{
+    int64_t d = 0;
+    for (int64_t i = 0; i < m; i++) d += a[i] != b[i];   /* code 4 never equals a text symbol */
+    return d;
+}
+
+static const uint8_t *win_R;
+static int64_t win_m;
+
+static int cmp_window(const void *pa, const void *pb)
+{
+    return memcmp(win_R + *(const int64_t *)pa, win_R + *(const int64_t *)pb, (size_t)win_m);
+}
+
+/* Substitution hit set of one strand pattern P (length m, budget z) by the pigeonhole
+ * principle: a window W' of R within Hamming distance z of P agrees with P exactly on at
+ * least one of z+1 disjoint pieces of P (pieces are empty when m < z+1, and an empty piece
+ * agrees everywhere). Every occurrence of a piece fixes a candidate
+ * window; candidates within distance z are kept, identical windows merged, and each
+ * distinct W' gets its interval from the rank scan. Writes up to cap (k, l, d) triples,
+ * sorted by k, and returns their number. */
+int64_t oracle_hits_pigeonhole(const uint8_t *R, int64_t n, const uint8_t *P, int64_t m, int z,
+                               uint32_t *out, int64_t cap)
+{
+    if (m == 0) {
+        if (cap > 0) {
+            out[0] = 0;
+            out[1] = (uint32_t)n;
+            out[2] = 0;
+        }
+        return 1;
+    }
+    const int parts = z + 1;
+    int64_t a[8], b[8];
+    for (int i = 0; i < parts; i++) {
+        a[i] = m * i / parts;
+        b[i] = m * (i + 1) / parts;
+    }
+    int64_t ncand = 0, ccap = 1024;
+    int64_t *cand = malloc(sizeof(int64_t) * (size_t)ccap);
+    for (int64_t p = 0; p < n; p++) {
+        for (int i = 0; i < parts; i++) {
+            const int64_t len = b[i] - a[i];
+            const int64_t s = p - a[i];
+            if (s < 0 || s + m > n) continue;
+            /* an empty piece (m < z + 1) agrees everywhere */
+            if (len > 0 && (R[p] != P[a[i]] || memcmp(R + p, P + a[i], (size_t)len) != 0)) continue;
+            if (hamming(R + s, P, m) > z) continue;
+            if (ncand == ccap) {
+                ccap *= 2;
+                cand = realloc(cand, sizeof(int64_t) * (size_t)ccap);
+            }
+            cand[ncand++] = s;
+        }
+    }
+    win_R = R;
+    win_m = m;
+    if (ncand) qsort(cand, (size_t)ncand, sizeof(int64_t), cmp_window);
+    int64_t nh = 0;
+    for (int64_t c = 0; c < ncand; c++) {
+        if (c > 0 && memcmp(R + cand[c - 1], R + cand[c], (size_t)m) == 0) continue;
+        int64_t k, occ;
+        oracle_rank_scan(R, n, R + cand[c], m, &k, &occ);
+        if (nh < cap) {
+            out[3 * nh] = (uint32_t)k;
+            out[3 * nh + 1] = (uint32_t)(k + occ - 1);
+            out[3 * nh + 2] = (uint32_t)hamming(R + cand[c], P, m);
+        }
+        nh++;
+    }
+    free(cand);
+    return nh;
+}

@@ -300,7 +300,7 @@ class Workload:
     z_mode: str          # "exact", "fixed", "mixed"
 
 
-def cfg1_small() -> Workload:
+def small_exact_workload() -> Workload:
     """65,536 i.i.d. bases; 10,000 length-32 queries, half copied from uniform text
     positions, half uniform random; exact search on the forward strand."""
     ref = iid_reference(65536, 1001)
@@ -313,31 +313,31 @@ def cfg1_small() -> Workload:
     offs = np.arange(2 * half + 1, dtype=np.uint64) * np.uint64(32)
     reads = Reads(codes, offs, np.zeros(2 * half, np.uint8),
                   np.concatenate([starts, np.full(half, -1)]), np.zeros(2 * half, np.uint8))
-    return Workload("cfg1", ref, reads, "fwd", "exact")
+    return Workload("small-exact", ref, reads, "fwd", "exact")
 
 
-def cfg2_reference(n: int = 1 << 24) -> np.ndarray:
+def repeats_2e24_reference(n: int = 1 << 24) -> np.ndarray:
     return reference_with_repeats(n, 1002, copy_frac=0.05, copy_len=(500, 5000), copy_sub=0.02)
 
 
-def cfg2_reads(ref: np.ndarray, count: int = 1_000_000) -> Reads:
+def reads_2e24(ref: np.ndarray, count: int = 1_000_000) -> Reads:
     return simulate_reads(ref, count, 2002, length=(100, 100), sub=(0.01, 0.01), z=(1, 1))
 
 
-def cfg3_reference(n: int = 1 << 28) -> np.ndarray:
+def repeats_2e28_reference(n: int = 1 << 28) -> np.ndarray:
     return reference_with_repeats(n, 1003, copy_frac=0.05, copy_len=(500, 5000), copy_sub=0.02,
                                   tandem_frac=0.01, tandem_unit=(2, 50), tandem_len=(100, 1000))
 
 
-def cfg3_reads(ref: np.ndarray, count: int = 4_000_000, seed: int = 2003) -> Reads:
+def mixed_reads_2e28(ref: np.ndarray, count: int = 4_000_000, seed: int = 2003) -> Reads:
     return simulate_reads(ref, count, seed, length=(50, 250), sub=(0.005, 0.03), z=(0, 2))
 
 
-def cfg4_reference(n: int = 3_100_000_000) -> np.ndarray:
+def genome_like_reference(n: int = 3_100_000_000) -> np.ndarray:
     return reference_families(n, 1004)
 
 
-def cfg4_reads(ref: np.ndarray, count: int = 16_000_000, seed: int = 2004) -> Reads:
+def genome_reads(ref: np.ndarray, count: int = 16_000_000, seed: int = 2004) -> Reads:
     return simulate_reads(ref, count, seed, length=(150, 150), sub=(0.01, 0.01), z=(2, 2))
 
 

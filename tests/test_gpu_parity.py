@@ -138,8 +138,8 @@ def test_exact_plain_and_batched(small, flags):
     idx.set_tuning(fm.FM_OP_EXACT, occ_interval=128, lanes=1, depth=1)
 
 
-def test_exact_cfg1_workload():
-    w = synth.cfg1_small()
+def test_exact_small_workload():
+    w = synth.small_exact_workload()
     x = oracle.OracleIndex(w.ref)
     want = x.exact(w.reads.codes, w.reads.offs, oracle.FWD, "definition")
     idx = fm.Index.from_text(w.ref, occ_interval=128)

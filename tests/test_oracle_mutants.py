@@ -35,6 +35,9 @@ MUTANTS = {
     "definition_dollar_high": ("if (s + j >= x->n) return -1;", "if (s + j >= x->n) return 1;"),
     "ball_budget_plus1": ("if (used == budget) return;", "if (used == budget + 1) return;"),
     "occ8_k_index": ("o[c] = occ_at(x, c, k - 1);", "o[c] = occ_at(x, c, k);"),
+    "rank_scan_prefix_not_smaller": ("if (r < 0 || (r == 0 && avail < m)) less++;", "if (r < 0) less++;"),
+    "pigeonhole_strict_budget": ("if (hamming(R + s, P, m) > z) continue;", "if (hamming(R + s, P, m) >= z) continue;"),
+    "pigeonhole_piece_offset": ("const int64_t s = p - a[i];", "const int64_t s = p;"),
 }
 
 
@@ -68,9 +71,17 @@ def battery(lib):
         for method in ("definition", "listing1"):
             got = [tuple(v) for v in x.exact(codes, offs, oracle.BOTH, method).tolist()]
             assert got == want
+        # the text-only checkers, on a pattern set that includes one running past the end
+        tail = [R[-2:].copy(), np.concatenate([R[-2:], [0]]).astype(np.uint8)]
+        c2, o2 = csr(pats + tail)
+        want2 = want + sum(([bf.interval(R, w), bf.interval(R, bf.revcomp(w))] for w in tail), [])
+        assert [tuple(v) for v in oracle.exact_by_rank_scan(R, c2, o2, oracle.BOTH, lib).tolist()] == want2
         z = np.array([rng.randint(0, 2) for _ in pats], np.uint8)
-        for method in ("definition", "listing2", "listing2_darray"):
-            hits, hoffs = x.inexact(codes, offs, z, oracle.BOTH, method, rev=xr)
+        for method in ("definition", "listing2", "listing2_darray", "pigeonhole"):
+            if method == "pigeonhole":
+                hits, hoffs = oracle.pigeonhole_hits(R, codes, offs, z, oracle.BOTH, lib)
+            else:
+                hits, hoffs = x.inexact(codes, offs, z, oracle.BOTH, method, rev=xr)
             for r, w in enumerate(pats):
                 seg = hits[int(hoffs[r]):int(hoffs[r + 1])]
                 got = sorted((int(h["strand"]), int(h["k"]), int(h["l"]), int(h["d"])) for h in seg)

@@ -301,3 +301,66 @@ def test_darray_zero_for_substrings_and_both_strands_layout():
     rc = np.array(bf.revcomp(w), np.uint8)
     c2, o2 = csr([rc, np.array(bf.revcomp(w[:10]), np.uint8)])
     assert np.array_equal(D[1], xr.darray(c2, o2, oracle.FWD)[0])
+
+
+# ------------------------------------------------------------------ text-only checkers
+
+def _text_with_repeats(seed, n):
+    rng = random.Random(seed)
+    base = [rng.randrange(4) for _ in range(n)]
+    for _ in range(n // 40):               # copies and short tandem runs, so intervals are wide
+        a = rng.randrange(n - 20)
+        b = rng.randrange(n - 20)
+        base[b:b + 12] = base[a:a + 12]
+    return np.array(base[:n], dtype=np.uint8)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_rank_scan_equals_sa_definition(seed):
+    """The text scan and the suffix-array binary search agree on every kind of pattern:
+    occurring, missing, with N, running past the text end, and empty."""
+    R = _text_with_repeats(seed, 3000)
+    x = OracleIndex(R)
+    rng = random.Random(seed)
+    pats = [np.zeros(0, np.uint8)]
+    for _ in range(150):
+        m = rng.randrange(1, 14)
+        p = rng.randrange(R.size - m)
+        pats.append(R[p:p + m].copy())                                  # occurs
+        pats.append(np.array([rng.randrange(4) for _ in range(m)], np.uint8))
+    pats.append(R[-5:].copy())                                          # a suffix of R
+    pats.append(np.concatenate([R[-5:], [0]]).astype(np.uint8))         # runs past the end
+    pats.append(np.array([0, 4, 1], np.uint8))                          # holds N
+    codes, offs = csr(pats)
+    want = x.exact(codes, offs, oracle.BOTH, "definition")
+    got = oracle.exact_by_rank_scan(R, codes, offs, oracle.BOTH)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("seed,z", [(4, 0), (5, 1), (6, 2), (7, 2)])
+def test_pigeonhole_equals_hamming_ball(seed, z):
+    """Hits from the pigeonhole windows and rank scans equal the Hamming-ball enumeration
+    over the suffix-array index (including reads with N and strand 1)."""
+    R = _text_with_repeats(seed, 2500)
+    x = OracleIndex(R)
+    rng = random.Random(seed)
+    reads = []
+    for i in range(40):
+        m = rng.randrange(6, 13)
+        p = rng.randrange(R.size - m)
+        w = R[p:p + m].copy()
+        for _ in range(rng.randrange(0, 3)):
+            w[rng.randrange(m)] = rng.randrange(4)
+        if i % 7 == 0:
+            w[rng.randrange(m)] = 4
+        if i % 3 == 0:
+            w = oracle.strand_pattern(w, 1)
+        reads.append(w)
+    codes, offs = csr(reads)
+    zz = np.full(len(reads), z, np.uint8)
+    wh, wo = x.inexact(codes, offs, zz, oracle.BOTH, "definition")
+    gh, go = oracle.pigeonhole_hits(R, codes, offs, zz, oracle.BOTH)
+    assert np.array_equal(go, wo)
+    for f in ("read", "k", "l", "strand", "d"):
+        assert np.array_equal(gh[f], wh[f]), f
+    assert wh.size > (len(reads) if z else len(reads) // 4)   # the check is not vacuous

@@ -33,8 +33,8 @@ def test_simulated_reads_come_from_the_text():
     assert set(np.unique(rd.z)) <= {0, 1, 2}
 
 
-def test_cfg1_workload():
-    w = synth.cfg1_small()
+def test_small_exact_workload():
+    w = synth.small_exact_workload()
     assert w.ref.size == 65536 and w.reads.count == 10_000
     assert np.all(np.diff(w.reads.offs.astype(np.int64)) == 32)
     p = int(w.reads.pos[3])
