@@ -127,6 +127,27 @@ struct Walker {
     uint64_t bp03;         // DBP: positions of failures 1..4 (16 bits each, 0xFFFF: none)
     uint32_t bp4;          // DBP: position of failure 5
     bool fin;              // finished; the result is stored by retire()
+    uint64_t wtag;         // 16-byte block of `codes` held in win, as its address / 16 (~0: none)
+    uint4 win;
+
+    // Loads the aligned 16-byte block that holds the next pattern symbol, unless win
+    // already holds it (a block serves up to 16 steps). The block lies in the same page
+    // as that symbol, so reading all of it cannot fault where it extends past the reads.
+    __device__ void fetch_code(const WalkArgs &a)
+    {
+        const uint8_t *p = a.codes + addr;
+        const uint64_t t = (uint64_t)(uintptr_t)p >> 4;
+        if (t != wtag) {
+            win = *(const uint4 *)(p - ((uintptr_t)p & 15u));
+            wtag = t;
+        }
+    }
+
+    __device__ uint32_t code(const WalkArgs &a) const
+    {
+        const uint32_t o = (uint32_t)((uintptr_t)(a.codes + addr) & 15u);
+        return (sel4(o >> 2, win.x, win.y, win.z, win.w) >> (8 * (o & 3))) & 0xFFu;
+    }
 
     __device__ void retire(const WalkArgs &a, bool lead_lane)
     {
@@ -181,6 +202,7 @@ struct Walker {
         cnt = 0;
         bp03 = ~0ull;
         bp4 = 0xFFFFu;
+        wtag = ~0ull;
         if (MODE == WALK_DBP) zr = hz < a.zmax ? hz : a.zmax;
         if (MODE == WALK_DFULL) outp = (a.nstr == 2 ? strand : 0u) * a.dstride + b0;
         fin = m == 0;
@@ -232,7 +254,8 @@ __global__ void __launch_bounds__(256) walk_plain(WalkArgs a)
     if (w.fin) w.retire(a, true);
     uint64_t steps = 0, bks = 0;
     while (w.rs != kEmpty) {
-        const uint32_t c = a.codes[w.addr];
+        w.fetch_code(a);
+        const uint32_t c = w.code(a);
         Pair<I, 1> pr;
         pr.load(a.lay, 0, w.k ? w.k : 1u, w.l);          // (0, n) needs no buckets; row 0's are harmless
         const uint32_t b = strand_sym(c, w.comp);
@@ -269,16 +292,21 @@ __global__ void __launch_bounds__(256) walk_batched(WalkArgs a)
     uint64_t steps = 0, bks = 0;
     for (;;) {
         // 1. the loads of every running slot
-        uint32_t c[P];
         Pair<I, L> pr[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const bool act = w[p].rs != kEmpty;
-            c[p] = act ? a.codes[w[p].addr] : 0u;
+            const bool act = w[p].rs != kEmpty && !w[p].fin;
+            if (act) w[p].fetch_code(a);
             pr[p].load(a.lay, q, act && w[p].k ? w[p].k : 1u, act ? w[p].l : 0u);
         }
-        // 2. idle slots take a read-strand and request its header, which arrives with the
-        //    round's bucket loads; it begins in step 3 and steps from the next round
+        // 2. results of the read-strands that finished last round: stored after this
+        //    round's loads, so waiting for those loads never waits for these stores, and
+        //    the stores are complete before their registers are written again
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            if (w[p].fin) w[p].retire(a, lead);
+        // 3. idle slots take a read-strand and request its header, which arrives with the
+        //    round's bucket loads; it begins in step 4 and steps from the next round
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             pending[p] = false;
@@ -291,8 +319,8 @@ __global__ void __launch_bounds__(256) walk_batched(WalkArgs a)
         bool any = false;
 #pragma unroll
         for (int p = 0; p < P; ++p) any |= w[p].rs != kEmpty;
-        if (!__any(any)) break;
-        // 3. steps of the running slots; pending ones begin
+        const bool quit = !__any(any);     // tested at the end of the round, after every load is read
+        // 4. steps of the running slots; pending ones begin
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             if (pending[p]) {
@@ -300,7 +328,7 @@ __global__ void __launch_bounds__(256) walk_batched(WalkArgs a)
                 continue;
             }
             if (w[p].rs == kEmpty) continue;
-            const uint32_t b = strand_sym(c[p], w[p].comp);
+            const uint32_t b = strand_sym(w[p].code(a), w[p].comp);
             uint32_t ok, ol;
             occ2<I, L>(a.lay, pr[p], q, b & 3, w[p].k ? w[p].k : 1u, w[p].l, ok, ol);
             if (lead && w[p].k && b < 4) {
@@ -311,17 +339,17 @@ __global__ void __launch_bounds__(256) walk_batched(WalkArgs a)
         }
         // The round's loads are issued and read under different conditions; reading
         // their registers here on every path lets the compiler retire them now rather
-        // than wait on every memory operation, stores included, where the registers are
-        // next written. Results are stored only after this point.
+        // than wait on every memory operation where the registers are next written.
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            asm volatile("" ::"v"(w[p].h0), "v"(w[p].h1), "v"(w[p].hz), "v"(c[p]));
+            asm volatile("" ::"v"(w[p].h0), "v"(w[p].h1), "v"(w[p].hz), "v"(w[p].win.x), "v"(w[p].win.y),
+                         "v"(w[p].win.z), "v"(w[p].win.w));
 #pragma unroll
             for (int t = 0; t < Bucket<I, L>::NPL; ++t)
                 asm volatile("" ::"v"(pr[p].a.v[t].x), "v"(pr[p].a.v[t].y), "v"(pr[p].a.v[t].z), "v"(pr[p].a.v[t].w),
                              "v"(pr[p].b.v[t].x), "v"(pr[p].b.v[t].y), "v"(pr[p].b.v[t].z), "v"(pr[p].b.v[t].w));
-            if (w[p].fin) w[p].retire(a, lead);
         }
+        if (quit) break;
     }
     wave_add(a.stat_steps, steps);
     wave_add(a.stat_bk, bks);
@@ -499,9 +527,27 @@ struct Dfs {
     // cannot lead to a hit (pos = -1: nothing is left to match, never pruned).
     __device__ bool dprune(uint32_t zc, int pos) const { return (int)bp_at(zc) <= pos; }
 
-    __device__ uint32_t sym(const DfsArgs &a, uint32_t pos) const
+    // 16-byte block of `codes` holding the pattern symbol in use (see Walker::fetch_code)
+    uint64_t wtag;
+    uint4 win;
+
+    __device__ const uint8_t *code_ptr(const DfsArgs &a) const { return a.codes + base + (strand ? m - 1 - i : i); }
+
+    __device__ void fetch_code(const DfsArgs &a)
     {
-        const uint32_t c = a.codes[base + (strand ? m - 1 - pos : pos)];
+        const uint8_t *p = code_ptr(a);
+        const uint64_t t = (uint64_t)(uintptr_t)p >> 4;
+        if (t != wtag) {
+            win = *(const uint4 *)(p - ((uintptr_t)p & 15u));
+            wtag = t;
+        }
+    }
+
+    // Pattern symbol i of the strand (complemented on strand 1).
+    __device__ uint32_t sym(const DfsArgs &a) const
+    {
+        const uint32_t o = (uint32_t)((uintptr_t)code_ptr(a) & 15u);
+        const uint32_t c = (sel4(o >> 2, win.x, win.y, win.z, win.w) >> (8 * (o & 3))) & 0xFFu;
         return strand_sym(c, strand);
     }
 
@@ -536,6 +582,7 @@ struct Dfs {
         l = a.lay.n;
         i = m - 1;
         zr = z0;
+        wtag = ~0ull;
         uint32_t nbp = 0;
         bp03 = ~0ull;
         bp4 = 0xFFFFu;
@@ -560,14 +607,13 @@ struct Dfs {
 // Loads of one expansion, issued before anything waits on them.
 template <int I, int L>
 struct NodeLoads {
-    uint32_t code;
     Pair<I, L> pr;
 };
 
 template <int I, int L>
-__device__ __forceinline__ void dfs_load(const DfsArgs &a, const Dfs &d, uint32_t q, NodeLoads<I, L> &nl)
+__device__ __forceinline__ void dfs_load(const DfsArgs &a, Dfs &d, uint32_t q, NodeLoads<I, L> &nl)
 {
-    nl.code = a.codes[d.base + (d.strand ? d.m - 1 - d.i : d.i)];
+    d.fetch_code(a);
     nl.pr.load(a.lay, q, d.k ? d.k : 1u, d.l);
 }
 
@@ -586,7 +632,7 @@ __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeL
                                            Frame *fr, bool lead, uint64_t &n_occ, uint64_t &n_bk)
 {
     const uint32_t kk = d.k ? d.k : 1u;
-    const uint32_t wi = strand_sym(nl.code, d.strand);
+    const uint32_t wi = d.sym(a);
     Occ4 o1, o2;
     occ8<I, L>(a.lay, nl.pr, q, kk, d.l, o1, o2);
     // children; at the root (0, n) Occ(., -1) is zero and Occ(., n) is every symbol's total
@@ -835,12 +881,15 @@ static hipError_t dfs_by_lanes(const fm_index *idx, const fm_tuning &t, const Df
 // Per read: the worst strand status, the number of hits to list (0 unless FM_OK), and
 // the number every read would need (FM_OK and FM_EOVERFLOW reads). Clears the
 // overflow cursors.
-__global__ void finalize_reads(uint32_t nreads, uint32_t nstr, const uint32_t *rs_count, const uint32_t *rs_status,
-                               uint32_t *rd_status, uint32_t *cnt, uint32_t *cursor, unsigned long long *required)
+// Grid-stride over reads; the required total is summed per block and added with one
+// atomic per block (one per wave contends on the single counter).
+__global__ void __launch_bounds__(256) finalize_reads(uint32_t nreads, uint32_t nstr, const uint32_t *rs_count,
+                                                      const uint32_t *rs_status, uint32_t *rd_status, uint32_t *cnt,
+                                                      uint32_t *cursor, unsigned long long *required)
 {
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ uint64_t part[4];
     uint64_t need = 0;
-    if (r < nreads) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nreads; r += gridDim.x * blockDim.x) {
         uint32_t st = 0, c = 0;
         for (uint32_t s = 0; s < nstr; ++s) {
             const uint32_t v = rs_status[r * nstr + s];
@@ -850,9 +899,15 @@ __global__ void finalize_reads(uint32_t nreads, uint32_t nstr, const uint32_t *r
         }
         rd_status[r] = st;
         cnt[r] = st == FM_OK ? c : 0u;
-        need = (st == FM_OK || st == FM_EOVERFLOW) ? c : 0u;
+        need += (st == FM_OK || st == FM_EOVERFLOW) ? c : 0u;
     }
-    wave_add(required, need);
+    for (int d = 32; d >= 1; d >>= 1) need += __shfl_xor(need, d);
+    if (__lane_id() == 0) part[threadIdx.x >> 6] = need;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint64_t t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd(required, (unsigned long long)t);
+    }
 }
 
 constexpr int kTile = 8;
@@ -1074,7 +1129,9 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     uint64_t *offs_tmp = (uint64_t *)(ws + W.offs);
     uint64_t *cut = (uint64_t *)(ws + kWsCut);
     const uint32_t nr = (uint32_t)c.nreads;
-    hipLaunchKernelGGL(finalize_reads, dim3((nr + 255) / 256), dim3(256), 0, s, nr, nstr, a.rs_count, a.rs_status,
+    uint32_t fgrid = (nr + 255) / 256;
+    if (fgrid > (uint32_t)idx->cu_count * 4) fgrid = (uint32_t)idx->cu_count * 4;
+    hipLaunchKernelGGL(finalize_reads, dim3(fgrid ? fgrid : 1), dim3(256), 0, s, nr, nstr, a.rs_count, a.rs_status,
                        rd_status, cnt, cursor, (unsigned long long *)(ws + kWsRequired));
     const uint64_t nblk = (c.nreads + kScanBlock * kTile - 1) / (kScanBlock * kTile);
     uint64_t *part = (uint64_t *)(ws + W.part);
