@@ -59,8 +59,10 @@ def parse():
     ap.add_argument("--reads", type=int, default=1_000_000)
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--occ8-queries", type=int, default=1 << 26)
-    ap.add_argument("--cpu-sample", type=int, default=100_000,
+    ap.add_argument("--cpu-sample", type=int, default=300_000,
                     help="reads the CPU oracle searches for the baseline (0 skips it)")
+    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
+                    help="host threads of the CPU baseline (the GPU box's share is 16 cores)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--serve-requests", type=int, default=2000,
@@ -246,7 +248,7 @@ def main():
     cpu = None
     parity = None
     if args.cpu_sample > 0:
-        cpu, parity = cpu_baseline(R, rd, min(args.cpu_sample, nreads), ex_batched, in_batched)
+        cpu, parity = cpu_baseline(R, rd, min(args.cpu_sample, nreads), ex_batched, in_batched, args.cpu_threads)
 
     serve = None
     if args.serve_requests > 0:
@@ -405,20 +407,38 @@ def serve_bench(args):
     return out
 
 
-def cpu_baseline(R, rd, sample, ex_batched, in_batched):
-    """The CPU oracle (Listing 1 exact + Listing 2 with the D bound, one thread) on the
-    first `sample` reads of the same batch; also checks the GPU's outputs for them."""
+def cpu_baseline(R, rd, sample, ex_batched, in_batched, threads):
+    """The CPU oracle (Listing 1 exact + Listing 2 with the D bound) on the first `sample`
+    reads of the same batch, split into equal parts searched by `threads` host threads
+    (the oracle's searches release the interpreter lock); also checks the GPU's outputs
+    for those reads."""
+    import concurrent.futures as cf
+
     import oracle
     t0 = time.time()
     x = oracle.OracleIndex(R)
     xr = oracle.OracleIndex(oracle.reverse_text(R))
     log("oracle indexes built in %.1fs" % (time.time() - t0))
     s = rd.subset(np.arange(sample))
+    bounds = np.linspace(0, sample, threads + 1).astype(np.int64)
+
+    def part(i):
+        p = s.subset(np.arange(bounds[i], bounds[i + 1]))
+        ex = x.exact(p.codes, p.offs, oracle.BOTH, "listing1")
+        h, o = x.inexact(p.codes, p.offs, p.z, oracle.BOTH, "listing2_darray", rev=xr)
+        h["read"] += np.uint32(bounds[i])
+        return ex, h, o
+
     t0 = time.time()
-    ex = x.exact(s.codes, s.offs, oracle.BOTH, "listing1")
-    hits, hoffs = x.inexact(s.codes, s.offs, s.z, oracle.BOTH, "listing2_darray", rev=xr)
+    with cf.ThreadPoolExecutor(max_workers=threads) as pool:
+        parts = list(pool.map(part, range(threads)))
     dt = time.time() - t0
-    log("oracle: %d reads in %.1fs" % (sample, dt))
+    log("oracle: %d reads in %.1fs on %d threads" % (sample, dt, threads))
+    ex = np.concatenate([p[0] for p in parts])
+    hits = np.concatenate([p[1] for p in parts])
+    hoffs = np.zeros(sample + 1, dtype=np.uint64)
+    for i, p in enumerate(parts):
+        hoffs[bounds[i] + 1:bounds[i + 1] + 1] = p[2][1:] + hoffs[bounds[i]]
     gex = ex_batched[:2 * sample].cpu().numpy().view(np.uint32)
     gh, go, gs = in_batched
     n = int(go[sample])
@@ -427,9 +447,9 @@ def cpu_baseline(R, rd, sample, ex_batched, in_batched):
     ok_in = bool(np.array_equal(go[:sample + 1], hoffs) and (gs[:sample] == 0).all()
                  and all(np.array_equal(g[f], hits[f]) for f in ("read", "k", "l", "strand"))
                  and np.array_equal(g["nmm"], hits["d"]))
-    cpu = {"value": round(sample / dt, 1), "unit": "reads/s", "cores": 1, "kind": "oracle",
+    cpu = {"value": round(sample / dt, 1), "unit": "reads/s", "cores": threads, "kind": "oracle",
            "sample": "first %d of the step's reads; exact (Listing 1) + z=1 inexact (Listing 2, D bound), "
-                     "both strands, single-threaded, index prebuilt" % sample}
+                     "both strands, %d host threads, index prebuilt" % (sample, threads)}
     parity = {"reads": sample, "exact_bit_exact": ok_ex, "inexact_bit_exact": ok_in}
     return cpu, parity
 

@@ -212,10 +212,11 @@ struct Walker {
     // Occ(b, k-1), Occ(b, l), unused while the interval is still (0, n).
     __device__ void step(const WalkArgs &a, uint32_t b, uint32_t ok, uint32_t ol, bool lead_lane)
     {
+        // From the root (0, n), Occ(b, -1) is zero and Occ(b, n) is read from the layout
+        // like any other value (ol was computed at l = n), which gives C[b+1].
         const uint32_t cb = c_of(a.lay, b & 3);
-        const uint32_t c1 = sel4(b & 3, a.lay.C[1], a.lay.C[2], a.lay.C[3], a.lay.C[4]);
-        uint32_t nk = k ? cb + ok + 1 : cb + 1;          // from (0, n) the step is C alone
-        uint32_t nl = k ? cb + ol : c1;
+        uint32_t nk = cb + (k ? ok : 0u) + 1;
+        uint32_t nl = cb + ol;
         if (b > 3) {                                     // a non-base occurs nowhere
             nk = 1;
             nl = 0;
@@ -257,11 +258,11 @@ __global__ void __launch_bounds__(256) walk_plain(WalkArgs a)
         w.fetch_code(a);
         const uint32_t c = w.code(a);
         Pair<I, 1> pr;
-        pr.load(a.lay, 0, w.k ? w.k : 1u, w.l);          // (0, n) needs no buckets; row 0's are harmless
+        pr.load(a.lay, 0, w.k ? w.k : 1u, w.l);          // at the root only the bucket of l = n is used
         const uint32_t b = strand_sym(c, w.comp);
         uint32_t ok, ol;
         occ2<I, 1>(a.lay, pr, 0, b & 3, w.k ? w.k : 1u, w.l, ok, ol);
-        if (w.k && b < 4) {
+        if (a.stat_steps && w.k && b < 4) {
             ++steps;
             bks += pr.same ? 1 : 2;
         }
@@ -331,7 +332,7 @@ __global__ void __launch_bounds__(256) walk_batched(WalkArgs a)
             const uint32_t b = strand_sym(w[p].code(a), w[p].comp);
             uint32_t ok, ol;
             occ2<I, L>(a.lay, pr[p], q, b & 3, w[p].k ? w[p].k : 1u, w[p].l, ok, ol);
-            if (lead && w[p].k && b < 4) {
+            if (a.stat_steps && lead && w[p].k && b < 4) {
                 ++steps;
                 bks += pr[p].same ? 1 : 2;
             }
@@ -604,17 +605,25 @@ struct Dfs {
     }
 };
 
-// Loads of one expansion, issued before anything waits on them.
+// Loads of one expansion, issued before anything waits on them: the symbol, the buckets
+// and the frame on top of the stack, which is the one a pop takes (a node pops only
+// when it pushes nothing).
 template <int I, int L>
 struct NodeLoads {
     Pair<I, L> pr;
+    uint4 tk, tl;
+    uint32_t tmeta;
 };
 
 template <int I, int L>
-__device__ __forceinline__ void dfs_load(const DfsArgs &a, Dfs &d, uint32_t q, NodeLoads<I, L> &nl)
+__device__ __forceinline__ void dfs_load(const DfsArgs &a, Dfs &d, uint32_t q, const Frame *fr, NodeLoads<I, L> &nl)
 {
     d.fetch_code(a);
     nl.pr.load(a.lay, q, d.k ? d.k : 1u, d.l);
+    const Frame *ft = fr + (d.sp ? d.sp - 1 : a.fcap - 1);
+    nl.tk = ft->k;
+    nl.tl = ft->l;
+    nl.tmeta = ft->meta.x;
 }
 
 // Expands the current node: one Occ8 at (k-1, l) gives the intervals of all four
@@ -647,7 +656,7 @@ __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeL
     lb[1] = C1 + o2.c;
     lb[2] = C2 + o2.g;
     lb[3] = C3 + o2.t;
-    if (lead) {
+    if (a.stat_occ && lead) {
         n_occ += 1;
         n_bk += root ? 0 : (nl.pr.same ? 1 : 2);
     }
@@ -689,8 +698,8 @@ __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeL
     // one, then the match child, which retires the frame
     const bool pop = !advance && nsp > 0;
     Frame *ft = fr + (pop ? nsp - 1 : spare);
-    const uint4 tk = ft->k, tl = ft->l;
-    const uint32_t meta = ft->meta.x;
+    const uint4 tk = nl.tk, tl = nl.tl;
+    const uint32_t meta = nl.tmeta;
     const uint32_t trest = (meta >> 24) & 0xFu, twi = (meta >> 20) & 0xFu;
     const uint32_t tmm = trest & ~(twi < 4 ? 1u << twi : 0u);
     const uint32_t bt = (uint32_t)__builtin_ctz((tmm ? tmm : trest) | 0x10u) & 3u;
@@ -795,7 +804,7 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
         if (!__any(active)) break;
         if (active && !d.done) {
             NodeLoads<I, 1> nl;
-            dfs_load<I, 1>(a, d, 0, nl);
+            dfs_load<I, 1>(a, d, 0, fr, nl);
             dfs_expand<I, 1>(a, d, nl, 0, fr, true, n_occ, n_bk);
         }
         dfs_emit<1>(a, d, active, true);
@@ -831,7 +840,7 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
         }
         if (running) {
             NodeLoads<I, L> nl;
-            dfs_load<I, L>(a, d, q, nl);
+            dfs_load<I, L>(a, d, q, fr, nl);
             dfs_expand<I, L>(a, d, nl, q, fr, lead, n_occ, n_bk);
         }
         if (fresh) d.begin(a);
