@@ -203,21 +203,23 @@ def main():
             np.array_equal(a, b) for a, b in zip(in_plain, in_batched))
         log("plain: %.3f ms/step, identical to batched: %s" % (plain_ms, plain_equal))
 
-    # Occ8 micro-benchmark: independent uniform (k, l) pairs
-    occ8_rate = None
+    # Occ8 micro-benchmark: independent uniform (k, l) pairs (two buckets each) and narrow
+    # ones, l uniform and k = l + 1 - w with w in [0, 8] (mostly one bucket)
+    occ8_rate = {}
     if args.occ8_queries:
-        q = torch.from_numpy(synth.occ8_queries(R.size, args.occ8_queries, 4242, "uniform").view(np.int32)).to(dev)
-        qo = torch.empty((args.occ8_queries, 8), dtype=torch.int32, device=dev)
-        fm.fm_occ8(idx, q, out=qo)
-        torch.cuda.synchronize()
-        q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        q0.record()
-        for _ in range(3):
+        for kind in ("uniform", "narrow"):
+            q = torch.from_numpy(synth.occ8_queries(R.size, args.occ8_queries, 4242, kind).view(np.int32)).to(dev)
+            qo = torch.empty((args.occ8_queries, 8), dtype=torch.int32, device=dev)
             fm.fm_occ8(idx, q, out=qo)
-        q1.record()
-        torch.cuda.synchronize()
-        occ8_rate = args.occ8_queries / (q0.elapsed_time(q1) / 3 / 1e3)
-        del q, qo
+            torch.cuda.synchronize()
+            q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            q0.record()
+            for _ in range(3):
+                fm.fm_occ8(idx, q, out=qo)
+            q1.record()
+            torch.cuda.synchronize()
+            occ8_rate[kind] = args.occ8_queries / (q0.elapsed_time(q1) / 3 / 1e3)
+            del q, qo
 
     # roofline of the dominant kernel: algorithmic bytes per launch / its event-timed duration
     I = tuning["inexact"]["config"]["occ_interval"]
@@ -281,7 +283,7 @@ def main():
         "batched_equals_plain": plain_equal,
         "graph_ms_per_step": round(graph_ms, 4),
         "graph_equals_eager": graph_equal,
-        "occ8_queries_per_s": {"fm_occ8_uniform": round(occ8_rate, 1) if occ8_rate else None,
+        "occ8_queries_per_s": {**{"fm_occ8_" + k: round(v, 1) for k, v in occ8_rate.items()},
                                "dfs_in_step": round(in_stats["occ8"] / (phase_ms["dfs"] / 1e3), 1)},
         "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
         "work_per_step": {"exact_steps": ex_stats["steps"], "exact_buckets": ex_stats["buckets"],
@@ -335,59 +337,60 @@ def serve_bench(args):
         lo, hi = int(pool.offs[s0]), int(pool.offs[s0 + n])
         reqs.append((pool.codes[lo:hi], pool.offs[s0:s0 + n + 1] - np.uint64(lo), pool.z[s0:s0 + n]))
     log("serving requests drawn in %.1fs: %d requests, %d reads" % (time.time() - t0, nreq, int(sizes.sum())))
+    mixed = mixed_batch(idx, pool)
     opts = dict(lanes=args.serve_lanes, flags=fm.FM_BOTH | fm.FM_DARRAY, zmax=2, hit_reserve=4,
-                arena_bytes=2 << 30)
+                arena_bytes=2 << 30, ring_bytes=1 << 30)
     mean_size = float(sizes.mean())
 
+    srv = fm.Server(idx, **opts)
     # capacity: the first requests all queued at once
-    with fm.Server(idx, **opts) as srv:
-        warm = [srv.submit(*r) for r in reqs[:20]]
-        for t in warm:
-            srv.wait(t)
-            srv.release(t)
-        m = min(200, nreq)
-        c0 = srv.clock()
-        tick = [srv.submit(*r) for r in reqs[:m]]
-        last = 0.0
-        for t in tick:
-            last = max(last, srv.wait(t).t_done)
-            srv.release(t)
-        capacity = float(sizes[:m].sum()) / (last - c0)
+    warm = [srv.submit(*r) for r in reqs[:20]]
+    for t in warm:
+        srv.wait(t)
+        srv.release(t)
+    m = min(200, nreq)
+    c0 = srv.clock()
+    tick = [srv.submit(*r) for r in reqs[:m]]
+    last = 0.0
+    for t in tick:
+        last = max(last, srv.wait(t).t_done)
+        srv.release(t)
+    capacity = float(sizes[:m].sum()) / (last - c0)
     rate = args.serve_load * capacity / mean_size            # requests per second
     log("serving capacity %.3g reads/s; arrival rate %.1f requests/s" % (capacity, rate))
 
     arrivals = np.cumsum(gaps / rate)
     results = [None] * nreq
-    with fm.Server(idx, **opts) as srv:
-        tickets = [None] * nreq
-        ready = threading.Semaphore(0)
+    tickets = [None] * nreq
+    ready = threading.Semaphore(0)
 
-        def producer():
-            base = time.perf_counter()
-            for i, r in enumerate(reqs):
-                d = base + arrivals[i] - time.perf_counter()
-                if d > 0:
-                    time.sleep(d)
-                tickets[i] = srv.submit(*r)
-                ready.release()
+    def producer():
+        base = time.perf_counter()
+        for i, r in enumerate(reqs):
+            d = base + arrivals[i] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tickets[i] = srv.submit(*r)
+            ready.release()
 
-        th = threading.Thread(target=producer)
-        th.start()
-        for i in range(nreq):
-            ready.acquire()
-            results[i] = srv.wait(tickets[i])
-            srv.release(tickets[i])
-        th.join()
-        st = srv.stats()
-        # a few requests again, alone: their results must not depend on the batch
-        same = True
-        for i in range(0, nreq, max(1, nreq // 8)):
-            t = srv.submit(*reqs[i])
-            a = srv.wait(t)
-            srv.release(t)
-            b = results[i]
-            same &= bool(np.array_equal(a.status, b.status) and np.array_equal(a.hit_offs, b.hit_offs)
-                         and a.hits.tobytes() == b.hits.tobytes())
+    th = threading.Thread(target=producer)
+    th.start()
+    for i in range(nreq):
+        ready.acquire()
+        results[i] = srv.wait(tickets[i])
+        srv.release(tickets[i])
+    th.join()
+    st = srv.stats()
+    # a few requests again, alone: their results must not depend on the batch
+    same = True
+    for i in range(0, nreq, max(1, nreq // 8)):
+        t = srv.submit(*reqs[i])
+        a = srv.wait(t)
+        srv.release(t)
+        b = results[i]
+        same &= bool(np.array_equal(a.status, b.status) and np.array_equal(a.hit_offs, b.hit_offs)
+                     and a.hits.tobytes() == b.hits.tobytes())
+    srv.close()
     idx.free()
     lat = np.array([r.latency for r in results]) * 1e3
     t_first = min(r.t_submit for r in results)
@@ -402,8 +405,44 @@ def serve_bench(args):
            "capacity_reads_per_s": round(capacity, 1), "reads_per_s": round(reads / (t_last - t_first), 1),
            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
            "mean_ms": round(float(lat.mean()), 3), "requests_per_batch": round(per_batch, 2),
-           "retries": st["retries"], "all_ok": ok, "alone_equals_mixed": same}
+           "retries": st["retries"], "all_ok": ok, "alone_equals_mixed": same, "mixed_batch": mixed}
     log("serving:", out)
+    return out
+
+
+def mixed_batch(idx, pool):
+    """The whole read pool (budgets 0-2, lengths 50-250) in one persistent launch of the
+    inexact search, both strands with the D bound, against the plain kernels."""
+    import torch
+
+    from paper_1811_06127_amd import fm
+
+    n = pool.count
+    codes, offs, z = fm.reads_to_device(pool.codes, pool.offs, pool.z)
+    flags = fm.FM_BOTH | fm.FM_DARRAY
+    cap = 6 * n
+    bufs = fm.InexactBuffers(idx, n, int(pool.offs[-1]), flags | fm.FM_PLAIN, 2, cap, "cuda")
+
+    def timed(extra, reps):
+        fm.fm_search_inexact(idx, codes, offs, z, flags | extra, 2, cap, bufs=bufs)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            fm.fm_search_inexact(idx, codes, offs, z, flags | extra, 2, cap, bufs=bufs)
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / reps, fm.hits_to_numpy(bufs, n)
+
+    ms, hb = timed(0, 3)
+    pms, hp = timed(fm.FM_PLAIN, 1)
+    out = {"reads": n, "total_bases": int(pool.offs[-1]), "ms": round(ms, 3), "reads_per_s": round(n / ms * 1e3, 1),
+           "plain_reads_per_s": round(n / pms * 1e3, 1), "batched_equals_plain": all(
+               np.array_equal(a, b) for a, b in zip(hb, hp)), "hits": int(hb[1][-1]),
+           "tuning": idx.get_tuning(fm.FM_OP_INEXACT)}
+    log("mixed-budget batch on the 2^28 index:", out)
+    del bufs, codes, offs, z
+    torch.cuda.empty_cache()
     return out
 
 

@@ -310,6 +310,8 @@ typedef struct {
     uint64_t arena_bytes;           /* device memory for batches in flight (split evenly
                                        among lanes; the same again is pinned on the host) */
     uint64_t max_batch_reads;       /* reads per batch; 0 = only memory limits a batch */
+    uint64_t ring_bytes;            /* pinned host ring holding the symbols of queued requests
+                                       until their upload; 0 = arena_bytes */
 } fm_server_opts;
 
 typedef struct {
@@ -341,8 +343,9 @@ int fm_server_create(const fm_index *idx, const fm_server_opts *opts, fm_server 
 
 /* Queues a request: codes (host) with nreads+1 nondecreasing offsets (host, codes of
  * read r at offs[r] .. offs[r+1]) and nreads budgets z (host). The data are copied
- * before the call returns. *ticket names the request. FM_ERANGE if the request alone
- * does not fit a lane. Thread-safe. */
+ * before the call returns (the symbols into the server's pinned ring, waiting while
+ * the ring is full of requests not yet uploaded). *ticket names the request.
+ * FM_ERANGE if the request alone does not fit a lane or the ring. Thread-safe. */
 int fm_server_submit(fm_server *s, const uint8_t *codes, const uint64_t *offs, const uint8_t *z,
                      uint64_t nreads, uint64_t *ticket);
 

@@ -1,16 +1,18 @@
 // server.cpp -- a request server over the inexact search with continuous batching.
 //
-// Requests (reads with per-read budgets) are queued in arrival order. A worker thread
-// keeps up to `lanes` batches in flight, each on a stream of its own with a fixed
-// share of a device arena: whenever a lane is idle it admits queued requests, oldest
-// first, while the batch still fits the lane's memory (and the read cap), uploads
-// them in one copy, runs the search and brings back status and hit offsets, then the
-// hits. Requests that arrive while batches run join the next batch of whichever lane
+// Requests (reads with per-read budgets) are queued in arrival order; their symbols are
+// copied once, at submission, into a ring of pinned host memory. A worker thread keeps
+// up to `lanes` batches in flight, each on a stream of its own with a fixed share of a
+// device arena: whenever a lane is idle it admits queued requests, oldest first, while
+// the batch still fits the lane's memory (and the read cap), uploads their symbols
+// straight from the ring and their offsets and budgets from the lane's pinned mirror,
+// runs the search and brings back status and hit offsets, then the hits. Requests that arrive while batches run join the next batch of whichever lane
 // frees up first, so their work overlaps with the batches already on the device.
 // Every read is searched independently of its batch, so a request's result does not
 // depend on what it was batched with.
 #include "fm_internal.hpp"
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -60,7 +62,8 @@ uint64_t reserve_of(const fm_server_opts &o, uint64_t n) { return (uint64_t)o.hi
 
 struct Req {
     uint64_t ticket = 0;
-    std::vector<uint8_t> codes;
+    uint64_t rv = 0, len = 0;       // symbols: ring bytes [rv, rv + len) (positions grow without wrapping)
+    bool ring_free = false;         // the symbols have been uploaded; their ring space may be reused
     std::vector<uint64_t> offs;     // request-local, offs[0] = 0
     std::vector<uint8_t> z;
     uint64_t nreads = 0;
@@ -96,7 +99,12 @@ struct fm_server {
     fm_server_opts o{};
     std::vector<Lane> lanes;
     std::mutex mu;
-    std::condition_variable cv_submit, cv_done;
+    std::condition_variable cv_submit, cv_done, cv_space;
+    // pinned ring for the symbols of queued and in-flight requests: [ring_tail, ring_head)
+    // of a position space that only grows; a position p lives at ring[p % ring_bytes]
+    uint8_t *ring = nullptr;
+    uint64_t ring_bytes = 0, ring_head = 0, ring_tail = 0;
+    std::deque<std::shared_ptr<Req>> ring_order;   // requests holding ring space, oldest first
     std::deque<std::shared_ptr<Req>> pending;
     std::unordered_map<uint64_t, std::shared_ptr<Req>> table;
     uint64_t next_ticket = 1, batches = 0, retries = 0, reads_done = 0, requests_done = 0;
@@ -110,10 +118,21 @@ struct fm_server {
 
 namespace {
 
+// Returns the ring space of the batch's requests (caller holds s->mu): space is reused
+// oldest first, so the tail moves past every request released so far in order.
+void release_ring(fm_server *s, Lane &ln)
+{
+    for (auto &r : ln.reqs) r->ring_free = true;
+    while (!s->ring_order.empty() && s->ring_order.front()->ring_free) s->ring_order.pop_front();
+    s->ring_tail = s->ring_order.empty() ? s->ring_head : s->ring_order.front()->rv;
+    s->cv_space.notify_all();
+}
+
 // Ends every request of the lane's batch with `err` (device failure).
 void fail_batch(fm_server *s, Lane &ln, int err)
 {
     std::lock_guard<std::mutex> lk(s->mu);
+    release_ring(s, ln);
     const double t = s->now();
     for (auto &r : ln.reqs) {
         r->error = err;
@@ -157,7 +176,7 @@ bool admit(fm_server *s, Lane &ln)
         std::lock_guard<std::mutex> lk(s->mu);
         while (!s->pending.empty()) {
             const auto &r = s->pending.front();
-            const uint64_t n2 = n + r->nreads, len2 = len + r->codes.size();
+            const uint64_t n2 = n + r->nreads, len2 = len + r->len;
             if (!take.empty()) {
                 if (s->o.max_batch_reads && n2 > s->o.max_batch_reads) break;
                 if (batch_layout(s->o, n2, len2, reserve_of(s->o, n2)).end > ln.bytes) break;
@@ -175,24 +194,46 @@ bool admit(fm_server *s, Lane &ln)
     ln.total_len = len;
     ln.big = false;
     ln.lay = batch_layout(s->o, n, len, reserve_of(s->o, n));
-    // pack the inputs into the pinned mirror, in the device layout
+    // offsets and budgets go through the pinned mirror, in the device layout; the symbols
+    // are uploaded straight from the ring, one copy per run of adjacent requests
     uint8_t *h = ln.host;
     uint64_t *offs = (uint64_t *)(h + ln.lay.offs);
     uint64_t rbase = 0, cbase = 0;
     offs[0] = 0;
+    int e = FM_OK;
+    uint64_t run_src = 0, run_dst = 0, run_len = 0;
+    auto flush = [&]() {
+        if (run_len && e == FM_OK)
+            e = hip_err(hipMemcpyAsync(ln.dev + ln.lay.codes + run_dst, s->ring + run_src, run_len,
+                                       hipMemcpyHostToDevice, ln.stream));
+        run_len = 0;
+    };
     for (auto &r : ln.reqs) {
-        if (!r->codes.empty()) std::memcpy(h + ln.lay.codes + cbase, r->codes.data(), r->codes.size());
         if (r->nreads) std::memcpy(h + ln.lay.z + rbase, r->z.data(), r->nreads);
         for (uint64_t i = 1; i <= r->nreads; ++i) offs[rbase + i] = cbase + r->offs[i];
+        if (r->len) {
+            const uint64_t src = r->rv % s->ring_bytes;
+            if (run_len && run_src + run_len == src) {
+                run_len += r->len;
+            } else {
+                flush();
+                run_src = src;
+                run_dst = cbase;
+                run_len = r->len;
+            }
+        }
         rbase += r->nreads;
-        cbase += r->codes.size();
+        cbase += r->len;
     }
+    flush();
     const double t = s->now();
     for (auto &r : ln.reqs) {
         r->t_launch = t;
         r->batch = ln.batch;
     }
-    int e = hip_err(hipMemcpyAsync(ln.dev, ln.host, ln.lay.status, hipMemcpyHostToDevice, ln.stream));
+    if (e == FM_OK)
+        e = hip_err(hipMemcpyAsync(ln.dev + ln.lay.offs, h + ln.lay.offs, ln.lay.status - ln.lay.offs,
+                                   hipMemcpyHostToDevice, ln.stream));
     if (e == FM_OK) e = enqueue_search(s, ln);
     if (e != FM_OK) {
         fail_batch(s, ln, e);
@@ -261,6 +302,11 @@ bool advance(fm_server *s, Lane &ln)
     if (ln.stage == 2) {
         distribute(s, ln);
         return true;
+    }
+    {
+        // the uploads of this batch are complete: its ring space may be reused
+        std::lock_guard<std::mutex> lk(s->mu);
+        release_ring(s, ln);
     }
     const uint8_t *h = ln.h();
     const uint64_t required = *(const uint64_t *)(h + ln.lay.ws + fm::kWsRequired);
@@ -337,6 +383,25 @@ void free_lanes(fm_server *s)
         if (ln.xhost) (void)hipHostFree(ln.xhost);
     }
     s->lanes.clear();
+    if (s->ring) (void)hipHostFree(s->ring);
+    s->ring = nullptr;
+}
+
+// Writes every page of freshly pinned host memory once, on several threads: the first
+// write to each page is a fault that runs about ten times slower than the copies that
+// follow, and those copies are on the submission path.
+void prefault(uint8_t *p, size_t bytes)
+{
+    const unsigned nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+    const size_t part = (bytes / nt + 4095) & ~(size_t)4095;
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t) {
+        const size_t a = (size_t)t * part;
+        if (a >= bytes) break;
+        const size_t len = std::min(part, bytes - a);
+        th.emplace_back([p, a, len] { std::memset(p + a, 0, len); });
+    }
+    for (auto &x : th) x.join();
 }
 
 bool valid_opts(const fm_server_opts *o)
@@ -377,6 +442,8 @@ int fm_server_create(const fm_index *idx, const fm_server_opts *opts, fm_server 
         e = FM_ENOMEM;
     }
     const size_t per = (size_t)(opts->arena_bytes / opts->lanes) & ~(size_t)255;
+    s->ring_bytes = opts->ring_bytes ? opts->ring_bytes : opts->arena_bytes;
+    if (hipHostMalloc((void **)&s->ring, s->ring_bytes, hipHostMallocDefault) != hipSuccess) e = FM_ENOMEM;
     for (auto &ln : s->lanes) {
         if (e != FM_OK) break;
         ln.bytes = per;
@@ -394,6 +461,8 @@ int fm_server_create(const fm_index *idx, const fm_server_opts *opts, fm_server 
         return e;
     }
     try {
+        prefault(s->ring, s->ring_bytes);
+        for (auto &ln : s->lanes) prefault(ln.host, ln.bytes);
         s->worker = std::thread(run, s);
     } catch (...) {
         free_lanes(s);
@@ -408,15 +477,16 @@ int fm_server_submit(fm_server *s, const uint8_t *codes, const uint64_t *offs, c
                      uint64_t *ticket)
 {
     if (!s || !ticket || !offs || (nreads && !z)) return FM_EINVAL;
+    const double t_call = s->now();                // latency counts any wait for ring space
     const uint64_t base = offs[0], len = offs[nreads] - base;
     if (offs[nreads] < base || (len && !codes)) return FM_EINVAL;
     for (uint64_t i = 0; i < nreads; ++i)
         if (offs[i + 1] < offs[i]) return FM_EINVAL;
     if (nreads * strands_of(s->o.flags) >= 0xFFFFFFFFull) return FM_ERANGE;
     if (batch_layout(s->o, nreads, len, reserve_of(s->o, nreads)).end > s->lanes[0].bytes) return FM_ERANGE;
+    if (len > s->ring_bytes) return FM_ERANGE;
     auto r = std::make_shared<Req>();
     try {
-        r->codes.assign(codes + base, codes + base + len);
         r->offs.resize(nreads + 1);
         for (uint64_t i = 0; i <= nreads; ++i) r->offs[i] = offs[i] - base;
         r->z.assign(z, z + nreads);
@@ -424,10 +494,31 @@ int fm_server_submit(fm_server *s, const uint8_t *codes, const uint64_t *offs, c
         return FM_ENOMEM;
     }
     r->nreads = nreads;
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) return FM_EINVAL;
+    r->len = len;
+    std::unique_lock<std::mutex> lk(s->mu);
+    // reserve ring space (a request is never split across the end of the ring), waiting
+    // for older requests' uploads when the ring is full
+    for (;;) {
+        if (s->stop) return FM_EINVAL;
+        if (s->ring_order.empty()) {                 // empty ring: restart at its beginning
+            s->ring_head = s->ring_tail = (s->ring_head + s->ring_bytes - 1) / s->ring_bytes * s->ring_bytes;
+        }
+        uint64_t start = s->ring_head;
+        const uint64_t phys = start % s->ring_bytes;
+        if (len && phys + len > s->ring_bytes) start += s->ring_bytes - phys;
+        if (start + len - s->ring_tail <= s->ring_bytes) {
+            r->rv = start;
+            s->ring_head = start + len;
+            break;
+        }
+        s->cv_space.wait(lk);
+    }
+    s->ring_order.push_back(r);
+    lk.unlock();
+    if (len) std::memcpy(s->ring + r->rv % s->ring_bytes, codes + base, len);
+    lk.lock();
     r->ticket = s->next_ticket++;
-    r->t_submit = s->now();
+    r->t_submit = t_call;
     s->table[r->ticket] = r;
     s->pending.push_back(r);
     *ticket = r->ticket;
@@ -493,6 +584,7 @@ void fm_server_free(fm_server *s)
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
         s->cv_submit.notify_all();
+        s->cv_space.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
     int prev = -1;

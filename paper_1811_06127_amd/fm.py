@@ -56,7 +56,7 @@ class Tuning(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("lanes", C.c_uint32), ("flags", C.c_uint32), ("zmax", C.c_uint32), ("hit_reserve", C.c_uint32),
-                ("arena_bytes", C.c_uint64), ("max_batch_reads", C.c_uint64)]
+                ("arena_bytes", C.c_uint64), ("max_batch_reads", C.c_uint64), ("ring_bytes", C.c_uint64)]
 
 
 class ServerResult(C.Structure):
@@ -443,8 +443,8 @@ def reads_to_device(codes: np.ndarray, offs: np.ndarray, z: np.ndarray | None = 
 # ---------------------------------------------------------------- serving
 
 def server_opts(lanes: int = 2, flags: int = FM_BOTH | FM_DARRAY, zmax: int = 2, hit_reserve: int = 4,
-                arena_bytes: int = 1 << 30, max_batch_reads: int = 0) -> ServerOpts:
-    return ServerOpts(lanes, flags, zmax, hit_reserve, arena_bytes, max_batch_reads)
+                arena_bytes: int = 1 << 30, max_batch_reads: int = 0, ring_bytes: int = 0) -> ServerOpts:
+    return ServerOpts(lanes, flags, zmax, hit_reserve, arena_bytes, max_batch_reads, ring_bytes)
 
 
 def fm_server_bytes(opts: ServerOpts, nreads: int, total_len: int) -> int:

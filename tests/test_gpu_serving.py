@@ -132,3 +132,17 @@ def test_hit_overflow_retry_and_limits(setup):
         t = s.submit(np.zeros(0, np.uint8), np.zeros(1, np.uint64), np.zeros(0, np.uint8))
         r = s.wait(t, timeout=30.0)
         assert r is not None and r.hits.size == 0 and r.hit_offs.tolist() == [0]
+
+
+def test_small_ring_backpressure(setup):
+    """A ring that holds about two requests' symbols: submissions wait for uploads, and
+    every result still equals the request served alone."""
+    R, idx, reqs = setup
+    sub = reqs[:16]
+    base, _ = serve_alone(idx, sub, lanes=2, flags=FLAGS, zmax=2, arena_bytes=256 << 20)
+    biggest = max(int(r.reads.offs[-1]) for r in sub)
+    got, st = serve_mixed(idx, sub, lanes=2, flags=FLAGS, zmax=2, arena_bytes=256 << 20, ring_bytes=2 * biggest + 64)
+    assert st["requests_done"] == len(sub) and st["error"] == 0
+    for a, b in zip(base, got):
+        assert same(a, b)
+        assert b.t_submit <= b.t_launch <= b.t_done
