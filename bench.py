@@ -135,39 +135,58 @@ def main():
         tuning[name] = {"config": idx.get_tuning(op), "ms": tuning[name][1]}
 
     def step(extra=0):
+        # both searches in one pass: the exact searches ride in the DFS launch
+        fm.fm_search_both(idx, codes, offs, z, EXACT, INEXACT | extra, ZMAX, hit_cap, out=ex_out, bufs=bufs)
+
+    def separate(extra=0):
         fm.fm_search_exact(idx, codes, offs, EXACT | extra, out=ex_out, ws=ex_ws)
         fm.fm_search_inexact(idx, codes, offs, z, INEXACT | extra, ZMAX, hit_cap, bufs=bufs)
 
+    def timed(f, steps, calls_per_step):
+        idx.phase_timing(calls_per_step * steps)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(steps):
+            f()
+        t1.record()
+        torch.cuda.synchronize()
+        ph, calls = idx.phase_times()
+        idx.phase_timing(0)
+        assert calls == calls_per_step * steps, calls
+        return t0.elapsed_time(t1) / steps, {k: v / steps for k, v in ph.items()}
+
     # work counters of one step (untimed)
-    step(fm.FM_STATS)
+    separate(fm.FM_STATS)
     torch.cuda.synchronize()
     ex_stats = fm.exact_stats(ex_ws)
     in_stats = bufs.stats()
-    log("stats:", ex_stats, in_stats)
+    step(fm.FM_STATS)
+    torch.cuda.synchronize()
+    ex_stats_both = fm.both_exact_stats(bufs)      # on the inexact search's layout
+    assert ex_stats_both["steps"] == ex_stats["steps"], (ex_stats_both, ex_stats)
+    log("stats:", ex_stats, ex_stats_both, in_stats)
 
     for _ in range(args.warmup):
+        separate()
+    sep_ms, sep_phase = timed(separate, args.steps, 2)
+    log("separate calls: %.3f ms/step, phases %s" % (sep_ms, sep_phase))
+    ex_separate = ex_out.clone()
+    in_separate = fm.hits_to_numpy(bufs, nreads)
+    for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
-    idx.phase_timing(2 * args.steps)          # two calls per step: exact, then inexact
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    ms_step = e0.elapsed_time(e1) / args.steps
-    phases, calls = idx.phase_times()
-    idx.phase_timing(0)
-    assert calls == 2 * args.steps, calls
-    phase_ms = {k: v / args.steps for k, v in phases.items()}
+    ms_step, both_phase = timed(step, args.steps, 1)
+    phase_ms = {"d_walk": both_phase["d_walk"], "dfs_and_exact": both_phase["dfs"],
+                "compaction": both_phase["compaction"]}
     log("batched: %.3f ms/step, phases per step %s" % (ms_step, phase_ms))
     ex_batched = ex_out.clone()
     in_batched = fm.hits_to_numpy(bufs, nreads)
+    fused_equal = bool(torch.equal(ex_batched, ex_separate)) and all(
+        np.array_equal(a, b) for a, b in zip(in_batched, in_separate))
+    log("one pass equals separate calls:", fused_equal)
 
-    # the same step replayed from launch graphs captured for this batch shape
-    plans = [fm.Plan(idx, fm.FM_OP_EXACT, codes, offs, None, EXACT, out=ex_out, ws=ex_ws),
-             fm.Plan(idx, fm.FM_OP_INEXACT, codes, offs, z, INEXACT, ZMAX, bufs=bufs)]
+    # the same step replayed from a launch graph captured for this batch shape
+    plans = [fm.Plan.both(idx, codes, offs, z, EXACT, INEXACT, ZMAX, ex_out, bufs)]
     for p in plans:
         p.launch()
     torch.cuda.synchronize()
@@ -194,7 +213,7 @@ def main():
         p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         p0.record()
         for _ in range(args.plain_steps):
-            step(fm.FM_PLAIN)
+            step(fm.FM_PLAIN)       # the plain exact kernel, then the plain inexact kernels
         p1.record()
         torch.cuda.synchronize()
         plain_ms = p0.elapsed_time(p1) / args.plain_steps
@@ -224,18 +243,18 @@ def main():
     # roofline of the dominant kernel: algorithmic bytes per launch / its event-timed duration
     I = tuning["inexact"]["config"]["occ_interval"]
     Iw = tuning["d_walk"]["config"]["occ_interval"]
-    Ie = tuning["exact"]["config"]["occ_interval"]
     nrs = 2 * nreads
     n_hits = int(in_batched[1][-1])
+    # the exact searches of the step run in the DFS launch, on its layout
     alg = {
-        "exact_walk": ex_stats["buckets"] * (16 + Ie // 4) + 2 * total_len + 8 * nrs,
         "d_walk": in_stats["walk_buckets"] * (16 + Iw // 4) + 2 * total_len + 16 * nrs,
-        "dfs": in_stats["buckets"] * (16 + I // 4) + 2 * total_len + 24 * nrs + 16 * n_hits,
+        "dfs_and_exact": (in_stats["buckets"] * (16 + I // 4) + 2 * total_len + 24 * nrs + 16 * n_hits)
+                         + (ex_stats_both["buckets"] * (16 + I // 4) + 2 * total_len + 8 * nrs),
     }
-    dom = max(("exact_walk", "d_walk", "dfs"), key=lambda k: phase_ms[k])
+    dom = max(("d_walk", "dfs_and_exact"), key=lambda k: phase_ms[k])
     achieved = alg[dom] / (phase_ms[dom] / 1e3) / 1e9
-    kname = {"exact_walk": "walk_batched<EXACT>", "d_walk": "walk_batched<DBP>", "dfs": "dfs_batched"}[dom]
-    tcfg = tuning[{"exact_walk": "exact", "d_walk": "d_walk", "dfs": "inexact"}[dom]]["config"]
+    kname = {"d_walk": "walk_batched<DBP>", "dfs_and_exact": "dfs_batched<EX>"}[dom]
+    tcfg = tuning[{"d_walk": "d_walk", "dfs_and_exact": "inexact"}[dom]]["config"]
     key = (kernel_source_hash(), kname, tuple(tcfg[f] for f in ("occ_interval", "lanes", "depth", "block",
                                                                 "waves_per_cu")))
     traffic = MEASURED_TRAFFIC.get(key)
@@ -284,8 +303,10 @@ def main():
         "graph_ms_per_step": round(graph_ms, 4),
         "graph_equals_eager": graph_equal,
         "occ8_queries_per_s": {**{"fm_occ8_" + k: round(v, 1) for k, v in occ8_rate.items()},
-                               "dfs_in_step": round(in_stats["occ8"] / (phase_ms["dfs"] / 1e3), 1)},
+                               "dfs_in_separate_call": round(in_stats["occ8"] / (sep_phase["dfs"] / 1e3), 1)},
         "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
+        "separate_calls": {"ms_per_step": round(sep_ms, 4), "phase_ms": {k: round(v, 4) for k, v in sep_phase.items()},
+                           "equal_to_one_pass": fused_equal},
         "work_per_step": {"exact_steps": ex_stats["steps"], "exact_buckets": ex_stats["buckets"],
                           "d_walk_steps": in_stats["walk_steps"], "d_walk_buckets": in_stats["walk_buckets"],
                           "dfs_nodes": in_stats["occ8"], "dfs_buckets": in_stats["buckets"], "hits": n_hits},

@@ -256,6 +256,22 @@ int fm_search_inexact(const fm_index *idx, const uint8_t *codes, const uint64_t 
                       fm_hit *hits, uint64_t hit_cap, uint64_t *hit_offs, uint32_t *status,
                       void *ws, size_t ws_bytes, void *stream);
 
+/* Both searches of one batch: exactly the results of fm_search_exact(codes, offs, nreads,
+ * exact_flags, intervals) and of fm_search_inexact(codes, offs, z, nreads, flags, zmax,
+ * hits, hit_cap, hit_offs, status, ws, ws_bytes), bit for bit. The exact searches
+ * (Listing 1 on the same forward index) are carried by the persistent launch of the
+ * inexact search's DFS: their read-strands follow the DFS's in its work queue, so lanes
+ * that find the DFS work taken fill the time in which the last DFS read-strands finish.
+ * Arguments and errors are those of the two calls; ws is sized by
+ * fm_search_inexact_workspace. exact_flags: FM_FWD/FM_REVCOMP (FM_STATS and FM_PLAIN are
+ * taken from flags). With FM_PLAIN the two plain searches run one after the other. With
+ * FM_STATS the uint64s at byte offsets 96 and 104 of ws count the exact searches' steps
+ * that fetched and the buckets they fetched. */
+int fm_search_both(const fm_index *idx, const uint8_t *codes, const uint64_t *offs, const uint8_t *z,
+                   uint64_t nreads, uint32_t exact_flags, uint32_t flags, uint32_t zmax,
+                   fm_interval *intervals, fm_hit *hits, uint64_t hit_cap, uint64_t *hit_offs,
+                   uint32_t *status, void *ws, size_t ws_bytes, void *stream);
+
 /* ----------------------------------------------------------------- phase timing */
 
 /* Diagnostics. With capacity > 0, every later search call on idx records HIP events on
@@ -280,6 +296,12 @@ int fm_plan_create(const fm_index *idx, int op, const uint8_t *codes, const uint
                    const uint8_t *z, uint64_t nreads, uint32_t flags, uint32_t zmax,
                    void *out_buf, uint64_t hit_cap, uint64_t *hit_offs, uint32_t *status,
                    void *ws, size_t ws_bytes, fm_plan **out);
+
+/* A plan capturing one fm_search_both call (arguments as there). */
+int fm_plan_create_both(const fm_index *idx, const uint8_t *codes, const uint64_t *offs, const uint8_t *z,
+                        uint64_t nreads, uint32_t exact_flags, uint32_t flags, uint32_t zmax,
+                        fm_interval *intervals, fm_hit *hits, uint64_t hit_cap, uint64_t *hit_offs,
+                        uint32_t *status, void *ws, size_t ws_bytes, fm_plan **out);
 
 /* Enqueues one replay of the plan on stream. */
 int fm_plan_launch(fm_plan *plan, void *stream);

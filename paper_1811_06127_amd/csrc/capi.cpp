@@ -380,6 +380,36 @@ int fm_search_inexact(const fm_index *idx, const uint8_t *codes, const uint64_t 
                                      (hipStream_t)stream, &pe));
 }
 
+int fm_search_both(const fm_index *idx, const uint8_t *codes, const uint64_t *offs, const uint8_t *z, uint64_t nreads,
+                   uint32_t exact_flags, uint32_t flags, uint32_t zmax, fm_interval *intervals, fm_hit *hits,
+                   uint64_t hit_cap, uint64_t *hit_offs, uint32_t *status, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!idx || !nstrands(exact_flags) || (exact_flags & ~(uint32_t)(FM_BOTH | FM_PLAIN | FM_STATS))) return FM_EINVAL;
+    if (nreads && !intervals) return FM_EINVAL;
+    if (nreads * nstrands(exact_flags) >= 0xFFFFFFFFull) return FM_ERANGE;
+    if (flags & FM_PLAIN) {
+        // the plain kernels of both searches, one after the other
+        const int e = fm_search_exact(idx, codes, offs, nreads, (exact_flags & FM_BOTH) | FM_PLAIN, intervals, nullptr,
+                                      0, stream);
+        if (e != FM_OK) return e;
+        return fm_search_inexact(idx, codes, offs, z, nreads, flags, zmax, hits, hit_cap, hit_offs, status, ws,
+                                 ws_bytes, stream);
+    }
+    if (!nstrands(flags) || zmax > FM_ZMAX || !hit_offs || !ws) return FM_EINVAL;
+    if (nreads && (!codes || !offs || !z || !status || (hit_cap && !hits))) return FM_EINVAL;
+    if (nreads * nstrands(flags) + nreads * nstrands(exact_flags) >= 0xFFFFFFFFull) return FM_ERANGE;
+    if ((flags & FM_DARRAY) && (!idx->has_rev || !idx->rlay[ilog(idx->tune[FM_OP_DARRAY].occ_interval)]))
+        return FM_EINVAL;
+    if (ws_bytes < inexact_ws_layout(nreads, nstrands(flags), zmax, hit_cap).total) return FM_EINVAL;
+    DeviceGuard g(idx->device);
+    DfsCall c{codes, offs, z, nreads, flags, zmax, hits, hit_cap, hit_offs, status, ws};
+    c.ex_out = intervals;
+    c.ex_flags = exact_flags & FM_BOTH;
+    const PhaseEvents pe = take_events(idx, 1);
+    return hip_status(launch_inexact(idx, idx->tune[FM_OP_INEXACT], idx->tune[FM_OP_DARRAY], false, c,
+                                     (hipStream_t)stream, &pe));
+}
+
 int fm_phase_timing(fm_index *idx, uint32_t capacity)
 {
     if (!idx) return FM_EINVAL;

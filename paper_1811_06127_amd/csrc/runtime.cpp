@@ -128,6 +128,41 @@ int fm_plan_create(const fm_index *idx, int op, const uint8_t *codes, const uint
     return FM_OK;
 }
 
+int fm_plan_create_both(const fm_index *idx, const uint8_t *codes, const uint64_t *offs, const uint8_t *z,
+                        uint64_t nreads, uint32_t exact_flags, uint32_t flags, uint32_t zmax, fm_interval *intervals,
+                        fm_hit *hits, uint64_t hit_cap, uint64_t *hit_offs, uint32_t *status, void *ws, size_t ws_bytes,
+                        fm_plan **out)
+{
+    if (!idx || !out) return FM_EINVAL;
+    *out = nullptr;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(idx->device);
+    fm_plan *p = new fm_plan();
+    p->device = idx->device;
+    hipStream_t s = nullptr;
+    int st = hs(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    if (!st) st = hs(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    if (!st) {
+        const uint32_t cap = idx->timing_cap;   // no phase events inside a graph
+        idx->timing_cap = 0;
+        const int cs = fm_search_both(idx, codes, offs, z, nreads, exact_flags, flags, zmax, intervals, hits, hit_cap,
+                                      hit_offs, status, ws, ws_bytes, s);
+        idx->timing_cap = cap;
+        const int es = hs(hipStreamEndCapture(s, &p->graph));
+        st = cs ? cs : es;
+    }
+    if (!st) st = hs(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    if (s) (void)hipStreamDestroy(s);
+    (void)hipSetDevice(prev);
+    if (st) {
+        fm_plan_free(p);
+        return st;
+    }
+    *out = p;
+    return FM_OK;
+}
+
 int fm_plan_launch(fm_plan *plan, void *stream)
 {
     if (!plan || !plan->exec) return FM_EINVAL;

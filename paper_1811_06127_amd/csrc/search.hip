@@ -494,6 +494,11 @@ struct DfsArgs {
     uint32_t *rs_count, *rs_status;
     uint32_t *queue;
     unsigned long long *stat_occ, *stat_bk;
+    // exact searches carried by the same launch (see dfs_batched): their read-strands
+    // follow the DFS's in the work queue
+    uint2 *ex_out;
+    uint32_t ex_total, ex_nstr, ex_strand0;
+    unsigned long long *ex_stat_steps, *ex_stat_bk;
 };
 
 // Stack frame (48 bytes in LDS): the intervals of a node's four children and, in
@@ -817,7 +822,12 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
 // header loads; running groups issue their node loads and expand their nodes, by which
 // time the older header loads have arrived too; new read-strands begin; hits are stored
 // and finished read-strands retired.
-template <int I, int L>
+//
+// With EX, the work queue continues past the DFS's read-strands with exact searches
+// (Listing 1 on the same forward index, the walk code of walk_batched): groups that find
+// the DFS work taken start exact searches, so those fill the lanes that the last, long
+// DFS read-strands would leave idle.
+template <int I, int L, bool EX>
 __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
 {
     extern __shared__ Frame lds_frames[];
@@ -827,59 +837,107 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
     Dfs d;
     d.rs = kEmpty;
     d.done = false;
+    Walker<WALK_EXACT> w;
+    w.rs = kEmpty;
+    w.fin = false;
+    WalkArgs wa;
+    if (EX) {
+        wa.lay = a.lay;
+        wa.codes = a.codes;
+        wa.offs = a.offs;
+        wa.z = nullptr;
+        wa.total = a.ex_total;
+        wa.nstr = a.ex_nstr;
+        wa.strand0 = a.ex_strand0;
+        wa.zmax = 0;
+        wa.out = a.ex_out;
+        wa.dstride = 0;
+        wa.queue = nullptr;
+        wa.stat_steps = a.ex_stat_steps;
+        wa.stat_bk = a.ex_stat_bk;
+    }
+    const uint32_t all = a.total + (EX ? a.ex_total : 0u);
     WaveQueue wq;
     wq.start(a.queue);
-    uint64_t n_occ = 0, n_bk = 0;
+    uint64_t n_occ = 0, n_bk = 0, ex_steps = 0, ex_bks = 0;
     for (;;) {
         const bool running = d.rs != kEmpty;
-        bool fresh = false;
-        if (refill_now<L>(lead && !running)) {
-            const uint32_t it = wave_take<L>(wq, !running, a.queue, a.total);
-            fresh = it != kEmpty;
-            if (fresh) d.request(a, it);
+        const bool walking = EX && w.rs != kEmpty;
+        bool fresh = false, wfresh = false;
+        if (refill_now<L>(lead && !running && !walking)) {
+            const uint32_t it = wave_take<L>(wq, !running && !walking, a.queue, all);
+            if (it != kEmpty) {
+                if (!EX || it < a.total) {
+                    fresh = true;
+                    d.request(a, it);
+                } else {
+                    wfresh = true;
+                    w.request(wa, it - a.total);
+                }
+            }
         }
         if (running) {
             NodeLoads<I, L> nl;
             dfs_load<I, L>(a, d, q, fr, nl);
             dfs_expand<I, L>(a, d, nl, q, fr, lead, n_occ, n_bk);
         }
+        if (EX && walking) {
+            w.fetch_code(wa);
+            Pair<I, L> pr;
+            pr.load(a.lay, q, w.k ? w.k : 1u, w.l);
+            const uint32_t b = strand_sym(w.code(wa), w.comp);
+            uint32_t ok, ol;
+            occ2<I, L>(a.lay, pr, q, b & 3, w.k ? w.k : 1u, w.l, ok, ol);
+            if (wa.stat_steps && lead && w.k && b < 4) {
+                ++ex_steps;
+                ex_bks += pr.same ? 1 : 2;
+            }
+            w.step(wa, b, ok, ol, lead);
+        }
         if (fresh) d.begin(a);
+        if (EX && wfresh) w.begin(wa, lead);
         // The header registers are loaded and read under two separate conditions; reading
         // them here on every path lets the compiler retire those loads now instead of
         // waiting on all memory operations where the registers are next written.
         asm volatile("" ::"v"(d.h0), "v"(d.h1), "v"(d.hz), "v"(d.hbp.x), "v"(d.hbp.y), "v"(d.hbp.z), "v"(d.hbp.w));
+        if (EX) asm volatile("" ::"v"(w.h0), "v"(w.h1));
         dfs_emit<L>(a, d, running || fresh, lead);
-        if (!__any(d.rs != kEmpty) && wq.exhausted) break;
+        if (EX && w.fin) w.retire(wa, lead);
+        if (!__any(d.rs != kEmpty || (EX && w.rs != kEmpty)) && wq.exhausted) break;
     }
     wave_add(a.stat_occ, n_occ);
     wave_add(a.stat_bk, n_bk);
+    if (EX) {
+        wave_add(a.ex_stat_steps, ex_steps);
+        wave_add(a.ex_stat_bk, ex_bks);
+    }
 }
 
-template <int I, int L>
+template <int I, int L, bool EX>
 static hipError_t dfs_launch_batched(const fm_index *idx, const fm_tuning &t, const DfsArgs &a, hipStream_t s)
 {
     const int block = (int)t.block;
     const size_t lds = (size_t)(block / L) * a.fcap * sizeof(Frame);
-    int per = max_blocks_per_cu((const void *)dfs_batched<I, L>, block, lds);
+    int per = max_blocks_per_cu((const void *)dfs_batched<I, L, EX>, block, lds);
     if (t.waves_per_cu) {
         int want = (int)(t.waves_per_cu * 64 / block);
         if (want >= 1 && want < per) per = want;
     }
     uint64_t grid = (uint64_t)idx->cu_count * per;
-    const uint64_t need = ((uint64_t)a.total * L + block - 1) / block;
+    const uint64_t need = ((uint64_t)(a.total + (EX ? a.ex_total : 0u)) * L + block - 1) / block;
     if (need < grid) grid = need ? need : 1;
-    hipLaunchKernelGGL((dfs_batched<I, L>), dim3((uint32_t)grid), dim3(block), lds, s, a);
+    hipLaunchKernelGGL((dfs_batched<I, L, EX>), dim3((uint32_t)grid), dim3(block), lds, s, a);
     return hipGetLastError();
 }
 
-template <int I>
+template <int I, bool EX>
 static hipError_t dfs_by_lanes(const fm_index *idx, const fm_tuning &t, const DfsArgs &a, hipStream_t s)
 {
     switch (t.lanes) {
-    case 1: return dfs_launch_batched<I, 1>(idx, t, a, s);
-    case 2: return dfs_launch_batched<I, 2>(idx, t, a, s);
-    case 4: if constexpr (Geo<I>::USED > 2) return dfs_launch_batched<I, 4>(idx, t, a, s); break;
-    case 8: if constexpr (Geo<I>::USED > 4) return dfs_launch_batched<I, 8>(idx, t, a, s); break;
+    case 1: return dfs_launch_batched<I, 1, EX>(idx, t, a, s);
+    case 2: return dfs_launch_batched<I, 2, EX>(idx, t, a, s);
+    case 4: if constexpr (Geo<I>::USED > 2) return dfs_launch_batched<I, 4, EX>(idx, t, a, s); break;
+    case 8: if constexpr (Geo<I>::USED > 4) return dfs_launch_batched<I, 8, EX>(idx, t, a, s); break;
     default: break;
     }
     return hipErrorInvalidValue;
@@ -1103,6 +1161,13 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     a.queue = (uint32_t *)(ws + kWsQueue2);
     a.stat_occ = (c.flags & FM_STATS) ? (unsigned long long *)(ws + kWsStatOcc) : nullptr;
     a.stat_bk = (c.flags & FM_STATS) ? (unsigned long long *)(ws + kWsStatBuckets) : nullptr;
+    const bool ex = c.ex_out != nullptr && !plain;
+    a.ex_out = (uint2 *)c.ex_out;
+    a.ex_nstr = strand_count(c.ex_flags);
+    a.ex_strand0 = (c.ex_flags & FM_FWD) ? 0u : 1u;
+    a.ex_total = ex ? (uint32_t)(c.nreads * a.ex_nstr) : 0u;
+    a.ex_stat_steps = (ex && (c.flags & FM_STATS)) ? (unsigned long long *)(ws + kWsStatExact) : nullptr;
+    a.ex_stat_bk = (ex && (c.flags & FM_STATS)) ? (unsigned long long *)(ws + kWsStatExactBk) : nullptr;
     pe->mark(2, s);
     if (plain) {
         const uint32_t grid = (a.total + 255) / 256;
@@ -1120,13 +1185,13 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
         e = hipGetLastError();
     } else {
         switch (t.occ_interval) {
-        case 64: e = dfs_by_lanes<64>(idx, t, a, s); break;
-        case 96: e = dfs_by_lanes<96>(idx, t, a, s); break;
-        case 128: e = dfs_by_lanes<128>(idx, t, a, s); break;
-        case 192: e = dfs_by_lanes<192>(idx, t, a, s); break;
-        case 224: e = dfs_by_lanes<224>(idx, t, a, s); break;
-        case 256: e = dfs_by_lanes<256>(idx, t, a, s); break;
-        case 448: e = dfs_by_lanes<448>(idx, t, a, s); break;
+        case 64: e = ex ? dfs_by_lanes<64, true>(idx, t, a, s) : dfs_by_lanes<64, false>(idx, t, a, s); break;
+        case 96: e = ex ? dfs_by_lanes<96, true>(idx, t, a, s) : dfs_by_lanes<96, false>(idx, t, a, s); break;
+        case 128: e = ex ? dfs_by_lanes<128, true>(idx, t, a, s) : dfs_by_lanes<128, false>(idx, t, a, s); break;
+        case 192: e = ex ? dfs_by_lanes<192, true>(idx, t, a, s) : dfs_by_lanes<192, false>(idx, t, a, s); break;
+        case 224: e = ex ? dfs_by_lanes<224, true>(idx, t, a, s) : dfs_by_lanes<224, false>(idx, t, a, s); break;
+        case 256: e = ex ? dfs_by_lanes<256, true>(idx, t, a, s) : dfs_by_lanes<256, false>(idx, t, a, s); break;
+        case 448: e = ex ? dfs_by_lanes<448, true>(idx, t, a, s) : dfs_by_lanes<448, false>(idx, t, a, s); break;
         default: return hipErrorInvalidValue;
         }
     }

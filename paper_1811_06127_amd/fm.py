@@ -113,6 +113,9 @@ def lib() -> C.CDLL:
         "fm_phase_timing": (i32, [vp, u32]),
         "fm_phase_times": (i32, [vp, C.POINTER(C.c_float), C.POINTER(C.c_uint32)]),
         "fm_plan_free": (None, [vp]),
+        "fm_search_both": (i32, [vp, vp, vp, vp, u64, u32, u32, u32, vp, vp, u64, vp, vp, vp, C.c_size_t, vp]),
+        "fm_plan_create_both": (i32, [vp, vp, vp, vp, u64, u32, u32, u32, vp, vp, u64, vp, vp, vp, C.c_size_t,
+                                      C.POINTER(vp)]),
         "fm_server_bytes": (i32, [C.POINTER(ServerOpts), u64, u64, C.POINTER(C.c_uint64)]),
         "fm_server_create": (i32, [vp, C.POINTER(ServerOpts), C.POINTER(vp)]),
         "fm_server_submit": (i32, [vp, vp, vp, vp, u64, C.POINTER(C.c_uint64)]),
@@ -367,6 +370,32 @@ def fm_search_inexact(idx: Index, codes: torch.Tensor, offs: torch.Tensor, z: to
     return bufs
 
 
+def fm_search_both(idx: Index, codes: torch.Tensor, offs: torch.Tensor, z: torch.Tensor, exact_flags: int,
+                   flags: int, zmax: int, hit_cap: int, out: torch.Tensor | None = None,
+                   bufs: InexactBuffers | None = None, stream=None):
+    """Exact and inexact search of one batch in one pass (fm_search_both). Returns
+    (intervals, bufs) as fm_search_exact and fm_search_inexact would."""
+    _dev(codes, torch.uint8, "codes")
+    _dev(offs, torch.int64, "offs")
+    _dev(z, torch.uint8, "z")
+    nreads = offs.numel() - 1
+    if out is None:
+        out = torch.empty((nreads * nstrands(exact_flags), 2), dtype=torch.int32, device=codes.device)
+    if bufs is None:
+        total_len = int(offs[-1].item()) if nreads else 0
+        bufs = InexactBuffers(idx, nreads, total_len, flags, zmax, hit_cap, codes.device)
+    _check(lib().fm_search_both(idx.handle, _ptr(codes), _ptr(offs), _ptr(z), nreads, exact_flags, flags, zmax,
+                                _ptr(out), _ptr(bufs.hits), bufs.hit_cap, _ptr(bufs.hit_offs), _ptr(bufs.status),
+                                _ptr(bufs.ws), bufs.ws.numel(), _stream(stream)), "fm_search_both")
+    return out, bufs
+
+
+def both_exact_stats(bufs: InexactBuffers) -> dict:
+    """With FM_STATS, the exact searches' steps and buckets counted by fm_search_both."""
+    w = bufs.ws[:112].cpu().numpy().view(np.uint64)
+    return {"steps": int(w[12]), "buckets": int(w[13])}
+
+
 def hits_to_numpy(bufs: InexactBuffers, nreads: int):
     """(hits as HIT_DTYPE array, hit_offs uint64, status uint32) copied to the host."""
     offs = bufs.hit_offs[:nreads + 1].cpu().numpy().view(np.uint64).copy()
@@ -417,6 +446,20 @@ class Plan:
                                       _ptr(bufs.ws), bufs.ws.numel(), C.byref(h))
         _check(st, "fm_plan_create")
         self._h = h
+
+    @classmethod
+    def both(cls, idx: Index, codes, offs, z, exact_flags: int, flags: int, zmax: int, out, bufs: InexactBuffers):
+        """A plan of one fm_search_both call."""
+        self = cls.__new__(cls)
+        nreads = offs.numel() - 1
+        h = C.c_void_p()
+        self._keep = (idx, codes, offs, z, out, bufs)
+        _check(lib().fm_plan_create_both(idx.handle, _ptr(codes), _ptr(offs), _ptr(z), nreads, exact_flags, flags, zmax,
+                                         _ptr(out), _ptr(bufs.hits), bufs.hit_cap, _ptr(bufs.hit_offs),
+                                         _ptr(bufs.status), _ptr(bufs.ws), bufs.ws.numel(), C.byref(h)),
+               "fm_plan_create_both")
+        self._h = h
+        return self
 
     def launch(self, stream=None):
         _check(lib().fm_plan_launch(self._h, _stream(stream)), "fm_plan_launch")

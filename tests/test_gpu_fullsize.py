@@ -66,6 +66,12 @@ def test_headline_workload_full_size():
     in_p = inexact_np(idx, codes, offs, z, fm.FM_BOTH | fm.FM_DARRAY | fm.FM_PLAIN, 1, 4 * n)
     assert same_hits(in_b, in_p)
     assert (in_b[2] == fm.FM_OK).all()
+    # both searches in one pass, as the benchmark's step runs them
+    ex_f, bufs_f = fm.fm_search_both(idx, codes, offs, z, fm.FM_BOTH, fm.FM_BOTH | fm.FM_DARRAY, 1, 4 * n)
+    torch.cuda.synchronize()
+    assert np.array_equal(ex_f.cpu().numpy().view(np.uint32), ex_b)
+    assert same_hits(fm.hits_to_numpy(bufs_f, n), in_b)
+    del bufs_f
     say("batched == plain over %d reads; %d hits" % (n, int(in_b[1][-1])))
     # sampled reads against the full oracle
     t0 = time.time()

@@ -56,3 +56,28 @@ def test_plan_replays_match_eager(use_d):
         eager(idx, other, flags, 2)
     for p in plans:
         p.free()
+
+
+def test_fused_plan_replays_match_eager():
+    """A plan of fm_search_both replays to the eager results of the separate calls."""
+    R = synth.reference_with_repeats(120_001, 516, copy_frac=0.06, copy_len=(300, 2000), copy_sub=0.02)
+    idx = fm.Index.from_text(R, occ_interval=64, flags=fm.FM_LOAD_REVERSE)
+    flags = fm.FM_BOTH | fm.FM_DARRAY
+    batches = [synth.simulate_reads(R, 600, s, length=(80, 80), sub=(0.0, 0.03), z=(0, 2)) for s in (71, 72)]
+    want = [eager(idx, rd, flags, 2) for rd in batches]
+    n = batches[0].count
+    codes, offs, z = fm.reads_to_device(batches[0].codes, batches[0].offs, batches[0].z)
+    ex_out = torch.empty((2 * n, 2), dtype=torch.int32, device="cuda")
+    bufs = fm.InexactBuffers(idx, n, int(batches[0].offs[-1]), flags, 2, 8 * n, "cuda")
+    plan = fm.Plan.both(idx, codes, offs, z, fm.FM_BOTH, flags, 2, ex_out, bufs)
+    other = synth.simulate_reads(R, 200, 73, length=(40, 160), sub=(0.0, 0.03), z=(0, 2))
+    for rep, b in enumerate([0, 1, 1, 0]):
+        rd = batches[b]
+        codes.copy_(torch.from_numpy(rd.codes))
+        z.copy_(torch.from_numpy(rd.z))
+        plan.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(ex_out.cpu().numpy(), want[b][0]), (rep, b)
+        assert all(np.array_equal(x, y) for x, y in zip(fm.hits_to_numpy(bufs, n), want[b][1])), (rep, b)
+        eager(idx, other, flags, 2)
+    plan.free()

@@ -209,6 +209,31 @@ def test_inexact_plain_and_batched(small, use_d):
     idx.set_tuning(fm.FM_OP_DARRAY, occ_interval=128, lanes=1)
 
 
+@pytest.mark.parametrize("use_d", [False, True])
+def test_search_both_equals_separate_calls(small, use_d):
+    """fm_search_both (exact searches carried by the DFS launch) gives the exact and the
+    inexact results of the separate calls for every layout, lane count and strand set."""
+    R, x, xr, idx = small
+    codes, offs, z = inexact_inputs(R)
+    flags = fm.FM_BOTH | (fm.FM_DARRAY if use_d else 0)
+    wh, wo = x.inexact(codes, offs, z, oracle.BOTH, "listing2_darray" if use_d else "listing2", rev=xr)
+    cd, od, zd = fm.reads_to_device(codes, offs, z)
+    for exf in (fm.FM_FWD, fm.FM_REVCOMP, fm.FM_BOTH):
+        want_ex = x.exact(codes, offs, exf, "listing1")
+        ex, bufs = fm.fm_search_both(idx, cd, od, zd, exf, flags | fm.FM_PLAIN, 2, 1 << 16)
+        assert np.array_equal(to_u32(ex), want_ex), ("plain", exf)
+        assert_same_hits(fm.hits_to_numpy(bufs, offs.size - 1), wh, wo, ("plain", exf))
+        for I in LAYOUTS:
+            for L in LANES[I]:
+                idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=I, lanes=L)
+                idx.set_tuning(fm.FM_OP_DARRAY, occ_interval=I, lanes=min(L, 4))
+                ex, bufs = fm.fm_search_both(idx, cd, od, zd, exf, flags, 2, 1 << 16)
+                assert np.array_equal(to_u32(ex), want_ex), (I, L, exf)
+                assert_same_hits(fm.hits_to_numpy(bufs, offs.size - 1), wh, wo, (I, L, exf))
+    idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=128, lanes=1)
+    idx.set_tuning(fm.FM_OP_DARRAY, occ_interval=128, lanes=1)
+
+
 def test_inexact_definition_and_node_count(small):
     """Hits equal the Hamming-ball definition; expanded nodes equal the oracle's."""
     R, x, xr, idx = small
