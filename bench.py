@@ -135,7 +135,7 @@ def main():
         tuning[name] = {"config": idx.get_tuning(op), "ms": tuning[name][1]}
 
     def step(extra=0):
-        # both searches in one pass: the exact searches ride in the DFS launch
+        # both searches in one pass: the exact intervals come out of the DFS
         fm.fm_search_both(idx, codes, offs, z, EXACT, INEXACT | extra, ZMAX, hit_cap, out=ex_out, bufs=bufs)
 
     def separate(extra=0):
@@ -163,9 +163,8 @@ def main():
     in_stats = bufs.stats()
     step(fm.FM_STATS)
     torch.cuda.synchronize()
-    ex_stats_both = fm.both_exact_stats(bufs)      # on the inexact search's layout
-    assert ex_stats_both["steps"] == ex_stats["steps"], (ex_stats_both, ex_stats)
-    log("stats:", ex_stats, ex_stats_both, in_stats)
+    both_stats = bufs.stats()
+    log("stats: exact", ex_stats, "inexact", in_stats, "one pass", both_stats)
 
     for _ in range(args.warmup):
         separate()
@@ -176,8 +175,7 @@ def main():
     for _ in range(args.warmup):
         step()
     ms_step, both_phase = timed(step, args.steps, 1)
-    phase_ms = {"d_walk": both_phase["d_walk"], "dfs_and_exact": both_phase["dfs"],
-                "compaction": both_phase["compaction"]}
+    phase_ms = {"d_walk": both_phase["d_walk"], "dfs": both_phase["dfs"], "compaction": both_phase["compaction"]}
     log("batched: %.3f ms/step, phases per step %s" % (ms_step, phase_ms))
     ex_batched = ex_out.clone()
     in_batched = fm.hits_to_numpy(bufs, nreads)
@@ -245,16 +243,17 @@ def main():
     Iw = tuning["d_walk"]["config"]["occ_interval"]
     nrs = 2 * nreads
     n_hits = int(in_batched[1][-1])
-    # the exact searches of the step run in the DFS launch, on its layout
+    # per read-strand: the D walk reads the pattern and writes a 16-byte D record; the DFS
+    # reads the pattern and the record and writes a hit count, a status and the exact
+    # interval (8 bytes), plus 16 bytes per hit
     alg = {
-        "d_walk": in_stats["walk_buckets"] * (16 + Iw // 4) + 2 * total_len + 16 * nrs,
-        "dfs_and_exact": (in_stats["buckets"] * (16 + I // 4) + 2 * total_len + 24 * nrs + 16 * n_hits)
-                         + (ex_stats_both["buckets"] * (16 + I // 4) + 2 * total_len + 8 * nrs),
+        "d_walk": both_stats["walk_buckets"] * (16 + Iw // 4) + 2 * total_len + 16 * nrs,
+        "dfs": both_stats["buckets"] * (16 + I // 4) + 2 * total_len + 32 * nrs + 16 * n_hits,
     }
-    dom = max(("d_walk", "dfs_and_exact"), key=lambda k: phase_ms[k])
+    dom = max(("d_walk", "dfs"), key=lambda k: phase_ms[k])
     achieved = alg[dom] / (phase_ms[dom] / 1e3) / 1e9
-    kname = {"d_walk": "walk_batched<DBP>", "dfs_and_exact": "dfs_batched<EX>"}[dom]
-    tcfg = tuning[{"d_walk": "d_walk", "dfs_and_exact": "inexact"}[dom]]["config"]
+    kname = {"d_walk": "walk_batched<DBP>", "dfs": "dfs_batched<XD>"}[dom]
+    tcfg = tuning[{"d_walk": "d_walk", "dfs": "inexact"}[dom]]["config"]
     key = (kernel_source_hash(), kname, tuple(tcfg[f] for f in ("occ_interval", "lanes", "depth", "block",
                                                                 "waves_per_cu")))
     traffic = MEASURED_TRAFFIC.get(key)
@@ -309,7 +308,7 @@ def main():
                            "equal_to_one_pass": fused_equal},
         "work_per_step": {"exact_steps": ex_stats["steps"], "exact_buckets": ex_stats["buckets"],
                           "d_walk_steps": in_stats["walk_steps"], "d_walk_buckets": in_stats["walk_buckets"],
-                          "dfs_nodes": in_stats["occ8"], "dfs_buckets": in_stats["buckets"], "hits": n_hits},
+                          "dfs_nodes": both_stats["occ8"], "dfs_buckets": both_stats["buckets"], "hits": n_hits},
         "tuning": tuning,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -258,15 +258,16 @@ int fm_search_inexact(const fm_index *idx, const uint8_t *codes, const uint64_t 
 
 /* Both searches of one batch: exactly the results of fm_search_exact(codes, offs, nreads,
  * exact_flags, intervals) and of fm_search_inexact(codes, offs, z, nreads, flags, zmax,
- * hits, hit_cap, hit_offs, status, ws, ws_bytes), bit for bit. The exact searches
- * (Listing 1 on the same forward index) are carried by the persistent launch of the
- * inexact search's DFS: their read-strands follow the DFS's in its work queue, so lanes
- * that find the DFS work taken fill the time in which the last DFS read-strands finish.
- * Arguments and errors are those of the two calls; ws is sized by
- * fm_search_inexact_workspace. exact_flags: FM_FWD/FM_REVCOMP (FM_STATS and FM_PLAIN are
- * taken from flags). With FM_PLAIN the two plain searches run one after the other. With
- * FM_STATS the uint64s at byte offsets 96 and 104 of ws count the exact searches' steps
- * that fetched and the buckets they fetched. */
+ * hits, hit_cap, hit_offs, status, ws, ws_bytes), bit for bit. When every strand of
+ * exact_flags is also searched by the inexact search, the exact intervals come out of
+ * its DFS (Listing 2): the branch that matches every symbol is Listing 1's backward
+ * search with the same interval updates, so a read-strand's exact interval is its hit
+ * with no substitution, or the miss (1, 0) when the DFS ends without one; a read-strand
+ * whose DFS stops early (FM_EINVAL, FM_ERANGE, FM_EBUDGET) finishes that branch alone,
+ * so its interval is still exact. Otherwise, and with FM_PLAIN, the two searches run one
+ * after the other. Arguments and errors are those of the two calls; ws is sized by
+ * fm_search_inexact_workspace. exact_flags: FM_FWD/FM_REVCOMP (FM_STATS and FM_PLAIN
+ * are taken from flags). */
 int fm_search_both(const fm_index *idx, const uint8_t *codes, const uint64_t *offs, const uint8_t *z,
                    uint64_t nreads, uint32_t exact_flags, uint32_t flags, uint32_t zmax,
                    fm_interval *intervals, fm_hit *hits, uint64_t hit_cap, uint64_t *hit_offs,

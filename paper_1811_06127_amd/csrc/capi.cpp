@@ -387,10 +387,11 @@ int fm_search_both(const fm_index *idx, const uint8_t *codes, const uint64_t *of
     if (!idx || !nstrands(exact_flags) || (exact_flags & ~(uint32_t)(FM_BOTH | FM_PLAIN | FM_STATS))) return FM_EINVAL;
     if (nreads && !intervals) return FM_EINVAL;
     if (nreads * nstrands(exact_flags) >= 0xFFFFFFFFull) return FM_ERANGE;
-    if (flags & FM_PLAIN) {
-        // the plain kernels of both searches, one after the other
-        const int e = fm_search_exact(idx, codes, offs, nreads, (exact_flags & FM_BOTH) | FM_PLAIN, intervals, nullptr,
-                                      0, stream);
+    if ((flags & FM_PLAIN) || (exact_flags & ~flags & FM_BOTH)) {
+        // the two searches one after the other: the plain kernels, or an exact search of
+        // a strand the inexact one does not search
+        const uint32_t ef = (exact_flags & FM_BOTH) | (flags & FM_PLAIN);
+        const int e = fm_search_exact(idx, codes, offs, nreads, ef, intervals, ws, ws_bytes, stream);
         if (e != FM_OK) return e;
         return fm_search_inexact(idx, codes, offs, z, nreads, flags, zmax, hits, hit_cap, hit_offs, status, ws,
                                  ws_bytes, stream);

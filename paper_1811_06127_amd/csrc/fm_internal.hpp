@@ -68,8 +68,6 @@ enum : size_t {
     kWsStatBuckets = 72, // uint64 distinct buckets fetched
     kWsStatWalk = 80,    // uint64 walk steps that fetched
     kWsStatWalkBk = 88,  // uint64 buckets those steps fetched
-    kWsStatExact = 96,   // uint64 exact-search steps that fetched (searches carried by the DFS launch)
-    kWsStatExactBk = 104, // uint64 buckets those steps fetched
     kWsHeader = 256
 };
 
@@ -117,7 +115,7 @@ struct DfsCall {
     uint64_t *hit_offs;
     uint32_t *status;
     void *ws;
-    fm_interval *ex_out = nullptr;   // non-null: the exact searches of ex_flags ride in the DFS launch
+    fm_interval *ex_out = nullptr;   // non-null: exact intervals of the ex_flags strands, taken from the DFS
     uint32_t ex_flags = 0;
 };
 // Phase boundary events of one call (nullptr entries: not recorded).

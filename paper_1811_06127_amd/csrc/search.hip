@@ -245,15 +245,13 @@ struct Walker {
 
 __device__ __forceinline__ uint32_t strand_sym(uint32_t c, uint32_t comp) { return (comp && c < 4) ? 3u - c : c; }
 
+// One walk from start to end on the calling lane (one thread per read-strand).
 template <int I, int MODE>
-__global__ void __launch_bounds__(256) walk_plain(WalkArgs a)
+__device__ void walk_one(const WalkArgs &a, uint32_t item, uint64_t &steps, uint64_t &bks)
 {
-    const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= a.total) return;
     Walker<MODE> w;
     w.init(a, item, true);
     if (w.fin) w.retire(a, true);
-    uint64_t steps = 0, bks = 0;
     while (w.rs != kEmpty) {
         w.fetch_code(a);
         const uint32_t c = w.code(a);
@@ -269,9 +267,38 @@ __global__ void __launch_bounds__(256) walk_plain(WalkArgs a)
         w.step(a, b, ok, ol, true);
         if (w.fin) w.retire(a, true);
     }
+}
+
+template <int I, int MODE>
+__global__ void __launch_bounds__(256) walk_plain(WalkArgs a)
+{
+    const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= a.total) return;
+    uint64_t steps = 0, bks = 0;
+    walk_one<I, MODE>(a, item, steps, bks);
     if (a.stat_steps && steps) {
         atomicAdd(a.stat_steps, (unsigned long long)steps);
         atomicAdd(a.stat_bk, (unsigned long long)bks);
+    }
+}
+
+// Exact intervals the DFS left undecided: read-strands of the DFS (dfs_total of them,
+// dfs_nstr strands per read) whose search stopped before its end (FM_EINVAL, FM_ERANGE,
+// FM_EBUDGET) get Listing 1's walk here, for the strands the exact output holds (a:
+// the exact search's arguments). Grid-stride; nearly every read-strand only has its
+// status read.
+template <int I>
+__global__ void __launch_bounds__(256) exact_rest(WalkArgs a, const uint32_t *rs_status, uint32_t dfs_total,
+                                                  uint32_t dfs_nstr, uint32_t dfs_strand0)
+{
+    uint64_t steps = 0, bks = 0;
+    for (uint32_t rs = blockIdx.x * blockDim.x + threadIdx.x; rs < dfs_total; rs += gridDim.x * blockDim.x) {
+        const uint32_t st = rs_status[rs];
+        if (st == FM_OK || st == FM_EOVERFLOW) continue;
+        const uint32_t read = dfs_nstr == 2 ? rs >> 1 : rs;
+        const uint32_t strand = dfs_nstr == 2 ? (rs & 1u) : dfs_strand0;
+        if (a.nstr == 1 && strand != a.strand0) continue;
+        walk_one<I, WALK_EXACT>(a, a.nstr == 2 ? 2 * read + strand : read, steps, bks);
     }
 }
 
@@ -494,11 +521,10 @@ struct DfsArgs {
     uint32_t *rs_count, *rs_status;
     uint32_t *queue;
     unsigned long long *stat_occ, *stat_bk;
-    // exact searches carried by the same launch (see dfs_batched): their read-strands
-    // follow the DFS's in the work queue
+    // exact intervals taken from the DFS (see dfs_emit), or ex_out == nullptr: ex_nstr
+    // slots per read, for the strands in ex_strands (bit s: strand s)
     uint2 *ex_out;
-    uint32_t ex_total, ex_nstr, ex_strand0;
-    unsigned long long *ex_stat_steps, *ex_stat_bk;
+    uint32_t ex_nstr, ex_strands;
 };
 
 // Stack frame (48 bytes in LDS): the intervals of a node's four children and, in
@@ -521,6 +547,9 @@ struct Dfs {
     bool done;
     // hits produced by the last expansion (children of a node with i == 0)
     uint32_t pend, pk[4], pl[4], pd;
+    // exact interval of the strand pattern: its hit with no substitution, (1, 0) while
+    // there is none
+    uint32_t ek, el;
 
     // First pattern position at which the D bound exceeds zc (0xFFFF: none).
     __device__ uint32_t bp_at(uint32_t zc) const
@@ -607,6 +636,8 @@ struct Dfs {
         pend = (ok && m == 0) ? 1u : 0u;
         pk[0] = 0;
         pl[0] = a.lay.n;
+        ek = 1;
+        el = 0;
     }
 };
 
@@ -727,13 +758,25 @@ __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeL
 // to its own slots with plain stores; later ones are appended to the overflow pool
 // (one atomic per wave, rarely needed). Then retires finished read-strands. Must be
 // called by the whole wave.
-template <int L>
+//
+// With XD the exact intervals come out of the same DFS. The path that matches every
+// symbol is Listing 1's search: its node intervals are computed by the same update,
+// and the D bound never prunes it when the pattern occurs (D is then zero). So a
+// read-strand whose DFS runs to the end (FM_OK, or FM_EOVERFLOW, which still explores
+// everything) has as exact interval its hit with no substitution, or none; a root
+// pruned by D (D(m-1) > z >= 0) has none either. A DFS that stops early leaves its
+// interval to exact_rest.
+template <int L, bool XD>
 __device__ void dfs_emit(const DfsArgs &a, Dfs &d, bool active, bool lead)
 {
     const uint32_t pend = active ? d.pend : 0u;
     const uint32_t wi = d.pd >> 8;
     uint32_t over = 0;                        // children whose hit goes to the overflow pool
     if (pend) {
+        if (XD && (d.pd & 0xFFu) == 0 && wi < 4 && ((pend >> wi) & 1u)) {
+            d.ek = sel4(wi, d.pk[0], d.pk[1], d.pk[2], d.pk[3]);
+            d.el = sel4(wi, d.pl[0], d.pl[1], d.pl[2], d.pl[3]);
+        }
         uint32_t h = d.hits;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
@@ -784,6 +827,9 @@ __device__ void dfs_emit(const DfsArgs &a, Dfs &d, bool active, bool lead)
             if (lead) {
                 a.rs_count[d.rs] = d.hits;
                 a.rs_status[d.rs] = d.status;
+                const uint32_t ran_to_end = (1u << FM_OK) | (1u << FM_EOVERFLOW);
+                if (XD && ((a.ex_strands >> d.strand) & 1u) && ((ran_to_end >> d.status) & 1u))
+                    a.ex_out[(size_t)d.read * a.ex_nstr + (a.ex_nstr == 2 ? d.strand : 0u)] = make_uint2(d.ek, d.el);
             }
             d.rs = kEmpty;
         }
@@ -812,7 +858,7 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
             dfs_load<I, 1>(a, d, 0, fr, nl);
             dfs_expand<I, 1>(a, d, nl, 0, fr, true, n_occ, n_bk);
         }
-        dfs_emit<1>(a, d, active, true);
+        dfs_emit<1, false>(a, d, active, true);
     }
     wave_add(a.stat_occ, n_occ);
     wave_add(a.stat_bk, n_bk);
@@ -821,13 +867,8 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
 // Each round: idle groups (refilled in batches) take read-strands and issue their
 // header loads; running groups issue their node loads and expand their nodes, by which
 // time the older header loads have arrived too; new read-strands begin; hits are stored
-// and finished read-strands retired.
-//
-// With EX, the work queue continues past the DFS's read-strands with exact searches
-// (Listing 1 on the same forward index, the walk code of walk_batched): groups that find
-// the DFS work taken start exact searches, so those fill the lanes that the last, long
-// DFS read-strands would leave idle.
-template <int I, int L, bool EX>
+// and finished read-strands retired. XD: exact intervals as well (see dfs_emit).
+template <int I, int L, bool XD>
 __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
 {
     extern __shared__ Frame lds_frames[];
@@ -837,43 +878,17 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
     Dfs d;
     d.rs = kEmpty;
     d.done = false;
-    Walker<WALK_EXACT> w;
-    w.rs = kEmpty;
-    w.fin = false;
-    WalkArgs wa;
-    if (EX) {
-        wa.lay = a.lay;
-        wa.codes = a.codes;
-        wa.offs = a.offs;
-        wa.z = nullptr;
-        wa.total = a.ex_total;
-        wa.nstr = a.ex_nstr;
-        wa.strand0 = a.ex_strand0;
-        wa.zmax = 0;
-        wa.out = a.ex_out;
-        wa.dstride = 0;
-        wa.queue = nullptr;
-        wa.stat_steps = a.ex_stat_steps;
-        wa.stat_bk = a.ex_stat_bk;
-    }
-    const uint32_t all = a.total + (EX ? a.ex_total : 0u);
     WaveQueue wq;
     wq.start(a.queue);
-    uint64_t n_occ = 0, n_bk = 0, ex_steps = 0, ex_bks = 0;
+    uint64_t n_occ = 0, n_bk = 0;
     for (;;) {
         const bool running = d.rs != kEmpty;
-        const bool walking = EX && w.rs != kEmpty;
-        bool fresh = false, wfresh = false;
-        if (refill_now<L>(lead && !running && !walking)) {
-            const uint32_t it = wave_take<L>(wq, !running && !walking, a.queue, all);
+        bool fresh = false;
+        if (refill_now<L>(lead && !running)) {
+            const uint32_t it = wave_take<L>(wq, !running, a.queue, a.total);
             if (it != kEmpty) {
-                if (!EX || it < a.total) {
-                    fresh = true;
-                    d.request(a, it);
-                } else {
-                    wfresh = true;
-                    w.request(wa, it - a.total);
-                }
+                fresh = true;
+                d.request(a, it);
             }
         }
         if (running) {
@@ -881,63 +896,43 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
             dfs_load<I, L>(a, d, q, fr, nl);
             dfs_expand<I, L>(a, d, nl, q, fr, lead, n_occ, n_bk);
         }
-        if (EX && walking) {
-            w.fetch_code(wa);
-            Pair<I, L> pr;
-            pr.load(a.lay, q, w.k ? w.k : 1u, w.l);
-            const uint32_t b = strand_sym(w.code(wa), w.comp);
-            uint32_t ok, ol;
-            occ2<I, L>(a.lay, pr, q, b & 3, w.k ? w.k : 1u, w.l, ok, ol);
-            if (wa.stat_steps && lead && w.k && b < 4) {
-                ++ex_steps;
-                ex_bks += pr.same ? 1 : 2;
-            }
-            w.step(wa, b, ok, ol, lead);
-        }
         if (fresh) d.begin(a);
-        if (EX && wfresh) w.begin(wa, lead);
         // The header registers are loaded and read under two separate conditions; reading
         // them here on every path lets the compiler retire those loads now instead of
         // waiting on all memory operations where the registers are next written.
         asm volatile("" ::"v"(d.h0), "v"(d.h1), "v"(d.hz), "v"(d.hbp.x), "v"(d.hbp.y), "v"(d.hbp.z), "v"(d.hbp.w));
-        if (EX) asm volatile("" ::"v"(w.h0), "v"(w.h1));
-        dfs_emit<L>(a, d, running || fresh, lead);
-        if (EX && w.fin) w.retire(wa, lead);
-        if (!__any(d.rs != kEmpty || (EX && w.rs != kEmpty)) && wq.exhausted) break;
+        dfs_emit<L, XD>(a, d, running || fresh, lead);
+        if (!__any(d.rs != kEmpty) && wq.exhausted) break;
     }
     wave_add(a.stat_occ, n_occ);
     wave_add(a.stat_bk, n_bk);
-    if (EX) {
-        wave_add(a.ex_stat_steps, ex_steps);
-        wave_add(a.ex_stat_bk, ex_bks);
-    }
 }
 
-template <int I, int L, bool EX>
+template <int I, int L, bool XD>
 static hipError_t dfs_launch_batched(const fm_index *idx, const fm_tuning &t, const DfsArgs &a, hipStream_t s)
 {
     const int block = (int)t.block;
     const size_t lds = (size_t)(block / L) * a.fcap * sizeof(Frame);
-    int per = max_blocks_per_cu((const void *)dfs_batched<I, L, EX>, block, lds);
+    int per = max_blocks_per_cu((const void *)dfs_batched<I, L, XD>, block, lds);
     if (t.waves_per_cu) {
         int want = (int)(t.waves_per_cu * 64 / block);
         if (want >= 1 && want < per) per = want;
     }
     uint64_t grid = (uint64_t)idx->cu_count * per;
-    const uint64_t need = ((uint64_t)(a.total + (EX ? a.ex_total : 0u)) * L + block - 1) / block;
+    const uint64_t need = ((uint64_t)a.total * L + block - 1) / block;
     if (need < grid) grid = need ? need : 1;
-    hipLaunchKernelGGL((dfs_batched<I, L, EX>), dim3((uint32_t)grid), dim3(block), lds, s, a);
+    hipLaunchKernelGGL((dfs_batched<I, L, XD>), dim3((uint32_t)grid), dim3(block), lds, s, a);
     return hipGetLastError();
 }
 
-template <int I, bool EX>
+template <int I, bool XD>
 static hipError_t dfs_by_lanes(const fm_index *idx, const fm_tuning &t, const DfsArgs &a, hipStream_t s)
 {
     switch (t.lanes) {
-    case 1: return dfs_launch_batched<I, 1, EX>(idx, t, a, s);
-    case 2: return dfs_launch_batched<I, 2, EX>(idx, t, a, s);
-    case 4: if constexpr (Geo<I>::USED > 2) return dfs_launch_batched<I, 4, EX>(idx, t, a, s); break;
-    case 8: if constexpr (Geo<I>::USED > 4) return dfs_launch_batched<I, 8, EX>(idx, t, a, s); break;
+    case 1: return dfs_launch_batched<I, 1, XD>(idx, t, a, s);
+    case 2: return dfs_launch_batched<I, 2, XD>(idx, t, a, s);
+    case 4: if constexpr (Geo<I>::USED > 2) return dfs_launch_batched<I, 4, XD>(idx, t, a, s); break;
+    case 8: if constexpr (Geo<I>::USED > 4) return dfs_launch_batched<I, 8, XD>(idx, t, a, s); break;
     default: break;
     }
     return hipErrorInvalidValue;
@@ -1127,6 +1122,8 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
 {
     const PhaseEvents none;
     if (!pe) pe = &none;
+    // exact intervals from the DFS: batched kernels only, and strands the DFS searches
+    if (c.ex_out && (plain || (c.ex_flags & ~c.flags & FM_BOTH))) return hipErrorInvalidValue;
     char *ws = (char *)c.ws;
     const uint32_t nstr = strand_count(c.flags);
     const InexactWs W = inexact_ws_layout(c.nreads, nstr, c.zmax, c.hit_cap);
@@ -1161,13 +1158,10 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     a.queue = (uint32_t *)(ws + kWsQueue2);
     a.stat_occ = (c.flags & FM_STATS) ? (unsigned long long *)(ws + kWsStatOcc) : nullptr;
     a.stat_bk = (c.flags & FM_STATS) ? (unsigned long long *)(ws + kWsStatBuckets) : nullptr;
-    const bool ex = c.ex_out != nullptr && !plain;
+    const bool ex = c.ex_out != nullptr;
     a.ex_out = (uint2 *)c.ex_out;
     a.ex_nstr = strand_count(c.ex_flags);
-    a.ex_strand0 = (c.ex_flags & FM_FWD) ? 0u : 1u;
-    a.ex_total = ex ? (uint32_t)(c.nreads * a.ex_nstr) : 0u;
-    a.ex_stat_steps = (ex && (c.flags & FM_STATS)) ? (unsigned long long *)(ws + kWsStatExact) : nullptr;
-    a.ex_stat_bk = (ex && (c.flags & FM_STATS)) ? (unsigned long long *)(ws + kWsStatExactBk) : nullptr;
+    a.ex_strands = c.ex_flags & FM_BOTH;
     pe->mark(2, s);
     if (plain) {
         const uint32_t grid = (a.total + 255) / 256;
@@ -1196,6 +1190,36 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
         }
     }
     if (e != hipSuccess) return e;
+    if (ex) {
+        WalkArgs w;
+        w.lay = a.lay;
+        w.codes = c.codes;
+        w.offs = c.offs;
+        w.z = nullptr;
+        w.nstr = a.ex_nstr;
+        w.strand0 = (c.ex_flags & FM_FWD) ? 0u : 1u;
+        w.total = (uint32_t)(c.nreads * w.nstr);
+        w.zmax = 0;
+        w.out = c.ex_out;
+        w.dstride = 0;
+        w.queue = nullptr;
+        w.stat_steps = nullptr;
+        w.stat_bk = nullptr;
+        const uint32_t blocks = (a.total + 255) / 256, cap = (uint32_t)idx->cu_count * 4;
+        const dim3 grid(blocks < cap ? blocks : cap);
+        switch (t.occ_interval) {
+        case 64: hipLaunchKernelGGL(exact_rest<64>, grid, dim3(256), 0, s, w, a.rs_status, a.total, a.nstr, a.strand0); break;
+        case 96: hipLaunchKernelGGL(exact_rest<96>, grid, dim3(256), 0, s, w, a.rs_status, a.total, a.nstr, a.strand0); break;
+        case 128: hipLaunchKernelGGL(exact_rest<128>, grid, dim3(256), 0, s, w, a.rs_status, a.total, a.nstr, a.strand0); break;
+        case 192: hipLaunchKernelGGL(exact_rest<192>, grid, dim3(256), 0, s, w, a.rs_status, a.total, a.nstr, a.strand0); break;
+        case 224: hipLaunchKernelGGL(exact_rest<224>, grid, dim3(256), 0, s, w, a.rs_status, a.total, a.nstr, a.strand0); break;
+        case 256: hipLaunchKernelGGL(exact_rest<256>, grid, dim3(256), 0, s, w, a.rs_status, a.total, a.nstr, a.strand0); break;
+        case 448: hipLaunchKernelGGL(exact_rest<448>, grid, dim3(256), 0, s, w, a.rs_status, a.total, a.nstr, a.strand0); break;
+        default: return hipErrorInvalidValue;
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     pe->mark(3, s);
     // compaction
     uint32_t *cnt = (uint32_t *)(ws + W.cnt), *cursor = (uint32_t *)(ws + W.cursor);

@@ -373,8 +373,9 @@ def fm_search_inexact(idx: Index, codes: torch.Tensor, offs: torch.Tensor, z: to
 def fm_search_both(idx: Index, codes: torch.Tensor, offs: torch.Tensor, z: torch.Tensor, exact_flags: int,
                    flags: int, zmax: int, hit_cap: int, out: torch.Tensor | None = None,
                    bufs: InexactBuffers | None = None, stream=None):
-    """Exact and inexact search of one batch in one pass (fm_search_both). Returns
-    (intervals, bufs) as fm_search_exact and fm_search_inexact would."""
+    """Exact and inexact search of one batch (fm_search_both; the exact intervals are taken
+    from the inexact search's DFS). Returns (intervals, bufs) as fm_search_exact and
+    fm_search_inexact would."""
     _dev(codes, torch.uint8, "codes")
     _dev(offs, torch.int64, "offs")
     _dev(z, torch.uint8, "z")
@@ -388,12 +389,6 @@ def fm_search_both(idx: Index, codes: torch.Tensor, offs: torch.Tensor, z: torch
                                 _ptr(out), _ptr(bufs.hits), bufs.hit_cap, _ptr(bufs.hit_offs), _ptr(bufs.status),
                                 _ptr(bufs.ws), bufs.ws.numel(), _stream(stream)), "fm_search_both")
     return out, bufs
-
-
-def both_exact_stats(bufs: InexactBuffers) -> dict:
-    """With FM_STATS, the exact searches' steps and buckets counted by fm_search_both."""
-    w = bufs.ws[:112].cpu().numpy().view(np.uint64)
-    return {"steps": int(w[12]), "buckets": int(w[13])}
 
 
 def hits_to_numpy(bufs: InexactBuffers, nreads: int):

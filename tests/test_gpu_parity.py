@@ -211,8 +211,8 @@ def test_inexact_plain_and_batched(small, use_d):
 
 @pytest.mark.parametrize("use_d", [False, True])
 def test_search_both_equals_separate_calls(small, use_d):
-    """fm_search_both (exact searches carried by the DFS launch) gives the exact and the
-    inexact results of the separate calls for every layout, lane count and strand set."""
+    """fm_search_both (exact intervals taken from the DFS) gives the exact and the inexact
+    results of the separate calls for every layout, lane count and strand set."""
     R, x, xr, idx = small
     codes, offs, z = inexact_inputs(R)
     flags = fm.FM_BOTH | (fm.FM_DARRAY if use_d else 0)
@@ -232,6 +232,52 @@ def test_search_both_equals_separate_calls(small, use_d):
                 assert_same_hits(fm.hits_to_numpy(bufs, offs.size - 1), wh, wo, (I, L, exf))
     idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=128, lanes=1)
     idx.set_tuning(fm.FM_OP_DARRAY, occ_interval=128, lanes=1)
+
+
+def test_search_both_where_the_dfs_stops_early(small):
+    """fm_search_both takes exact intervals from the DFS. Read-strands whose DFS ends
+    before reaching the match-only leaf still get theirs: budgets above zmax (FM_EINVAL),
+    reads longer than 65535 (FM_ERANGE; one occurs, one does not) and spent node budgets
+    (FM_EBUDGET). An exact strand that the inexact search does not cover runs as a
+    separate search."""
+    R, x, xr, idx = small
+    rd = synth.simulate_reads(R, 500, 31, length=(30, 90), sub=(0.0, 0.04), z=(0, 4))
+    occurs = R[1000:1000 + 66_000].copy()
+    differs = occurs.copy()
+    differs[33_000] = (differs[33_000] + 1) % 4
+    codes = np.concatenate([rd.codes, occurs, differs, R[5000:5080]])
+    ends = rd.offs[-1] + np.cumsum([occurs.size, differs.size, 80])
+    offs = np.concatenate([rd.offs, ends]).astype(np.uint64)
+    z = np.concatenate([rd.z, [1, 0, 3]]).astype(np.uint8)
+    nr = offs.size - 1
+    cd, od, zd = fm.reads_to_device(codes, offs, z)
+    want_ex = x.exact(codes, offs, oracle.BOTH, "listing1")
+    assert (want_ex[-6:, 0] <= want_ex[-6:, 1]).tolist() == [True, False, False, False, True, False]
+    flags = fm.FM_BOTH | fm.FM_DARRAY
+    for budget in (1 << 22, 30):
+        idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=64, lanes=1, node_budget=budget)
+        try:
+            sep = fm.hits_to_numpy(fm.fm_search_inexact(idx, cd, od, zd, flags, 2, 1 << 16), nr)
+            ex, bufs = fm.fm_search_both(idx, cd, od, zd, fm.FM_BOTH, flags, 2, 1 << 16)
+            got = fm.hits_to_numpy(bufs, nr)
+        finally:
+            idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=128, lanes=1, node_budget=1 << 22)
+        st = got[2]
+        say("budget", budget, "statuses", np.unique(st, return_counts=True))
+        assert st[-3] == fm.FM_ERANGE and st[-2] == fm.FM_ERANGE and st[-1] == fm.FM_EINVAL
+        assert ((st == fm.FM_EINVAL) == (z > 2)).all()
+        if budget == 30:
+            assert (st == fm.FM_EBUDGET).any()
+        assert np.array_equal(to_u32(ex), want_ex), budget
+        for u, v in zip(got, sep):
+            assert np.array_equal(u, v), budget
+    # exact on both strands, inexact on the forward strand only
+    for extra in (0, fm.FM_PLAIN):
+        ex, bufs = fm.fm_search_both(idx, cd, od, zd, fm.FM_BOTH, fm.FM_FWD | fm.FM_DARRAY | extra, 2, 1 << 16)
+        sep = fm.hits_to_numpy(fm.fm_search_inexact(idx, cd, od, zd, fm.FM_FWD | fm.FM_DARRAY | extra, 2, 1 << 16), nr)
+        assert np.array_equal(to_u32(ex), want_ex), extra
+        for u, v in zip(fm.hits_to_numpy(bufs, nr), sep):
+            assert np.array_equal(u, v), extra
 
 
 def test_inexact_definition_and_node_count(small):
