@@ -80,7 +80,9 @@ enum {
 /* Load flags. */
 enum {
     FM_LOAD_REVERSE = 1,            /* also build/keep the index of reverse(R) */
-    FM_LOAD_ALL_LAYOUTS = 2         /* build the layouts for every supported I */
+    FM_LOAD_ALL_LAYOUTS = 2,        /* build the layouts for every supported I */
+    FM_LOAD_DEVICE_SORT = 4         /* fm_index_from_text: sort suffixes on the device (see
+                                       fm_bwt_device) instead of the host builder; same index */
 };
 
 #define FM_ZMAX 4                   /* largest per-read mismatch budget */
@@ -137,6 +139,14 @@ int fm_version(void);
  * and 4 at the '$' row, which is stored in *dollar_row. FM_EINVAL on a code above 3
  * or n + 1 >= 2^32; FM_ENOMEM when the builder's memory cannot be allocated. */
 int fm_bwt_host(const uint8_t *text, uint64_t n, uint8_t *bwt, uint64_t *dollar_row);
+
+/* The same BWT computed on a device: the suffixes of R$ are sorted by prefix doubling
+ * (first by their first 21 symbols, then, for the suffixes that still tie, by pairs of
+ * ranks of prefixes of length L and 2L, with device radix sorts), and Eq. 2 is applied
+ * to the result. text and bwt are host arrays as in fm_bwt_host; the device allocates
+ * about 41(n+1) bytes of working memory during the call. FM_EINVAL on a code above 3,
+ * FM_ERANGE when n + 1 >= 2^32, FM_ENOMEM when the device memory cannot be allocated. */
+int fm_bwt_device(const uint8_t *text, uint64_t n, uint8_t *bwt, uint64_t *dollar_row, int device);
 
 /* The library's 2-bit packing (host): code j of `codes` goes to bits 2(j mod 16) and
  * 2(j mod 16)+1 of words[j / 16], least significant first -- the ordering of the

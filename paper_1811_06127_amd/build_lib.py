@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfmocc.so")
-SOURCES = ["layout.hip", "search.hip", "capi.cpp", "build.cpp", "runtime.cpp", "server.cpp"]
+SOURCES = ["sa_build.hip", "layout.hip", "search.hip", "capi.cpp", "build.cpp", "runtime.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

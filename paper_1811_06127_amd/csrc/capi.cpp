@@ -92,7 +92,8 @@ void default_tunings(fm_index *idx, uint32_t I)
     idx->tune[FM_OP_INEXACT] = in;
 }
 
-// Moves packed BWTs to the device and builds the requested layouts.
+// Moves packed BWTs to the device (unless they are there already) and builds the
+// requested layouts.
 int create_index(const fm_load_opts *opts, uint64_t n, const HostSide &fwd, const HostSide *rev, fm_index **out)
 {
     *out = nullptr;
@@ -127,12 +128,18 @@ int create_index(const fm_load_opts *opts, uint64_t n, const HostSide &fwd, cons
     for (uint32_t J : kIntervals) sbytes = std::max(sbytes, build_layout_scratch(n, J));
     void *packed = nullptr, *scratch = nullptr;
     int st = FM_OK;
-    if (hipMalloc(&packed, pbytes ? pbytes : 16) != hipSuccess || hipMalloc(&scratch, sbytes) != hipSuccess) st = FM_ENOMEM;
+    if ((!fwd.dev_words && hipMalloc(&packed, pbytes ? pbytes : 16) != hipSuccess) ||
+        hipMalloc(&scratch, sbytes) != hipSuccess)
+        st = FM_ENOMEM;
     for (int side = 0; side < (rev ? 2 : 1) && !st; ++side) {
         const HostSide &h = side ? *rev : fwd;
-        if (hipMemcpy(packed, h.words.data(), pbytes, hipMemcpyHostToDevice) != hipSuccess) {
-            st = FM_EDEVICE;
-            break;
+        const uint32_t *src = h.dev_words;
+        if (!src) {
+            if (hipMemcpy(packed, h.words.data(), pbytes, hipMemcpyHostToDevice) != hipSuccess) {
+                st = FM_EDEVICE;
+                break;
+            }
+            src = (const uint32_t *)packed;
         }
         for (uint32_t J : kIntervals) {
             if (!all && J != I) continue;
@@ -144,7 +151,7 @@ int create_index(const fm_load_opts *opts, uint64_t n, const HostSide &fwd, cons
             }
             (side ? idx->rlay : idx->lay)[ilog(J)] = buf;
             idx->device_bytes += lb;
-            if (hipError_t e = build_layout((const uint32_t *)packed, n, J, buf, scratch, nullptr)) {
+            if (hipError_t e = build_layout(src, n, J, buf, scratch, nullptr)) {
                 st = hip_status(e);
                 break;
             }
@@ -185,10 +192,74 @@ const char *fm_strerror(int s)
 
 int fm_version(void) { return 1; }
 
+// The BWTs of text$ and (want_rev) reverse(text)$ sorted on the device, as device words.
+static int device_sides(const uint8_t *text, uint64_t n, int dev, bool want_rev, HostSide &fwd, HostSide &rev,
+                        void **words_out)
+{
+    if (n + 1 >= (1ull << 32)) return FM_ERANGE;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || dev < 0 || dev >= ndev) return FM_EDEVICE;
+    DeviceGuard g(dev);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return FM_EDEVICE;
+    const uint64_t nw = (n + 1 + 15) / 16;
+    void *t = nullptr, *w = nullptr;
+    if (hipMalloc(&t, n ? n : 16) != hipSuccess) return FM_ENOMEM;
+    if (hipMalloc(&w, nw * 4 * (want_rev ? 2 : 1)) != hipSuccess) {
+        (void)hipFree(t);
+        return FM_ENOMEM;
+    }
+    int st = FM_OK;
+    uint64_t cnt[5];
+    if (n && hipMemcpy(t, text, n, hipMemcpyHostToDevice) != hipSuccess) st = FM_EDEVICE;
+    if (!st) st = hip_status(device_symbol_counts((const uint8_t *)t, n, cnt, prop.multiProcessorCount, nullptr));
+    if (!st && cnt[4]) st = FM_EINVAL;
+    for (int side = 0; side < (want_rev ? 2 : 1) && !st; ++side) {
+        HostSide &h = side ? rev : fwd;
+        h.dev_words = (const uint32_t *)w + side * nw;
+        hipError_t e = device_bwt((const uint8_t *)t, n, side == 1, (uint32_t *)h.dev_words, &h.dollar,
+                                  prop.multiProcessorCount, nullptr);
+        if (e == hipErrorOutOfMemory) st = FM_ENOMEM;
+        else if (e != hipSuccess) st = FM_EDEVICE;
+        h.C[0] = 0;
+        for (int c = 1; c < 5; ++c) h.C[c] = h.C[c - 1] + cnt[c - 1];
+    }
+    (void)hipFree(t);
+    if (st) {
+        (void)hipFree(w);
+        return st;
+    }
+    *words_out = w;
+    return FM_OK;
+}
+
 int fm_bwt_host(const uint8_t *text, uint64_t n, uint8_t *bwt, uint64_t *dollar_row)
 {
     if ((!text && n) || !bwt || !dollar_row) return FM_EINVAL;
     return build_bwt(text, n, bwt, dollar_row);
+}
+
+int fm_bwt_device(const uint8_t *text, uint64_t n, uint8_t *bwt, uint64_t *dollar_row, int device)
+{
+    if ((!text && n) || !bwt || !dollar_row) return FM_EINVAL;
+    HostSide fwd, rev;
+    void *words = nullptr;
+    int st = device_sides(text, n, device, false, fwd, rev, &words);
+    if (st) return st;
+    std::vector<uint32_t> w;
+    try {
+        w.resize((n + 1 + 15) / 16);
+    } catch (const std::bad_alloc &) {
+        st = FM_ENOMEM;
+    }
+    DeviceGuard g(device);
+    if (!st && hipMemcpy(w.data(), words, w.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) st = FM_EDEVICE;
+    (void)hipFree(words);
+    if (st) return st;
+    for (uint64_t j = 0; j <= n; ++j) bwt[j] = (uint8_t)((w[j / 16] >> (2 * (j % 16))) & 3u);
+    bwt[fwd.dollar] = 4;
+    *dollar_row = fwd.dollar;
+    return FM_OK;
 }
 
 int fm_pack_host(const uint8_t *codes, uint64_t count, uint32_t *words)
@@ -212,6 +283,15 @@ int fm_index_from_text(const uint8_t *text, uint64_t n, const fm_load_opts *opts
     if ((!text && n) || !out) return FM_EINVAL;
     HostSide fwd, rev;
     const bool want_rev = opts && (opts->flags & FM_LOAD_REVERSE);
+    if (opts && (opts->flags & FM_LOAD_DEVICE_SORT)) {
+        void *words = nullptr;
+        int st = device_sides(text, n, opts->device, want_rev, fwd, rev, &words);
+        if (st) return st;
+        st = create_index(opts, n, fwd, want_rev ? &rev : nullptr, out);
+        DeviceGuard g(opts->device);
+        (void)hipFree(words);
+        return st;
+    }
     int st = build_side(text, n, false, fwd);
     if (!st && want_rev) st = build_side(text, n, true, rev);
     if (st) return st;

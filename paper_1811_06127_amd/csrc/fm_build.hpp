@@ -13,6 +13,7 @@ struct HostSide {                 // one text's packed BWT and its constants
     std::vector<uint32_t> words;  // 2-bit codes, '$' stored as 0
     uint64_t dollar = 0;
     uint64_t C[5] = {0, 0, 0, 0, 0};
+    const uint32_t *dev_words = nullptr;   // the same words already in device memory (then `words` is empty)
 };
 
 int build_bwt(const uint8_t *text, uint64_t n, uint8_t *bwt, uint64_t *dollar_row);

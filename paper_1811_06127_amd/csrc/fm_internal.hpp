@@ -82,6 +82,15 @@ hipError_t build_layout(const uint32_t *packed_dev, uint64_t n, uint32_t I, void
                         void *scratch, hipStream_t s);
 size_t build_layout_scratch(uint64_t n, uint32_t I);
 
+// Device suffix sorting (sa_build.hip). device_bwt writes the 2-bit BWT words of text$
+// (or reverse(text)$) and its '$' row; text_dev holds n codes 0..3. It allocates
+// device_bwt_bytes(n) of working memory for the call. device_symbol_counts counts codes
+// 0..3 into out[0..3] and codes above 3 into out[4].
+hipError_t device_bwt(const uint8_t *text_dev, uint64_t n, bool rev, uint32_t *words, uint64_t *dollar_row,
+                      int cu_count, hipStream_t s);
+size_t device_bwt_bytes(uint64_t n);
+hipError_t device_symbol_counts(const uint8_t *text_dev, uint64_t n, uint64_t out[5], int cu_count, hipStream_t s);
+
 hipError_t launch_fill(void *p, uint32_t value, size_t words, hipStream_t s);
 
 hipError_t launch_occ8(const fm_index *idx, const fm_tuning &t, const fm_interval *q, uint64_t nq,

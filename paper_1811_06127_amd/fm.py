@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libfmocc.so")
 
 FM_OK, FM_EINVAL, FM_EIO, FM_EFORMAT, FM_ENOMEM, FM_EDEVICE, FM_EOVERFLOW, FM_EBUDGET, FM_ERANGE, FM_EAGAIN = range(10)
 FM_FWD, FM_REVCOMP, FM_BOTH, FM_DARRAY, FM_PLAIN, FM_STATS = 1, 2, 3, 4, 16, 32
-FM_LOAD_REVERSE, FM_LOAD_ALL_LAYOUTS = 1, 2
+FM_LOAD_REVERSE, FM_LOAD_ALL_LAYOUTS, FM_LOAD_DEVICE_SORT = 1, 2, 4
 FM_OP_EXACT, FM_OP_DARRAY, FM_OP_INEXACT = 0, 1, 2
 FM_ZMAX = 4
 
@@ -90,6 +90,7 @@ def lib() -> C.CDLL:
         "fm_strerror": (C.c_char_p, [i32]),
         "fm_version": (i32, []),
         "fm_bwt_host": (i32, [vp, u64, vp, C.POINTER(C.c_uint64)]),
+        "fm_bwt_device": (i32, [vp, u64, vp, C.POINTER(C.c_uint64), C.c_int]),
         "fm_pack_host": (i32, [vp, u64, vp]),
         "fm_index_build_file": (i32, [vp, u64, C.c_char_p, u32]),
         "fm_index_from_text": (i32, [vp, u64, C.POINTER(LoadOpts), C.POINTER(vp)]),
@@ -176,6 +177,15 @@ def fm_bwt_host(text: np.ndarray):
     bwt = np.zeros(text.size + 1, np.uint8)
     dr = C.c_uint64(0)
     _check(lib().fm_bwt_host(_ptr(text), text.size, _ptr(bwt), C.byref(dr)), "fm_bwt_host")
+    return bwt, int(dr.value)
+
+
+def fm_bwt_device(text: np.ndarray, device: int = 0):
+    """fm_bwt_host's result, computed by the device suffix sort."""
+    text = np.ascontiguousarray(text, dtype=np.uint8)
+    bwt = np.zeros(text.size + 1, np.uint8)
+    dr = C.c_uint64(0)
+    _check(lib().fm_bwt_device(_ptr(text), text.size, _ptr(bwt), C.byref(dr), device), "fm_bwt_device")
     return bwt, int(dr.value)
 
 

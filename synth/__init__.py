@@ -14,6 +14,9 @@ Symbol codes: A=0, C=1, G=2, T=3; 4 marks any non-ACGT read symbol (N).
 from __future__ import annotations
 
 import dataclasses
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 _GAMMA = np.uint64(0x9E3779B97F4A7C15)
@@ -38,6 +41,19 @@ def splitmix64(seed: int, counters: np.ndarray) -> np.ndarray:
         return z
 
 
+def _in_blocks(n: int, block: int, fn) -> None:
+    """fn(a, b) over [0, n) in blocks, on host threads when there are several blocks
+    (numpy releases the GIL inside its array operations)."""
+    spans = [(a, min(n, a + block)) for a in range(0, n, block)]
+    if len(spans) <= 1:
+        for a, b in spans:
+            fn(a, b)
+        return
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1, len(spans))) as ex:
+        for f in [ex.submit(fn, a, b) for a, b in spans]:
+            f.result()
+
+
 class Rng:
     """A SplitMix64 stream that hands out consecutive blocks of outputs."""
 
@@ -60,11 +76,25 @@ class Rng:
         return lo + np.minimum((self.uniform(n) * span).astype(np.int64), span - 1)
 
     def bases(self, n: int) -> np.ndarray:
-        """n i.i.d. uniform codes 0..3 (32 codes per 64-bit output)."""
-        words = self.u64((n + 31) // 32)
-        shifts = np.arange(0, 64, 2, dtype=np.uint64)
-        codes = ((words[:, None] >> shifts[None, :]) & np.uint64(3)).astype(np.uint8)
-        return codes.reshape(-1)[:n].copy()
+        """n i.i.d. uniform codes 0..3 (32 codes per 64-bit output, lowest bits first)."""
+        nw = (n + 31) // 32
+        out = np.empty(nw * 32, np.uint8)
+        ctr0 = self.ctr
+        self.ctr += nw
+
+        def fill(a, b):
+            words = splitmix64(self.seed, np.arange(ctr0 + a, ctr0 + b, dtype=np.uint64))
+            shifts = np.arange(0, 64, 2, dtype=np.uint64)
+            out[32 * a:32 * b] = ((words[:, None] >> shifts[None, :]) & np.uint64(3)).astype(np.uint8).reshape(-1)
+        _in_blocks(nw, 1 << 20, fill)
+        return out[:n] if n == out.size else out[:n].copy()
+
+    def fork(self, n: int) -> "Rng":
+        """A view of the next n outputs of this stream, which is advanced past them."""
+        r = Rng(self.seed)
+        r.ctr = self.ctr
+        self.ctr += n
+        return r
 
     def exponential(self, rate: float, n: int) -> np.ndarray:
         return -np.log1p(-self.uniform(n)) / rate
@@ -158,35 +188,71 @@ def reference_families(n: int, seed: int, iid_frac: float = 0.55, families: int 
     """Genome-like text: iid_frac of n i.i.d. bases with interspersed copies of
     `families` consensus sequences (length log-uniform in fam_len). Each copy is a
     random 5'-truncation of its consensus with i.i.d. substitutions at a per-copy rate
-    ~ U[div]. Copies are inserted at uniform positions until the length is n."""
+    ~ U[div]. Copies are inserted at uniform positions until the length is n.
+
+    Draw order: the i.i.d. bases; the family lengths and consensus bases; then, in
+    blocks of 2^16 copies, the family, start and divergence of each (the last copy is
+    truncated to fill n exactly); the substitution draws of the copies in order; the
+    insertion positions. Copies inserted at the same position keep their draw order."""
     rng = Rng(seed)
     base_len = int(round(n * iid_frac))
     base = rng.bases(base_len)
     lens = np.exp(np.log(fam_len[0]) + rng.uniform(families) * (np.log(fam_len[1]) - np.log(fam_len[0])))
     cons = [rng.bases(int(x)) for x in lens]
-    inserts = []
-    total = base_len
-    while total < n:
-        f = int(rng.integers(0, families - 1, 1)[0])
-        c = cons[f]
-        start = int(rng.integers(0, c.size - 1, 1)[0])
-        piece = c[start:]
-        piece = piece[: n - total]
-        rate = float(div[0] + rng.uniform(1)[0] * (div[1] - div[0]))
-        inserts.append(substitute(piece, rate, rng))
-        total += piece.size
-    pos = rng.integers(0, base_len, len(inserts))
+    clen = np.array([c.size for c in cons], np.int64)
+    coff = np.zeros(families + 1, np.int64)
+    np.cumsum(clen, out=coff[1:])
+    allc = np.concatenate(cons)
+    need = n - base_len
+    fams, starts, rates, plens = [], [], [], []
+    got = 0
+    while got < need:
+        k = 1 << 16
+        f = rng.integers(0, families - 1, k)
+        st = np.minimum((rng.uniform(k) * clen[f]).astype(np.int64), clen[f] - 1)
+        rt = div[0] + rng.uniform(k) * (div[1] - div[0])
+        pl = clen[f] - st
+        take = min(k, int(np.searchsorted(np.cumsum(pl), need - got, side="left")) + 1)
+        pl = pl[:take].copy()
+        over = got + int(pl.sum()) - need
+        if over > 0:
+            pl[-1] -= over
+        fams.append(f[:take])
+        starts.append(st[:take])
+        rates.append(rt[:take])
+        plens.append(pl)
+        got += int(pl.sum())
+    f = np.concatenate(fams) if fams else np.zeros(0, np.int64)
+    st = np.concatenate(starts) if starts else np.zeros(0, np.int64)
+    rt = np.concatenate(rates) if rates else np.zeros(0)
+    pl = np.concatenate(plens) if plens else np.zeros(0, np.int64)
+    poff = np.zeros(pl.size + 1, np.int64)
+    np.cumsum(pl, out=poff[1:])
+    copies = np.empty(need, np.uint8)
+    sub = rng.fork(need)             # one substitution draw per copied position, in order
+
+    def make(a, b):
+        lo, hi = int(poff[a]), int(poff[b])
+        src = np.repeat(coff[f[a:b]] + st[a:b] - (poff[a:b] - lo), pl[a:b]) + np.arange(hi - lo, dtype=np.int64)
+        r = Rng(seed)
+        r.ctr = sub.ctr + lo
+        copies[lo:hi] = substitute(allc[src], np.repeat(rt[a:b], pl[a:b]), r)
+    _in_blocks(pl.size, 1 << 13, make)
+    pos = rng.integers(0, base_len, pl.size)
     order = np.argsort(pos, kind="stable")
-    pieces = []
-    prev = 0
-    for j in order:
+    out = np.empty(n, np.uint8)
+    o = prev = 0
+    for j in order.tolist():
         p = int(pos[j])
-        pieces.append(base[prev:p])
-        pieces.append(inserts[j])
-        prev = p
-    pieces.append(base[prev:])
-    out = np.concatenate(pieces)
-    assert out.size == n
+        if p > prev:
+            out[o:o + p - prev] = base[prev:p]
+            o += p - prev
+            prev = p
+        c0, c1 = int(poff[j]), int(poff[j + 1])
+        out[o:o + c1 - c0] = copies[c0:c1]
+        o += c1 - c0
+    out[o:] = base[prev:]
+    assert o + base_len - prev == n
     return out
 
 

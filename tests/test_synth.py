@@ -46,3 +46,21 @@ def test_occ8_queries_ranges():
     assert q[:, 0].max() <= 1001 and q[:, 1].max() <= 1000
     q = synth.occ8_queries(1000, 10_000, 4, "narrow")
     assert np.all(q[:, 0].astype(np.int64) <= q[:, 1].astype(np.int64) + 1)
+
+
+def test_stream_helpers_and_threaded_blocks():
+    """Exponential gaps, forked streams and the block-threaded bases draw the same values
+    as one sequential stream."""
+    r = synth.Rng(77)
+    g = r.exponential(2.0, 200_000)
+    assert (g > 0).all() and abs(g.mean() - 0.5) < 0.01
+    a, b = synth.Rng(9), synth.Rng(9)
+    f = a.fork(1000)
+    assert a.ctr == 1000 and np.array_equal(f.u64(1000), b.u64(1000))
+    n = (1 << 20) * 32 * 3 + 17                      # several blocks and a ragged tail
+    x = synth.Rng(5).bases(n)
+    w = synth.Rng(5).u64((n + 31) // 32)
+    assert np.array_equal(x[:64], ((w[:2, None] >> np.arange(0, 64, 2, dtype=np.uint64)) & np.uint64(3)).reshape(-1))
+    assert np.array_equal(x[-17:], ((w[-1] >> np.arange(0, 34, 2, dtype=np.uint64)) & np.uint64(3)).astype(np.uint8))
+    ref = synth.reference_families(300_000, 4)
+    assert np.array_equal(ref, synth.reference_families(300_000, 4)) and ref.size == 300_000
