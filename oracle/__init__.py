@@ -47,7 +47,7 @@ def build(src: str = _SRC, out: str = _LIB, extra: tuple = ()) -> str:
     """Compile the oracle with gcc into a shared object."""
     os.makedirs(os.path.dirname(out), exist_ok=True)
     tmp = out + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", *extra, "-o", tmp, src])
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-pthread", *extra, "-o", tmp, src])
     os.replace(tmp, out)
     return out
 
@@ -87,6 +87,10 @@ def load(path: str = _LIB) -> C.CDLL:
     lib.oracle_rank_scan.restype = None
     lib.oracle_hits_pigeonhole.argtypes = [u8p, i64, u8p, i64, C.c_int, u32p, i64]
     lib.oracle_hits_pigeonhole.restype = i64
+    lib.oracle_rank_scan_batch.argtypes = [u8p, i64, u8p, u64p, i64, C.c_int, p, p]
+    lib.oracle_rank_scan_batch.restype = C.c_int
+    lib.oracle_hits_pigeonhole_batch.argtypes = [u8p, i64, u8p, u64p, p, i64, C.c_int, u32p, i64, p]
+    lib.oracle_hits_pigeonhole_batch.restype = i64
     _lib_cache[path] = lib
     return lib
 
@@ -268,3 +272,78 @@ def pigeonhole_hits(R: np.ndarray, codes, offs, z, strands: int = BOTH, lib_path
                 rows.append((r, int(h[0]), int(h[1]), s, int(h[2]), 0))
         hit_offs[r + 1] = len(rows)
     return np.array(rows, dtype=HIT_DTYPE), hit_offs
+
+
+# ---------------------------------------------------------------- batched text-only checkers
+
+def _strand_patterns(codes, offs, strands: int):
+    """The strand patterns of every read (strand order within a read) as codes + offsets,
+    with their read and strand."""
+    offs = np.asarray(offs, dtype=np.uint64)
+    pats, rid, sid = [], [], []
+    for r in range(offs.size - 1):
+        W = np.asarray(codes[int(offs[r]):int(offs[r + 1])], dtype=np.uint8)
+        for s in (0, 1):
+            if strands & (1 << s):
+                pats.append(strand_pattern(W, s))
+                rid.append(r)
+                sid.append(s)
+    po = np.zeros(len(pats) + 1, dtype=np.uint64)
+    np.cumsum([x.size for x in pats], out=po[1:])
+    pc = np.concatenate(pats) if pats and po[-1] else np.zeros(1, np.uint8)
+    return pc, po, np.array(rid, dtype=np.int64), np.array(sid, dtype=np.int64)
+
+
+def exact_by_rank_scan_batch(R: np.ndarray, codes, offs, strands: int = FWD, threads: int = 1,
+                             lib_path: str = _LIB) -> np.ndarray:
+    """exact_by_rank_scan for a whole batch: two passes over the text on `threads`
+    host threads."""
+    lib = load(lib_path)
+    R = np.ascontiguousarray(R, dtype=np.uint8)
+    pc, po, _, _ = _strand_patterns(codes, offs, strands)
+    npat = po.size - 1
+    k = np.zeros(npat, np.int64)
+    occ = np.zeros(npat, np.int64)
+    if lib.oracle_rank_scan_batch(_ptr(R), R.size, _ptr(pc), _ptr(po), npat, threads, _ptr(k), _ptr(occ)):
+        raise MemoryError("oracle_rank_scan_batch")
+    out = np.zeros((npat, 2), np.uint32)
+    hit = occ > 0
+    out[hit, 0] = k[hit]
+    out[hit, 1] = k[hit] + occ[hit] - 1
+    out[~hit] = (1, 0)
+    return out
+
+
+def pigeonhole_hits_batch(R: np.ndarray, codes, offs, z, strands: int = BOTH, threads: int = 1,
+                          lib_path: str = _LIB):
+    """pigeonhole_hits for a whole batch: one pass over the text for the seeds and two for
+    the intervals of the distinct windows, on `threads` host threads."""
+    lib = load(lib_path)
+    R = np.ascontiguousarray(R, dtype=np.uint8)
+    nreads = np.asarray(offs).size - 1
+    zr = np.broadcast_to(np.asarray(z, dtype=np.uint8), (nreads,))
+    pc, po, rid, sid = _strand_patterns(codes, offs, strands)
+    npat = po.size - 1
+    zq = zr[rid].astype(np.int32) if npat else np.zeros(0, np.int32)
+    cap = max(1024, 4 * npat)
+    while True:
+        buf = np.zeros(3 * cap, np.uint32)
+        hoff = np.zeros(npat + 1, np.int64)
+        tot = int(lib.oracle_hits_pigeonhole_batch(_ptr(R), R.size, _ptr(pc), _ptr(po), _ptr(zq), npat, threads,
+                                                    _ptr(buf), cap, _ptr(hoff)))
+        if tot < 0:
+            raise MemoryError("oracle_hits_pigeonhole_batch")
+        if tot <= cap:
+            break
+        cap = tot
+    trip = buf[:3 * tot].reshape(-1, 3)
+    hits = np.zeros(tot, dtype=HIT_DTYPE)
+    per = np.diff(hoff)
+    hits["read"] = np.repeat(rid, per)
+    hits["strand"] = np.repeat(sid, per)
+    hits["k"] = trip[:, 0]
+    hits["l"] = trip[:, 1]
+    hits["d"] = trip[:, 2]
+    hit_offs = np.zeros(nreads + 1, dtype=np.uint64)
+    np.cumsum(np.bincount(hits["read"].astype(np.int64), minlength=nreads), out=hit_offs[1:])
+    return hits, hit_offs

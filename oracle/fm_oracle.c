@@ -33,6 +33,7 @@
  *
  * Symbol codes: A=0, C=1, G=2, T=3; '$' is kept out of band (BWT code 4).
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -578,4 +579,459 @@ int64_t oracle_hits_pigeonhole(const uint8_t *R, int64_t n, const uint8_t *P, in
     }
     free(cand);
     return nh;
+}
+
+/* ----------------------------------------------------------------- batched scale checkers
+ *
+ * The rank scan and the pigeonhole checker above take one pass over T per pattern. The
+ * functions below give the same results for a whole batch of patterns in a few passes,
+ * on host threads, so that texts of billions of symbols can be checked on thousands of
+ * reads. They use nothing but T itself: no suffix array, BWT or Occ.
+ *
+ * Keys: the first KEYLEN symbols of a string as base-5 digits (codes 0..4, first symbol
+ * most significant), so keys order like the strings they start. A text position whose
+ * suffix has fewer than KEYLEN symbols before '$' has no key and is compared in full.
+ */
+#define KEYLEN 10
+#define NKEYS 9765625            /* 5^10 */
+
+static uint32_t key_of(const uint8_t *s)
+{
+    uint32_t k = 0;
+    for (int i = 0; i < KEYLEN; i++) k = k * 5u + s[i];
+    return k;
+}
+
+/* Three-way comparison of suffix j of T = R$ with P (length m): -1 when the suffix is
+ * smaller ('$' sorts first), 0 when P is a prefix of the suffix (an occurrence), 1 when
+ * larger. */
+static int suffix_vs(const uint8_t *R, int64_t n, int64_t j, const uint8_t *P, int64_t m)
+{
+    const int64_t avail = n - j;
+    const int64_t t = avail < m ? avail : m;
+    const int r = t ? memcmp(R + j, P, (size_t)t) : 0;
+    if (r < 0) return -1;
+    if (r > 0) return 1;
+    return avail < m ? -1 : 0;
+}
+
+typedef struct {
+    const uint8_t *R;
+    int64_t n, lo, hi;          /* text positions [lo, hi) */
+    uint32_t *hist;             /* NKEYS counters (pass 1) */
+    /* pass 2 */
+    const uint8_t *inset;       /* NKEYS flags: some long pattern has this key */
+    const uint32_t *bkey;       /* sorted keys of the long patterns */
+    const int64_t *border;      /* pattern ids in bkey order */
+    int64_t nb;
+    const uint8_t *codes;
+    const uint64_t *offs;
+    int64_t *less, *occ;        /* per pattern, this thread's counts */
+} ScanPart;
+
+static void *hist_pass(void *arg)
+{
+    ScanPart *p = arg;
+    const int64_t end = p->n - KEYLEN;        /* last position with a key */
+    for (int64_t j = p->lo; j < p->hi && j <= end; j++) p->hist[key_of(p->R + j)]++;
+    return NULL;
+}
+
+static void *bucket_pass(void *arg)
+{
+    ScanPart *p = arg;
+    const int64_t end = p->n - KEYLEN;
+    for (int64_t j = p->lo; j < p->hi && j <= end; j++) {
+        const uint32_t k = key_of(p->R + j);
+        if (!p->inset[k]) continue;
+        int64_t a = 0, b = p->nb;             /* first bucket entry with this key */
+        while (a < b) {
+            const int64_t mid = (a + b) / 2;
+            if (p->bkey[mid] < k) a = mid + 1;
+            else b = mid;
+        }
+        for (int64_t e = a; e < p->nb && p->bkey[e] == k; e++) {
+            const int64_t q = p->border[e];
+            const int64_t m = (int64_t)(p->offs[q + 1] - p->offs[q]);
+            const int c = suffix_vs(p->R, p->n, j, p->codes + p->offs[q], m);
+            if (c < 0) p->less[q]++;
+            else if (c == 0) p->occ[q]++;
+        }
+    }
+    return NULL;
+}
+
+static int cmp_u32_pair(const void *a, const void *b)
+{
+    const uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : x > y;
+}
+
+/* For patterns q = 0..np-1 (codes[offs[q] .. offs[q+1]), codes 0..4): k[q] = number of
+ * suffixes of T = R$ smaller than the pattern and occ[q] = number of its occurrences in
+ * R -- oracle_rank_scan for every pattern, in two passes over R on `threads` threads.
+ * A suffix with a key and a pattern of at least KEYLEN symbols compare by key unless the
+ * keys are equal; then, and for shorter patterns or suffixes, the comparison is made in
+ * full (shorter patterns P compare against keys through the range of keys that start
+ * with P). Returns 0, or -1 when memory runs out. */
+int oracle_rank_scan_batch(const uint8_t *R, int64_t n, const uint8_t *codes, const uint64_t *offs, int64_t np,
+                           int threads, int64_t *k, int64_t *occ)
+{
+    if (threads < 1) threads = 1;
+    int rc = -1;
+    uint64_t *cum = NULL;                       /* cum[key] = text keys below key */
+    uint32_t **hist = calloc((size_t)threads, sizeof *hist);
+    ScanPart *part = calloc((size_t)threads, sizeof *part);
+    pthread_t *tid = calloc((size_t)threads, sizeof *tid);
+    uint8_t *inset = NULL;
+    uint64_t *kb = NULL;
+    uint32_t *bkey = NULL;
+    int64_t *border = NULL, *lessv = NULL, *occv = NULL;
+    if (!hist || !part || !tid) goto out;
+    for (int64_t q = 0; q < np; q++) k[q] = occ[q] = 0;
+    const int64_t chunk = (n + threads - 1) / threads;
+
+    /* pass 1: histogram of the text's keys */
+    for (int t = 0; t < threads; t++) {
+        hist[t] = calloc(NKEYS, sizeof(uint32_t));
+        if (!hist[t]) goto out;
+        part[t].R = R;
+        part[t].n = n;
+        part[t].lo = t * chunk;
+        part[t].hi = (t + 1) * chunk < n ? (t + 1) * chunk : n;
+        part[t].hist = hist[t];
+        pthread_create(&tid[t], NULL, hist_pass, &part[t]);
+    }
+    for (int t = 0; t < threads; t++) pthread_join(tid[t], NULL);
+    cum = malloc(sizeof(uint64_t) * (NKEYS + 1));
+    if (!cum) goto out;
+    cum[0] = 0;
+    for (uint32_t key = 0; key < NKEYS; key++) {
+        uint64_t s = 0;
+        for (int t = 0; t < threads; t++) s += hist[t][key];
+        cum[key + 1] = cum[key] + s;
+    }
+
+    /* keyed part of each pattern's counts */
+    int64_t nlong = 0;
+    for (int64_t q = 0; q < np; q++) {
+        const uint8_t *P = codes + offs[q];
+        const int64_t m = (int64_t)(offs[q + 1] - offs[q]);
+        if (m >= KEYLEN) {
+            k[q] = (int64_t)cum[key_of(P)];        /* keyed suffixes with a smaller key */
+            nlong++;
+        } else {
+            /* keys starting with P: [P 0..0, P 4..4]; smaller keys are smaller suffixes,
+               keys in the range are suffixes that P is a prefix of */
+            uint32_t lo = 0, hi = 0;
+            for (int i = 0; i < KEYLEN; i++) {
+                lo = lo * 5u + (i < m ? P[i] : 0u);
+                hi = hi * 5u + (i < m ? P[i] : 4u);
+            }
+            k[q] = (int64_t)cum[lo];
+            occ[q] = (int64_t)(cum[hi + 1] - cum[lo]);
+        }
+    }
+
+    /* pass 2: keyed suffixes in the bucket of a long pattern, compared in full */
+    if (nlong) {
+        inset = calloc(NKEYS, 1);
+        kb = malloc(sizeof(uint64_t) * (size_t)nlong);
+        bkey = malloc(sizeof(uint32_t) * (size_t)nlong);
+        border = malloc(sizeof(int64_t) * (size_t)nlong);
+        lessv = calloc((size_t)np * (size_t)threads, sizeof(int64_t));
+        occv = calloc((size_t)np * (size_t)threads, sizeof(int64_t));
+        if (!inset || !kb || !bkey || !border || !lessv || !occv) goto out;
+        int64_t e = 0;
+        for (int64_t q = 0; q < np; q++) {
+            const int64_t m = (int64_t)(offs[q + 1] - offs[q]);
+            if (m < KEYLEN) continue;
+            const uint32_t key = key_of(codes + offs[q]);
+            kb[e++] = ((uint64_t)key << 32) | (uint64_t)q;   /* np < 2^32 */
+            inset[key] = 1;
+        }
+        qsort(kb, (size_t)nlong, sizeof(uint64_t), cmp_u32_pair);
+        for (e = 0; e < nlong; e++) {
+            bkey[e] = (uint32_t)(kb[e] >> 32);
+            border[e] = (int64_t)(kb[e] & 0xFFFFFFFFu);
+        }
+        for (int t = 0; t < threads; t++) {
+            part[t].inset = inset;
+            part[t].bkey = bkey;
+            part[t].border = border;
+            part[t].nb = nlong;
+            part[t].codes = codes;
+            part[t].offs = offs;
+            part[t].less = lessv + (size_t)t * (size_t)np;
+            part[t].occ = occv + (size_t)t * (size_t)np;
+            pthread_create(&tid[t], NULL, bucket_pass, &part[t]);
+        }
+        for (int t = 0; t < threads; t++) pthread_join(tid[t], NULL);
+        for (int t = 0; t < threads; t++)
+            for (int64_t q = 0; q < np; q++) {
+                k[q] += lessv[(size_t)t * (size_t)np + q];
+                occ[q] += occv[(size_t)t * (size_t)np + q];
+            }
+    }
+
+    /* suffixes without a key (fewer than KEYLEN symbols before '$'), compared in full */
+    for (int64_t j = n - KEYLEN + 1 < 0 ? 0 : n - KEYLEN + 1; j <= n; j++)
+        for (int64_t q = 0; q < np; q++) {
+            const int c = suffix_vs(R, n, j, codes + offs[q], (int64_t)(offs[q + 1] - offs[q]));
+            if (c < 0) k[q]++;
+            else if (c == 0) occ[q]++;
+        }
+    rc = 0;
+out:
+    if (hist)
+        for (int t = 0; t < threads; t++) free(hist[t]);
+    free(hist);
+    free(part);
+    free(tid);
+    free(cum);
+    free(inset);
+    free(kb);
+    free(bkey);
+    free(border);
+    free(lessv);
+    free(occv);
+    return rc;
+}
+
+/* ---- pigeonhole for a batch of patterns */
+
+#define SEEDLEN 12               /* seeds are found by their first 12 symbols, 2 bits each */
+
+typedef struct {
+    const uint8_t *R;
+    int64_t n, lo, hi;
+    const uint64_t *seedbits;    /* 4^12 bits: some seed starts with these 12 symbols */
+    const uint64_t *seeds;       /* sorted (key << 32 | seed id) */
+    int64_t ns;
+    const int64_t *seed_q, *seed_a, *seed_len;   /* per seed: pattern, piece start, piece length */
+    const uint8_t *codes;
+    const uint64_t *offs;
+    const int *z;
+    int64_t *cand;               /* (pattern, window start) pairs found by this thread */
+    int64_t ncand, ccap;
+    int failed;
+} SeedPart;
+
+static void *seed_pass(void *arg)
+{
+    SeedPart *p = arg;
+    const int64_t last = p->n - SEEDLEN;
+    uint32_t key = 0;
+    const uint32_t mask = (1u << (2 * SEEDLEN)) - 1u;
+    int64_t j0 = p->lo;
+    for (int i = 0; i < SEEDLEN - 1 && j0 + i < p->n; i++) key = (key << 2) | p->R[j0 + i];
+    for (int64_t j = j0; j < p->hi && j <= last; j++) {
+        key = ((key << 2) | p->R[j + SEEDLEN - 1]) & mask;
+        if (!((p->seedbits[key >> 6] >> (key & 63)) & 1u)) continue;
+        int64_t a = 0, b = p->ns;
+        while (a < b) {
+            const int64_t mid = (a + b) / 2;
+            if ((p->seeds[mid] >> 32) < key) a = mid + 1;
+            else b = mid;
+        }
+        for (int64_t e = a; e < p->ns && (p->seeds[e] >> 32) == key; e++) {
+            const int64_t sd = (int64_t)(p->seeds[e] & 0xFFFFFFFFu);
+            const int64_t q = p->seed_q[sd], pa = p->seed_a[sd], len = p->seed_len[sd];
+            const uint8_t *P = p->codes + p->offs[q];
+            const int64_t m = (int64_t)(p->offs[q + 1] - p->offs[q]);
+            const int64_t s = j - pa;
+            if (s < 0 || s + m > p->n) continue;
+            if (memcmp(p->R + j, P + pa, (size_t)len) != 0) continue;
+            if (hamming(p->R + s, P, m) > p->z[q]) continue;
+            if (p->ncand == p->ccap) {
+                const int64_t nc = p->ccap ? 2 * p->ccap : 1024;
+                int64_t *c = realloc(p->cand, sizeof(int64_t) * 2 * (size_t)nc);
+                if (!c) {
+                    p->failed = 1;
+                    return NULL;
+                }
+                p->cand = c;
+                p->ccap = nc;
+            }
+            p->cand[2 * p->ncand] = q;
+            p->cand[2 * p->ncand + 1] = s;
+            p->ncand++;
+        }
+    }
+    return NULL;
+}
+
+static const uint8_t *pg_R;
+static const int64_t *pg_len;   /* window length per pattern */
+
+/* order of candidates: pattern, then window content, then start */
+static int cmp_cand(const void *pa, const void *pb)
+{
+    const int64_t *x = pa, *y = pb;
+    if (x[0] != y[0]) return x[0] < y[0] ? -1 : 1;
+    const int r = memcmp(pg_R + x[1], pg_R + y[1], (size_t)pg_len[x[0]]);
+    if (r) return r;
+    return (x[1] > y[1]) - (x[1] < y[1]);
+}
+
+/* oracle_hits_pigeonhole for patterns q = 0..np-1 with budgets z[q] <= 7: hits of pattern
+ * q go to out[3*hoff[q] .. 3*hoff[q+1]) as (k, l, d) triples sorted by k, for up to cap
+ * triples in all; hoff (np + 1 entries) is written even when cap is exceeded. Seeds
+ * (pieces of at least SEEDLEN symbols holding no N) are found in one pass over R on
+ * `threads` threads; patterns with a shorter piece use oracle_hits_pigeonhole. The
+ * distinct windows get their intervals from oracle_rank_scan_batch. Returns the total
+ * number of hits, or -1 when memory runs out. */
+int64_t oracle_hits_pigeonhole_batch(const uint8_t *R, int64_t n, const uint8_t *codes, const uint64_t *offs,
+                                     const int *z, int64_t np, int threads, uint32_t *out, int64_t cap,
+                                     int64_t *hoff)
+{
+    if (threads < 1) threads = 1;
+    int64_t total = -1;
+    int64_t ns = 0, scap = 0;
+    int64_t *seed_q = NULL, *seed_a = NULL, *seed_len = NULL, *wlen = NULL, *cand = NULL, *nh = NULL;
+    uint64_t *seeds = NULL, *seedbits = NULL, *woffs = NULL;
+    uint8_t *slow = NULL, *wcodes = NULL;
+    int64_t *wk = NULL, *wocc = NULL;
+    SeedPart *part = calloc((size_t)threads, sizeof *part);
+    pthread_t *tid = calloc((size_t)threads, sizeof *tid);
+    slow = calloc((size_t)np + 1, 1);
+    wlen = malloc(sizeof(int64_t) * ((size_t)np + 1));
+    nh = calloc((size_t)np + 1, sizeof(int64_t));
+    if (!part || !tid || !slow || !wlen || !nh) goto out;
+
+    for (int64_t q = 0; q < np; q++) {
+        const uint8_t *P = codes + offs[q];
+        const int64_t m = (int64_t)(offs[q + 1] - offs[q]);
+        const int parts = z[q] + 1;
+        wlen[q] = m;
+        for (int i = 0; i < parts; i++)
+            if (m * (i + 1) / parts - m * i / parts < SEEDLEN) slow[q] = 1;
+        if (slow[q]) continue;
+        for (int i = 0; i < parts; i++) {
+            const int64_t a = m * i / parts, b = m * (i + 1) / parts;
+            int has_n = 0;
+            for (int64_t x = a; x < b; x++) has_n |= P[x] > 3;
+            if (has_n) continue;
+            if (ns == scap) {
+                scap = scap ? 2 * scap : 1024;
+                seeds = realloc(seeds, sizeof(uint64_t) * (size_t)scap);
+                seed_q = realloc(seed_q, sizeof(int64_t) * (size_t)scap);
+                seed_a = realloc(seed_a, sizeof(int64_t) * (size_t)scap);
+                seed_len = realloc(seed_len, sizeof(int64_t) * (size_t)scap);
+                if (!seeds || !seed_q || !seed_a || !seed_len) goto out;
+            }
+            uint32_t key = 0;
+            for (int x = 0; x < SEEDLEN; x++) key = (key << 2) | P[a + x];
+            seeds[ns] = ((uint64_t)key << 32) | (uint64_t)ns;
+            seed_q[ns] = q;
+            seed_a[ns] = a;
+            seed_len[ns] = b - a;
+            ns++;
+        }
+    }
+    seedbits = calloc((size_t)1 << (2 * SEEDLEN - 6), sizeof(uint64_t));
+    if (!seedbits) goto out;
+    if (ns) qsort(seeds, (size_t)ns, sizeof(uint64_t), cmp_u32_pair);
+    for (int64_t e = 0; e < ns; e++) {
+        const uint32_t key = (uint32_t)(seeds[e] >> 32);
+        seedbits[key >> 6] |= 1ull << (key & 63);
+    }
+    const int64_t chunk = (n + threads - 1) / threads;
+    for (int t = 0; t < threads; t++) {
+        SeedPart *p = &part[t];
+        p->R = R;
+        p->n = n;
+        p->lo = t * chunk;
+        p->hi = (t + 1) * chunk < n ? (t + 1) * chunk : n;
+        p->seedbits = seedbits;
+        p->seeds = seeds;
+        p->ns = ns;
+        p->seed_q = seed_q;
+        p->seed_a = seed_a;
+        p->seed_len = seed_len;
+        p->codes = codes;
+        p->offs = offs;
+        p->z = z;
+        pthread_create(&tid[t], NULL, seed_pass, p);
+    }
+    int64_t nc = 0;
+    for (int t = 0; t < threads; t++) {
+        pthread_join(tid[t], NULL);
+        if (part[t].failed) goto out;
+        nc += part[t].ncand;
+    }
+    cand = malloc(sizeof(int64_t) * 2 * (size_t)(nc ? nc : 1));
+    if (!cand) goto out;
+    nc = 0;
+    for (int t = 0; t < threads; t++) {
+        memcpy(cand + 2 * nc, part[t].cand, sizeof(int64_t) * 2 * (size_t)part[t].ncand);
+        nc += part[t].ncand;
+    }
+    pg_R = R;
+    pg_len = wlen;
+    if (nc) qsort(cand, (size_t)nc, 2 * sizeof(int64_t), cmp_cand);
+    /* distinct windows per pattern, in content order */
+    int64_t nw = 0;
+    for (int64_t c = 0; c < nc; c++) {
+        const int64_t q = cand[2 * c], s = cand[2 * c + 1];
+        if (c > 0 && cand[2 * c - 2] == q && memcmp(R + cand[2 * c - 1], R + s, (size_t)wlen[q]) == 0) continue;
+        cand[2 * nw] = q;
+        cand[2 * nw + 1] = s;
+        nw++;
+    }
+    woffs = malloc(sizeof(uint64_t) * ((size_t)nw + 1));
+    wk = malloc(sizeof(int64_t) * ((size_t)nw + 1));
+    wocc = malloc(sizeof(int64_t) * ((size_t)nw + 1));
+    if (!woffs || !wk || !wocc) goto out;
+    woffs[0] = 0;
+    for (int64_t w = 0; w < nw; w++) woffs[w + 1] = woffs[w] + (uint64_t)wlen[cand[2 * w]];
+    wcodes = malloc(woffs[nw] ? woffs[nw] : 1);
+    if (!wcodes) goto out;
+    for (int64_t w = 0; w < nw; w++) memcpy(wcodes + woffs[w], R + cand[2 * w + 1], (size_t)wlen[cand[2 * w]]);
+    if (oracle_rank_scan_batch(R, n, wcodes, woffs, nw, threads, wk, wocc)) goto out;
+
+    /* hits per pattern: the batch's windows, or the per-pattern checker for slow ones */
+    for (int64_t w = 0; w < nw; w++) nh[cand[2 * w]]++;
+    total = 0;
+    int64_t w = 0;
+    for (int64_t q = 0; q < np; q++) {
+        hoff[q] = total;
+        const uint8_t *P = codes + offs[q];
+        const int64_t m = wlen[q];
+        if (slow[q] || m == 0) {
+            uint32_t *dst = total < cap ? out + 3 * total : NULL;
+            const int64_t room = total < cap ? cap - total : 0;
+            const int64_t h = oracle_hits_pigeonhole(R, n, P, m, z[q], dst, room);
+            total += h;
+            continue;
+        }
+        for (; w < nw && cand[2 * w] == q; w++) {
+            if (total < cap) {
+                out[3 * total] = (uint32_t)wk[w];
+                out[3 * total + 1] = (uint32_t)(wk[w] + wocc[w] - 1);
+                out[3 * total + 2] = (uint32_t)hamming(R + cand[2 * w + 1], P, m);
+            }
+            total++;
+        }
+    }
+    hoff[np] = total;
+out:
+    if (part)
+        for (int t = 0; t < threads; t++) free(part[t].cand);
+    free(part);
+    free(tid);
+    free(slow);
+    free(wlen);
+    free(nh);
+    free(seeds);
+    free(seed_q);
+    free(seed_a);
+    free(seed_len);
+    free(seedbits);
+    free(cand);
+    free(woffs);
+    free(wcodes);
+    free(wk);
+    free(wocc);
+    return total;
 }

@@ -109,16 +109,17 @@ def substitute(codes: np.ndarray, rate, rng: Rng) -> np.ndarray:
     to the code, mod 4). Positions holding code 4 (N) are left alone."""
     out = codes.copy()
     rate = np.broadcast_to(np.asarray(rate, dtype=np.float64), codes.shape)
-    step = 1 << 24
-    for a in range(0, codes.size, step):
-        b = min(codes.size, a + step)
-        u = rng.u64(b - a)
+    draws = rng.fork(codes.size)
+
+    def block(a, b):
+        u = splitmix64(draws.seed, np.arange(draws.ctr + a, draws.ctr + b, dtype=np.uint64))
         thr = (rate[a:b] * 4294967296.0).astype(np.uint64)
         hit = (u >> np.uint64(32)) < thr
         shift = (((u & np.uint64(0xFFFFFFFF)) * np.uint64(3)) >> np.uint64(32)).astype(np.uint8) + np.uint8(1)
         seg = out[a:b]
         m = hit & (seg < 4)
         seg[m] = (seg[m] + shift[m]) & 3
+    _in_blocks(codes.size, 1 << 24, block)
     return out
 
 
@@ -290,9 +291,8 @@ def _gather(ref: np.ndarray, starts: np.ndarray, lens: np.ndarray, minus: np.nda
     offs = np.zeros(lens.size + 1, dtype=np.int64)
     np.cumsum(lens, out=offs[1:])
     out = np.empty(int(offs[-1]), dtype=np.uint8)
-    step = 1 << 18
-    for a in range(0, lens.size, step):
-        b = min(lens.size, a + step)
+
+    def block(a, b):
         ln = lens[a:b].astype(np.int64)
         base = offs[a:b] - offs[a]
         rid = np.repeat(np.arange(b - a, dtype=np.int32), ln)
@@ -303,6 +303,7 @@ def _gather(ref: np.ndarray, starts: np.ndarray, lens: np.ndarray, minus: np.nda
         seg = ref[idx]
         seg[mrow] = 3 - seg[mrow]
         out[offs[a]:offs[b]] = seg
+    _in_blocks(lens.size, 1 << 18, block)
     return out
 
 

@@ -1,0 +1,115 @@
+"""Batching at genome scale: a 3.1e9-base text (55% i.i.d., 45% copies of 500 repeat
+families with 5-15% divergence), 16M reads of 150 bp with 1% substitutions, z = 2 with
+the D bound on both strands, in 16 batches of 1M replayed from one captured launch graph.
+Every batch equals the plain kernels bit for bit; a sample of reads is checked against
+the oracle's text-only checkers (batched rank scans and pigeonhole hit sets)."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_1811_06127_amd import fm
+
+pytestmark = pytest.mark.gpu
+
+BATCH = 1_000_000
+LENGTH = 150
+ZMAX = 2
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.timeout(1200)
+def test_genome_scale_batches_from_one_graph():
+    t0 = time.time()
+    R = synth.genome_like_reference()
+    say("3.1e9-base text in %.1fs" % (time.time() - t0))
+    t0 = time.time()
+    idx = fm.Index.from_text(R, occ_interval=64, flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_DEVICE_SORT)
+    say("index (device suffix sort, both directions) in %.1fs:" % (time.time() - t0), idx.info())
+    t0 = time.time()
+    rd = synth.genome_reads(R)
+    nb = rd.count // BATCH
+    assert rd.count == nb * BATCH == 16_000_000 and (np.diff(rd.offs) == LENGTH).all() and (rd.z == ZMAX).all()
+    say("16M reads in %.1fs" % (time.time() - t0))
+
+    flags = fm.FM_BOTH | fm.FM_DARRAY
+    first = rd.subset(np.arange(BATCH))
+    codes, offs, z = fm.reads_to_device(first.codes, first.offs, first.z)
+    cap = 16 * BATCH
+    # launch settings tuned on a prefix of the first batch (each candidate is checked
+    # against the plain kernel by the tuner)
+    pre = rd.subset(np.arange(1 << 18))
+    pc, po, pz = fm.reads_to_device(pre.codes, pre.offs, pre.z)
+    pbufs = fm.InexactBuffers(idx, pre.count, int(pre.offs[-1]), flags | fm.FM_PLAIN, ZMAX, 16 * pre.count, "cuda")
+    t0 = time.time()
+    tin = fm.fm_autotune(idx, fm.FM_OP_INEXACT, pc, po, pz, flags, ZMAX, bufs=pbufs)
+    tdw = fm.fm_autotune(idx, fm.FM_OP_DARRAY, pc, po, pz, flags, ZMAX, bufs=pbufs)
+    say("tuned in %.1fs: inexact %s, D walk %s" % (time.time() - t0, tin, tdw))
+    del pbufs, pc, po, pz
+
+    ex_out = torch.empty((2 * BATCH, 2), dtype=torch.int32, device="cuda")
+    bufs = fm.InexactBuffers(idx, BATCH, BATCH * LENGTH, flags, ZMAX, cap, "cuda")
+    plan = fm.Plan.both(idx, codes, offs, z, fm.FM_BOTH, flags, ZMAX, ex_out, bufs)
+    plain_ex = torch.empty_like(ex_out)
+    plain_bufs = fm.InexactBuffers(idx, BATCH, BATCH * LENGTH, flags | fm.FM_PLAIN, ZMAX, cap, "cuda")
+
+    # oracle sample: the first 1,000 reads and 1,000 spread over the whole set
+    sample = np.unique(np.concatenate([np.arange(1000), np.linspace(1000, rd.count - 1, 1000).astype(np.int64)]))
+    got_ex = np.zeros((sample.size * 2, 2), np.uint32)
+    got_hits = [None] * sample.size
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    batched_ms = plain_ms = 0.0
+    total_hits = 0
+    for b in range(nb):
+        lo, hi = b * BATCH * LENGTH, (b + 1) * BATCH * LENGTH
+        codes.copy_(torch.from_numpy(rd.codes[lo:hi]))
+        z.copy_(torch.from_numpy(rd.z[b * BATCH:(b + 1) * BATCH]))
+        ev[0].record()
+        plan.launch()
+        ev[1].record()
+        torch.cuda.synchronize()
+        batched_ms += ev[0].elapsed_time(ev[1])
+        ex = ex_out.cpu().numpy().view(np.uint32).copy()
+        hits, hoffs, status = fm.hits_to_numpy(bufs, BATCH)
+        assert (status == fm.FM_OK).all(), (b, np.unique(status, return_counts=True))
+        ev[0].record()
+        fm.fm_search_both(idx, codes, offs, z, fm.FM_BOTH, flags | fm.FM_PLAIN, ZMAX, cap, out=plain_ex,
+                          bufs=plain_bufs)
+        ev[1].record()
+        torch.cuda.synchronize()
+        plain_ms += ev[0].elapsed_time(ev[1])
+        assert np.array_equal(plain_ex.cpu().numpy().view(np.uint32), ex), b
+        for u, v in zip(fm.hits_to_numpy(plain_bufs, BATCH), (hits, hoffs, status)):
+            assert np.array_equal(u, v), b
+        total_hits += hits.size
+        for j in np.nonzero((sample >= b * BATCH) & (sample < (b + 1) * BATCH))[0]:
+            r = int(sample[j]) - b * BATCH
+            got_ex[2 * j:2 * j + 2] = ex[2 * r:2 * r + 2]
+            got_hits[j] = hits[int(hoffs[r]):int(hoffs[r + 1])]
+        say("batch %d: %.1f ms graph replay, %d hits, plain equal" % (b, batched_ms / (b + 1), hits.size))
+    say("16M reads: graph replays %.1f M reads/s, plain %.1f M reads/s (%.2fx); %d hits" % (
+        rd.count / batched_ms / 1e3, rd.count / plain_ms / 1e3, plain_ms / batched_ms, total_hits))
+    assert plain_ms > batched_ms
+
+    t0 = time.time()
+    srd = rd.subset(sample)
+    want_ex = oracle.exact_by_rank_scan_batch(R, srd.codes, srd.offs, oracle.BOTH, threads=16)
+    assert np.array_equal(got_ex, want_ex)
+    wh, wo = oracle.pigeonhole_hits_batch(R, srd.codes, srd.offs, srd.z, oracle.BOTH, threads=16)
+    for j in range(sample.size):
+        a = got_hits[j]
+        w = wh[int(wo[j]):int(wo[j + 1])]
+        assert np.array_equal(a["k"], w["k"]) and np.array_equal(a["l"], w["l"]), j
+        assert np.array_equal(a["strand"], w["strand"]) and np.array_equal(a["nmm"], w["d"]), j
+    say("oracle sample of %d reads (%d exact hits, %d hits) in %.1fs" % (
+        sample.size, int((want_ex[:, 0] <= want_ex[:, 1]).sum()), wh.size, time.time() - t0))
+    assert wh.size > sample.size // 2          # the sample is not vacuous
+    plan.free()
+    idx.free()

@@ -364,3 +364,62 @@ def test_pigeonhole_equals_hamming_ball(seed, z):
     for f in ("read", "k", "l", "strand", "d"):
         assert np.array_equal(gh[f], wh[f]), f
     assert wh.size > (len(reads) if z else len(reads) // 4)   # the check is not vacuous
+
+
+@pytest.mark.parametrize("seed", [8, 9])
+def test_rank_scan_batch_equals_sa_definition(seed):
+    """The batched rank scan (key histogram plus full comparisons) agrees with the
+    suffix-array definition on short and long patterns, patterns with N, patterns that
+    reach the end of the text, and the empty pattern."""
+    R = _text_with_repeats(seed, 6000)
+    x = OracleIndex(R)
+    rng = random.Random(seed)
+    pats = [np.zeros(0, np.uint8)]
+    for _ in range(200):
+        m = rng.choice([1, 2, 5, 9, 10, 11, 17, 30, 45])
+        p = rng.randrange(R.size - m)
+        w = R[p:p + m].copy()
+        if rng.random() < 0.3:
+            w[rng.randrange(m)] = rng.randrange(4)
+        if rng.random() < 0.1:
+            w[rng.randrange(m)] = 4
+        pats.append(w)
+    for t in (3, 9, 10, 11, 25):
+        pats.append(R[-t:].copy())                                      # suffixes of R
+        pats.append(np.concatenate([R[-t:], [1, 2]]).astype(np.uint8))  # run past the end
+    codes, offs = csr(pats)
+    want = x.exact(codes, offs, oracle.BOTH, "definition")
+    for threads in (1, 3):
+        got = oracle.exact_by_rank_scan_batch(R, codes, offs, oracle.BOTH, threads=threads)
+        assert np.array_equal(got, want), threads
+
+
+@pytest.mark.parametrize("seed,z", [(10, 0), (11, 1), (12, 2)])
+def test_pigeonhole_batch_equals_hamming_ball(seed, z):
+    """The batched pigeonhole checker (seeds of at least 12 symbols found in one pass)
+    equals the Hamming-ball enumeration, with reads long enough for the seed path, reads
+    with N, and short reads that take the per-pattern path."""
+    R = _text_with_repeats(seed, 8000)
+    x = OracleIndex(R)
+    rng = random.Random(seed)
+    reads = []
+    for i in range(36):
+        m = rng.randrange(12 * (z + 1), 12 * (z + 1) + 14) if i % 6 else rng.randrange(5, 12)
+        p = rng.randrange(R.size - m)
+        w = R[p:p + m].copy()
+        for _ in range(rng.randrange(0, z + 2)):
+            w[rng.randrange(m)] = rng.randrange(4)
+        if i % 7 == 0:
+            w[rng.randrange(m)] = 4
+        if i % 3 == 0:
+            w = oracle.strand_pattern(w, 1)
+        reads.append(w)
+    codes, offs = csr(reads)
+    zz = np.full(len(reads), z, np.uint8)
+    wh, wo = x.inexact(codes, offs, zz, oracle.BOTH, "definition")
+    for threads in (1, 4):
+        gh, go = oracle.pigeonhole_hits_batch(R, codes, offs, zz, oracle.BOTH, threads=threads)
+        assert np.array_equal(go, wo), threads
+        for f in ("read", "k", "l", "strand", "d"):
+            assert np.array_equal(gh[f], wh[f]), (threads, f)
+    assert wh.size > len(reads) // 2                                    # the check is not vacuous
