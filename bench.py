@@ -29,11 +29,13 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "reads/s & Occ8 queries/s, batched vs plain kernel, bit-exact; p99 latency"
 
 # Bytes per launch of the dominant kernel measured with rocprofv3 (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by
-# the same counters on a plain 1 GiB copy kernel; profiles/search_kernels_2e24_counters.md). They hold only for the
-# kernel sources and launch settings they were measured with: the key is a hash of the kernel sources and the
-# tuning of the kernel; any other combination reports traffic as null.
+# the same counters on a plain 1 GiB copy kernel; profiles/search_kernels_2e24_counters.md and
+# profiles/genome_dfs_3e9_counters.md). They hold only for the kernel sources, launch settings and workload they
+# were measured with: the key is a hash of the kernel sources, the kernel, its tuning and the workload; any other
+# combination reports traffic as null.
 MEASURED_TRAFFIC = {
-    ("343807224c005330", "dfs_batched<XD>", (64, 1, 1, 256, 8)): (12_618_122_818, 143_568_040),
+    ("343807224c005330", "dfs_batched<XD>", (64, 1, 1, 256, 8), "2^24"): (12_618_122_818, 143_568_040),
+    ("343807224c005330", "dfs_batched<XD>", (64, 1, 1, 256, 8), "3.1e9"): (342_325_208_400, 152_932_948),
 }
 KERNEL_SOURCES = ("search.hip", "fm_device.hpp", "fm_internal.hpp")
 
@@ -70,6 +72,8 @@ def parse():
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of capacity")
     ap.add_argument("--serve-lanes", type=int, default=2)
     ap.add_argument("--serve-pool", type=int, default=2_000_000, help="reads the requests are drawn from")
+    ap.add_argument("--genome-batches", type=int, default=16,
+                    help="batches of 1M reads in the genome-scale run on the 3.1e9-base index (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain device-to-device copy of this many MiB (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -255,7 +259,7 @@ def main():
     kname = {"d_walk": "walk_batched<DBP>", "dfs": "dfs_batched<XD>"}[dom]
     tcfg = tuning[{"d_walk": "d_walk", "dfs": "inexact"}[dom]]["config"]
     key = (kernel_source_hash(), kname, tuple(tcfg[f] for f in ("occ_interval", "lanes", "depth", "block",
-                                                                "waves_per_cu")))
+                                                                "waves_per_cu")), "2^24")
     traffic = MEASURED_TRAFFIC.get(key)
     roofline = {"bound": "hbm", "kernel": kname,
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -270,12 +274,16 @@ def main():
     if args.cpu_sample > 0:
         cpu, parity = cpu_baseline(R, rd, min(args.cpu_sample, nreads), ex_batched, in_batched, args.cpu_threads)
 
-    serve = None
-    if args.serve_requests > 0:
+    serve = genome = None
+    if args.serve_requests > 0 or args.genome_batches > 0:
         del codes, offs, z, ex_out, ex_ws, bufs
         idx.free()
         torch.cuda.empty_cache()
+    if args.serve_requests > 0:
         serve = serve_bench(args)
+        torch.cuda.empty_cache()
+    if args.genome_batches > 0:
+        genome = genome_bench(args)
 
     reads_s = nreads / (ms_step / 1e3)
     out = {
@@ -314,9 +322,138 @@ def main():
         "cpu_baseline": cpu,
         "parity_sample": parity,
         "serving": serve,
+        "genome_scale": genome,
         "p99_latency_ms": serve["p99_ms"] if serve else None,
     }
     print(json.dumps(out), flush=True)
+
+
+def genome_bench(args):
+    """Batching at genome scale: the 3.1e9-base text (55% i.i.d., 45% copies of 500 repeat
+    families with 5-15% divergence), reads of 150 bp with 1% substitutions, z=2 with the D
+    bound on both strands, in batches of 1M replayed from one launch graph captured for the
+    batch shape. Each batch's reads are copied into the captured buffers before its replay;
+    the timed region is the replays."""
+    import torch
+
+    import synth
+    from paper_1811_06127_amd import fm
+
+    B, LEN, Z = 1_000_000, 150, 2
+    flags = fm.FM_BOTH | fm.FM_DARRAY
+    t0 = time.time()
+    R = synth.genome_like_reference()
+    idx = fm.Index.from_text(R, occ_interval=64, flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_DEVICE_SORT)
+    build_s = time.time() - t0
+    rd = synth.genome_reads(R, args.genome_batches * B)
+    log("genome-scale inputs in %.1fs (index %.1fs, suffixes sorted on the device)" % (time.time() - t0, build_s))
+    pre = rd.subset(np.arange(1 << 18))
+    pc, po, pz = fm.reads_to_device(pre.codes, pre.offs, pre.z)
+    pbufs = fm.InexactBuffers(idx, pre.count, int(pre.offs[-1]), flags | fm.FM_PLAIN, Z, 16 * pre.count, "cuda")
+    tuning = {"inexact": fm.fm_autotune(idx, fm.FM_OP_INEXACT, pc, po, pz, flags, Z, bufs=pbufs)[0],
+              "d_walk": fm.fm_autotune(idx, fm.FM_OP_DARRAY, pc, po, pz, flags, Z, bufs=pbufs)[0]}
+    del pbufs, pc, po, pz
+    first = rd.subset(np.arange(B))
+    codes, offs, z = fm.reads_to_device(first.codes, first.offs, first.z)
+    ex_out = torch.empty((2 * B, 2), dtype=torch.int32, device="cuda")
+    bufs = fm.InexactBuffers(idx, B, B * LEN, flags | fm.FM_PLAIN, Z, 16 * B, "cuda")
+
+    def call(extra=0):
+        fm.fm_search_both(idx, codes, offs, z, fm.FM_BOTH, flags | extra, Z, 16 * B, out=ex_out, bufs=bufs)
+
+    # work counters and kernel phases of the first batch (eager calls)
+    call(fm.FM_STATS)
+    torch.cuda.synchronize()
+    st = bufs.stats()
+    call()
+    idx.phase_timing(3)
+    for _ in range(3):
+        call()
+    torch.cuda.synchronize()
+    ph, _ = idx.phase_times()
+    idx.phase_timing(0)
+    phase = {"d_walk": ph["d_walk"] / 3, "dfs": ph["dfs"] / 3, "compaction": ph["compaction"] / 3}
+    eager = (ex_out.clone(), fm.hits_to_numpy(bufs, B))
+    t = time.time()
+    call(fm.FM_PLAIN)
+    torch.cuda.synchronize()
+    plain_s = time.time() - t
+    plain_equal = bool(torch.equal(ex_out, eager[0])) and all(
+        np.array_equal(a, b) for a, b in zip(fm.hits_to_numpy(bufs, B), eager[1]))
+
+    plan = fm.Plan.both(idx, codes, offs, z, fm.FM_BOTH, flags, Z, ex_out, bufs)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ms = 0.0
+    hits = 0
+    replay_equal = True
+    for b in range(args.genome_batches):
+        codes.copy_(torch.from_numpy(rd.codes[b * B * LEN:(b + 1) * B * LEN]))
+        z.copy_(torch.from_numpy(rd.z[b * B:(b + 1) * B]))
+        torch.cuda.synchronize()
+        ev[0].record()
+        plan.launch()
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms += ev[0].elapsed_time(ev[1])
+        h = fm.hits_to_numpy(bufs, B)
+        hits += int(h[1][-1])
+        if b == 0:
+            replay_equal = bool(torch.equal(ex_out, eager[0])) and all(np.array_equal(a, c) for a, c in zip(h, eager[1]))
+    plan.free()
+    # the same index under independent random Occ8 queries: the rate of random bucket
+    # fetches the memory system sustains when nothing depends on a previous fetch
+    occ8 = {}
+    nq = 1 << 26
+    for kind in ("uniform", "narrow"):
+        q = torch.from_numpy(synth.occ8_queries(R.size, nq, 4343, kind).view(np.int32)).cuda()
+        qo = torch.empty((nq, 8), dtype=torch.int32, device="cuda")
+        fm.fm_occ8(idx, q, out=qo)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(3):
+            fm.fm_occ8(idx, q, out=qo)
+        ev[1].record()
+        torch.cuda.synchronize()
+        occ8[kind] = nq / (ev[0].elapsed_time(ev[1]) / 3 / 1e3)
+        del q, qo
+    reads = args.genome_batches * B
+    nrs = 2 * B
+    alg = st["buckets"] * 32 + 2 * B * LEN + 32 * nrs + 16 * int(eager[1][1][-1])
+    achieved = alg / (phase["dfs"] / 1e3) / 1e9
+    tcfg = tuning["inexact"]
+    key = (kernel_source_hash(), "dfs_batched<XD>", tuple(tcfg[f] for f in ("occ_interval", "lanes", "depth", "block",
+                                                                          "waves_per_cu")), "3.1e9")
+    traffic = MEASURED_TRAFFIC.get(key)
+    out = {
+        "workload": "3.1e9-base reference (55%% i.i.d., 45%% copies of 500 families, 5-15%% divergence); %d batches of "
+                    "1M reads x 150 bp, 1%% substitutions, either strand; exact + z=2 substitution search, both "
+                    "strands, D bound; one launch graph replayed per batch" % args.genome_batches,
+        "reads": reads,
+        "reads_per_s": round(reads / (ms / 1e3), 1),
+        "ms_per_batch": round(ms / args.genome_batches, 3),
+        "plain_reads_per_s": round(B / plain_s, 1),
+        "batched_vs_plain": round(plain_s * 1e3 / (ms / args.genome_batches), 3),
+        "batched_equals_plain": plain_equal,
+        "replay_equals_eager": replay_equal,
+        "hits": hits,
+        "index_build_s": round(build_s, 2),
+        "phase_ms_per_batch": {k: round(v, 3) for k, v in phase.items()},
+        "work_per_batch": {"dfs_nodes": st["occ8"], "dfs_buckets": st["buckets"], "d_walk_steps": st["walk_steps"],
+                           "d_walk_buckets": st["walk_buckets"]},
+        "dfs_buckets_per_s": round(st["buckets"] / (phase["dfs"] / 1e3), 1),
+        "occ8_queries_per_s": {"fm_occ8_" + k: round(v, 1) for k, v in occ8.items()},
+        "tuning": tuning,
+        "roofline": {"bound": "hbm", "kernel": "dfs_batched<XD>", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": int(sum(traffic)) if traffic else None,
+                     "traffic_gb_per_s": round(sum(traffic) / (phase["dfs"] / 1e3) / 1e9, 1) if traffic else None,
+                     "bytes_per_launch": int(alg), "avg_launch_ms": round(phase["dfs"], 3),
+                     "kernel_source_hash": key[0]},
+    }
+    log("genome scale:", out)
+    del codes, offs, z, ex_out, bufs
+    idx.free()
+    return out
 
 
 def serve_bench(args):
