@@ -81,8 +81,10 @@ enum {
 enum {
     FM_LOAD_REVERSE = 1,            /* also build/keep the index of reverse(R) */
     FM_LOAD_ALL_LAYOUTS = 2,        /* build the layouts for every supported I */
-    FM_LOAD_DEVICE_SORT = 4         /* fm_index_from_text: sort suffixes on the device (see
+    FM_LOAD_DEVICE_SORT = 4,        /* fm_index_from_text: sort suffixes on the device (see
                                        fm_bwt_device) instead of the host builder; same index */
+    FM_LOAD_LOCATE = 8              /* fm_index_from_text: keep the SA values of every 32nd row,
+                                       so that fm_locate works (4 bytes per 32 rows) */
 };
 
 #define FM_ZMAX 4                   /* largest per-read mismatch budget */
@@ -104,7 +106,7 @@ typedef struct {
     uint32_t layouts;               /* built layouts: bits 0..6 = I of 64, 96, 128, 192, 224,
                                        256, 448 */
     uint32_t has_reverse;
-    uint32_t pad;
+    uint32_t sa_sample;             /* 32 when SA samples are kept (fm_locate), else 0 */
     uint64_t device_bytes;          /* device memory owned by the index */
 } fm_info;
 
@@ -282,6 +284,30 @@ int fm_search_both(const fm_index *idx, const uint8_t *codes, const uint64_t *of
                    uint64_t nreads, uint32_t exact_flags, uint32_t flags, uint32_t zmax,
                    fm_interval *intervals, fm_hit *hits, uint64_t hit_cap, uint64_t *hit_offs,
                    uint32_t *status, void *ws, size_t ws_bytes, void *stream);
+
+/* ----------------------------------------------------------------- locate */
+
+/* Workspace bytes fm_locate needs for niv intervals. */
+int fm_locate_workspace(const fm_index *idx, uint64_t niv, size_t *bytes);
+
+/* Text positions of the rows of SA intervals (Background, Eq. 4-5): pos holds SA[k_j + t]
+ * for every interval j and t = 0 .. l_j - k_j, intervals in order. Only the SA values of
+ * rows that are multiples of 32 are kept; any other row k is walked with
+ * Psi^-1(i) = C[BWT[i]] + Occ(BWT[i], i) until it reaches a kept row (or the '$' row,
+ * whose SA value is 0), and SA[k] is that value plus the number of steps. Needs an index
+ * built by fm_index_from_text with FM_LOAD_LOCATE (FM_EINVAL otherwise).
+ *   kl: device, niv intervals; interval j is (kl[j*stride], kl[j*stride+1]) as uint32
+ *      (stride >= 2: 2 for an fm_interval array; an fm_hit array passes &hits[0].k and
+ *      stride 4). Intervals with k > l or l > n hold no rows (misses such as (1, 0)).
+ *   offs: device, niv+1 uint64, written: offs[j] = rows of the intervals before j, so the
+ *      rows of interval j go to pos[offs[j] ..]; offs[niv] = total rows.
+ *   pos: device, pos_cap uint32 (pos_cap <= 2^31). Only the first min(pos_cap, total)
+ *      rows are located; call with pos_cap = 0 to size pos from offs[niv] first.
+ *   flags: FM_STATS counts the Psi^-1 steps into the uint64 at byte offset 80 of ws.
+ *   ws: device workspace of fm_locate_workspace bytes.
+ * Uses the forward layout and launch settings of FM_OP_EXACT. Asynchronous on stream. */
+int fm_locate(const fm_index *idx, const uint32_t *kl, uint64_t niv, uint32_t stride, uint64_t *offs,
+              uint32_t *pos, uint64_t pos_cap, uint32_t flags, void *ws, size_t ws_bytes, void *stream);
 
 /* ----------------------------------------------------------------- phase timing */
 

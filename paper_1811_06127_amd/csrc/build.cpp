@@ -102,7 +102,7 @@ void sais(const Sym *T, Idx *SA, Idx n, Idx K)
 }
 
 template <typename Idx>
-int bwt_with(const uint8_t *text, uint64_t n, uint8_t *bwt, uint64_t *dollar_row)
+int bwt_with(const uint8_t *text, uint64_t n, uint8_t *bwt, uint64_t *dollar_row, std::vector<uint32_t> *samples)
 {
     const Idx N = (Idx)(n + 1);
     std::vector<uint8_t> T;
@@ -116,6 +116,14 @@ int bwt_with(const uint8_t *text, uint64_t n, uint8_t *bwt, uint64_t *dollar_row
     for (uint64_t i = 0; i < n; ++i) T[i] = (uint8_t)(text[i] + 1);   // '$' = 0 below every base
     T[n] = 0;
     sais<Idx, uint8_t>(T.data(), SA.data(), N, (Idx)5);
+    if (samples) {
+        try {
+            samples->resize((n + 1 + kSaSample - 1) / kSaSample);
+        } catch (const std::bad_alloc &) {
+            return FM_ENOMEM;
+        }
+        for (uint64_t j = 0; j < samples->size(); ++j) (*samples)[j] = (uint32_t)SA[j * kSaSample];
+    }
     for (uint64_t i = 0; i <= n; ++i) {
         const Idx s = SA[i];
         if (s > 0) {
@@ -147,13 +155,13 @@ struct FileHeader {
 
 }  // namespace
 
-int build_bwt(const uint8_t *text, uint64_t n, uint8_t *bwt, uint64_t *dollar_row)
+int build_bwt(const uint8_t *text, uint64_t n, uint8_t *bwt, uint64_t *dollar_row, std::vector<uint32_t> *samples)
 {
     if (n + 1 >= (1ull << 32)) return FM_ERANGE;
     for (uint64_t i = 0; i < n; ++i)
         if (text[i] > 3) return FM_EINVAL;
-    if (n + 1 < (1ull << 31) - 1) return bwt_with<int32_t>(text, n, bwt, dollar_row);
-    return bwt_with<int64_t>(text, n, bwt, dollar_row);
+    if (n + 1 < (1ull << 31) - 1) return bwt_with<int32_t>(text, n, bwt, dollar_row, samples);
+    return bwt_with<int64_t>(text, n, bwt, dollar_row, samples);
 }
 
 int pack_codes(const uint8_t *codes, uint64_t count, uint32_t *words, uint64_t dollar_row)
@@ -186,7 +194,7 @@ int bwt_stats(const uint8_t *bwt, uint64_t rows, uint64_t *dollar_row, uint64_t 
     return FM_OK;
 }
 
-int build_side(const uint8_t *text, uint64_t n, bool reverse, HostSide &out)
+int build_side(const uint8_t *text, uint64_t n, bool reverse, HostSide &out, bool want_samples)
 {
     std::vector<uint8_t> rtext;
     const uint8_t *src = text;
@@ -206,7 +214,7 @@ int build_side(const uint8_t *text, uint64_t n, bool reverse, HostSide &out)
     } catch (const std::bad_alloc &) {
         return FM_ENOMEM;
     }
-    int st = build_bwt(src, n, bwt.data(), &out.dollar);
+    int st = build_bwt(src, n, bwt.data(), &out.dollar, want_samples ? &out.samples : nullptr);
     if (st) return st;
     st = bwt_stats(bwt.data(), n + 1, &out.dollar, out.C);
     if (st) return st;

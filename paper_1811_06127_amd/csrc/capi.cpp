@@ -160,6 +160,19 @@ int create_index(const fm_load_opts *opts, uint64_t n, const HostSide &fwd, cons
     }
     if (packed) (void)hipFree(packed);
     if (scratch) (void)hipFree(scratch);
+    // SA samples for fm_locate
+    const uint64_t ns = (n + 1 + kSaSample - 1) / kSaSample;
+    if (!st && (!fwd.samples.empty() || fwd.dev_samples)) {
+        if (!fwd.dev_samples && fwd.samples.size() != ns) st = FM_EINVAL;
+        else if (hipMalloc(&idx->sa_samples, ns * 4) != hipSuccess) st = FM_ENOMEM;
+        else {
+            idx->device_bytes += ns * 4;
+            const hipError_t e = fwd.dev_samples
+                                     ? hipMemcpy(idx->sa_samples, fwd.dev_samples, ns * 4, hipMemcpyDeviceToDevice)
+                                     : hipMemcpy(idx->sa_samples, fwd.samples.data(), ns * 4, hipMemcpyHostToDevice);
+            if (e != hipSuccess) st = FM_EDEVICE;
+        }
+    }
     if (st) {
         fm_index_free(idx);
         return st;
@@ -193,8 +206,8 @@ const char *fm_strerror(int s)
 int fm_version(void) { return 1; }
 
 // The BWTs of text$ and (want_rev) reverse(text)$ sorted on the device, as device words.
-static int device_sides(const uint8_t *text, uint64_t n, int dev, bool want_rev, HostSide &fwd, HostSide &rev,
-                        void **words_out)
+static int device_sides(const uint8_t *text, uint64_t n, int dev, bool want_rev, bool want_samples, HostSide &fwd,
+                        HostSide &rev, void **words_out)
 {
     if (n + 1 >= (1ull << 32)) return FM_ERANGE;
     int ndev = 0;
@@ -202,10 +215,11 @@ static int device_sides(const uint8_t *text, uint64_t n, int dev, bool want_rev,
     DeviceGuard g(dev);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return FM_EDEVICE;
-    const uint64_t nw = (n + 1 + 15) / 16;
+    const uint64_t nw = (n + 1 + 15) / 16, ns = (n + 1 + kSaSample - 1) / kSaSample;
     void *t = nullptr, *w = nullptr;
     if (hipMalloc(&t, n ? n : 16) != hipSuccess) return FM_ENOMEM;
-    if (hipMalloc(&w, nw * 4 * (want_rev ? 2 : 1)) != hipSuccess) {
+    // packed words of each side, then the forward side's SA samples
+    if (hipMalloc(&w, nw * 4 * (want_rev ? 2 : 1) + (want_samples ? ns * 4 : 0)) != hipSuccess) {
         (void)hipFree(t);
         return FM_ENOMEM;
     }
@@ -217,7 +231,9 @@ static int device_sides(const uint8_t *text, uint64_t n, int dev, bool want_rev,
     for (int side = 0; side < (want_rev ? 2 : 1) && !st; ++side) {
         HostSide &h = side ? rev : fwd;
         h.dev_words = (const uint32_t *)w + side * nw;
-        hipError_t e = device_bwt((const uint8_t *)t, n, side == 1, (uint32_t *)h.dev_words, &h.dollar,
+        uint32_t *samples = (want_samples && side == 0) ? (uint32_t *)w + (want_rev ? 2 : 1) * nw : nullptr;
+        h.dev_samples = samples;
+        hipError_t e = device_bwt((const uint8_t *)t, n, side == 1, (uint32_t *)h.dev_words, &h.dollar, samples,
                                   prop.multiProcessorCount, nullptr);
         if (e == hipErrorOutOfMemory) st = FM_ENOMEM;
         else if (e != hipSuccess) st = FM_EDEVICE;
@@ -244,7 +260,7 @@ int fm_bwt_device(const uint8_t *text, uint64_t n, uint8_t *bwt, uint64_t *dolla
     if ((!text && n) || !bwt || !dollar_row) return FM_EINVAL;
     HostSide fwd, rev;
     void *words = nullptr;
-    int st = device_sides(text, n, device, false, fwd, rev, &words);
+    int st = device_sides(text, n, device, false, false, fwd, rev, &words);
     if (st) return st;
     std::vector<uint32_t> w;
     try {
@@ -283,16 +299,17 @@ int fm_index_from_text(const uint8_t *text, uint64_t n, const fm_load_opts *opts
     if ((!text && n) || !out) return FM_EINVAL;
     HostSide fwd, rev;
     const bool want_rev = opts && (opts->flags & FM_LOAD_REVERSE);
+    const bool want_samples = opts && (opts->flags & FM_LOAD_LOCATE);
     if (opts && (opts->flags & FM_LOAD_DEVICE_SORT)) {
         void *words = nullptr;
-        int st = device_sides(text, n, opts->device, want_rev, fwd, rev, &words);
+        int st = device_sides(text, n, opts->device, want_rev, want_samples, fwd, rev, &words);
         if (st) return st;
         st = create_index(opts, n, fwd, want_rev ? &rev : nullptr, out);
         DeviceGuard g(opts->device);
         (void)hipFree(words);
         return st;
     }
-    int st = build_side(text, n, false, fwd);
+    int st = build_side(text, n, false, fwd, want_samples);
     if (!st && want_rev) st = build_side(text, n, true, rev);
     if (st) return st;
     return create_index(opts, n, fwd, want_rev ? &rev : nullptr, out);
@@ -348,6 +365,7 @@ int fm_index_info(const fm_index *idx, fm_info *out)
     for (int i = 0; i < kLayouts; ++i)
         if (idx->lay[i]) out->layouts |= 1u << i;
     out->has_reverse = idx->has_rev ? 1u : 0u;
+    out->sa_sample = idx->sa_samples ? kSaSample : 0u;
     out->device_bytes = idx->device_bytes;
     return FM_OK;
 }
@@ -361,6 +379,7 @@ void fm_index_free(fm_index *idx)
         if (idx->lay[i]) (void)hipFree(idx->lay[i]);
         if (idx->rlay[i]) (void)hipFree(idx->rlay[i]);
     }
+    if (idx->sa_samples) (void)hipFree(idx->sa_samples);
     delete idx;
 }
 
@@ -489,6 +508,27 @@ int fm_search_both(const fm_index *idx, const uint8_t *codes, const uint64_t *of
     const PhaseEvents pe = take_events(idx, 1);
     return hip_status(launch_inexact(idx, idx->tune[FM_OP_INEXACT], idx->tune[FM_OP_DARRAY], false, c,
                                      (hipStream_t)stream, &pe));
+}
+
+int fm_locate_workspace(const fm_index *idx, uint64_t niv, size_t *bytes)
+{
+    if (!idx || !bytes) return FM_EINVAL;
+    *bytes = locate_ws_bytes(niv);
+    return FM_OK;
+}
+
+int fm_locate(const fm_index *idx, const uint32_t *kl, uint64_t niv, uint32_t stride, uint64_t *offs, uint32_t *pos,
+              uint64_t pos_cap, uint32_t flags, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!idx || !offs || !ws || stride < 2 || (flags & ~(uint32_t)FM_STATS)) return FM_EINVAL;
+    if (niv && !kl) return FM_EINVAL;
+    if (pos_cap && !pos) return FM_EINVAL;
+    if (!idx->sa_samples) return FM_EINVAL;                 // built without FM_LOAD_LOCATE
+    if (pos_cap > (1ull << 31) || niv >= (1ull << 40)) return FM_ERANGE;
+    if (ws_bytes < locate_ws_bytes(niv)) return FM_EINVAL;
+    DeviceGuard g(idx->device);
+    return hip_status(launch_locate(idx, idx->tune[FM_OP_EXACT], kl, niv, stride, offs, pos, pos_cap, ws,
+                                    (flags & FM_STATS) != 0, (hipStream_t)stream));
 }
 
 int fm_phase_timing(fm_index *idx, uint32_t capacity)

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/fm.h"
+#include "fm_build.hpp"
 #include "fm_device.hpp"
 
 struct fm_index {
@@ -19,6 +20,7 @@ struct fm_index {
     void *lay[7] = {};     // forward layouts for I = 64, 96, 128, 192, 224, 256, 448
     void *rlay[7] = {};    // layouts of reverse(R)
     uint64_t device_bytes = 0;
+    uint32_t *sa_samples = nullptr;   // SA[32 j] for j = 0 .. n / 32 (fm_locate), or nullptr
     fm_tuning tune[3] = {};
     int cu_count = 0;
     std::string arch;
@@ -83,15 +85,22 @@ hipError_t build_layout(const uint32_t *packed_dev, uint64_t n, uint32_t I, void
 size_t build_layout_scratch(uint64_t n, uint32_t I);
 
 // Device suffix sorting (sa_build.hip). device_bwt writes the 2-bit BWT words of text$
-// (or reverse(text)$) and its '$' row; text_dev holds n codes 0..3. It allocates
+// (or reverse(text)$) and its '$' row, and (samples != nullptr) the SA values of rows
+// 0, 32, 64, ...; text_dev holds n codes 0..3. It allocates
 // device_bwt_bytes(n) of working memory for the call. device_symbol_counts counts codes
 // 0..3 into out[0..3] and codes above 3 into out[4].
 hipError_t device_bwt(const uint8_t *text_dev, uint64_t n, bool rev, uint32_t *words, uint64_t *dollar_row,
-                      int cu_count, hipStream_t s);
+                      uint32_t *samples, int cu_count, hipStream_t s);
 size_t device_bwt_bytes(uint64_t n);
 hipError_t device_symbol_counts(const uint8_t *text_dev, uint64_t n, uint64_t out[5], int cu_count, hipStream_t s);
 
 hipError_t launch_fill(void *p, uint32_t value, size_t words, hipStream_t s);
+
+// fm_locate: prefix sums of the interval sizes into offs, then the SA value of every row
+// of the intervals (the first cap of them) into pos (search.hip).
+size_t locate_ws_bytes(uint64_t niv);
+hipError_t launch_locate(const fm_index *idx, const fm_tuning &t, const uint32_t *kl, uint64_t niv, uint32_t stride,
+                         uint64_t *offs, uint32_t *pos, uint64_t cap, void *ws, bool stats, hipStream_t s);
 
 hipError_t launch_occ8(const fm_index *idx, const fm_tuning &t, const fm_interval *q, uint64_t nq,
                        uint32_t *out, hipStream_t s);

@@ -107,6 +107,13 @@ __global__ void __launch_bounds__(256) settle(const uint32_t *ids, const uint32_
     }
 }
 
+// SA values kept for locating: rows that are multiples of kSaSample.
+__global__ void __launch_bounds__(256) take_samples(const uint32_t *sa, uint64_t N, uint32_t *samples)
+{
+    const uint64_t ns = (N + kSaSample - 1) / kSaSample;
+    for (uint64_t j = gid(); j < ns; j += gstride()) samples[j] = sa[j * kSaSample];
+}
+
 // 2-bit BWT words (row j at bits 2(j mod 16), '$' stored as 0) and the '$' row.
 __global__ void __launch_bounds__(256) pack_bwt(const uint32_t *sa, const uint8_t *t, uint64_t n, bool rev,
                                                 uint32_t *words, unsigned long long *dollar)
@@ -168,7 +175,7 @@ size_t device_bwt_bytes(uint64_t n)
 }
 
 hipError_t device_bwt(const uint8_t *text_dev, uint64_t n, bool rev, uint32_t *words, uint64_t *dollar_row,
-                      int cu_count, hipStream_t s)
+                      uint32_t *samples, int cu_count, hipStream_t s)
 {
     const uint64_t N = n + 1;
     const dim3 grid(cu_count * 8), block(256);
@@ -256,6 +263,10 @@ hipError_t device_bwt(const uint8_t *text_dev, uint64_t n, bool rev, uint32_t *w
         FM_TRY(hipStreamSynchronize(s));
     }
 
+    if (samples) {
+        hipLaunchKernelGGL(take_samples, grid, block, 0, s, (const uint32_t *)sa, N, samples);
+        FM_TRY(hipGetLastError());
+    }
     Buf dl;
     FM_TRY(dl.alloc(sizeof(unsigned long long)));
     hipLaunchKernelGGL(pack_bwt, grid, block, 0, s, (const uint32_t *)sa, text_dev, n, rev, words,

@@ -1249,4 +1249,184 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ locate (Eq. 4-5)
+
+struct LocateArgs {
+    DevLayout lay;               // forward index
+    const uint32_t *kl;          // interval j: k = kl[j * stride], l = kl[j * stride + 1]
+    uint64_t niv;
+    uint32_t stride;
+    const uint64_t *offs;        // niv + 1: exclusive prefix sums of the interval sizes
+    const uint32_t *samples;     // SA at every kSaSample-th row
+    uint32_t *pos;
+    uint64_t cap;                // rows located: the first min(cap, offs[niv])
+    uint32_t *queue;
+    unsigned long long *stat_steps;
+};
+
+// Sizes of the intervals: l - k + 1 for k <= l <= n, else 0 (misses such as (1, 0), and
+// rows past the index, which are never located).
+__global__ void __launch_bounds__(256) interval_sizes(const uint32_t *kl, uint64_t niv, uint32_t stride, uint32_t n,
+                                                      uint32_t *cnt)
+{
+    for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < niv; j += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = kl[j * stride], l = kl[j * stride + 1];
+        cnt[j] = (k <= l && l <= n) ? l - k + 1 : 0u;
+    }
+}
+
+// The interval holding item r of the concatenated rows: the last j with offs[j] <= r.
+// A lane's items only increase (work is claimed in increasing chunks), so the search
+// gallops forward from the lane's previous interval.
+__device__ __forceinline__ uint64_t locate_interval(const LocateArgs &a, uint64_t r, uint64_t from)
+{
+    uint64_t lo = from, step = 1, hi = from + 1;
+    while (hi < a.niv && a.offs[hi] <= r) {
+        lo = hi;
+        step *= 2;
+        hi = lo + step;
+    }
+    if (hi > a.niv) hi = a.niv;
+    while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) / 2;
+        if (a.offs[mid] <= r) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Eq. 4-5: from row k, apply Psi^-1(i) = C[BWT[i]] + Occ(BWT[i], i) until the row is a
+// multiple of kSaSample (its SA value is stored) or is the '$' row (SA = 0); SA[k] is
+// that value plus the number of steps. One bucket fetch per step gives both BWT[i] and
+// Occ(BWT[i], i). Persistent, with the work queue and round order of walk_batched.
+template <int I>
+__global__ void __launch_bounds__(256) locate_batched(LocateArgs a)
+{
+    const uint64_t all = a.offs[a.niv];
+    const uint32_t total = (uint32_t)(all < a.cap ? all : a.cap);
+    uint32_t item = kEmpty, row = 0, steps = 0, sv = 0;
+    uint64_t jprev = 0, nsteps = 0;
+    bool fin = false;
+    WaveQueue wq;
+    wq.start(a.queue);
+    for (;;) {
+        // 1. the bucket of every running row
+        const bool act = item != kEmpty && !fin;
+        const uint32_t j = (act ? row : 0u) / I;
+        Bucket<I, 1> bk;
+        fetch<I, 1>(a.lay, j, 0, bk);
+        uint4 sbc = make_uint4(0, 0, 0, 0);
+        if constexpr (Geo<I>::COMPACT) sbc = a.lay.sb[j / Geo<I>::SB];
+        // 2. positions of the rows that finished last round (their sample loads are in)
+        if (fin) {
+            a.pos[item] = sv + steps;
+            item = kEmpty;
+            fin = false;
+        }
+        // 3. idle lanes take an item and find its row
+        bool fresh = false;
+        if (refill_now<1>(item == kEmpty)) {
+            const uint32_t it = wave_take<1>(wq, item == kEmpty, a.queue, total);
+            if (it != kEmpty) {
+                item = it;
+                fresh = true;
+            }
+        }
+        const bool quit = !__any(item != kEmpty);
+        // 4. one step of the running rows; new rows begin
+        if (fresh) {
+            jprev = locate_interval(a, item, jprev);
+            row = a.kl[jprev * a.stride] + (uint32_t)(item - a.offs[jprev]);
+            steps = 0;
+        } else if (act) {
+            const uint32_t r = row % I;
+            const uint32_t c = symbol_at<I>(bk, r);
+            const Occ4 o = part4<I, 1>(bk, 0, r, sbc);
+            // '$' is stored as A: rows past it hold one A too many (row is never the '$' row here)
+            const uint32_t occ = sel4(c, o.a - (row > a.lay.dollar ? 1u : 0u), o.c, o.g, o.t);
+            row = c_of(a.lay, c) + occ;
+            steps += 1;
+            nsteps += 1;
+        }
+        if (fresh || act) {
+            fin = row % kSaSample == 0 || row == a.lay.dollar;
+            if (fin) sv = row == a.lay.dollar ? 0u : a.samples[row / kSaSample];
+        }
+#pragma unroll
+        for (int t = 0; t < Bucket<I, 1>::NPL; ++t)
+            asm volatile("" ::"v"(bk.v[t].x), "v"(bk.v[t].y), "v"(bk.v[t].z), "v"(bk.v[t].w));
+        asm volatile("" ::"v"(sbc.x), "v"(sbc.y), "v"(sbc.z), "v"(sbc.w));
+        if (quit) break;
+    }
+    wave_add(a.stat_steps, nsteps);
+}
+
+size_t locate_ws_bytes(uint64_t niv)
+{
+    const uint64_t nblk = (niv + kScanBlock * kTile - 1) / (kScanBlock * kTile);
+    return kWsHeader + ((niv * 4 + 255) & ~(uint64_t)255) + nblk * 8 + 256;
+}
+
+hipError_t launch_locate(const fm_index *idx, const fm_tuning &t, const uint32_t *kl, uint64_t niv, uint32_t stride,
+                         uint64_t *offs, uint32_t *pos, uint64_t cap, void *ws, bool stats, hipStream_t s)
+{
+    char *w = (char *)ws;
+    hipError_t e = launch_fill(w, 0, kWsHeader / 4, s);
+    if (e != hipSuccess) return e;
+    uint32_t *cnt = (uint32_t *)(w + kWsHeader);
+    uint64_t *part = (uint64_t *)(w + kWsHeader + ((niv * 4 + 255) & ~(uint64_t)255));
+    const uint64_t nblk = (niv + kScanBlock * kTile - 1) / (kScanBlock * kTile);
+    if (niv == 0) return launch_fill(offs, 0, 2, s);
+    uint64_t g = (niv + 255) / 256;
+    if (g > (uint64_t)idx->cu_count * 8) g = (uint64_t)idx->cu_count * 8;
+    hipLaunchKernelGGL(interval_sizes, dim3((uint32_t)g), dim3(256), 0, s, kl, niv, stride, (uint32_t)idx->n, cnt);
+    hipLaunchKernelGGL(scan_reduce_u64, dim3((uint32_t)nblk), dim3(kScanBlock), 0, s, cnt, niv, part);
+    hipLaunchKernelGGL(scan_partials_u64, dim3(1), dim3(1024), 0, s, part, nblk);
+    hipLaunchKernelGGL(scan_write_u64, dim3((uint32_t)nblk), dim3(kScanBlock), 0, s, cnt, niv, part, offs);
+    e = hipGetLastError();
+    if (e != hipSuccess || cap == 0) return e;
+    LocateArgs a;
+    a.lay = dev_layout(idx, t.occ_interval, false);
+    a.kl = kl;
+    a.niv = niv;
+    a.stride = stride;
+    a.offs = offs;
+    a.samples = idx->sa_samples;
+    a.pos = pos;
+    a.cap = cap;
+    a.queue = (uint32_t *)(w + kWsQueue);
+    a.stat_steps = stats ? (unsigned long long *)(w + kWsStatWalk) : nullptr;
+    const int block = 256;
+    const void *kern = nullptr;
+    switch (t.occ_interval) {
+    case 64: kern = (const void *)locate_batched<64>; break;
+    case 96: kern = (const void *)locate_batched<96>; break;
+    case 128: kern = (const void *)locate_batched<128>; break;
+    case 192: kern = (const void *)locate_batched<192>; break;
+    case 224: kern = (const void *)locate_batched<224>; break;
+    case 256: kern = (const void *)locate_batched<256>; break;
+    case 448: kern = (const void *)locate_batched<448>; break;
+    default: return hipErrorInvalidValue;
+    }
+    int per = max_blocks_per_cu(kern, block, 0);
+    if (t.waves_per_cu) {
+        const int want = (int)(t.waves_per_cu * 64 / block);
+        if (want >= 1 && want < per) per = want;
+    }
+    uint64_t grid = (uint64_t)idx->cu_count * per;
+    const uint64_t need = (cap + block - 1) / block;
+    if (need < grid) grid = need;
+    switch (t.occ_interval) {
+    case 64: hipLaunchKernelGGL(locate_batched<64>, dim3((uint32_t)grid), dim3(block), 0, s, a); break;
+    case 96: hipLaunchKernelGGL(locate_batched<96>, dim3((uint32_t)grid), dim3(block), 0, s, a); break;
+    case 128: hipLaunchKernelGGL(locate_batched<128>, dim3((uint32_t)grid), dim3(block), 0, s, a); break;
+    case 192: hipLaunchKernelGGL(locate_batched<192>, dim3((uint32_t)grid), dim3(block), 0, s, a); break;
+    case 224: hipLaunchKernelGGL(locate_batched<224>, dim3((uint32_t)grid), dim3(block), 0, s, a); break;
+    case 256: hipLaunchKernelGGL(locate_batched<256>, dim3((uint32_t)grid), dim3(block), 0, s, a); break;
+    case 448: hipLaunchKernelGGL(locate_batched<448>, dim3((uint32_t)grid), dim3(block), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace fm

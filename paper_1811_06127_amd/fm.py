@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libfmocc.so")
 
 FM_OK, FM_EINVAL, FM_EIO, FM_EFORMAT, FM_ENOMEM, FM_EDEVICE, FM_EOVERFLOW, FM_EBUDGET, FM_ERANGE, FM_EAGAIN = range(10)
 FM_FWD, FM_REVCOMP, FM_BOTH, FM_DARRAY, FM_PLAIN, FM_STATS = 1, 2, 3, 4, 16, 32
-FM_LOAD_REVERSE, FM_LOAD_ALL_LAYOUTS, FM_LOAD_DEVICE_SORT = 1, 2, 4
+FM_LOAD_REVERSE, FM_LOAD_ALL_LAYOUTS, FM_LOAD_DEVICE_SORT, FM_LOAD_LOCATE = 1, 2, 4, 8
 FM_OP_EXACT, FM_OP_DARRAY, FM_OP_INEXACT = 0, 1, 2
 FM_ZMAX = 4
 
@@ -42,7 +42,7 @@ class LoadOpts(C.Structure):
 class Info(C.Structure):
     _fields_ = [("n", C.c_uint64), ("dollar_row", C.c_uint64), ("C", C.c_uint64 * 5),
                 ("rev_dollar_row", C.c_uint64), ("rev_C", C.c_uint64 * 5), ("occ_interval", C.c_uint32),
-                ("layouts", C.c_uint32), ("has_reverse", C.c_uint32), ("pad", C.c_uint32),
+                ("layouts", C.c_uint32), ("has_reverse", C.c_uint32), ("sa_sample", C.c_uint32),
                 ("device_bytes", C.c_uint64)]
 
 
@@ -115,6 +115,8 @@ def lib() -> C.CDLL:
         "fm_phase_times": (i32, [vp, C.POINTER(C.c_float), C.POINTER(C.c_uint32)]),
         "fm_plan_free": (None, [vp]),
         "fm_search_both": (i32, [vp, vp, vp, vp, u64, u32, u32, u32, vp, vp, u64, vp, vp, vp, C.c_size_t, vp]),
+        "fm_locate_workspace": (i32, [vp, u64, C.POINTER(C.c_size_t)]),
+        "fm_locate": (i32, [vp, vp, u64, u32, vp, vp, u64, u32, vp, C.c_size_t, vp]),
         "fm_plan_create_both": (i32, [vp, vp, vp, vp, u64, u32, u32, u32, vp, vp, u64, vp, vp, vp, C.c_size_t,
                                       C.POINTER(vp)]),
         "fm_server_bytes": (i32, [C.POINTER(ServerOpts), u64, u64, C.POINTER(C.c_uint64)]),
@@ -250,7 +252,7 @@ class Index:
         _check(lib().fm_index_info(self.handle, C.byref(i)), "fm_index_info")
         return {"n": i.n, "dollar_row": i.dollar_row, "C": list(i.C), "rev_dollar_row": i.rev_dollar_row,
                 "rev_C": list(i.rev_C), "occ_interval": i.occ_interval, "layouts": i.layouts,
-                "has_reverse": bool(i.has_reverse), "device_bytes": i.device_bytes}
+                "has_reverse": bool(i.has_reverse), "sa_sample": i.sa_sample, "device_bytes": i.device_bytes}
 
     def get_tuning(self, op: int) -> dict:
         t = Tuning()
@@ -399,6 +401,37 @@ def fm_search_both(idx: Index, codes: torch.Tensor, offs: torch.Tensor, z: torch
                                 _ptr(out), _ptr(bufs.hits), bufs.hit_cap, _ptr(bufs.hit_offs), _ptr(bufs.status),
                                 _ptr(bufs.ws), bufs.ws.numel(), _stream(stream)), "fm_search_both")
     return out, bufs
+
+
+def fm_locate(idx: Index, kl: torch.Tensor, cap: int | None = None, stats: bool = False, stream=None):
+    """Text positions of the rows of SA intervals (fm_locate). kl: device int32 tensor of
+    (k, l) pairs, shape (niv, 2), or of fm_hit records, shape (nhits, 4) (k, l are then
+    columns 1 and 2). Returns (offs, pos[, steps]): offs (niv+1 int64) and pos (int32,
+    the located rows in interval order). With cap None, the total is read back first and
+    every row is located."""
+    if kl.dtype not in (torch.int32, torch.uint32) or kl.device.type != "cuda" or kl.dim() != 2 or \
+            kl.shape[1] not in (2, 4) or not kl.is_contiguous():
+        raise ValueError("kl: contiguous device int32 tensor of shape (n, 2) or (n, 4)")
+    niv = kl.shape[0]
+    stride = kl.shape[1]
+    base = _ptr(kl) + (4 if stride == 4 else 0)
+    nb = C.c_size_t(0)
+    _check(lib().fm_locate_workspace(idx.handle, niv, C.byref(nb)), "fm_locate_workspace")
+    ws = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=kl.device)
+    offs = torch.empty(niv + 1, dtype=torch.int64, device=kl.device)
+    flags = FM_STATS if stats else 0
+    if cap is None:
+        _check(lib().fm_locate(idx.handle, base, niv, stride, _ptr(offs), None, 0, 0, _ptr(ws), ws.numel(),
+                               _stream(stream)), "fm_locate")
+        cap = int(offs[-1].item())
+    pos = torch.empty(max(cap, 1), dtype=torch.int32, device=kl.device)
+    _check(lib().fm_locate(idx.handle, base, niv, stride, _ptr(offs), _ptr(pos), cap, flags, _ptr(ws), ws.numel(),
+                           _stream(stream)), "fm_locate")
+    if stats:
+        torch.cuda.synchronize(kl.device)
+        steps = int(ws[80:88].cpu().numpy().view(np.uint64)[0])
+        return offs, pos[:cap], steps
+    return offs, pos[:cap]
 
 
 def hits_to_numpy(bufs: InexactBuffers, nreads: int):
