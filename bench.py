@@ -53,6 +53,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def locate_rate(fm, torch, idx, hits, nh: int, reps: int = 3) -> dict:
+    """fm_locate over the rows of the first nh hit records (Eq. 4-5): rows located per
+    second and Psi^-1 steps per row, event-timed on the current stream."""
+    offs, pos, steps = fm.fm_locate(idx, hits[:nh], stats=True)
+    rows = int(offs[-1].item())
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        fm.fm_locate(idx, hits[:nh], cap=rows)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    return {"hits": nh, "rows": rows, "ms": round(ms, 4), "rows_per_s": round(rows / (ms / 1e3), 1),
+            "steps_per_row": round(steps / max(rows, 1), 2), "steps_per_s": round(steps / (ms / 1e3), 1)}
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,7 +125,8 @@ def main():
     rd = synth.reads_2e24(R, args.reads)
     log("inputs generated in %.1fs: n=%d reads=%d" % (time.time() - t0, R.size, rd.count))
     t0 = time.time()
-    idx = fm.Index.from_text(R, occ_interval=64, flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_ALL_LAYOUTS)
+    idx = fm.Index.from_text(R, occ_interval=64,
+                             flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_ALL_LAYOUTS | fm.FM_LOAD_LOCATE)
     log("index built in %.1fs" % (time.time() - t0))
 
     nreads = rd.count
@@ -186,6 +203,9 @@ def main():
     fused_equal = bool(torch.equal(ex_batched, ex_separate)) and all(
         np.array_equal(a, b) for a, b in zip(in_batched, in_separate))
     log("one pass equals separate calls:", fused_equal)
+    # text positions of the step's hits (fm_locate)
+    loc = locate_rate(fm, torch, idx, bufs.hits, int(in_batched[1][-1]))
+    log("locate:", loc)
 
     # the same step replayed from a launch graph captured for this batch shape
     plans = [fm.Plan.both(idx, codes, offs, z, EXACT, INEXACT, ZMAX, ex_out, bufs)]
@@ -321,6 +341,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_sample": parity,
+        "locate": loc,
         "serving": serve,
         "genome_scale": genome,
         "p99_latency_ms": serve["p99_ms"] if serve else None,
@@ -343,7 +364,8 @@ def genome_bench(args):
     flags = fm.FM_BOTH | fm.FM_DARRAY
     t0 = time.time()
     R = synth.genome_like_reference()
-    idx = fm.Index.from_text(R, occ_interval=64, flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_DEVICE_SORT)
+    idx = fm.Index.from_text(R, occ_interval=64,
+                             flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_DEVICE_SORT | fm.FM_LOAD_LOCATE)
     build_s = time.time() - t0
     rd = synth.genome_reads(R, args.genome_batches * B)
     log("genome-scale inputs in %.1fs (index %.1fs, suffixes sorted on the device)" % (time.time() - t0, build_s))
@@ -399,6 +421,7 @@ def genome_bench(args):
         hits += int(h[1][-1])
         if b == 0:
             replay_equal = bool(torch.equal(ex_out, eager[0])) and all(np.array_equal(a, c) for a, c in zip(h, eager[1]))
+            gloc = locate_rate(fm, torch, idx, bufs.hits, int(h[1][-1]))
     plan.free()
     # the same index under independent random Occ8 queries: the rate of random bucket
     # fetches the memory system sustains when nothing depends on a previous fetch
@@ -442,6 +465,7 @@ def genome_bench(args):
                            "d_walk_buckets": st["walk_buckets"]},
         "dfs_buckets_per_s": round(st["buckets"] / (phase["dfs"] / 1e3), 1),
         "occ8_queries_per_s": {"fm_occ8_" + k: round(v, 1) for k, v in occ8.items()},
+        "locate_first_batch": gloc,
         "tuning": tuning,
         "roofline": {"bound": "hbm", "kernel": "dfs_batched<XD>", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

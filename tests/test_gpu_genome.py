@@ -30,7 +30,8 @@ def test_genome_scale_batches_from_one_graph():
     R = synth.genome_like_reference()
     say("3.1e9-base text in %.1fs" % (time.time() - t0))
     t0 = time.time()
-    idx = fm.Index.from_text(R, occ_interval=64, flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_DEVICE_SORT)
+    idx = fm.Index.from_text(R, occ_interval=64,
+                             flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_DEVICE_SORT | fm.FM_LOAD_LOCATE)
     say("index (device suffix sort, both directions) in %.1fs:" % (time.time() - t0), idx.info())
     t0 = time.time()
     rd = synth.genome_reads(R)
@@ -89,6 +90,19 @@ def test_genome_scale_batches_from_one_graph():
         for u, v in zip(fm.hits_to_numpy(plain_bufs, BATCH), (hits, hoffs, status)):
             assert np.array_equal(u, v), b
         total_hits += hits.size
+        if b == 0:
+            # text positions of the batch's hits (Eq. 4-5): every located window is within
+            # the hit's distance of its strand pattern (checked for a spread of hits)
+            loffs, lpos = fm.fm_locate(idx, bufs.hits[:hits.size])
+            loffs, lpos = loffs.cpu().numpy(), lpos.cpu().numpy().view(np.uint32)
+            assert loffs[-1] == int((hits["l"].astype(np.int64) - hits["k"] + 1).sum())
+            for h in np.linspace(0, hits.size - 1, 3000).astype(np.int64):
+                r = int(hits["read"][h])
+                W = oracle.strand_pattern(rd.read(r), int(hits["strand"][h]))
+                for p in lpos[loffs[h]:loffs[h + 1]][:8]:
+                    win = R[int(p):int(p) + LENGTH]
+                    assert win.size == LENGTH and int((win != W).sum()) == int(hits["nmm"][h]), (h, p)
+            say("batch 0: %d hits located at %d rows" % (hits.size, loffs[-1]))
         for j in np.nonzero((sample >= b * BATCH) & (sample < (b + 1) * BATCH))[0]:
             r = int(sample[j]) - b * BATCH
             got_ex[2 * j:2 * j + 2] = ex[2 * r:2 * r + 2]
