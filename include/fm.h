@@ -74,7 +74,8 @@ enum {
     FM_BOTH = 3,
     FM_DARRAY = 4,                  /* prune with the D lower bound (needs the reverse index) */
     FM_PLAIN = 16,                  /* use the plain one-thread-per-read-strand kernels */
-    FM_STATS = 32                   /* count Occ queries and bucket fetches into the workspace */
+    FM_STATS = 32,                  /* count Occ queries and bucket fetches into the workspace */
+    FM_FULL_RANK = 64               /* fm_search_exact: no early exit; misses report (rank, rank-1) */
 };
 
 /* Load flags. */
@@ -221,7 +222,11 @@ int fm_search_exact_workspace(const fm_index *idx, uint64_t nreads, uint32_t fla
  * uint64 CSR offsets, offs[0] = 0. out: device, one fm_interval per read and strand,
  * out[s_count * r + j] for the j-th requested strand. ws: device workspace (may be
  * NULL with FM_PLAIN and no FM_STATS). An empty read gives (0, n); a miss or a non-ACGT symbol gives
- * (1, 0). Reads may have any length below 2^32. */
+ * (1, 0). Reads may have any length below 2^32.
+ * With FM_FULL_RANK the search takes every step of Listing 1 even after the interval is
+ * empty, and reports it as it ends: (k, l) with k = the number of suffixes of R$ smaller
+ * than the pattern and l = k - 1 + its occurrences, so a miss gives its insertion rank
+ * (k, k - 1). A non-ACGT symbol ranks above T (C = n for it, no occurrences). */
 int fm_search_exact(const fm_index *idx, const uint8_t *codes, const uint64_t *offs,
                     uint64_t nreads, uint32_t flags, fm_interval *out, void *ws,
                     size_t ws_bytes, void *stream);
@@ -278,8 +283,8 @@ int fm_search_inexact(const fm_index *idx, const uint8_t *codes, const uint64_t 
  * whose DFS stops early (FM_EINVAL, FM_ERANGE, FM_EBUDGET) finishes that branch alone,
  * so its interval is still exact. Otherwise, and with FM_PLAIN, the two searches run one
  * after the other. Arguments and errors are those of the two calls; ws is sized by
- * fm_search_inexact_workspace. exact_flags: FM_FWD/FM_REVCOMP (FM_STATS and FM_PLAIN
- * are taken from flags). */
+ * fm_search_inexact_workspace. exact_flags: FM_FWD/FM_REVCOMP, and FM_FULL_RANK, which
+ * also makes the two searches separate (FM_STATS and FM_PLAIN are taken from flags). */
 int fm_search_both(const fm_index *idx, const uint8_t *codes, const uint64_t *offs, const uint8_t *z,
                    uint64_t nreads, uint32_t exact_flags, uint32_t flags, uint32_t zmax,
                    fm_interval *intervals, fm_hit *hits, uint64_t hit_cap, uint64_t *hit_offs,

@@ -295,9 +295,10 @@ def _strand_patterns(codes, offs, strands: int):
 
 
 def exact_by_rank_scan_batch(R: np.ndarray, codes, offs, strands: int = FWD, threads: int = 1,
-                             lib_path: str = _LIB) -> np.ndarray:
+                             full_rank: bool = False, lib_path: str = _LIB) -> np.ndarray:
     """exact_by_rank_scan for a whole batch: two passes over the text on `threads`
-    host threads."""
+    host threads. With full_rank every pattern gets (k, k + occ - 1) as the definition
+    gives it (k = suffixes smaller than the pattern), misses included."""
     lib = load(lib_path)
     R = np.ascontiguousarray(R, dtype=np.uint8)
     pc, po, _, _ = _strand_patterns(codes, offs, strands)
@@ -307,6 +308,10 @@ def exact_by_rank_scan_batch(R: np.ndarray, codes, offs, strands: int = FWD, thr
     if lib.oracle_rank_scan_batch(_ptr(R), R.size, _ptr(pc), _ptr(po), npat, threads, _ptr(k), _ptr(occ)):
         raise MemoryError("oracle_rank_scan_batch")
     out = np.zeros((npat, 2), np.uint32)
+    if full_rank:
+        out[:, 0] = k
+        out[:, 1] = (k + occ - 1).astype(np.int64).astype(np.uint32)
+        return out
     hit = occ > 0
     out[hit, 0] = k[hit]
     out[hit, 1] = k[hit] + occ[hit] - 1

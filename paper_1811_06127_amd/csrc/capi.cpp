@@ -483,13 +483,14 @@ int fm_search_both(const fm_index *idx, const uint8_t *codes, const uint64_t *of
                    uint32_t exact_flags, uint32_t flags, uint32_t zmax, fm_interval *intervals, fm_hit *hits,
                    uint64_t hit_cap, uint64_t *hit_offs, uint32_t *status, void *ws, size_t ws_bytes, void *stream)
 {
-    if (!idx || !nstrands(exact_flags) || (exact_flags & ~(uint32_t)(FM_BOTH | FM_PLAIN | FM_STATS))) return FM_EINVAL;
+    if (!idx || !nstrands(exact_flags) || (exact_flags & ~(uint32_t)(FM_BOTH | FM_PLAIN | FM_STATS | FM_FULL_RANK)))
+        return FM_EINVAL;
     if (nreads && !intervals) return FM_EINVAL;
     if (nreads * nstrands(exact_flags) >= 0xFFFFFFFFull) return FM_ERANGE;
-    if ((flags & FM_PLAIN) || (exact_flags & ~flags & FM_BOTH)) {
-        // the two searches one after the other: the plain kernels, or an exact search of
-        // a strand the inexact one does not search
-        const uint32_t ef = (exact_flags & FM_BOTH) | (flags & FM_PLAIN);
+    if ((flags & FM_PLAIN) || (exact_flags & ~flags & FM_BOTH) || (exact_flags & FM_FULL_RANK)) {
+        // the two searches one after the other: the plain kernels, an exact search of a
+        // strand the inexact one does not search, or full ranks (the DFS stops at misses)
+        const uint32_t ef = (exact_flags & (FM_BOTH | FM_FULL_RANK)) | (flags & FM_PLAIN);
         const int e = fm_search_exact(idx, codes, offs, nreads, ef, intervals, ws, ws_bytes, stream);
         if (e != FM_OK) return e;
         return fm_search_inexact(idx, codes, offs, z, nreads, flags, zmax, hits, hit_cap, hit_offs, status, ws,

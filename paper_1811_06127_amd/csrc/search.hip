@@ -110,6 +110,7 @@ struct WalkArgs {
     uint64_t dstride;      // DFULL: bytes per strand block
     uint32_t *queue;
     unsigned long long *stat_steps, *stat_bk;
+    uint32_t full_rank;    // EXACT: no early exit, report (k, l) as Listing 1 leaves it
 };
 
 template <int MODE>
@@ -153,7 +154,7 @@ struct Walker {
     {
         if (lead_lane) {
             if (MODE == WALK_EXACT) {
-                ((uint2 *)a.out)[rs] = (k <= l) ? make_uint2(k, l) : make_uint2(1u, 0u);
+                ((uint2 *)a.out)[rs] = (k <= l || a.full_rank) ? make_uint2(k, l) : make_uint2(1u, 0u);
             } else if (MODE == WALK_DBP) {
                 const uint32_t lo = (uint32_t)bp03, hi = (uint32_t)(bp03 >> 32);
                 ((uint4 *)a.out)[rs] = make_uint4(cnt | (lo << 16), (lo >> 16) | (hi << 16), (hi >> 16) | (bp4 << 16), 0u);
@@ -218,15 +219,16 @@ struct Walker {
         uint32_t nk = cb + (k ? ok : 0u) + 1;
         uint32_t nl = cb + ol;
         if (b > 3) {                                     // a non-base occurs nowhere
-            nk = 1;
-            nl = 0;
+            // ranked above T (C = n, no occurrences) when the rank is reported
+            nk = (MODE == WALK_EXACT && a.full_rank) ? a.lay.n + 1 : 1u;
+            nl = (MODE == WALK_EXACT && a.full_rank) ? a.lay.n : 0u;
         }
         addr += dir;
         rem -= 1;
         if (MODE == WALK_EXACT) {
             k = nk;
             l = nl;
-            fin = nk > nl || rem == 0;
+            fin = (nk > nl && !a.full_rank) || rem == 0;
             return;
         }
         const bool fail = nk > nl;                       // a difference is certain in this segment
@@ -468,6 +470,7 @@ hipError_t launch_walk(const fm_index *idx, const fm_tuning &t, int mode, bool p
     a.out = c.out;
     a.dstride = 0;
     a.queue = (uint32_t *)((char *)c.ws + kWsQueue);
+    a.full_rank = (mode == WALK_EXACT && (c.flags & FM_FULL_RANK)) ? 1u : 0u;
     a.stat_steps = nullptr;
     a.stat_bk = nullptr;
     if ((c.flags & FM_STATS) && c.ws) {
@@ -497,6 +500,7 @@ hipError_t launch_darray_full(const fm_index *idx, const fm_tuning &t, const Wal
     a.out = c.out;
     a.dstride = total_len;
     a.queue = nullptr;
+    a.full_rank = 0;
     a.stat_steps = nullptr;
     a.stat_bk = nullptr;
     if (a.total == 0) return hipSuccess;
@@ -1203,6 +1207,7 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
         w.out = c.ex_out;
         w.dstride = 0;
         w.queue = nullptr;
+        w.full_rank = 0;
         w.stat_steps = nullptr;
         w.stat_bk = nullptr;
         const uint32_t blocks = (a.total + 255) / 256, cap = (uint32_t)idx->cu_count * 4;

@@ -138,6 +138,29 @@ def test_exact_plain_and_batched(small, flags):
     idx.set_tuning(fm.FM_OP_EXACT, occ_interval=128, lanes=1, depth=1)
 
 
+@pytest.mark.parametrize("flags", [fm.FM_FWD, fm.FM_BOTH])
+def test_exact_full_rank(small, flags):
+    """FM_FULL_RANK: Listing 1 without the early exit reports (k, k - 1 + occ) with k the
+    number of smaller suffixes, for hits and misses alike (reading G5), as the oracle's
+    rank scan computes it from the text; patterns with N rank above T."""
+    R, x, xr, idx = small
+    codes, offs = exact_inputs(R)
+    want = oracle.exact_by_rank_scan_batch(R, codes, offs, flags, threads=4, full_rank=True)
+    canon = x.exact(codes, offs, flags, "definition")
+    hit = canon[:, 0] <= canon[:, 1]
+    assert np.array_equal(want[hit], canon[hit]) and (~hit).sum() > 100
+    cd, od, _ = fm.reads_to_device(codes, offs)
+    got = to_u32(fm.fm_search_exact(idx, cd, od, flags | fm.FM_PLAIN | fm.FM_FULL_RANK))
+    assert np.array_equal(got, want)
+    for I in LAYOUTS:
+        for L in LANES[I]:
+            idx.set_tuning(fm.FM_OP_EXACT, occ_interval=I, lanes=L)
+            got = to_u32(fm.fm_search_exact(idx, cd, od, flags | fm.FM_FULL_RANK))
+            bad = np.nonzero((got != want).any(axis=1))[0]
+            assert bad.size == 0, (I, L, bad[:5], got[bad[:5]], want[bad[:5]])
+    idx.set_tuning(fm.FM_OP_EXACT, occ_interval=128, lanes=1)
+
+
 def test_exact_small_workload():
     w = synth.small_exact_workload()
     x = oracle.OracleIndex(w.ref)

@@ -423,3 +423,29 @@ def test_pigeonhole_batch_equals_hamming_ball(seed, z):
         for f in ("read", "k", "l", "strand", "d"):
             assert np.array_equal(gh[f], wh[f]), (threads, f)
     assert wh.size > len(reads) // 2                                    # the check is not vacuous
+
+
+def test_full_rank_scan_equals_per_pattern_scan():
+    """Full ranks from the batched scan are the per-pattern scan's (smaller suffixes,
+    occurrences), misses and patterns with N included."""
+    R = _text_with_repeats(13, 4000)
+    rng = random.Random(13)
+    pats = [np.zeros(0, np.uint8), np.array([4], np.uint8), np.array([3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3], np.uint8)]
+    for _ in range(120):
+        m = rng.choice([1, 4, 10, 13, 30])
+        w = np.array([rng.randrange(4) for _ in range(m)], np.uint8)
+        if rng.random() < 0.4:
+            p = rng.randrange(R.size - m)
+            w = R[p:p + m].copy()
+        if rng.random() < 0.15:
+            w[rng.randrange(m)] = 4
+        pats.append(w)
+    codes, offs = csr(pats)
+    got = oracle.exact_by_rank_scan_batch(R, codes, offs, oracle.FWD, threads=2, full_rank=True)
+    lib = oracle.load()
+    import ctypes as C
+    for q, P in enumerate(pats):
+        k, occ = C.c_int64(), C.c_int64()
+        Pc = np.ascontiguousarray(P)
+        lib.oracle_rank_scan(R.ctypes.data, R.size, Pc.ctypes.data if P.size else None, P.size, C.byref(k), C.byref(occ))
+        assert got[q].tolist() == [k.value, (k.value + occ.value - 1) & 0xFFFFFFFF], q
