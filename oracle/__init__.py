@@ -177,13 +177,18 @@ class OracleIndex:
 
     def inexact(self, codes, offs, z, strands: int = BOTH, method: str = "listing2",
                 rev: "OracleIndex | None" = None, return_nodes: bool = False):
-        """Hits sorted by (read, strand, k) as a HIT_DTYPE array plus CSR offsets."""
+        """Hits sorted by (read, strand, k) as a HIT_DTYPE array plus CSR offsets.
+        Methods: "definition", "listing2", "listing2_darray" (substitutions only), and with
+        the deletion and insertion branches of Listing 2 too: "listing2_gaps",
+        "listing2_gaps_darray" and "definition_gaps" (edit costs, small inputs only),
+        whose hits are sorted by l as well and kept once per interval at the smallest cost."""
         codes = np.ascontiguousarray(codes, dtype=np.uint8)
         offs = np.ascontiguousarray(offs, dtype=np.uint64)
         nreads = offs.size - 1
         z = np.ascontiguousarray(np.broadcast_to(np.asarray(z, dtype=np.uint8), (nreads,)))
-        m = {"definition": 0, "listing2": 1, "listing2_darray": 2}[method]
-        if m == 2 and rev is None:
+        m = {"definition": 0, "listing2": 1, "listing2_darray": 2, "listing2_gaps": 3, "listing2_gaps_darray": 4,
+             "definition_gaps": 5}[method]
+        if m in (2, 4) and rev is None:
             raise ValueError("the D bound needs the index of reverse(R)")
         hit_offs = np.zeros(nreads + 1, dtype=np.uint64)
         nodes = np.zeros(max(nreads, 1), dtype=np.uint64)

@@ -393,6 +393,30 @@ static void inex_recur(inex_ctx *c, int64_t i, int z, int64_t k, int64_t l)
     }
 }
 
+/* InexRecur(W, i, z, k, l) with every branch of Listing 2: W[i] skipped (a deletion:
+ * i-1, z-1, same interval), a symbol b inserted before it (i, z-1, the interval of
+ * bW'), and W[i] matched or substituted by b (i-1, z or z-1, the interval of bW'); each
+ * b branch only for a non-empty interval. The bound test is as in inex_recur. */
+static void gap_recur(inex_ctx *c, int64_t i, int z, int64_t k, int64_t l)
+{
+    int bound = (c->D && i >= 0) ? c->D[i] : 0;
+    if (z < bound) return;
+    if (i < 0) {
+        push_hit(c->hits, c->read, c->strand, k, l, c->z0 - z);
+        return;
+    }
+    c->nodes++;
+    gap_recur(c, i - 1, z - 1, k, l);
+    for (int b = 0; b < 4; b++) {
+        int64_t kb = (int64_t)c->x->C[b] + occ_at(c->x, b, k - 1) + 1;
+        int64_t lb = (int64_t)c->x->C[b] + occ_at(c->x, b, l);
+        if (kb <= lb) {
+            gap_recur(c, i, z - 1, kb, lb);
+            gap_recur(c, i - 1, b == c->W[i] ? z : z - 1, kb, lb);
+        }
+    }
+}
+
 /* ------------------------------------------------------------------ definition of the hit set */
 
 /* Every W' over ACGT of the read's length with Hamming distance d <= z to W (a
@@ -430,11 +454,78 @@ static void ball_recur(ball_ctx *c, int64_t from, int used, int budget)
     }
 }
 
+/* Edit cost of aligning W (m symbols) with W' (mp symbols, codes 0..3) as Listing 2's
+ * recursion aligns them: substitutions, deletions of W symbols and insertions of W'
+ * symbols cost 1, a non-ACGT W symbol never matches, and no insertion may precede
+ * W[0] (the recursion stops once W[0] is consumed). dp holds (m+1)(mp+1) entries:
+ * dp[i][j] is the cost of W[0..i) against W'[0..j). */
+static int constrained_edit(const uint8_t *W, int64_t m, const uint8_t *Wp, int64_t mp, int *dp)
+{
+    const int inf = 1 << 28;
+    for (int64_t i = 0; i <= m; i++)
+        for (int64_t j = 0; j <= mp; j++) {
+            int v;
+            if (i == 0) v = j == 0 ? 0 : inf;
+            else if (j == 0) v = (int)i;
+            else {
+                v = dp[(i - 1) * (mp + 1) + j] + 1;                                 /* W[i-1] deleted */
+                const int ins = dp[i * (mp + 1) + j - 1] + 1;                       /* W'[j-1] inserted */
+                const int sub = dp[(i - 1) * (mp + 1) + j - 1] + (W[i - 1] != Wp[j - 1]);
+                if (ins < v) v = ins;
+                if (sub < v) v = sub;
+            }
+            dp[i * (mp + 1) + j] = v;
+        }
+    return dp[m * (mp + 1) + mp];
+}
+
+/* Definition of the gapped hit set: every W' over ACGT of length m-z .. m+z whose
+ * constrained edit cost d to W is at most z and which occurs in R contributes
+ * (k(W'), l(W'), d); the caller keeps the smallest d per interval. */
+static void gap_definition(const oracle_index *x, const uint8_t *P, int64_t m, int z, uint32_t read, uint8_t strand,
+                           hit_list *h)
+{
+    const int64_t lo = m - z > 0 ? m - z : 0, hi = m + z;
+    uint8_t *Wp = malloc((size_t)hi + 1);
+    int *dp = malloc(sizeof(int) * (size_t)(m + 1) * (size_t)(hi + 1));
+    for (int64_t L = lo; L <= hi; L++) {
+        uint64_t total = 1;
+        for (int64_t t = 0; t < L; t++) total *= 4;
+        for (uint64_t v = 0; v < total; v++) {
+            uint64_t u = v;
+            for (int64_t t = 0; t < L; t++) {
+                Wp[t] = (uint8_t)(u & 3);
+                u >>= 2;
+            }
+            const int d = constrained_edit(P, m, Wp, L, dp);
+            if (d > z) continue;
+            int64_t k, l;
+            interval_by_definition(x, Wp, L, &k, &l);
+            if (k <= l) push_hit(h, read, strand, k, l, d);
+        }
+    }
+    free(Wp);
+    free(dp);
+}
+
+static int cmp_hit_gap(const void *pa, const void *pb)
+{
+    const oracle_hit *a = pa, *b = pb;
+    if (a->read != b->read) return a->read < b->read ? -1 : 1;
+    if (a->strand != b->strand) return a->strand < b->strand ? -1 : 1;
+    if (a->k != b->k) return a->k < b->k ? -1 : 1;
+    if (a->l != b->l) return a->l < b->l ? -1 : 1;
+    return (a->d > b->d) - (a->d < b->d);
+}
+
 /* Inexact search of every read on the requested strands with per-read budgets z.
  * method 0: the Hamming-ball definition; 1: Listing 2 (substitutions); 2: Listing 2
- * with the D-array bound (needs rev). Hits are sorted by (read, strand, k). Writes at
- * most cap hits and returns the total number; hit_offs gets nreads+1 CSR offsets and
- * nodes_out (optional) the per-read count of expanded nodes (methods 1 and 2). */
+ * with the D-array bound (needs rev); 3: Listing 2 with all its branches (deletions and
+ * insertions too); 4: method 3 with the D-array bound; 5: the definition of method 3's
+ * hit set (small inputs only). Hits are sorted by (read, strand, k), and for methods
+ * 3-5 by l too, one per interval with its smallest cost. Writes at most cap hits and
+ * returns the total number; hit_offs gets nreads+1 CSR offsets and nodes_out
+ * (optional) the per-read count of expanded nodes (methods 1-4). */
 int64_t oracle_inexact(const oracle_index *x, const oracle_index *rev, const uint8_t *codes,
                        const uint64_t *offs, const uint8_t *z, int64_t nreads, int strands,
                        int method, oracle_hit *out, int64_t cap, uint64_t *hit_offs,
@@ -457,13 +548,16 @@ int64_t oracle_inexact(const oracle_index *x, const oracle_index *rev, const uin
                 ball_ctx b = {x, P, Wp, m, (uint32_t)r, (uint8_t)s, &h};
                 memcpy(Wp, P, (size_t)m);
                 ball_recur(&b, 0, 0, z[r]);
+            } else if (method == 5) {
+                gap_definition(x, P, m, z[r], (uint32_t)r, (uint8_t)s, &h);
             } else {
                 inex_ctx c = {x, P, NULL, z[r], (uint32_t)r, (uint8_t)s, &h, 0};
-                if (method == 2) {
+                if (method == 2 || method == 4) {
                     oracle_darray_one(rev, P, m, D);
                     c.D = D;
                 }
-                inex_recur(&c, m - 1, z[r], 0, x->n);
+                if (method >= 3) gap_recur(&c, m - 1, z[r], 0, x->n);
+                else inex_recur(&c, m - 1, z[r], 0, x->n);
                 nodes += c.nodes;
             }
         }
@@ -472,7 +566,22 @@ int64_t oracle_inexact(const oracle_index *x, const oracle_index *rev, const uin
     free(P);
     free(Wp);
     free(D);
-    if (h.len) qsort(h.buf, (size_t)h.len, sizeof(oracle_hit), cmp_hit);
+    if (method >= 3) {
+        /* one hit per (read, strand, interval): the smallest cost */
+        if (h.len) qsort(h.buf, (size_t)h.len, sizeof(oracle_hit), cmp_hit_gap);
+        int64_t u = 0;
+        for (int64_t e = 0; e < h.len; e++) {
+            const oracle_hit *a = &h.buf[e];
+            if (u > 0) {
+                const oracle_hit *p = &h.buf[u - 1];
+                if (p->read == a->read && p->strand == a->strand && p->k == a->k && p->l == a->l) continue;
+            }
+            h.buf[u++] = *a;
+        }
+        h.len = u;
+    } else if (h.len) {
+        qsort(h.buf, (size_t)h.len, sizeof(oracle_hit), cmp_hit);
+    }
     int64_t j = 0;
     for (int64_t r = 0; r < nreads; r++) {
         hit_offs[r] = (uint64_t)j;

@@ -73,3 +73,38 @@ def min_prefix_mismatch(R, W, i):
         d = sum(1 for a, b in zip(W[:L], R[j:j + L]) if int(a) != int(b))
         best = d if best is None else min(best, d)
     return best if best is not None else 10 ** 9
+
+
+def constrained_edit(W, Wp):
+    """Edit cost of aligning W with Wp the way Listing 2 builds alignments: substitutions,
+    deletions of W symbols and insertions of Wp symbols cost 1, a non-ACGT W symbol never
+    matches, and nothing may be inserted before W[0]."""
+    inf = 10 ** 9
+    prev = [0] + [inf] * len(Wp)                 # no W symbol consumed: only the empty Wp
+    for i in range(1, len(W) + 1):
+        cur = [i] + [0] * len(Wp)
+        for j in range(1, len(Wp) + 1):
+            cur[j] = min(prev[j] + 1, cur[j - 1] + 1, prev[j - 1] + (int(W[i - 1]) != Wp[j - 1]))
+        prev = cur
+    return prev[len(Wp)]
+
+
+def gapped_hits(R, W, z):
+    """{(k, l, d)}: every Wp over ACGT within constrained edit cost d <= z of W that occurs
+    in R (the empty Wp occurs everywhere: rows 0..n), once per interval at its smallest d."""
+    best = {}
+    m = len(W)
+    for L in range(max(0, m - z), m + z + 1):
+        for Wp in itertools.product(range(4), repeat=L):
+            d = constrained_edit(W, Wp)
+            if d > z:
+                continue
+            if L == 0:
+                kl = (0, len(R))
+            elif occurrences(R, Wp):
+                kl = interval(R, Wp)
+            else:
+                continue
+            if kl not in best or d < best[kl]:
+                best[kl] = d
+    return {(k, l, d) for (k, l), d in best.items()}

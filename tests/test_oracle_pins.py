@@ -449,3 +449,88 @@ def test_full_rank_scan_equals_per_pattern_scan():
         Pc = np.ascontiguousarray(P)
         lib.oracle_rank_scan(R.ctypes.data, R.size, Pc.ctypes.data if P.size else None, P.size, C.byref(k), C.byref(occ))
         assert got[q].tolist() == [k.value, (k.value + occ.value - 1) & 0xFFFFFFFF], q
+
+
+# ------------------------------------------------------------------ Listing 2 with gaps
+
+@pytest.mark.parametrize("seed", [21, 22, 23])
+def test_gapped_listing2_equals_bruteforce(seed):
+    """Listing 2 with its deletion and insertion branches, deduplicated per interval at the
+    smallest cost, equals the brute force over edit scripts (text scans, no suffix array)
+    and the oracle's own definition."""
+    rng = random.Random(seed)
+    n = rng.randrange(25, 60)
+    R = np.array([rng.randrange(4) for _ in range(n)], np.uint8)
+    for _ in range(4):                               # repeats, so intervals are wide
+        a, b = rng.randrange(n - 6), rng.randrange(n - 6)
+        R[b:b + 6] = R[a:a + 6]
+    x = OracleIndex(R)
+    xr = OracleIndex(reverse_text(R))
+    reads, zs = [np.zeros(0, np.uint8)], [1]
+    for i in range(14):
+        m = rng.randrange(1, 5)
+        p = rng.randrange(n - m)
+        w = R[p:p + m].copy()
+        if i % 3 == 0:
+            w[rng.randrange(m)] = rng.randrange(4)
+        if i % 5 == 0:
+            w[rng.randrange(m)] = 4
+        reads.append(w)
+        zs.append(rng.randrange(0, 3))
+    codes, offs = csr(reads)
+    zz = np.array(zs, np.uint8)
+    lh, lo = x.inexact(codes, offs, zz, oracle.FWD, "listing2_gaps")
+    dh, do = x.inexact(codes, offs, zz, oracle.FWD, "definition_gaps")
+    gh, go = x.inexact(codes, offs, zz, oracle.FWD, "listing2_gaps_darray", rev=xr)
+    assert np.array_equal(lo, do) and np.array_equal(lo, go)
+    for f in ("k", "l", "d"):
+        assert np.array_equal(lh[f], dh[f]) and np.array_equal(lh[f], gh[f]), f
+    total = 0
+    for r, w in enumerate(reads):
+        got = {(int(h["k"]), int(h["l"]), int(h["d"])) for h in lh[int(lo[r]):int(lo[r + 1])]}
+        assert got == bf.gapped_hits(R, w, zs[r]), (r, w, zs[r])
+        total += len(got)
+    assert total > len(reads)                        # not vacuous
+
+
+@pytest.mark.parametrize("seed", [24, 25])
+def test_gapped_properties_medium(seed):
+    """On reads of 20-40 bases: the D bound leaves the gapped hits unchanged; z = 0 gives
+    the exact search; every substitution hit is a gapped hit at no higher cost; both
+    strands behave alike."""
+    R = _text_with_repeats(seed, 3000)
+    x = OracleIndex(R)
+    xr = OracleIndex(reverse_text(R))
+    rng = random.Random(seed)
+    reads = []
+    for _ in range(40):
+        m = rng.randrange(20, 41)
+        p = rng.randrange(R.size - m)
+        w = R[p:p + m].copy()
+        for _ in range(rng.randrange(0, 3)):
+            j = rng.randrange(len(w))
+            if rng.random() < 0.5:
+                w = np.delete(w, j)
+            else:
+                w = np.insert(w, j, rng.randrange(4)).astype(np.uint8)
+        reads.append(w)
+    codes, offs = csr(reads)
+    for z in (0, 1, 2):
+        zz = np.full(len(reads), z, np.uint8)
+        gh, go = x.inexact(codes, offs, zz, oracle.BOTH, "listing2_gaps")
+        dh, do = x.inexact(codes, offs, zz, oracle.BOTH, "listing2_gaps_darray", rev=xr)
+        assert np.array_equal(go, do) and all(np.array_equal(gh[f], dh[f]) for f in ("k", "l", "strand", "d"))
+        sh, so = x.inexact(codes, offs, zz, oracle.BOTH, "listing2")
+        for r in range(len(reads)):
+            g = {(int(h["strand"]), int(h["k"]), int(h["l"])): int(h["d"]) for h in gh[int(go[r]):int(go[r + 1])]}
+            for h in sh[int(so[r]):int(so[r + 1])]:
+                key = (int(h["strand"]), int(h["k"]), int(h["l"]))
+                assert key in g and g[key] <= int(h["d"]), (z, r, key)
+        if z == 0:
+            ex = x.exact(codes, offs, oracle.BOTH, "definition")
+            want = [(r, s, int(ex[2 * r + s, 0]), int(ex[2 * r + s, 1])) for r in range(len(reads)) for s in (0, 1)
+                    if ex[2 * r + s, 0] <= ex[2 * r + s, 1]]
+            got = [(int(h["read"]), int(h["strand"]), int(h["k"]), int(h["l"])) for h in gh]
+            assert got == want and (gh["d"] == 0).all()
+        else:
+            assert gh.size > sh.size                 # gaps add hits
