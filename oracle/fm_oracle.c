@@ -399,20 +399,20 @@ static void inex_recur(inex_ctx *c, int64_t i, int z, int64_t k, int64_t l)
  * b branch only for a non-empty interval. The bound test is as in inex_recur. */
 static void gap_recur(inex_ctx *c, int64_t i, int z, int64_t k, int64_t l)
 {
-    int bound = (c->D && i >= 0) ? c->D[i] : 0;
-    if (z < bound) return;
+    const int lower = (c->D && i >= 0) ? c->D[i] : 0;     /* the bound of inex_recur */
+    if (z < lower) return;
     if (i < 0) {
         push_hit(c->hits, c->read, c->strand, k, l, c->z0 - z);
         return;
     }
     c->nodes++;
-    gap_recur(c, i - 1, z - 1, k, l);
+    gap_recur(c, i - 1, z - 1, k, l);                     /* W[i] deleted */
     for (int b = 0; b < 4; b++) {
-        int64_t kb = (int64_t)c->x->C[b] + occ_at(c->x, b, k - 1) + 1;
-        int64_t lb = (int64_t)c->x->C[b] + occ_at(c->x, b, l);
-        if (kb <= lb) {
-            gap_recur(c, i, z - 1, kb, lb);
-            gap_recur(c, i - 1, b == c->W[i] ? z : z - 1, kb, lb);
+        const int64_t ck = (int64_t)c->x->C[b] + occ_at(c->x, b, k - 1) + 1;
+        const int64_t cl = (int64_t)c->x->C[b] + occ_at(c->x, b, l);
+        if (ck <= cl) {
+            gap_recur(c, i, z - 1, ck, cl);               /* b inserted */
+            gap_recur(c, i - 1, b == c->W[i] ? z : z - 1, ck, cl);
         }
     }
 }

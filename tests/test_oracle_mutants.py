@@ -38,6 +38,10 @@ MUTANTS = {
     "rank_scan_prefix_not_smaller": ("if (r < 0 || (r == 0 && avail < m)) less++;", "if (r < 0) less++;"),
     "pigeonhole_strict_budget": ("if (hamming(R + s, P, m) > z) continue;", "if (hamming(R + s, P, m) >= z) continue;"),
     "pigeonhole_piece_offset": ("const int64_t s = p - a[i];", "const int64_t s = p;"),
+    "gap_insert_consumes": ("gap_recur(c, i, z - 1, ck, cl);", "gap_recur(c, i - 1, z - 1, ck, cl);"),
+    "gap_delete_free": ("gap_recur(c, i - 1, z - 1, k, l);", "gap_recur(c, i - 1, z, k, l);"),
+    "gap_leading_insert_allowed": ("if (i == 0) v = j == 0 ? 0 : inf;", "if (i == 0) v = (int)j;"),
+    "gap_keeps_largest_cost": ("return (a->d > b->d) - (a->d < b->d);", "return (a->d < b->d) - (a->d > b->d);"),
 }
 
 
@@ -88,6 +92,16 @@ def battery(lib):
                 exp = sorted([(0, *t) for t in bf.hamming_hits(R, w, int(z[r]))] +
                              [(1, *t) for t in bf.hamming_hits(R, bf.revcomp(w), int(z[r]))])
                 assert got == exp
+        # Listing 2 with gaps, its D-bounded form and its definition, against edit scripts
+        gp = [p[:3] for p in pats[:6]] + [np.zeros(0, np.uint8)]
+        gc, go = csr(gp)
+        gz = np.array([rng.randint(0, 1) for _ in gp], np.uint8)
+        for method in ("listing2_gaps", "listing2_gaps_darray", "definition_gaps"):
+            hits, hoffs = x.inexact(gc, go, gz, oracle.FWD, method, rev=xr)
+            for r, w in enumerate(gp):
+                seg = hits[int(hoffs[r]):int(hoffs[r + 1])]
+                assert sorted((int(h["k"]), int(h["l"]), int(h["d"])) for h in seg) == sorted(
+                    bf.gapped_hits(R, w, int(gz[r]))), method
         D = xr.darray(codes, offs, oracle.FWD)[0]
         for r, w in enumerate(pats):
             d = D[int(offs[r]):int(offs[r + 1])]
