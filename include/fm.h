@@ -75,7 +75,9 @@ enum {
     FM_DARRAY = 4,                  /* prune with the D lower bound (needs the reverse index) */
     FM_PLAIN = 16,                  /* use the plain one-thread-per-read-strand kernels */
     FM_STATS = 32,                  /* count Occ queries and bucket fetches into the workspace */
-    FM_FULL_RANK = 64               /* fm_search_exact: no early exit; misses report (rank, rank-1) */
+    FM_FULL_RANK = 64,              /* fm_search_exact: no early exit; misses report (rank, rank-1) */
+    FM_GAPS = 128                   /* fm_search_inexact: Listing 2 with its deletion and insertion
+                                       branches too (edit differences, not only substitutions) */
 };
 
 /* Load flags. */
@@ -253,10 +255,17 @@ int fm_search_inexact_workspace(const fm_index *idx, uint64_t nreads, uint64_t t
  * substitutions (non-ACGT positions always count) that occurs in R, reported once
  * as (read, k, l, strand, nmm). With FM_DARRAY the search is pruned with the D bound,
  * which never changes the result.
+ * With FM_GAPS the search takes every branch of Listing 2: besides the substitution of
+ * pattern symbol i it may skip it (a deletion) or insert any symbol before it, each
+ * costing 1; the recursion stops once the first pattern symbol is consumed, so nothing
+ * is inserted before it. Every interval reached is reported once, with the smallest
+ * number of edits nmm; hits are sorted by (strand, k, l), and the D bound (a lower bound
+ * on edits too) still never changes the result. The count at byte offset 8 of ws counts
+ * hits before this merging, an upper bound for a retry.
  *   z: device, nreads uint8 budgets; zmax: host, an upper bound on them (<= FM_ZMAX);
  *      a read with z[r] > zmax gets status FM_EINVAL and no hits.
  *   hits: device, hit_cap entries; hit_offs: device, nreads+1 uint64: the hits of
- *      read r are hits[hit_offs[r] .. hit_offs[r+1]) sorted by (strand, k).
+ *      read r are hits[hit_offs[r] .. hit_offs[r+1]) sorted by (strand, k) (and l).
  *   status: device, nreads uint32: FM_OK, FM_EINVAL, FM_ERANGE (read longer than
  *      65535), FM_EOVERFLOW (hits did not fit in hit_cap; the read has no hits
  *      listed) or FM_EBUDGET (node budget reached; no hits listed).

@@ -487,9 +487,10 @@ int fm_search_both(const fm_index *idx, const uint8_t *codes, const uint64_t *of
         return FM_EINVAL;
     if (nreads && !intervals) return FM_EINVAL;
     if (nreads * nstrands(exact_flags) >= 0xFFFFFFFFull) return FM_ERANGE;
-    if ((flags & FM_PLAIN) || (exact_flags & ~flags & FM_BOTH) || (exact_flags & FM_FULL_RANK)) {
-        // the two searches one after the other: the plain kernels, an exact search of a
-        // strand the inexact one does not search, or full ranks (the DFS stops at misses)
+    if ((flags & (FM_PLAIN | FM_GAPS)) || (exact_flags & ~flags & FM_BOTH) || (exact_flags & FM_FULL_RANK)) {
+        // the two searches one after the other: the plain kernels, the gapped search, an
+        // exact search of a strand the inexact one does not search, or full ranks (the
+        // DFS stops at misses)
         const uint32_t ef = (exact_flags & (FM_BOTH | FM_FULL_RANK)) | (flags & FM_PLAIN);
         const int e = fm_search_exact(idx, codes, offs, nreads, ef, intervals, ws, ws_bytes, stream);
         if (e != FM_OK) return e;

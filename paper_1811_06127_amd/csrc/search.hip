@@ -549,8 +549,9 @@ struct Dfs {
     uint32_t sp;                    // frames on the stack
     uint32_t hits, status, nodes;
     bool done;
-    // hits produced by the last expansion (children of a node with i == 0)
-    uint32_t pend, pk[4], pl[4], pd;
+    // hits produced by the last expansion (children of a node with i == 0): bits 0-3 the
+    // steps by b, bit 4 (gapped search) the deletion of the last symbol
+    uint32_t pend, pk[5], pl[5], pd;
     // exact interval of the strand pattern: its hit with no substitution, (1, 0) while
     // there is none
     uint32_t ek, el;
@@ -758,6 +759,127 @@ __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeL
     }
 }
 
+// DFS kinds: substitutions (Listing 2's substitution branches), the same with the exact
+// intervals taken from it (see dfs_emit), and Listing 2 with all its branches.
+enum { kDfsSub = 0, kDfsSubExact = 1, kDfsGap = 2 };
+
+// Loads of one gapped expansion: as dfs_load, with the whole top frame (the gapped frame
+// also holds its node's interval and the children still to visit).
+template <int I, int L>
+struct GapLoads {
+    Pair<I, L> pr;
+    uint4 tk, tl, tmeta;
+};
+
+template <int I, int L>
+__device__ __forceinline__ void gap_load(const DfsArgs &a, Dfs &d, uint32_t q, const Frame *fr, GapLoads<I, L> &nl)
+{
+    d.fetch_code(a);
+    nl.pr.load(a.lay, q, d.k ? d.k : 1u, d.l);
+    const Frame *ft = fr + (d.sp ? d.sp - 1 : a.fcap - 1);
+    nl.tk = ft->k;
+    nl.tl = ft->l;
+    nl.tmeta = ft->meta;
+}
+
+// Child `c` of a gapped node (i, zr, interval (k, l), pattern symbol wi, child intervals
+// kb, lb): c = 0-3 the step by symbol c (to i - 1, a substitution unless c = wi), 4-7
+// the insertion of symbol c - 4 (stays at i), 8 the deletion of pattern symbol i (to
+// i - 1, same interval). Every one but a matching step costs 1.
+__device__ __forceinline__ void gap_child(uint32_t c, uint32_t i, uint32_t zr, uint32_t wi, uint32_t k, uint32_t l,
+                                          const uint4 &kb, const uint4 &lb, uint32_t &ni, uint32_t &nz, uint32_t &nk,
+                                          uint32_t &nl)
+{
+    const uint32_t b = c & 3u;
+    const bool del = c >= 8;
+    ni = (c >= 4 && c < 8) ? i : i - 1;
+    nz = zr - ((c < 4 && c == wi) ? 0u : 1u);
+    nk = del ? k : sel4(b, kb.x, kb.y, kb.z, kb.w);
+    nl = del ? l : sel4(b, lb.x, lb.y, lb.z, lb.w);
+}
+
+// Expands a node of Listing 2 with all its branches. One Occ8 at (k-1, l) gives the
+// intervals of the four one-symbol extensions, which serve both the steps over pattern
+// symbol i and the insertions before it; the deletion keeps the node's interval. A child
+// is dropped when its interval is empty or when its remaining budget is below the D
+// bound of the pattern left to match (positions i - 1 for steps and the deletion, i for
+// insertions). At i == 0 the steps and the deletion are hits and only insertions go on.
+// The node continues with a costly child if there is one and pushes the rest as one
+// frame (children: bits 0-3 steps, 4-7 insertions, 8 deletion, with the node's i, budget,
+// symbol and interval); frames hand out costly children first and the matching step
+// last, so every frame on the stack lies on a costly edge of the current path and at
+// most z frames are stacked, as in the substitution search.
+template <int I, int L>
+__device__ __forceinline__ void gap_expand(const DfsArgs &a, Dfs &d, const GapLoads<I, L> &nl, uint32_t q,
+                                           Frame *fr, bool lead, uint64_t &n_occ, uint64_t &n_bk)
+{
+    const uint32_t kk = d.k ? d.k : 1u;
+    const uint32_t wi = d.sym(a);
+    Occ4 o1, o2;
+    occ8<I, L>(a.lay, nl.pr, q, kk, d.l, o1, o2);
+    const bool root = d.k == 0;
+    const uint32_t C0 = a.lay.C[0], C1 = a.lay.C[1], C2 = a.lay.C[2], C3 = a.lay.C[3];
+    const uint4 kb = make_uint4(C0 + 1 + (root ? 0u : o1.a), C1 + 1 + (root ? 0u : o1.c),
+                                C2 + 1 + (root ? 0u : o1.g), C3 + 1 + (root ? 0u : o1.t));
+    const uint4 lb = make_uint4(C0 + o2.a, C1 + o2.c, C2 + o2.g, C3 + o2.t);
+    if (a.stat_occ && lead) {
+        n_occ += 1;
+        n_bk += root ? 0 : (nl.pr.same ? 1 : 2);
+    }
+    const int ipos = (int)d.i, cpos = ipos - 1;
+    const bool keep_match = !d.dprune(d.zr, cpos);
+    const bool keep_costly = d.zr >= 1 && !d.dprune(d.zr - 1, cpos);   // substitutions, the deletion
+    const bool keep_ins = d.zr >= 1 && !d.dprune(d.zr - 1, ipos);
+    const uint32_t mbit = wi < 4 ? 1u << wi : 0u;
+    const uint32_t le = (kb.x <= lb.x ? 1u : 0u) | (kb.y <= lb.y ? 2u : 0u) | (kb.z <= lb.z ? 4u : 0u) |
+                        (kb.w <= lb.w ? 8u : 0u);
+    const uint32_t step = le & ((keep_match ? mbit : 0u) | (keep_costly ? (0xFu & ~mbit) : 0u));
+    const uint32_t ins = keep_ins ? le : 0u;
+    const uint32_t del = keep_costly ? 1u : 0u;
+    const bool leaf = d.i == 0;
+    d.pend = leaf ? (step | (del << 4)) : 0u;
+    d.pk[0] = kb.x, d.pk[1] = kb.y, d.pk[2] = kb.z, d.pk[3] = kb.w, d.pk[4] = d.k;
+    d.pl[0] = lb.x, d.pl[1] = lb.y, d.pl[2] = lb.z, d.pl[3] = lb.w, d.pl[4] = d.l;
+    d.pd = (d.z0 - d.zr) | (wi << 8);
+    const uint32_t go = (leaf ? 0u : (step | (del << 8))) | (ins << 4);
+    const uint32_t costly = go & ~mbit;
+    const bool advance = go != 0;
+    const uint32_t cont = (uint32_t)__builtin_ctz((costly ? costly : go) | 0x200u);
+    const uint32_t rest = costly ? (go & ~(1u << cont)) : 0u;
+    const uint32_t spare = a.fcap - 1;
+    Frame *fw = fr + (rest ? d.sp : spare);
+    if (lead) {
+        fw->k = kb;
+        fw->l = lb;
+        fw->meta = make_uint4((d.i & 0xFFFFu) | (d.zr << 16) | (wi << 20), d.k, d.l, rest);
+    }
+    const uint32_t nsp = d.sp + (rest ? 1u : 0u);
+    // otherwise the next node comes from the top frame: a costly child while there is one,
+    // then the matching step, which retires the frame
+    const bool pop = !advance && nsp > 0;
+    Frame *ft = fr + (pop ? nsp - 1 : spare);
+    const uint4 tm = nl.tmeta;
+    const uint32_t trest = tm.w & 0x1FFu, twi = (tm.x >> 20) & 0xFu;
+    const uint32_t tcostly = trest & ~(twi < 4 ? 1u << twi : 0u);
+    const uint32_t bt = (uint32_t)__builtin_ctz((tcostly ? tcostly : trest) | 0x200u);
+    const uint32_t left = trest & ~(1u << bt);
+    if (lead) ft->meta.w = left;
+    uint32_t ai, az, ak, al, pi, pz, pk, pl;
+    gap_child(cont, d.i, d.zr, wi, d.k, d.l, kb, lb, ai, az, ak, al);
+    gap_child(bt, tm.x & 0xFFFFu, (tm.x >> 16) & 0xFu, twi, tm.y, tm.z, nl.tk, nl.tl, pi, pz, pk, pl);
+    d.i = advance ? ai : pi;
+    d.zr = advance ? az : pz;
+    d.k = advance ? ak : pk;
+    d.l = advance ? al : pl;
+    d.sp = pop && !left ? nsp - 1 : nsp;
+    d.done = !advance && !pop;
+    d.nodes += 1;
+    if (!d.done && d.nodes >= a.budget) {
+        d.status = FM_EBUDGET;
+        d.done = true;
+    }
+}
+
 // Stores the hits of the last expansion: the first kHitSlots hits of a read-strand go
 // to its own slots with plain stores; later ones are appended to the overflow pool
 // (one atomic per wave, rarely needed). Then retires finished read-strands. Must be
@@ -770,9 +892,11 @@ __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeL
 // everything) has as exact interval its hit with no substitution, or none; a root
 // pruned by D (D(m-1) > z >= 0) has none either. A DFS that stops early leaves its
 // interval to exact_rest.
-template <int L, bool XD>
+template <int L, int K>
 __device__ void dfs_emit(const DfsArgs &a, Dfs &d, bool active, bool lead)
 {
+    constexpr bool XD = K == kDfsSubExact;
+    constexpr int NB = K == kDfsGap ? 5 : 4;   // hit kinds: steps by b, and the deletion (gapped)
     const uint32_t pend = active ? d.pend : 0u;
     const uint32_t wi = d.pd >> 8;
     uint32_t over = 0;                        // children whose hit goes to the overflow pool
@@ -783,9 +907,9 @@ __device__ void dfs_emit(const DfsArgs &a, Dfs &d, bool active, bool lead)
         }
         uint32_t h = d.hits;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < NB; ++b) {
             if ((pend >> b) & 1u) {
-                const uint32_t nmm = (d.pd & 0xFFu) + ((uint32_t)b != wi ? 1u : 0u);
+                const uint32_t nmm = (d.pd & 0xFFu) + ((b == 4 || (uint32_t)b != wi) ? 1u : 0u);
                 if (h < kHitSlots) {
                     if (lead)
                         ((uint4 *)a.slots)[(size_t)d.rs * kHitSlots + h] =
@@ -799,10 +923,10 @@ __device__ void dfs_emit(const DfsArgs &a, Dfs &d, bool active, bool lead)
     }
     if (__ballot(over != 0)) {
         const uint32_t lane = __lane_id(), leadlane = lane & ~(uint32_t)(L - 1);
-        uint64_t mb[4];
+        uint64_t mb[NB];
         uint32_t tot = 0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < NB; ++b) {
             mb[b] = __ballot(lead && ((over >> b) & 1u));
             tot += (uint32_t)__popcll(mb[b]);
         }
@@ -811,10 +935,10 @@ __device__ void dfs_emit(const DfsArgs &a, Dfs &d, bool active, bool lead)
         base = __shfl(base, 0);
         uint64_t off = base;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < NB; ++b) {
             if ((over >> b) & 1u) {
                 const uint64_t pos = off + rank_below(mb[b], leadlane);
-                const uint32_t nmm = (d.pd & 0xFFu) + ((uint32_t)b != wi ? 1u : 0u);
+                const uint32_t nmm = (d.pd & 0xFFu) + ((b == 4 || (uint32_t)b != wi) ? 1u : 0u);
                 if (pos < a.ocap) {
                     if (lead) ((uint4 *)a.opool)[pos] = make_uint4(d.read, d.pk[b], d.pl[b], d.strand | (nmm << 8));
                 } else {
@@ -840,7 +964,7 @@ __device__ void dfs_emit(const DfsArgs &a, Dfs &d, bool active, bool lead)
     }
 }
 
-template <int I>
+template <int I, int K>
 __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
 {
     extern __shared__ Frame lds_frames[];
@@ -858,11 +982,17 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
         const bool active = d.rs != kEmpty;
         if (!__any(active)) break;
         if (active && !d.done) {
-            NodeLoads<I, 1> nl;
-            dfs_load<I, 1>(a, d, 0, fr, nl);
-            dfs_expand<I, 1>(a, d, nl, 0, fr, true, n_occ, n_bk);
+            if constexpr (K == kDfsGap) {
+                GapLoads<I, 1> nl;
+                gap_load<I, 1>(a, d, 0, fr, nl);
+                gap_expand<I, 1>(a, d, nl, 0, fr, true, n_occ, n_bk);
+            } else {
+                NodeLoads<I, 1> nl;
+                dfs_load<I, 1>(a, d, 0, fr, nl);
+                dfs_expand<I, 1>(a, d, nl, 0, fr, true, n_occ, n_bk);
+            }
         }
-        dfs_emit<1, false>(a, d, active, true);
+        dfs_emit<1, K>(a, d, active, true);
     }
     wave_add(a.stat_occ, n_occ);
     wave_add(a.stat_bk, n_bk);
@@ -871,8 +1001,9 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
 // Each round: idle groups (refilled in batches) take read-strands and issue their
 // header loads; running groups issue their node loads and expand their nodes, by which
 // time the older header loads have arrived too; new read-strands begin; hits are stored
-// and finished read-strands retired. XD: exact intervals as well (see dfs_emit).
-template <int I, int L, bool XD>
+// and finished read-strands retired. K: the kind of search (kDfsSubExact: exact intervals
+// as well, see dfs_emit; kDfsGap: Listing 2 with all its branches).
+template <int I, int L, int K>
 __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
 {
     extern __shared__ Frame lds_frames[];
@@ -896,28 +1027,34 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
             }
         }
         if (running) {
-            NodeLoads<I, L> nl;
-            dfs_load<I, L>(a, d, q, fr, nl);
-            dfs_expand<I, L>(a, d, nl, q, fr, lead, n_occ, n_bk);
+            if constexpr (K == kDfsGap) {
+                GapLoads<I, L> nl;
+                gap_load<I, L>(a, d, q, fr, nl);
+                gap_expand<I, L>(a, d, nl, q, fr, lead, n_occ, n_bk);
+            } else {
+                NodeLoads<I, L> nl;
+                dfs_load<I, L>(a, d, q, fr, nl);
+                dfs_expand<I, L>(a, d, nl, q, fr, lead, n_occ, n_bk);
+            }
         }
         if (fresh) d.begin(a);
         // The header registers are loaded and read under two separate conditions; reading
         // them here on every path lets the compiler retire those loads now instead of
         // waiting on all memory operations where the registers are next written.
         asm volatile("" ::"v"(d.h0), "v"(d.h1), "v"(d.hz), "v"(d.hbp.x), "v"(d.hbp.y), "v"(d.hbp.z), "v"(d.hbp.w));
-        dfs_emit<L, XD>(a, d, running || fresh, lead);
+        dfs_emit<L, K>(a, d, running || fresh, lead);
         if (!__any(d.rs != kEmpty) && wq.exhausted) break;
     }
     wave_add(a.stat_occ, n_occ);
     wave_add(a.stat_bk, n_bk);
 }
 
-template <int I, int L, bool XD>
+template <int I, int L, int K>
 static hipError_t dfs_launch_batched(const fm_index *idx, const fm_tuning &t, const DfsArgs &a, hipStream_t s)
 {
     const int block = (int)t.block;
     const size_t lds = (size_t)(block / L) * a.fcap * sizeof(Frame);
-    int per = max_blocks_per_cu((const void *)dfs_batched<I, L, XD>, block, lds);
+    int per = max_blocks_per_cu((const void *)dfs_batched<I, L, K>, block, lds);
     if (t.waves_per_cu) {
         int want = (int)(t.waves_per_cu * 64 / block);
         if (want >= 1 && want < per) per = want;
@@ -925,18 +1062,18 @@ static hipError_t dfs_launch_batched(const fm_index *idx, const fm_tuning &t, co
     uint64_t grid = (uint64_t)idx->cu_count * per;
     const uint64_t need = ((uint64_t)a.total * L + block - 1) / block;
     if (need < grid) grid = need ? need : 1;
-    hipLaunchKernelGGL((dfs_batched<I, L, XD>), dim3((uint32_t)grid), dim3(block), lds, s, a);
+    hipLaunchKernelGGL((dfs_batched<I, L, K>), dim3((uint32_t)grid), dim3(block), lds, s, a);
     return hipGetLastError();
 }
 
-template <int I, bool XD>
+template <int I, int K>
 static hipError_t dfs_by_lanes(const fm_index *idx, const fm_tuning &t, const DfsArgs &a, hipStream_t s)
 {
     switch (t.lanes) {
-    case 1: return dfs_launch_batched<I, 1, XD>(idx, t, a, s);
-    case 2: return dfs_launch_batched<I, 2, XD>(idx, t, a, s);
-    case 4: if constexpr (Geo<I>::USED > 2) return dfs_launch_batched<I, 4, XD>(idx, t, a, s); break;
-    case 8: if constexpr (Geo<I>::USED > 4) return dfs_launch_batched<I, 8, XD>(idx, t, a, s); break;
+    case 1: return dfs_launch_batched<I, 1, K>(idx, t, a, s);
+    case 2: return dfs_launch_batched<I, 2, K>(idx, t, a, s);
+    case 4: if constexpr (Geo<I>::USED > 2) return dfs_launch_batched<I, 4, K>(idx, t, a, s); break;
+    case 8: if constexpr (Geo<I>::USED > 4) return dfs_launch_batched<I, 8, K>(idx, t, a, s); break;
     default: break;
     }
     return hipErrorInvalidValue;
@@ -1078,6 +1215,15 @@ __global__ void scatter_overflow(const fm_hit *opool, const unsigned long long *
 
 // Hits of one read sorted by (strand, k): in substitution mode every (strand, k) is
 // distinct, so the order is unique whatever order the hits were found in.
+// Order of a read's hits: strand, then k, then l, then the number of differences.
+__device__ __forceinline__ bool hit_before(const uint4 &u, const uint4 &v)
+{
+    if ((u.w & 0xFFu) != (v.w & 0xFFu)) return (u.w & 0xFFu) < (v.w & 0xFFu);
+    if (u.y != v.y) return u.y < v.y;
+    if (u.z != v.z) return u.z < v.z;
+    return ((u.w >> 8) & 0xFFu) < ((v.w >> 8) & 0xFFu);
+}
+
 __global__ void sort_read_hits(uint64_t nreads, const uint64_t *hit_offs, fm_hit *hits)
 {
     const uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
@@ -1086,17 +1232,58 @@ __global__ void sort_read_hits(uint64_t nreads, const uint64_t *hit_offs, fm_hit
     uint4 *h = (uint4 *)hits;
     for (uint64_t x = b + 1; x < e; ++x) {
         const uint4 v = h[x];
-        const uint64_t key = ((uint64_t)(v.w & 0xFFu) << 32) | v.y;
         uint64_t y = x;
         while (y > b) {
             const uint4 u = h[y - 1];
-            const uint64_t ku = ((uint64_t)(u.w & 0xFFu) << 32) | u.y;
-            if (ku <= key) break;
+            if (!hit_before(v, u)) break;
             h[y] = u;
             --y;
         }
         h[y] = v;
     }
+}
+
+// Gapped search: one hit per (strand, k, l), the one with the fewest differences (the
+// first of its run in the sorted order), moved to the front of the read's hits; cnt[r]
+// gets how many remain.
+__global__ void dedupe_read_hits(uint64_t nreads, const uint64_t *hit_offs, fm_hit *hits, uint32_t *cnt)
+{
+    const uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (r >= nreads) return;
+    const uint64_t b = hit_offs[r], e = hit_offs[r + 1];
+    uint4 *h = (uint4 *)hits;
+    uint64_t u = 0;
+    for (uint64_t x = b; x < e; ++x) {
+        const uint4 v = h[x];
+        if (u > 0) {
+            const uint4 p = h[b + u - 1];
+            if ((p.w & 0xFFu) == (v.w & 0xFFu) && p.y == v.y && p.z == v.z) continue;
+        }
+        h[b + u++] = v;
+    }
+    cnt[r] = (uint32_t)u;
+}
+
+// Moves each read's remaining hits to their new offsets in tmp.
+__global__ void move_read_hits(uint64_t nreads, const uint64_t *hit_offs, const uint64_t *new_offs, const fm_hit *hits,
+                               fm_hit *tmp)
+{
+    const uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (r >= nreads) return;
+    const uint64_t b = hit_offs[r], d = new_offs[r], u = new_offs[r + 1] - new_offs[r];
+    for (uint64_t x = 0; x < u; ++x) ((uint4 *)tmp)[d + x] = ((const uint4 *)hits)[b + x];
+}
+
+// The new offsets, and the hits back from tmp.
+__global__ void place_read_hits(uint64_t nreads, const uint64_t *new_offs, const fm_hit *tmp, uint64_t *hit_offs,
+                                fm_hit *hits)
+{
+    const uint64_t total = new_offs[nreads];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j <= nreads; j += stride)
+        hit_offs[j] = new_offs[j];
+    for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < total; j += stride)
+        ((uint4 *)hits)[j] = ((const uint4 *)tmp)[j];
 }
 
 InexactWs inexact_ws_layout(uint64_t nreads, uint32_t nstr, uint32_t zmax, uint64_t hit_cap)
@@ -1119,6 +1306,39 @@ InexactWs inexact_ws_layout(uint64_t nreads, uint32_t nstr, uint32_t zmax, uint6
     w.opool = off;     off = al(off + hit_cap * 16);
     w.total = off;
     return w;
+}
+
+template <int K>
+static hipError_t dfs_plain_launch(const fm_tuning &t, const DfsArgs &a, hipStream_t s)
+{
+    const uint32_t grid = (a.total + 255) / 256;
+    const size_t lds = (size_t)256 * a.fcap * sizeof(Frame);
+    switch (t.occ_interval) {
+    case 64: hipLaunchKernelGGL((dfs_plain<64, K>), dim3(grid), dim3(256), lds, s, a); break;
+    case 96: hipLaunchKernelGGL((dfs_plain<96, K>), dim3(grid), dim3(256), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((dfs_plain<128, K>), dim3(grid), dim3(256), lds, s, a); break;
+    case 192: hipLaunchKernelGGL((dfs_plain<192, K>), dim3(grid), dim3(256), lds, s, a); break;
+    case 224: hipLaunchKernelGGL((dfs_plain<224, K>), dim3(grid), dim3(256), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((dfs_plain<256, K>), dim3(grid), dim3(256), lds, s, a); break;
+    case 448: hipLaunchKernelGGL((dfs_plain<448, K>), dim3(grid), dim3(256), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int K>
+static hipError_t dfs_batched_launch(const fm_index *idx, const fm_tuning &t, const DfsArgs &a, hipStream_t s)
+{
+    switch (t.occ_interval) {
+    case 64: return dfs_by_lanes<64, K>(idx, t, a, s);
+    case 96: return dfs_by_lanes<96, K>(idx, t, a, s);
+    case 128: return dfs_by_lanes<128, K>(idx, t, a, s);
+    case 192: return dfs_by_lanes<192, K>(idx, t, a, s);
+    case 224: return dfs_by_lanes<224, K>(idx, t, a, s);
+    case 256: return dfs_by_lanes<256, K>(idx, t, a, s);
+    case 448: return dfs_by_lanes<448, K>(idx, t, a, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuning &tw, bool plain, const DfsCall &c,
@@ -1167,32 +1387,13 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     a.ex_nstr = strand_count(c.ex_flags);
     a.ex_strands = c.ex_flags & FM_BOTH;
     pe->mark(2, s);
-    if (plain) {
-        const uint32_t grid = (a.total + 255) / 256;
-        const size_t lds = (size_t)256 * a.fcap * sizeof(Frame);
-        switch (t.occ_interval) {
-        case 64: hipLaunchKernelGGL(dfs_plain<64>, dim3(grid), dim3(256), lds, s, a); break;
-        case 96: hipLaunchKernelGGL(dfs_plain<96>, dim3(grid), dim3(256), lds, s, a); break;
-        case 128: hipLaunchKernelGGL(dfs_plain<128>, dim3(grid), dim3(256), lds, s, a); break;
-        case 192: hipLaunchKernelGGL(dfs_plain<192>, dim3(grid), dim3(256), lds, s, a); break;
-        case 224: hipLaunchKernelGGL(dfs_plain<224>, dim3(grid), dim3(256), lds, s, a); break;
-        case 256: hipLaunchKernelGGL(dfs_plain<256>, dim3(grid), dim3(256), lds, s, a); break;
-        case 448: hipLaunchKernelGGL(dfs_plain<448>, dim3(grid), dim3(256), lds, s, a); break;
-        default: return hipErrorInvalidValue;
-        }
-        e = hipGetLastError();
-    } else {
-        switch (t.occ_interval) {
-        case 64: e = ex ? dfs_by_lanes<64, true>(idx, t, a, s) : dfs_by_lanes<64, false>(idx, t, a, s); break;
-        case 96: e = ex ? dfs_by_lanes<96, true>(idx, t, a, s) : dfs_by_lanes<96, false>(idx, t, a, s); break;
-        case 128: e = ex ? dfs_by_lanes<128, true>(idx, t, a, s) : dfs_by_lanes<128, false>(idx, t, a, s); break;
-        case 192: e = ex ? dfs_by_lanes<192, true>(idx, t, a, s) : dfs_by_lanes<192, false>(idx, t, a, s); break;
-        case 224: e = ex ? dfs_by_lanes<224, true>(idx, t, a, s) : dfs_by_lanes<224, false>(idx, t, a, s); break;
-        case 256: e = ex ? dfs_by_lanes<256, true>(idx, t, a, s) : dfs_by_lanes<256, false>(idx, t, a, s); break;
-        case 448: e = ex ? dfs_by_lanes<448, true>(idx, t, a, s) : dfs_by_lanes<448, false>(idx, t, a, s); break;
-        default: return hipErrorInvalidValue;
-        }
-    }
+    const bool gap = (c.flags & FM_GAPS) != 0;
+    if (plain)
+        e = gap ? dfs_plain_launch<kDfsGap>(t, a, s) : dfs_plain_launch<kDfsSub>(t, a, s);
+    else if (gap)
+        e = dfs_batched_launch<kDfsGap>(idx, t, a, s);
+    else
+        e = ex ? dfs_batched_launch<kDfsSubExact>(idx, t, a, s) : dfs_batched_launch<kDfsSub>(idx, t, a, s);
     if (e != hipSuccess) return e;
     if (ex) {
         WalkArgs w;
@@ -1250,6 +1451,17 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     hipLaunchKernelGGL(scatter_overflow, dim3((uint32_t)sgrid), dim3(256), 0, s, a.opool, a.ocount, a.ocap, nstr,
                        a.rs_count, c.status, c.hit_offs, cursor, c.hits);
     hipLaunchKernelGGL(sort_read_hits, dim3((nr + 255) / 256), dim3(256), 0, s, c.nreads, c.hit_offs, c.hits);
+    if (gap) {
+        // one hit per interval: dedupe in place, then re-pack through the (spent) overflow pool
+        hipLaunchKernelGGL(dedupe_read_hits, dim3((nr + 255) / 256), dim3(256), 0, s, c.nreads, c.hit_offs, c.hits, cnt);
+        hipLaunchKernelGGL(scan_reduce_u64, dim3((uint32_t)nblk), dim3(kScanBlock), 0, s, cnt, c.nreads, part);
+        hipLaunchKernelGGL(scan_partials_u64, dim3(1), dim3(1024), 0, s, part, nblk);
+        hipLaunchKernelGGL(scan_write_u64, dim3((uint32_t)nblk), dim3(kScanBlock), 0, s, cnt, c.nreads, part, offs_tmp);
+        hipLaunchKernelGGL(move_read_hits, dim3((nr + 255) / 256), dim3(256), 0, s, c.nreads, c.hit_offs, offs_tmp,
+                           c.hits, a.opool);
+        hipLaunchKernelGGL(place_read_hits, dim3((uint32_t)sgrid), dim3(256), 0, s, c.nreads, offs_tmp, a.opool,
+                           c.hit_offs, c.hits);
+    }
     pe->mark(4, s);
     return hipGetLastError();
 }

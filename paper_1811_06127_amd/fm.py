@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfmocc.so")
 
 FM_OK, FM_EINVAL, FM_EIO, FM_EFORMAT, FM_ENOMEM, FM_EDEVICE, FM_EOVERFLOW, FM_EBUDGET, FM_ERANGE, FM_EAGAIN = range(10)
-FM_FWD, FM_REVCOMP, FM_BOTH, FM_DARRAY, FM_PLAIN, FM_STATS, FM_FULL_RANK = 1, 2, 3, 4, 16, 32, 64
+FM_FWD, FM_REVCOMP, FM_BOTH, FM_DARRAY, FM_PLAIN, FM_STATS, FM_FULL_RANK, FM_GAPS = 1, 2, 3, 4, 16, 32, 64, 128
 FM_LOAD_REVERSE, FM_LOAD_ALL_LAYOUTS, FM_LOAD_DEVICE_SORT, FM_LOAD_LOCATE = 1, 2, 4, 8
 FM_OP_EXACT, FM_OP_DARRAY, FM_OP_INEXACT = 0, 1, 2
 FM_ZMAX = 4
