@@ -206,6 +206,9 @@ def main():
     # text positions of the step's hits (fm_locate)
     loc = locate_rate(fm, torch, idx, bufs.hits, int(in_batched[1][-1]))
     log("locate:", loc)
+    # Listing 2 with all its branches (z=1 edits) on the same reads
+    gap = gapped_rate(fm, torch, idx, codes, offs, z, nreads, total_len, args)
+    log("gapped:", gap)
 
     # the same step replayed from a launch graph captured for this batch shape
     plans = [fm.Plan.both(idx, codes, offs, z, EXACT, INEXACT, ZMAX, ex_out, bufs)]
@@ -342,6 +345,7 @@ def main():
         "cpu_baseline": cpu,
         "parity_sample": parity,
         "locate": loc,
+        "gapped": gap,
         "serving": serve,
         "genome_scale": genome,
         "p99_latency_ms": serve["p99_ms"] if serve else None,
@@ -478,6 +482,43 @@ def genome_bench(args):
     del codes, offs, z, ex_out, bufs
     idx.free()
     return out
+
+
+def gapped_rate(fm, torch, idx, codes, offs, z, nreads, total_len, args) -> dict:
+    """Listing 2 with its deletion and insertion branches (FM_GAPS), z=1 edits, both
+    strands, D bound, on the step's reads: batched and plain, bit-identical."""
+    flags = fm.FM_BOTH | fm.FM_DARRAY | fm.FM_GAPS
+    cap = 16 * nreads
+    gb = fm.InexactBuffers(idx, nreads, total_len, flags | fm.FM_PLAIN, 1, cap, codes.device)
+
+    def call(extra=0):
+        fm.fm_search_inexact(idx, codes, offs, z, flags | extra, 1, cap, bufs=gb)
+
+    call(fm.FM_STATS)
+    torch.cuda.synchronize()
+    st = gb.stats()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    out = {}
+    for name, extra, reps in (("batched", 0, args.steps), ("plain", fm.FM_PLAIN, max(args.plain_steps, 1))):
+        call(extra)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            call(extra)
+        ev[1].record()
+        torch.cuda.synchronize()
+        out[name] = (ev[0].elapsed_time(ev[1]) / reps, fm.hits_to_numpy(gb, nreads))
+    equal = all(np.array_equal(a, b) for a, b in zip(out["batched"][1], out["plain"][1]))
+    hits, _, status = out["batched"][1]
+    res = {"workload": "the step's 1M reads x 100 bp; z=1 edit (substitution, deletion or insertion), both strands, "
+                       "D bound; one hit per interval",
+           "ms": round(out["batched"][0], 4), "reads_per_s": round(nreads / (out["batched"][0] / 1e3), 1),
+           "plain_reads_per_s": round(nreads / (out["plain"][0] / 1e3), 1),
+           "batched_vs_plain": round(out["plain"][0] / out["batched"][0], 3), "batched_equals_plain": equal,
+           "hits": int(hits.size), "all_ok": bool((status == fm.FM_OK).all()),
+           "dfs_nodes": st["occ8"], "dfs_buckets": st["buckets"]}
+    del gb
+    return res
 
 
 def serve_bench(args):
