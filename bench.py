@@ -65,8 +65,12 @@ def locate_rate(fm, torch, idx, hits, nh: int, reps: int = 3) -> dict:
     ev[1].record()
     torch.cuda.synchronize()
     ms = ev[0].elapsed_time(ev[1]) / reps
+    # algorithmic bytes: a 32 B bucket per Psi^-1 step (I=64), a sample and a position per row,
+    # an interval and an offset per hit
+    alg = steps * 32 + rows * 8 + nh * 16
     return {"hits": nh, "rows": rows, "ms": round(ms, 4), "rows_per_s": round(rows / (ms / 1e3), 1),
-            "steps_per_row": round(steps / max(rows, 1), 2), "steps_per_s": round(steps / (ms / 1e3), 1)}
+            "steps_per_row": round(steps / max(rows, 1), 2), "steps_per_s": round(steps / (ms / 1e3), 1),
+            "algorithmic_gb_per_s": round(alg / (ms / 1e3) / 1e9, 1)}
 
 
 def parse():
@@ -497,6 +501,13 @@ def gapped_rate(fm, torch, idx, codes, offs, z, nreads, total_len, args) -> dict
     call(fm.FM_STATS)
     torch.cuda.synchronize()
     st = gb.stats()
+    idx.phase_timing(3)
+    for _ in range(3):
+        call()
+    torch.cuda.synchronize()
+    ph, _ = idx.phase_times()
+    idx.phase_timing(0)
+    dfs_ms = ph["dfs"] / 3
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     out = {}
     for name, extra, reps in (("batched", 0, args.steps), ("plain", fm.FM_PLAIN, max(args.plain_steps, 1))):
@@ -516,7 +527,12 @@ def gapped_rate(fm, torch, idx, codes, offs, z, nreads, total_len, args) -> dict
            "plain_reads_per_s": round(nreads / (out["plain"][0] / 1e3), 1),
            "batched_vs_plain": round(out["plain"][0] / out["batched"][0], 3), "batched_equals_plain": equal,
            "hits": int(hits.size), "all_ok": bool((status == fm.FM_OK).all()),
-           "dfs_nodes": st["occ8"], "dfs_buckets": st["buckets"]}
+           "dfs_nodes": st["occ8"], "dfs_buckets": st["buckets"],
+           "phase_ms": {"d_walk": round(ph["d_walk"] / 3, 4), "dfs": round(dfs_ms, 4),
+                        "compaction": round(ph["compaction"] / 3, 4)},
+           # the DFS kernel: 32 B buckets, read codes, D records, counts and statuses, hits
+           "dfs_algorithmic_gb_per_s": round((st["buckets"] * 32 + 2 * total_len + 24 * 2 * nreads +
+                                              16 * int(hits.size)) / (dfs_ms / 1e3) / 1e9, 1)}
     del gb
     return res
 
