@@ -34,8 +34,8 @@ METRIC = "reads/s & Occ8 queries/s, batched vs plain kernel, bit-exact; p99 late
 # were measured with: the key is a hash of the kernel sources, the kernel, its tuning and the workload; any other
 # combination reports traffic as null.
 MEASURED_TRAFFIC = {
-    ("b65c4cfc2748b552", "dfs_batched<XD>", (64, 1, 1, 256, 8), "2^24"): (12_619_279_699, 143_570_256),
-    ("b65c4cfc2748b552", "dfs_batched<XD>", (64, 1, 1, 256, 8), "3.1e9"): (342_332_193_848, 152_927_322),
+    ("b65c4cfc2748b552", "dfs_batched<64, 1, 1>", (64, 1, 1, 256, 8), "2^24"): (12_619_279_699, 143_570_256),
+    ("b65c4cfc2748b552", "dfs_batched<64, 1, 1>", (64, 1, 1, 256, 8), "3.1e9"): (342_332_193_848, 152_927_322),
 }
 KERNEL_SOURCES = ("search.hip", "fm_device.hpp", "fm_internal.hpp")
 
@@ -283,8 +283,10 @@ def main():
     }
     dom = max(("d_walk", "dfs"), key=lambda k: phase_ms[k])
     achieved = alg[dom] / (phase_ms[dom] / 1e3) / 1e9
-    kname = {"d_walk": "walk_batched<DBP>", "dfs": "dfs_batched<XD>"}[dom]
     tcfg = tuning[{"d_walk": "d_walk", "dfs": "inexact"}[dom]]["config"]
+    # the kernel as compiled: DFS kind 1 takes the exact intervals from the DFS; walk mode 1 is the D walk
+    kname = ("dfs_batched<%d, %d, 1>" % (tcfg["occ_interval"], tcfg["lanes"]) if dom == "dfs" else
+             "walk_batched<%d, %d, %d, 1>" % (tcfg["occ_interval"], tcfg["lanes"], tcfg["depth"]))
     key = (kernel_source_hash(), kname, tuple(tcfg[f] for f in ("occ_interval", "lanes", "depth", "block",
                                                                 "waves_per_cu")), "2^24")
     traffic = MEASURED_TRAFFIC.get(key)
@@ -452,8 +454,8 @@ def genome_bench(args):
     alg = st["buckets"] * 32 + 2 * B * LEN + 32 * nrs + 16 * int(eager[1][1][-1])
     achieved = alg / (phase["dfs"] / 1e3) / 1e9
     tcfg = tuning["inexact"]
-    key = (kernel_source_hash(), "dfs_batched<XD>", tuple(tcfg[f] for f in ("occ_interval", "lanes", "depth", "block",
-                                                                          "waves_per_cu")), "3.1e9")
+    key = (kernel_source_hash(), "dfs_batched<%d, %d, 1>" % (tcfg["occ_interval"], tcfg["lanes"]),
+           tuple(tcfg[f] for f in ("occ_interval", "lanes", "depth", "block", "waves_per_cu")), "3.1e9")
     traffic = MEASURED_TRAFFIC.get(key)
     out = {
         "workload": "3.1e9-base reference (55%% i.i.d., 45%% copies of 500 families, 5-15%% divergence); %d batches of "
@@ -475,7 +477,7 @@ def genome_bench(args):
         "occ8_queries_per_s": {"fm_occ8_" + k: round(v, 1) for k, v in occ8.items()},
         "locate_first_batch": gloc,
         "tuning": tuning,
-        "roofline": {"bound": "hbm", "kernel": "dfs_batched<XD>", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": key[1], "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": int(sum(traffic)) if traffic else None,
                      "traffic_gb_per_s": round(sum(traffic) / (phase["dfs"] / 1e3) / 1e9, 1) if traffic else None,
