@@ -125,6 +125,11 @@ typedef struct {
     uint32_t waves_per_cu;          /* persistent grid = CUs * waves_per_cu * 64 / block;
                                        0 = as many as fit */
     uint32_t node_budget;           /* inexact: DFS nodes per read-strand before FM_EBUDGET */
+    uint32_t order;                 /* substitution search with FM_DARRAY, batched kernels:
+                                       1 = the DFS claims read-strands heaviest first,
+                                       weighing each by its D bound's slack, sum over i of
+                                       max(0, z - D(i)); 0 = in read order (always so with
+                                       FM_GAPS). Results are the same either way. */
 } fm_tuning;
 
 enum { FM_OP_EXACT = 0, FM_OP_DARRAY = 1, FM_OP_INEXACT = 2 };
@@ -276,7 +281,11 @@ int fm_search_inexact_workspace(const fm_index *idx, uint64_t nreads, uint64_t t
  *      them; a node whose interval is still (0, n) takes its children from C and
  *      fetches none), 80 (D-walk steps that fetched) and 88 (buckets they fetched)
  *      count the work done.
- * Output is deterministic: independent of scheduling, batch order and launch tuning. */
+ * Output is deterministic (independent of scheduling, batch order and launch tuning)
+ * whenever hit_cap suffices. When it does not, hits beyond the per-read-strand slots
+ * compete for hit_cap places in arrival order, so which reads end FM_EOVERFLOW can vary
+ * from call to call; every read listed FM_OK still has all its hits, and the required
+ * total at byte offset 8 of ws is exact. */
 int fm_search_inexact(const fm_index *idx, const uint8_t *codes, const uint64_t *offs,
                       const uint8_t *z, uint64_t nreads, uint32_t flags, uint32_t zmax,
                       fm_hit *hits, uint64_t hit_cap, uint64_t *hit_offs, uint32_t *status,

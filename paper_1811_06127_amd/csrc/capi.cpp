@@ -77,6 +77,7 @@ bool valid_tuning(const fm_index *idx, const fm_tuning &t)
     if (t.lanes > max_lanes(t.occ_interval)) return false;
     if (t.depth != 1 && t.depth != 2) return false;
     if (t.block < 64 || t.block > 256 || t.block % 64) return false;
+    if (t.order > 1) return false;
     return true;
 }
 
@@ -84,9 +85,9 @@ bool valid_tuning(const fm_index *idx, const fm_tuning &t)
 // best setting measured on MI355X for all three searches; fm_autotune refines it.
 void default_tunings(fm_index *idx, uint32_t I)
 {
-    fm_tuning ex = {I, 1, 1, 256, 8, 0};
-    fm_tuning dw = {I, 1, 1, 256, 8, 0};
-    fm_tuning in = {I, 1, 1, 256, 8, 1u << 22};
+    fm_tuning ex = {I, 1, 1, 256, 8, 0, 0};
+    fm_tuning dw = {I, 1, 1, 256, 8, 0, 0};
+    fm_tuning in = {I, 1, 1, 256, 8, 1u << 22, 1};
     idx->tune[FM_OP_EXACT] = ex;
     idx->tune[FM_OP_DARRAY] = dw;
     idx->tune[FM_OP_INEXACT] = in;

@@ -35,6 +35,8 @@ namespace fm {
 
 constexpr uint32_t kQueueChunk = 64;   // read-strands a wave takes from the work queue at once
 constexpr uint32_t kHitSlots = 4;      // hits stored per read-strand without an atomic
+constexpr uint32_t kOrderBins = 256;   // weight classes of the DFS claim order
+constexpr uint32_t kOrderBlocks = 1024; // workgroups that count and place the claim order
 
 constexpr int kLayouts = 7;
 constexpr uint32_t kIntervals[kLayouts] = {64, 96, 128, 192, 224, 256, 448};
@@ -74,7 +76,7 @@ enum : size_t {
 };
 
 struct InexactWs {       // sub-buffers of the inexact workspace
-    size_t bp, rs_count, rs_status, cursor, rd_status, cnt, offs, part, slots, opool, total;
+    size_t bp, rs_count, rs_status, cursor, rd_status, cnt, offs, part, slots, opool, bin, ohist, rec, total;
 };
 InexactWs inexact_ws_layout(uint64_t nreads, uint32_t nstr, uint32_t zmax, uint64_t hit_cap);
 

@@ -70,8 +70,8 @@ bool cache_lookup(const char *path, const std::string &key, fm_tuning *t, float 
         char k[300];
         fm_tuning v = {};
         float m = 0;
-        if (sscanf(line, "%299s %u %u %u %u %u %u %f", k, &v.occ_interval, &v.lanes, &v.depth, &v.block,
-                   &v.waves_per_cu, &v.node_budget, &m) == 8 && key == k) {
+        if (sscanf(line, "%299s %u %u %u %u %u %u %u %f", k, &v.occ_interval, &v.lanes, &v.depth, &v.block,
+                   &v.waves_per_cu, &v.node_budget, &v.order, &m) == 9 && key == k) {
             *t = v;
             *ms = m;
             found = true;   // last entry wins
@@ -85,8 +85,8 @@ void cache_store(const char *path, const std::string &key, const fm_tuning &t, f
 {
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %u %u %u %u %u %u %.6f\n", key.c_str(), t.occ_interval, t.lanes, t.depth, t.block, t.waves_per_cu,
-            t.node_budget, ms);
+    fprintf(f, "%s %u %u %u %u %u %u %u %.6f\n", key.c_str(), t.occ_interval, t.lanes, t.depth, t.block,
+            t.waves_per_cu, t.node_budget, t.order, ms);
     fclose(f);
 }
 
@@ -226,12 +226,16 @@ int fm_autotune(fm_index *idx, int op, const uint8_t *codes, const uint64_t *off
         if (op == FM_OP_DARRAY && !idx->rlay[ilog(I)]) continue;
         for (uint32_t lanes = 1; lanes <= max_lanes(I); lanes *= 2) {
             for (uint32_t depth = 1; depth <= (op == FM_OP_INEXACT ? 1u : 2u); ++depth) {
-                for (uint32_t waves : {0u, 4u, 8u, 12u, 16u}) {
+                // the claim order matters only to the substitution DFS with the D bound
+                const bool orders = op == FM_OP_INEXACT && (flags & FM_DARRAY) && !(flags & FM_GAPS);
+                for (uint32_t cand = 0; cand < (orders ? 10u : 5u); ++cand) {
+                    static const uint32_t kWaves[5] = {0u, 4u, 8u, 12u, 16u};
                     fm_tuning t = base;
                     t.occ_interval = I;
                     t.lanes = lanes;
                     t.depth = depth;
-                    t.waves_per_cu = waves;
+                    t.waves_per_cu = kWaves[cand % 5];
+                    if (orders) t.order = cand < 5 ? 1u : 0u;
                     if (fm_set_tuning(idx, op, &t) != FM_OK) continue;
                     st = run_op(idx, call_op, codes, offs, z, nreads, run_flags, zmax, out_buf, hit_cap, hit_offs,
                                 status, ws, ws_bytes, s);

@@ -515,6 +515,9 @@ struct DfsArgs {
     const uint64_t *offs;
     const uint8_t *z;
     const uint4 *bp;       // D breakpoint records per read-strand, or nullptr
+    // claim order (nullptr: read-strand order): item j of the queue is the read-strand
+    // whose header is rec[2j], rec[2j+1] (see order_place)
+    const uint4 *rec;
     uint32_t total, nstr, strand0, zmax;
     uint32_t fcap;         // stack frames per read-strand: zmax, plus one spare
     uint32_t budget;       // expanded nodes per read-strand
@@ -593,13 +596,25 @@ struct Dfs {
 
     // Header of a new read-strand (offsets, budget, D record): loaded into registers of
     // its own by request() and used by begin() after the round's loads have arrived.
+    // With a claim order the header is one record: h0 = its start, h1 = its length, hrs
+    // = the read-strand; the loads go straight into these registers, nothing waits.
     uint64_t h0, h1;
-    uint32_t hz;
+    uint32_t hz, hrs;
     uint4 hbp;
 
     __device__ void request(const DfsArgs &a, uint32_t item)
     {
-        rs = item;
+        rs = item;                                   // busy from now on; begin() sets rs
+        if (a.rec) {
+            const uint4 r0 = a.rec[2 * (size_t)item], r1 = a.rec[2 * (size_t)item + 1];
+            hrs = r0.x;
+            h0 = u64_of(r0.y, r0.z);
+            h1 = r0.w;
+            hz = r1.x;
+            hbp = make_uint4(r1.y, r1.z, r1.w, 0u);
+            return;
+        }
+        hrs = item;
         const uint32_t rd = a.nstr == 2 ? item >> 1 : item;
         h0 = a.offs[rd];
         h1 = a.offs[rd + 1];
@@ -609,10 +624,11 @@ struct Dfs {
 
     __device__ void begin(const DfsArgs &a)
     {
+        rs = hrs;
         read = a.nstr == 2 ? rs >> 1 : rs;
         strand = a.nstr == 2 ? (rs & 1u) : a.strand0;
         base = h0;
-        m = (uint32_t)(h1 - h0);
+        m = a.rec ? (uint32_t)h1 : (uint32_t)(h1 - h0);
         z0 = hz;
         sp = 0;
         hits = 0;
@@ -1041,7 +1057,8 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
         // The header registers are loaded and read under two separate conditions; reading
         // them here on every path lets the compiler retire those loads now instead of
         // waiting on all memory operations where the registers are next written.
-        asm volatile("" ::"v"(d.h0), "v"(d.h1), "v"(d.hz), "v"(d.hbp.x), "v"(d.hbp.y), "v"(d.hbp.z), "v"(d.hbp.w));
+        asm volatile("" ::"v"(d.h0), "v"(d.h1), "v"(d.hz), "v"(d.hrs), "v"(d.hbp.x), "v"(d.hbp.y), "v"(d.hbp.z),
+                     "v"(d.hbp.w));
         dfs_emit<L, K>(a, d, running || fresh, lead);
         if (!__any(d.rs != kEmpty) && wq.exhausted) break;
     }
@@ -1077,6 +1094,159 @@ static hipError_t dfs_by_lanes(const fm_index *idx, const fm_tuning &t, const Df
     default: break;
     }
     return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ claim order
+
+// The persistent DFS claims read-strands heaviest first (longest processing time first).
+// Its node count is largest where the D bound leaves the most room for substitutions:
+// the weight is sum_i max(0, z - D(i)), i.e. the sum over c < z of the first position at
+// which D exceeds c (the breakpoints of the D walk). A launch in read order ends with the
+// last few heavy trees running on a mostly idle chip; heaviest first leaves the light and
+// root-pruned read-strands for the end, where they fill lanes as they free up. The order
+// only decides which lane searches which read-strand and when: results are unchanged.
+// Weights are bucketed into kOrderBins classes (exact below 64, then 16 per octave);
+// read-strands of one class are claimed in no particular order. The gapped search keeps
+// read order: there the heaviest class (patterns that occur, D zero throughout) spans
+// ten-fold node counts, so the weight cannot rank the trees that decide the tail.
+
+struct OrderArgs {
+    const uint64_t *offs;
+    const uint8_t *z;
+    const uint4 *bp;
+    uint32_t total, nstr, zmax;
+    uint32_t chunk;        // read-strands per workgroup of the counting and placing passes
+    uint8_t *bin;          // per read-strand: kOrderBins - 1 - its weight class
+    uint32_t *hist;        // per workgroup and bin: count, then the bin's first slot
+    uint32_t *tot;         // per bin: read-strands in it
+    uint4 *rec;            // two uint4 per slot of the claim order (see Dfs::request)
+};
+
+static_assert(kOrderBins == 256, "the claim-order passes keep one bin per thread of a 256-thread workgroup");
+
+// Workgroups of the counting and placing passes: one per kOrderChunk read-strands, at
+// most kOrderBlocks (one thread of the scan pass per workgroup).
+constexpr uint32_t kOrderChunk = 2048;
+
+static uint32_t order_blocks(uint64_t nrs)
+{
+    const uint64_t b = (nrs + kOrderChunk - 1) / kOrderChunk;
+    return (uint32_t)(b < 1 ? 1 : (b < kOrderBlocks ? b : kOrderBlocks));
+}
+
+__device__ __forceinline__ uint32_t order_class(uint32_t w)
+{
+    if (w < 64) return w;
+    const uint32_t e = 31u - __clz(w);               // 6 ... 31
+    const uint32_t v = 64u + (e - 6u) * 16u + ((w >> (e - 4u)) & 15u);
+    return v < kOrderBins - 1 ? v : kOrderBins - 1;
+}
+
+// Weight of a read-strand from its D record (first 16 bits: breakpoints found, then
+// breakpoint c at bits 16 (c + 1) ..., 0xFFFF when D never exceeds c); zero when the
+// search decides the read-strand at once (budget above zmax, read over 65535, root pruned).
+__device__ __forceinline__ uint32_t order_weight(const OrderArgs &o, uint64_t b0, uint64_t b1, uint32_t z, uint4 r)
+{
+    const uint64_t len = b1 - b0;
+    const uint32_t nbp = r.x & 0xFFFFu;
+    if (z > o.zmax || len > 65535u || nbp > z) return 0u;
+    const uint32_t m = (uint32_t)len;
+    const uint32_t f[4] = {r.x >> 16, r.y & 0xFFFFu, r.y >> 16, r.z & 0xFFFFu};
+    uint32_t w = 0;
+    for (uint32_t c = 0; c < 4; ++c)
+        if (c < z) w += f[c] < m ? f[c] : m;
+    return w;
+}
+
+// Inclusive sum over the block's N threads (one value each), in s[N].
+template <uint32_t N>
+__device__ __forceinline__ uint32_t block_inclusive(uint32_t *s, uint32_t v)
+{
+    const uint32_t t = threadIdx.x;
+    s[t] = v;
+    __syncthreads();
+    for (uint32_t d = 1; d < N; d <<= 1) {
+        const uint32_t u = t >= d ? s[t - d] : 0u;
+        __syncthreads();
+        s[t] += u;
+        __syncthreads();
+    }
+    return s[t];
+}
+
+// Pass 1: each workgroup classifies its chunk and counts the bins.
+__global__ void __launch_bounds__(256) order_count(OrderArgs o)
+{
+    __shared__ uint32_t h[kOrderBins];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t lo = (uint64_t)blockIdx.x * o.chunk;
+    const uint64_t hi = lo + o.chunk < o.total ? lo + o.chunk : o.total;
+    for (uint64_t j = lo + threadIdx.x; j < hi; j += 256) {
+        const uint32_t rs = (uint32_t)j, rd = o.nstr == 2 ? rs >> 1 : rs;
+        const uint32_t w = order_weight(o, o.offs[rd], o.offs[rd + 1], o.z[rd], o.bp[rs]);
+        const uint32_t b = kOrderBins - 1 - order_class(w);
+        o.bin[rs] = (uint8_t)b;
+        atomicAdd(&h[b], 1u);
+    }
+    __syncthreads();
+    o.hist[blockIdx.x * kOrderBins + threadIdx.x] = h[threadIdx.x];
+}
+
+// Pass 2, a workgroup per bin and a thread per counting workgroup: each workgroup's first
+// slot within the bin, and the bin's total.
+__global__ void __launch_bounds__(kOrderBlocks) order_scan(uint32_t *hist, uint32_t *tot, uint32_t nblk)
+{
+    __shared__ uint32_t s[kOrderBlocks];
+    const uint32_t b = blockIdx.x, g = threadIdx.x;
+    const uint32_t v = g < nblk ? hist[g * kOrderBins + b] : 0u;
+    const uint32_t inc = block_inclusive<kOrderBlocks>(s, v);
+    if (g < nblk) hist[g * kOrderBins + b] = inc - v;
+    if (g == kOrderBlocks - 1) tot[b] = inc;
+}
+
+// Pass 3: each workgroup finds the bins' first slots (bins in order, heaviest first) and
+// writes the header records of its chunk into its slots.
+__global__ void __launch_bounds__(256) order_place(OrderArgs o)
+{
+    __shared__ uint32_t s[256];
+    __shared__ uint32_t cur[kOrderBins];
+    const uint32_t t = o.tot[threadIdx.x];
+    const uint32_t first = block_inclusive<kOrderBins>(s, t) - t + o.hist[blockIdx.x * kOrderBins + threadIdx.x];
+    cur[threadIdx.x] = first;
+    __syncthreads();
+    const uint64_t lo = (uint64_t)blockIdx.x * o.chunk;
+    const uint64_t hi = lo + o.chunk < o.total ? lo + o.chunk : o.total;
+    for (uint64_t j = lo + threadIdx.x; j < hi; j += 256) {
+        const uint32_t rs = (uint32_t)j, rd = o.nstr == 2 ? rs >> 1 : rs;
+        const uint64_t b0 = o.offs[rd], b1 = o.offs[rd + 1];
+        const uint4 r = o.bp[rs];
+        const uint32_t slot = atomicAdd(&cur[o.bin[rs]], 1u);
+        o.rec[2 * (size_t)slot] = make_uint4(rs, (uint32_t)b0, (uint32_t)(b0 >> 32), (uint32_t)(b1 - b0));
+        o.rec[2 * (size_t)slot + 1] = make_uint4(o.z[rd], r.x, r.y, r.z);
+    }
+}
+
+static hipError_t launch_order(const DfsCall &c, const InexactWs &W, uint32_t nstr, uint32_t total, hipStream_t s)
+{
+    char *ws = (char *)c.ws;
+    OrderArgs o;
+    o.offs = c.offs;
+    o.z = c.z;
+    o.bp = (const uint4 *)(ws + W.bp);
+    o.total = total;
+    o.nstr = nstr;
+    o.zmax = c.zmax;
+    const uint32_t nblk = order_blocks(total);
+    o.chunk = (uint32_t)(((uint64_t)total + nblk - 1) / nblk);
+    o.bin = (uint8_t *)(ws + W.bin);
+    o.hist = (uint32_t *)(ws + W.ohist);
+    o.tot = o.hist + (size_t)nblk * kOrderBins;
+    o.rec = (uint4 *)(ws + W.rec);
+    hipLaunchKernelGGL(order_count, dim3(nblk), dim3(256), 0, s, o);
+    hipLaunchKernelGGL(order_scan, dim3(kOrderBins), dim3(kOrderBlocks), 0, s, o.hist, o.tot, nblk);
+    hipLaunchKernelGGL(order_place, dim3(nblk), dim3(256), 0, s, o);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ compaction
@@ -1304,6 +1474,9 @@ InexactWs inexact_ws_layout(uint64_t nreads, uint32_t nstr, uint32_t zmax, uint6
     w.part = off;      off = al(off + (nblk + 1) * 8);
     w.slots = off;     off = al(off + nrs * kHitSlots * 16);
     w.opool = off;     off = al(off + hit_cap * 16);
+    w.bin = off;       off = al(off + nrs);
+    w.ohist = off;     off = al(off + ((size_t)order_blocks(nrs) + 1) * kOrderBins * 4);
+    w.rec = off;       off = al(off + nrs * 32);
     w.total = off;
     return w;
 }
@@ -1367,6 +1540,7 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     a.offs = c.offs;
     a.z = c.z;
     a.bp = use_d ? (const uint4 *)(ws + W.bp) : nullptr;
+    a.rec = nullptr;
     a.nstr = nstr;
     a.strand0 = (c.flags & FM_FWD) ? 0u : 1u;
     a.total = (uint32_t)(c.nreads * nstr);
@@ -1386,8 +1560,14 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     a.ex_out = (uint2 *)c.ex_out;
     a.ex_nstr = strand_count(c.ex_flags);
     a.ex_strands = c.ex_flags & FM_BOTH;
-    pe->mark(2, s);
     const bool gap = (c.flags & FM_GAPS) != 0;
+    if (use_d && !plain && t.order && !gap) {
+        // claim order for the persistent DFS, from the D records just written
+        e = launch_order(c, W, nstr, a.total, s);
+        if (e != hipSuccess) return e;
+        a.rec = (const uint4 *)(ws + W.rec);
+    }
+    pe->mark(2, s);
     if (plain)
         e = gap ? dfs_plain_launch<kDfsGap>(t, a, s) : dfs_plain_launch<kDfsSub>(t, a, s);
     else if (gap)

@@ -48,7 +48,8 @@ class Info(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("occ_interval", C.c_uint32), ("lanes", C.c_uint32), ("depth", C.c_uint32),
-                ("block", C.c_uint32), ("waves_per_cu", C.c_uint32), ("node_budget", C.c_uint32)]
+                ("block", C.c_uint32), ("waves_per_cu", C.c_uint32), ("node_budget", C.c_uint32),
+                ("order", C.c_uint32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -43,22 +43,18 @@ def test_genome_scale_batches_from_one_graph():
     first = rd.subset(np.arange(BATCH))
     codes, offs, z = fm.reads_to_device(first.codes, first.offs, first.z)
     cap = 16 * BATCH
-    # launch settings tuned on a prefix of the first batch (each candidate is checked
-    # against the plain kernel by the tuner)
-    pre = rd.subset(np.arange(1 << 18))
-    pc, po, pz = fm.reads_to_device(pre.codes, pre.offs, pre.z)
-    pbufs = fm.InexactBuffers(idx, pre.count, int(pre.offs[-1]), flags | fm.FM_PLAIN, ZMAX, 16 * pre.count, "cuda")
+    plain_ex = torch.empty((2 * BATCH, 2), dtype=torch.int32, device="cuda")
+    plain_bufs = fm.InexactBuffers(idx, BATCH, BATCH * LENGTH, flags | fm.FM_PLAIN, ZMAX, cap, "cuda")
+    # launch settings tuned on the first batch (each candidate is checked against the
+    # plain kernel by the tuner)
     t0 = time.time()
-    tin = fm.fm_autotune(idx, fm.FM_OP_INEXACT, pc, po, pz, flags, ZMAX, bufs=pbufs)
-    tdw = fm.fm_autotune(idx, fm.FM_OP_DARRAY, pc, po, pz, flags, ZMAX, bufs=pbufs)
+    tin = fm.fm_autotune(idx, fm.FM_OP_INEXACT, codes, offs, z, flags, ZMAX, bufs=plain_bufs)
+    tdw = fm.fm_autotune(idx, fm.FM_OP_DARRAY, codes, offs, z, flags, ZMAX, bufs=plain_bufs)
     say("tuned in %.1fs: inexact %s, D walk %s" % (time.time() - t0, tin, tdw))
-    del pbufs, pc, po, pz
 
-    ex_out = torch.empty((2 * BATCH, 2), dtype=torch.int32, device="cuda")
+    ex_out = torch.empty_like(plain_ex)
     bufs = fm.InexactBuffers(idx, BATCH, BATCH * LENGTH, flags, ZMAX, cap, "cuda")
     plan = fm.Plan.both(idx, codes, offs, z, fm.FM_BOTH, flags, ZMAX, ex_out, bufs)
-    plain_ex = torch.empty_like(ex_out)
-    plain_bufs = fm.InexactBuffers(idx, BATCH, BATCH * LENGTH, flags | fm.FM_PLAIN, ZMAX, cap, "cuda")
 
     # oracle sample: the first 1,000 reads and 1,000 spread over the whole set
     sample = np.unique(np.concatenate([np.arange(1000), np.linspace(1000, rd.count - 1, 1000).astype(np.int64)]))

@@ -257,6 +257,53 @@ def test_search_both_equals_separate_calls(small, use_d):
     idx.set_tuning(fm.FM_OP_DARRAY, occ_interval=128, lanes=1)
 
 
+def test_claim_order_changes_nothing(small):
+    """The DFS may claim read-strands heaviest first (tuning field `order`, weights from
+    the D records) or in read order: hits, statuses, exact intervals and node counts are
+    the same, with every decided-at-once case in the batch (budgets above zmax, a read
+    over 65535, reads with N, an empty read, root-pruned strands), for substitutions and
+    for the gapped search, one and two strands."""
+    R, x, xr, idx = small
+    rd = synth.simulate_reads(R, 3000, 37, length=(0, 120), sub=(0.0, 0.05), z=(0, 3))
+    long_read = R[2000:2000 + 66_000]
+    codes = np.concatenate([rd.codes, long_read, np.array([4, 0, 4, 1], np.uint8)])
+    offs = np.concatenate([rd.offs, rd.offs[-1] + np.cumsum([long_read.size, 4])]).astype(np.uint64)
+    z = np.concatenate([rd.z, [1, 2]]).astype(np.uint8)
+    nr = offs.size - 1
+    cd, od, zd = fm.reads_to_device(codes, offs, z)
+    want_ex = x.exact(codes, offs, oracle.BOTH, "listing1")
+    for flags in (fm.FM_BOTH | fm.FM_DARRAY, fm.FM_FWD | fm.FM_DARRAY, fm.FM_REVCOMP | fm.FM_DARRAY,
+                  fm.FM_BOTH | fm.FM_DARRAY | fm.FM_GAPS):
+        runs = []
+        for order in (0, 1):
+            idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=64, lanes=1, order=order)
+            try:
+                bufs = fm.fm_search_inexact(idx, cd, od, zd, flags | fm.FM_STATS, 2, 1 << 17)
+                got = fm.hits_to_numpy(bufs, nr)
+                stats = bufs.stats()
+                ex = None
+                if not flags & fm.FM_GAPS and flags & fm.FM_BOTH == fm.FM_BOTH:
+                    ex, b2 = fm.fm_search_both(idx, cd, od, zd, fm.FM_BOTH, flags, 2, 1 << 17)
+                    ex = to_u32(ex)
+                    for u, v in zip(fm.hits_to_numpy(b2, nr), got):
+                        assert np.array_equal(u, v), (flags, order)
+            finally:
+                idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=128, lanes=1, order=1)
+            runs.append((got, stats["occ8"], ex))
+        (g0, n0, e0), (g1, n1, e1) = runs
+        for u, v in zip(g0, g1):
+            assert np.array_equal(u, v), flags
+        assert n0 == n1, flags
+        st = g1[2]
+        assert st[-2] == fm.FM_ERANGE and ((st == fm.FM_EINVAL) == (z > 2)).all()
+        if e1 is not None:
+            assert np.array_equal(e0, want_ex) and np.array_equal(e1, want_ex)
+        plain = fm.hits_to_numpy(fm.fm_search_inexact(idx, cd, od, zd, flags | fm.FM_PLAIN, 2, 1 << 17), nr)
+        for u, v in zip(plain, g1):
+            assert np.array_equal(u, v), flags
+        say(hex(flags), "hits", g1[0].size, "nodes", n1)
+
+
 def test_search_both_where_the_dfs_stops_early(small):
     """fm_search_both takes exact intervals from the DFS. Read-strands whose DFS ends
     before reaching the match-only leaf still get theirs: budgets above zmax (FM_EINVAL),
