@@ -34,8 +34,8 @@ METRIC = "reads/s & Occ8 queries/s, batched vs plain kernel, bit-exact; p99 late
 # were measured with: the key is a hash of the kernel sources, the kernel, its tuning and the workload; any other
 # combination reports traffic as null.
 MEASURED_TRAFFIC = {
-    ("caa6a727b6ab3e46", "dfs_batched<64, 1, 1>", (64, 1, 1, 256, 8, 1), "2^24"): (12_446_497_887, 140_663_416),
-    ("caa6a727b6ab3e46", "dfs_batched<64, 1, 1>", (64, 1, 1, 256, 4, 1), "3.1e9"): (338_162_142_816, 142_273_572),
+    ("d451f468bd8592d4", "dfs_batched<64, 1, 1, false>", (64, 1, 1, 256, 8, 1), "2^24"): (12_446_949_598, 140_787_480),
+    ("d451f468bd8592d4", "dfs_batched<64, 1, 1, true>", (64, 1, 1, 256, 8, 0), "3.1e9"): (341_904_302_848, 371_728_750),
 }
 TRAFFIC_KEY_FIELDS = ("occ_interval", "lanes", "depth", "block", "waves_per_cu", "order")
 KERNEL_SOURCES = ("search.hip", "fm_device.hpp", "fm_internal.hpp")
@@ -48,6 +48,14 @@ def kernel_source_hash() -> str:
         with open(os.path.join(ROOT, "paper_1811_06127_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def dfs_kernel_name(tcfg: dict, zmax: int) -> str:
+    """The compiled DFS of fm_search_both: kind 1 takes the exact intervals from the DFS; the
+    last argument says whether its lanes split trees at the end of the launch (one lane
+    per read-strand and zmax >= 2)."""
+    steal = tcfg["lanes"] == 1 and zmax >= 2
+    return "dfs_batched<%d, %d, 1, %s>" % (tcfg["occ_interval"], tcfg["lanes"], "true" if steal else "false")
 
 
 def log(*a):
@@ -286,7 +294,7 @@ def main():
     achieved = alg[dom] / (phase_ms[dom] / 1e3) / 1e9
     tcfg = tuning[{"d_walk": "d_walk", "dfs": "inexact"}[dom]]["config"]
     # the kernel as compiled: DFS kind 1 takes the exact intervals from the DFS; walk mode 1 is the D walk
-    kname = ("dfs_batched<%d, %d, 1>" % (tcfg["occ_interval"], tcfg["lanes"]) if dom == "dfs" else
+    kname = (dfs_kernel_name(tcfg, ZMAX) if dom == "dfs" else
              "walk_batched<%d, %d, %d, 1>" % (tcfg["occ_interval"], tcfg["lanes"], tcfg["depth"]))
     key = (kernel_source_hash(), kname, tuple(tcfg[f] for f in TRAFFIC_KEY_FIELDS), "2^24")
     traffic = MEASURED_TRAFFIC.get(key)
@@ -451,7 +459,7 @@ def genome_bench(args):
     alg = st["buckets"] * 32 + 2 * B * LEN + 32 * nrs + 16 * int(eager[1][1][-1])
     achieved = alg / (phase["dfs"] / 1e3) / 1e9
     tcfg = tuning["inexact"]
-    key = (kernel_source_hash(), "dfs_batched<%d, %d, 1>" % (tcfg["occ_interval"], tcfg["lanes"]),
+    key = (kernel_source_hash(), dfs_kernel_name(tcfg, Z),
            tuple(tcfg[f] for f in TRAFFIC_KEY_FIELDS), "3.1e9")
     traffic = MEASURED_TRAFFIC.get(key)
     out = {

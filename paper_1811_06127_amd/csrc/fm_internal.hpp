@@ -76,7 +76,8 @@ enum : size_t {
 };
 
 struct InexactWs {       // sub-buffers of the inexact workspace
-    size_t bp, rs_count, rs_status, cursor, rd_status, cnt, offs, part, slots, opool, bin, ohist, rec, total;
+    size_t bp, rs_count, rs_status, rs_nodes, tf_count, tf_status, tf_nodes, cursor, rd_status, cnt, offs, part, slots,
+        opool, bin, ohist, rec, total;
 };
 InexactWs inexact_ws_layout(uint64_t nreads, uint32_t nstr, uint32_t zmax, uint64_t hit_cap);
 

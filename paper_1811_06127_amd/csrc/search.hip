@@ -525,7 +525,11 @@ struct DfsArgs {
     fm_hit *opool;         // hits beyond the slots
     uint64_t ocap;
     unsigned long long *ocount;
-    uint32_t *rs_count, *rs_status;
+    // per read-strand: hits, status and expanded nodes of the lane that took it (its
+    // owner), and the same summed over the subtrees other lanes took from it (see
+    // dfs_steal; zeroed before the launch, nullptr when no launch lane steals)
+    uint32_t *rs_count, *rs_status, *rs_nodes;
+    uint32_t *tf_count, *tf_status, *tf_nodes;
     uint32_t *queue;
     unsigned long long *stat_occ, *stat_bk;
     // exact intervals taken from the DFS (see dfs_emit), or ex_out == nullptr: ex_nstr
@@ -552,6 +556,7 @@ struct Dfs {
     uint32_t sp;                    // frames on the stack
     uint32_t hits, status, nodes;
     bool done;
+    bool thief;                     // searching a subtree taken from another lane's stack
     // hits produced by the last expansion (children of a node with i == 0): bits 0-3 the
     // steps by b, bit 4 (gapped search) the deletion of the last symbol
     uint32_t pend, pk[5], pl[5], pd;
@@ -633,6 +638,7 @@ struct Dfs {
         sp = 0;
         hits = 0;
         nodes = 0;
+        thief = false;
         pd = 0;
         k = 0;
         l = a.lay.n;
@@ -908,7 +914,7 @@ __device__ __forceinline__ void gap_expand(const DfsArgs &a, Dfs &d, const GapLo
 // everything) has as exact interval its hit with no substitution, or none; a root
 // pruned by D (D(m-1) > z >= 0) has none either. A DFS that stops early leaves its
 // interval to exact_rest.
-template <int L, int K>
+template <int L, int K, bool S>
 __device__ void dfs_emit(const DfsArgs &a, Dfs &d, bool active, bool lead)
 {
     constexpr bool XD = K == kDfsSubExact;
@@ -926,7 +932,7 @@ __device__ void dfs_emit(const DfsArgs &a, Dfs &d, bool active, bool lead)
         for (int b = 0; b < NB; ++b) {
             if ((pend >> b) & 1u) {
                 const uint32_t nmm = (d.pd & 0xFFu) + ((b == 4 || (uint32_t)b != wi) ? 1u : 0u);
-                if (h < kHitSlots) {
+                if (h < kHitSlots && !(S && d.thief)) {
                     if (lead)
                         ((uint4 *)a.slots)[(size_t)d.rs * kHitSlots + h] =
                             make_uint4(d.read, d.pk[b], d.pl[b], d.strand | (nmm << 8));
@@ -958,7 +964,7 @@ __device__ void dfs_emit(const DfsArgs &a, Dfs &d, bool active, bool lead)
                 if (pos < a.ocap) {
                     if (lead) ((uint4 *)a.opool)[pos] = make_uint4(d.read, d.pk[b], d.pl[b], d.strand | (nmm << 8));
                 } else {
-                    d.status = FM_EOVERFLOW;
+                    d.status = d.status > FM_EOVERFLOW ? d.status : FM_EOVERFLOW;   // a spent budget wins
                 }
             }
             off += (uint64_t)__popcll(mb[b]);
@@ -968,9 +974,17 @@ __device__ void dfs_emit(const DfsArgs &a, Dfs &d, bool active, bool lead)
         d.hits += (uint32_t)__popc(pend);
         d.pend = 0;
         if (d.done) {
-            if (lead) {
+            if (S && lead && d.thief) {
+                // a stolen subtree adds its part
+                atomicAdd(&a.tf_count[d.rs], d.hits);
+                atomicMax(&a.tf_status[d.rs], d.status);
+                atomicAdd(&a.tf_nodes[d.rs], d.nodes);
+            } else if (lead) {
+                // the owner, whose first kHitSlots hits are in the slots and who followed the
+                // path that matches every symbol (the exact interval)
                 a.rs_count[d.rs] = d.hits;
                 a.rs_status[d.rs] = d.status;
+                if (S) a.rs_nodes[d.rs] = d.nodes;
                 const uint32_t ran_to_end = (1u << FM_OK) | (1u << FM_EOVERFLOW);
                 if (XD && ((a.ex_strands >> d.strand) & 1u) && ((ran_to_end >> d.status) & 1u))
                     a.ex_out[(size_t)d.read * a.ex_nstr + (a.ex_nstr == 2 ? d.strand : 0u)] = make_uint2(d.ek, d.el);
@@ -1008,7 +1022,7 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
                 dfs_expand<I, 1>(a, d, nl, 0, fr, true, n_occ, n_bk);
             }
         }
-        dfs_emit<1, K>(a, d, active, true);
+        dfs_emit<1, K, false>(a, d, active, true);
     }
     wave_add(a.stat_occ, n_occ);
     wave_add(a.stat_bk, n_bk);
@@ -1019,7 +1033,81 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
 // time the older header loads have arrived too; new read-strands begin; hits are stored
 // and finished read-strands retired. K: the kind of search (kDfsSubExact: exact intervals
 // as well, see dfs_emit; kDfsGap: Listing 2 with all its branches).
-template <int I, int L, int K>
+// The tail of a launch: once the work queue is exhausted, lanes fall idle while the
+// last trees are still being searched. An idle lane then takes a pending costly child
+// (a substitution, or in the gapped search also an insertion or the deletion) from the
+// bottom (shallowest, so largest) frame of a busy lane of its wave and searches that
+// subtree of the same read-strand; one transfer per wave and round, and only for children
+// left with a budget of one or more (so z >= 2). Only frames with two or more pending
+// children give one away, so a frame never empties under its owner, and the child that
+// matches is never taken, so the path that matches every symbol (and with it the exact
+// interval) stays with the owner. Hits of a stolen subtree go to the overflow pool; its
+// hit count, status and node count are summed per read-strand apart from the owner's
+// (tf_*), and the compaction adds the two. One lane per read-strand only (frames are
+// per lane).
+template <int K>
+__device__ __forceinline__ void dfs_steal(const DfsArgs &a, Dfs &d, Frame *frames, const Frame *fr)
+{
+    constexpr bool G = K == kDfsGap;
+    const uint32_t lane = __lane_id();
+    const bool busy = d.rs != kEmpty;
+    // this lane's bottom frame: its node's budget and symbol, and the children still to visit
+    const uint4 m = (busy && d.sp >= 1) ? fr->meta : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t pend = G ? (m.w & 0x1FFu) : ((m.x >> 24) & 0xFu);
+    const uint32_t wi = (m.x >> 20) & 0xFu;
+    const uint32_t costly = pend & ~(wi < 4 ? 1u << wi : 0u);
+    // a costly child keeps a budget of at least one (below that its subtree is a single
+    // exact walk, not worth a transfer)
+    const bool deep = ((m.x >> 16) & 0xFu) >= 2;
+    const uint64_t idle = __ballot(!busy);
+    const uint64_t rich = __ballot(busy && d.sp >= 1 && costly != 0 && __popc(pend) >= 2 && deep);
+    if (!idle || !rich) return;
+    const int t = __builtin_ctzll(idle), v = __builtin_ctzll(rich);
+    const uint32_t vmx = __shfl(m.x, v), vmy = __shfl(m.y, v), vmz = __shfl(m.z, v), vpend = __shfl(pend, v);
+    const uint32_t vrs = __shfl(d.rs, v), vread = __shfl(d.read, v);
+    const uint32_t vstrand = __shfl(d.strand, v), vm = __shfl(d.m, v), vz0 = __shfl(d.z0, v);
+    const uint32_t vb0 = __shfl((uint32_t)d.base, v), vb1 = __shfl((uint32_t)(d.base >> 32), v);
+    const uint32_t vp0 = __shfl((uint32_t)d.bp03, v), vp1 = __shfl((uint32_t)(d.bp03 >> 32), v);
+    const uint32_t vbp4 = __shfl(d.bp4, v);
+    if ((int)lane != t) return;
+    Frame *df = frames + (size_t)(threadIdx.x - lane + (uint32_t)v) * a.fcap;
+    const uint32_t vwi = (vmx >> 20) & 0xFu, vzr = (vmx >> 16) & 0xFu;
+    const uint32_t c = (uint32_t)__builtin_ctz(vpend & ~(vwi < 4 ? 1u << vwi : 0u));
+    const uint4 kk = df->k, ll = df->l;
+    const uint32_t left = vpend & ~(1u << c);
+    if constexpr (G) {
+        df->meta.w = left;
+        gap_child(c, vmx & 0xFFFFu, vzr, vwi, vmy, vmz, kk, ll, d.i, d.zr, d.k, d.l);
+    } else {
+        df->meta.x = (vmx & 0x00FFFFFFu) | (left << 24);
+        d.k = sel4(c, kk.x, kk.y, kk.z, kk.w);
+        d.l = sel4(c, ll.x, ll.y, ll.z, ll.w);
+        d.i = vmx & 0xFFFFu;
+        d.zr = vzr - 1u;
+    }
+    d.rs = vrs;
+    d.read = vread;
+    d.strand = vstrand;
+    d.m = vm;
+    d.z0 = vz0;
+    d.base = u64_of(vb0, vb1);
+    d.bp03 = u64_of(vp0, vp1);
+    d.bp4 = vbp4;
+    d.sp = 0;
+    d.hits = 0;
+    d.nodes = 0;
+    d.status = FM_OK;
+    d.done = false;
+    d.thief = true;
+    d.pend = 0;
+    d.pd = 0;
+    d.wtag = ~0ull;
+    d.ek = 1;
+    d.el = 0;
+}
+
+// S: lanes take subtrees from one another at the end of the launch (dfs_steal).
+template <int I, int L, int K, bool S>
 __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
 {
     extern __shared__ Frame lds_frames[];
@@ -1033,6 +1121,9 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
     wq.start(a.queue);
     uint64_t n_occ = 0, n_bk = 0;
     for (;;) {
+        if constexpr (S) {
+            if (wq.exhausted) dfs_steal<K>(a, d, lds_frames, fr);
+        }
         const bool running = d.rs != kEmpty;
         bool fresh = false;
         if (refill_now<L>(lead && !running)) {
@@ -1059,19 +1150,19 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
         // waiting on all memory operations where the registers are next written.
         asm volatile("" ::"v"(d.h0), "v"(d.h1), "v"(d.hz), "v"(d.hrs), "v"(d.hbp.x), "v"(d.hbp.y), "v"(d.hbp.z),
                      "v"(d.hbp.w));
-        dfs_emit<L, K>(a, d, running || fresh, lead);
+        dfs_emit<L, K, S>(a, d, running || fresh, lead);
         if (!__any(d.rs != kEmpty) && wq.exhausted) break;
     }
     wave_add(a.stat_occ, n_occ);
     wave_add(a.stat_bk, n_bk);
 }
 
-template <int I, int L, int K>
+template <int I, int L, int K, bool S>
 static hipError_t dfs_launch_batched(const fm_index *idx, const fm_tuning &t, const DfsArgs &a, hipStream_t s)
 {
     const int block = (int)t.block;
     const size_t lds = (size_t)(block / L) * a.fcap * sizeof(Frame);
-    int per = max_blocks_per_cu((const void *)dfs_batched<I, L, K>, block, lds);
+    int per = max_blocks_per_cu((const void *)dfs_batched<I, L, K, S>, block, lds);
     if (t.waves_per_cu) {
         int want = (int)(t.waves_per_cu * 64 / block);
         if (want >= 1 && want < per) per = want;
@@ -1079,7 +1170,7 @@ static hipError_t dfs_launch_batched(const fm_index *idx, const fm_tuning &t, co
     uint64_t grid = (uint64_t)idx->cu_count * per;
     const uint64_t need = ((uint64_t)a.total * L + block - 1) / block;
     if (need < grid) grid = need ? need : 1;
-    hipLaunchKernelGGL((dfs_batched<I, L, K>), dim3((uint32_t)grid), dim3(block), lds, s, a);
+    hipLaunchKernelGGL((dfs_batched<I, L, K, S>), dim3((uint32_t)grid), dim3(block), lds, s, a);
     return hipGetLastError();
 }
 
@@ -1087,10 +1178,12 @@ template <int I, int K>
 static hipError_t dfs_by_lanes(const fm_index *idx, const fm_tuning &t, const DfsArgs &a, hipStream_t s)
 {
     switch (t.lanes) {
-    case 1: return dfs_launch_batched<I, 1, K>(idx, t, a, s);
-    case 2: return dfs_launch_batched<I, 2, K>(idx, t, a, s);
-    case 4: if constexpr (Geo<I>::USED > 2) return dfs_launch_batched<I, 4, K>(idx, t, a, s); break;
-    case 8: if constexpr (Geo<I>::USED > 4) return dfs_launch_batched<I, 8, K>(idx, t, a, s); break;
+    case 1:
+        return a.tf_count ? dfs_launch_batched<I, 1, K, true>(idx, t, a, s)
+                          : dfs_launch_batched<I, 1, K, false>(idx, t, a, s);
+    case 2: return dfs_launch_batched<I, 2, K, false>(idx, t, a, s);
+    case 4: if constexpr (Geo<I>::USED > 2) return dfs_launch_batched<I, 4, K, false>(idx, t, a, s); break;
+    case 8: if constexpr (Geo<I>::USED > 4) return dfs_launch_batched<I, 8, K, false>(idx, t, a, s); break;
     default: break;
     }
     return hipErrorInvalidValue;
@@ -1257,18 +1350,29 @@ static hipError_t launch_order(const DfsCall &c, const InexactWs &W, uint32_t ns
 // Grid-stride over reads; the required total is summed per block and added with one
 // atomic per block (one per wave contends on the single counter).
 __global__ void __launch_bounds__(256) finalize_reads(uint32_t nreads, uint32_t nstr, const uint32_t *rs_count,
-                                                      const uint32_t *rs_status, uint32_t *rd_status, uint32_t *cnt,
-                                                      uint32_t *cursor, unsigned long long *required)
+                                                      const uint32_t *rs_status, const uint32_t *rs_nodes,
+                                                      const uint32_t *tf_count, const uint32_t *tf_status,
+                                                      const uint32_t *tf_nodes, uint32_t budget, uint32_t *rd_status,
+                                                      uint32_t *cnt, uint32_t *cursor, unsigned long long *required)
 {
     __shared__ uint64_t part[4];
     uint64_t need = 0;
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nreads; r += gridDim.x * blockDim.x) {
         uint32_t st = 0, c = 0;
         for (uint32_t s = 0; s < nstr; ++s) {
-            const uint32_t v = rs_status[r * nstr + s];
+            const uint32_t rs = r * nstr + s;
+            uint32_t v = rs_status[rs];
+            c += rs_count[rs];
+            if (tf_count) {
+                // parts taken by other lanes: their hits and statuses, and the node budget,
+                // which a tree searched in parts can exceed with no part doing so
+                const uint32_t u = tf_status[rs];
+                v = u > v ? u : v;
+                c += tf_count[rs];
+                if ((uint64_t)rs_nodes[rs] + tf_nodes[rs] > budget && v < FM_EBUDGET) v = FM_EBUDGET;
+            }
             st = v > st ? v : st;
-            c += rs_count[r * nstr + s];
-            cursor[r * nstr + s] = 0;
+            cursor[rs] = 0;
         }
         rd_status[r] = st;
         cnt[r] = st == FM_OK ? c : 0u;
@@ -1344,9 +1448,9 @@ __global__ void find_cut(const uint64_t *offs, uint64_t n, uint64_t cap, uint64_
 
 // Final offsets and statuses, and the slot hits of every listed read (strand 0's hits,
 // then strand 1's; within a strand the slot hits precede its overflow-pool hits).
-__global__ void gather_hits(uint32_t nreads, uint32_t nstr, const uint32_t *rs_count, const uint32_t *rd_status,
-                            const uint64_t *offs, const uint64_t *cut, const fm_hit *slots, uint64_t *hit_offs,
-                            uint32_t *status, fm_hit *hits)
+__global__ void gather_hits(uint32_t nreads, uint32_t nstr, const uint32_t *rs_count, const uint32_t *tf_count,
+                            const uint32_t *rd_status, const uint64_t *offs, const uint64_t *cut, const fm_hit *slots,
+                            uint64_t *hit_offs, uint32_t *status, fm_hit *hits)
 {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nreads) return;
@@ -1361,8 +1465,8 @@ __global__ void gather_hits(uint32_t nreads, uint32_t nstr, const uint32_t *rs_c
     uint64_t dst = o0;
     for (uint32_t s = 0; s < nstr; ++s) {
         const uint32_t rs = r * nstr + s;
-        const uint32_t n = rs_count[rs];
-        const uint32_t ns = n < kHitSlots ? n : kHitSlots;
+        const uint32_t own = rs_count[rs], ns = own < kHitSlots ? own : kHitSlots;
+        const uint32_t n = own + (tf_count ? tf_count[rs] : 0u);
         for (uint32_t h = 0; h < ns; ++h) ((uint4 *)hits)[dst + h] = ((const uint4 *)slots)[(size_t)rs * kHitSlots + h];
         dst += n;
     }
@@ -1370,15 +1474,19 @@ __global__ void gather_hits(uint32_t nreads, uint32_t nstr, const uint32_t *rs_c
 
 // Overflow-pool hits of listed reads, after their read-strand's slot hits.
 __global__ void scatter_overflow(const fm_hit *opool, const unsigned long long *ocount, uint64_t ocap, uint32_t nstr,
-                                 const uint32_t *rs_count, const uint32_t *status, const uint64_t *hit_offs,
-                                 uint32_t *cursor, fm_hit *hits)
+                                 const uint32_t *rs_count, const uint32_t *tf_count, const uint32_t *status,
+                                 const uint64_t *hit_offs, uint32_t *cursor, fm_hit *hits)
 {
     const uint64_t total = *ocount < ocap ? *ocount : ocap;
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total; e += (uint64_t)gridDim.x * blockDim.x) {
         const uint4 h = ((const uint4 *)opool)[e];
         const uint32_t r = h.x, s = nstr == 2 ? (h.w & 0xFFu) : 0u;
         if (status[r] != FM_OK) continue;
-        const uint64_t start = hit_offs[r] + (s ? rs_count[r * nstr] : 0u) + kHitSlots;
+        // after the strand's slot hits (the first kHitSlots of its owner), and after all
+        // hits of strand 0
+        const uint32_t own = rs_count[r * nstr + s];
+        const uint64_t before = s ? (uint64_t)rs_count[r * nstr] + (tf_count ? tf_count[r * nstr] : 0u) : 0u;
+        const uint64_t start = hit_offs[r] + before + (own < kHitSlots ? own : kHitSlots);
         ((uint4 *)hits)[start + atomicAdd(&cursor[r * nstr + s], 1u)] = h;
     }
 }
@@ -1466,6 +1574,10 @@ InexactWs inexact_ws_layout(uint64_t nreads, uint32_t nstr, uint32_t zmax, uint6
     w.bp = off;        off = al(off + nrs * 16);
     w.rs_count = off;  off = al(off + nrs * 4);
     w.rs_status = off; off = al(off + nrs * 4);
+    w.rs_nodes = off;  off = al(off + nrs * 4);
+    w.tf_count = off;  off = al(off + nrs * 4);
+    w.tf_status = off; off = al(off + nrs * 4);
+    w.tf_nodes = off;  off = al(off + nrs * 4);
     w.cursor = off;    off = al(off + nrs * 4);
     w.rd_status = off; off = al(off + nreads * 4);
     w.cnt = off;       off = al(off + nreads * 4);
@@ -1553,6 +1665,8 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     a.ocount = (unsigned long long *)(ws + kWsPool);
     a.rs_count = (uint32_t *)(ws + W.rs_count);
     a.rs_status = (uint32_t *)(ws + W.rs_status);
+    a.rs_nodes = (uint32_t *)(ws + W.rs_nodes);
+    a.tf_count = a.tf_status = a.tf_nodes = nullptr;
     a.queue = (uint32_t *)(ws + kWsQueue2);
     a.stat_occ = (c.flags & FM_STATS) ? (unsigned long long *)(ws + kWsStatOcc) : nullptr;
     a.stat_bk = (c.flags & FM_STATS) ? (unsigned long long *)(ws + kWsStatBuckets) : nullptr;
@@ -1566,6 +1680,14 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
         e = launch_order(c, W, nstr, a.total, s);
         if (e != hipSuccess) return e;
         a.rec = (const uint4 *)(ws + W.rec);
+    }
+    if (!plain && t.lanes == 1 && c.zmax >= 2) {
+        // lanes of the batched DFS take subtrees from one another at the end of the launch
+        a.tf_count = (uint32_t *)(ws + W.tf_count);
+        a.tf_status = (uint32_t *)(ws + W.tf_status);
+        a.tf_nodes = (uint32_t *)(ws + W.tf_nodes);
+        e = launch_fill(a.tf_count, 0, (W.tf_nodes + (size_t)a.total * 4 - W.tf_count) / 4, s);
+        if (e != hipSuccess) return e;
     }
     pe->mark(2, s);
     if (plain)
@@ -1616,20 +1738,21 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     uint32_t fgrid = (nr + 255) / 256;
     if (fgrid > (uint32_t)idx->cu_count * 4) fgrid = (uint32_t)idx->cu_count * 4;
     hipLaunchKernelGGL(finalize_reads, dim3(fgrid ? fgrid : 1), dim3(256), 0, s, nr, nstr, a.rs_count, a.rs_status,
-                       rd_status, cnt, cursor, (unsigned long long *)(ws + kWsRequired));
+                       a.rs_nodes, a.tf_count, a.tf_status, a.tf_nodes, a.budget, rd_status, cnt, cursor,
+                       (unsigned long long *)(ws + kWsRequired));
     const uint64_t nblk = (c.nreads + kScanBlock * kTile - 1) / (kScanBlock * kTile);
     uint64_t *part = (uint64_t *)(ws + W.part);
     hipLaunchKernelGGL(scan_reduce_u64, dim3((uint32_t)nblk), dim3(kScanBlock), 0, s, cnt, c.nreads, part);
     hipLaunchKernelGGL(scan_partials_u64, dim3(1), dim3(1024), 0, s, part, nblk);
     hipLaunchKernelGGL(scan_write_u64, dim3((uint32_t)nblk), dim3(kScanBlock), 0, s, cnt, c.nreads, part, offs_tmp);
     hipLaunchKernelGGL(find_cut, dim3((nr + 1 + 255) / 256), dim3(256), 0, s, offs_tmp, c.nreads, c.hit_cap, cut);
-    hipLaunchKernelGGL(gather_hits, dim3((nr + 255) / 256), dim3(256), 0, s, nr, nstr, a.rs_count, rd_status, offs_tmp,
-                       cut, a.slots, c.hit_offs, c.status, c.hits);
+    hipLaunchKernelGGL(gather_hits, dim3((nr + 255) / 256), dim3(256), 0, s, nr, nstr, a.rs_count, a.tf_count, rd_status,
+                       offs_tmp, cut, a.slots, c.hit_offs, c.status, c.hits);
     uint64_t sgrid = (c.hit_cap + 255) / 256;
     if (sgrid > (uint64_t)idx->cu_count * 4) sgrid = (uint64_t)idx->cu_count * 4;
     if (sgrid == 0) sgrid = 1;
     hipLaunchKernelGGL(scatter_overflow, dim3((uint32_t)sgrid), dim3(256), 0, s, a.opool, a.ocount, a.ocap, nstr,
-                       a.rs_count, c.status, c.hit_offs, cursor, c.hits);
+                       a.rs_count, a.tf_count, c.status, c.hit_offs, cursor, c.hits);
     hipLaunchKernelGGL(sort_read_hits, dim3((nr + 255) / 256), dim3(256), 0, s, c.nreads, c.hit_offs, c.hits);
     if (gap) {
         // one hit per interval: dedupe in place, then re-pack through the (spent) overflow pool

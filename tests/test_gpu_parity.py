@@ -403,17 +403,23 @@ def test_inexact_overflow_and_retry(small):
 
 
 def test_inexact_node_budget(small):
+    """A read-strand whose tree needs more nodes than the budget ends FM_EBUDGET. The
+    batched DFS (whose lanes split trees between them at the end of a launch, z >= 2)
+    agrees with the plain kernel at budgets around the trees' sizes."""
     R, x, xr, idx = small
     codes, offs, z = inexact_inputs(R, count=200, seed=6)
-    idx.set_tuning(fm.FM_OP_INEXACT, node_budget=30)
-    try:
-        a = run_inexact(idx, codes, offs, z, fm.FM_BOTH | fm.FM_PLAIN, 2)[0]
-        b = run_inexact(idx, codes, offs, z, fm.FM_BOTH, 2)[0]
-    finally:
-        idx.set_tuning(fm.FM_OP_INEXACT, node_budget=1 << 22)
-    assert (a[2] == fm.FM_EBUDGET).any()
-    assert np.array_equal(a[2], b[2]) and np.array_equal(a[1], b[1])
-    assert np.array_equal(a[0], b[0])
+    for flags in (fm.FM_BOTH, fm.FM_BOTH | fm.FM_DARRAY):
+        for budget in (30, 90, 250):
+            idx.set_tuning(fm.FM_OP_INEXACT, node_budget=budget)
+            try:
+                a = run_inexact(idx, codes, offs, z, flags | fm.FM_PLAIN, 2)[0]
+                b = run_inexact(idx, codes, offs, z, flags, 2)[0]
+            finally:
+                idx.set_tuning(fm.FM_OP_INEXACT, node_budget=1 << 22)
+            if budget == 30:
+                assert (a[2] == fm.FM_EBUDGET).any()
+            assert np.array_equal(a[2], b[2]) and np.array_equal(a[1], b[1]), (flags, budget)
+            assert np.array_equal(a[0], b[0]), (flags, budget)
 
 
 def test_determinism_and_batch_independence(small):
