@@ -198,7 +198,9 @@ int fm_set_tuning(fm_index *idx, int op, const fm_tuning *t);
 /* Times every compiled launch configuration of op on a sample batch (same arguments
  * as the corresponding search, device buffers owned by the caller, ws sized with
  * the op's workspace call for the sample and hit_cap) and keeps the fastest that
- * reproduces the plain kernel's output bit for bit. Synchronises `stream`. If
+ * reproduces the plain kernel's output bit for bit (a candidate replaces the current
+ * choice only when it is at least 1% faster, so settings within timing noise of each
+ * other resolve to the one tried first). Synchronises `stream`. If
  * cache_path is non-NULL the choice is looked up there first (key: device
  * architecture, n, read count, total length, zmax, flags) and stored after tuning.
  * best (nullable) receives the choice; ms (nullable) its time per call. */
@@ -280,7 +282,8 @@ int fm_search_inexact_workspace(const fm_index *idx, uint64_t nreads, uint64_t t
  *      offsets 64 (expanded DFS nodes, each one Occ8 step), 72 (buckets fetched by
  *      them; a node whose interval is still (0, n) takes its children from C and
  *      fetches none), 80 (D-walk steps that fetched) and 88 (buckets they fetched)
- *      count the work done.
+ *      count the work done, and 96 the subtrees that idle lanes of the batched DFS took
+ *      over from busy ones at the end of the launch (one lane per read-strand, zmax >= 2).
  * Output is deterministic (independent of scheduling, batch order and launch tuning)
  * whenever hit_cap suffices. When it does not, hits beyond the per-read-strand slots
  * compete for hit_cap places in arrival order, so which reads end FM_EOVERFLOW can vary

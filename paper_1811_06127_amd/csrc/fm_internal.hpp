@@ -72,6 +72,7 @@ enum : size_t {
     kWsStatBuckets = 72, // uint64 distinct buckets fetched
     kWsStatWalk = 80,    // uint64 walk steps that fetched
     kWsStatWalkBk = 88,  // uint64 buckets those steps fetched
+    kWsStatSteal = 96,   // uint64 subtrees idle DFS lanes took over (dfs_steal)
     kWsHeader = 256
 };
 

@@ -531,7 +531,7 @@ struct DfsArgs {
     uint32_t *rs_count, *rs_status, *rs_nodes;
     uint32_t *tf_count, *tf_status, *tf_nodes;
     uint32_t *queue;
-    unsigned long long *stat_occ, *stat_bk;
+    unsigned long long *stat_occ, *stat_bk, *stat_steal;
     // exact intervals taken from the DFS (see dfs_emit), or ex_out == nullptr: ex_nstr
     // slots per read, for the strands in ex_strands (bit s: strand s)
     uint2 *ex_out;
@@ -1070,6 +1070,7 @@ __device__ __forceinline__ void dfs_steal(const DfsArgs &a, Dfs &d, Frame *frame
     const uint32_t vp0 = __shfl((uint32_t)d.bp03, v), vp1 = __shfl((uint32_t)(d.bp03 >> 32), v);
     const uint32_t vbp4 = __shfl(d.bp4, v);
     if ((int)lane != t) return;
+    if (a.stat_steal) atomicAdd(a.stat_steal, 1ull);
     Frame *df = frames + (size_t)(threadIdx.x - lane + (uint32_t)v) * a.fcap;
     const uint32_t vwi = (vmx >> 20) & 0xFu, vzr = (vmx >> 16) & 0xFu;
     const uint32_t c = (uint32_t)__builtin_ctz(vpend & ~(vwi < 4 ? 1u << vwi : 0u));
@@ -1670,6 +1671,7 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     a.queue = (uint32_t *)(ws + kWsQueue2);
     a.stat_occ = (c.flags & FM_STATS) ? (unsigned long long *)(ws + kWsStatOcc) : nullptr;
     a.stat_bk = (c.flags & FM_STATS) ? (unsigned long long *)(ws + kWsStatBuckets) : nullptr;
+    a.stat_steal = (c.flags & FM_STATS) ? (unsigned long long *)(ws + kWsStatSteal) : nullptr;
     const bool ex = c.ex_out != nullptr;
     a.ex_out = (uint2 *)c.ex_out;
     a.ex_nstr = strand_count(c.ex_flags);

@@ -22,7 +22,7 @@ FM_OP_EXACT, FM_OP_DARRAY, FM_OP_INEXACT = 0, 1, 2
 FM_ZMAX = 4
 
 # byte offsets inside the inexact workspace (see fm_search_inexact in fm.h)
-WS_REQUIRED, WS_STAT_OCC, WS_STAT_BUCKETS, WS_STAT_WALK, WS_STAT_WALK_BK = 8, 64, 72, 80, 88
+WS_REQUIRED, WS_STAT_OCC, WS_STAT_BUCKETS, WS_STAT_WALK, WS_STAT_WALK_BK, WS_STAT_STEAL = 8, 64, 72, 80, 88, 96
 
 
 class FmError(RuntimeError):
@@ -364,8 +364,9 @@ class InexactBuffers:
         return int(self.ws[WS_REQUIRED:WS_REQUIRED + 8].cpu().numpy().view(np.uint64)[0])
 
     def stats(self) -> dict:
-        v = self.ws[WS_STAT_OCC:WS_STAT_OCC + 32].cpu().numpy().view(np.uint64)
-        return {"occ8": int(v[0]), "buckets": int(v[1]), "walk_steps": int(v[2]), "walk_buckets": int(v[3])}
+        v = self.ws[WS_STAT_OCC:WS_STAT_OCC + 40].cpu().numpy().view(np.uint64)
+        return {"occ8": int(v[0]), "buckets": int(v[1]), "walk_steps": int(v[2]), "walk_buckets": int(v[3]),
+                "subtrees": int(v[4])}
 
 
 def fm_search_inexact(idx: Index, codes: torch.Tensor, offs: torch.Tensor, z: torch.Tensor, flags: int,

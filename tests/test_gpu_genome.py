@@ -45,12 +45,10 @@ def test_genome_scale_batches_from_one_graph():
     cap = 16 * BATCH
     plain_ex = torch.empty((2 * BATCH, 2), dtype=torch.int32, device="cuda")
     plain_bufs = fm.InexactBuffers(idx, BATCH, BATCH * LENGTH, flags | fm.FM_PLAIN, ZMAX, cap, "cuda")
-    # launch settings tuned on the first batch (each candidate is checked against the
-    # plain kernel by the tuner)
-    t0 = time.time()
-    tin = fm.fm_autotune(idx, fm.FM_OP_INEXACT, codes, offs, z, flags, ZMAX, bufs=plain_bufs)
-    tdw = fm.fm_autotune(idx, fm.FM_OP_DARRAY, codes, offs, z, flags, ZMAX, bufs=plain_bufs)
-    say("tuned in %.1fs: inexact %s, D walk %s" % (time.time() - t0, tin, tdw))
+    # the index's default launch settings (I=64, one lane per read-strand, 8 waves per CU,
+    # heaviest-first claims); at this scale the tuner's choice varies between runs within
+    # timing noise, and fixed settings keep runs and their profiles comparable
+    say("launch settings: inexact %s, D walk %s" % (idx.get_tuning(fm.FM_OP_INEXACT), idx.get_tuning(fm.FM_OP_DARRAY)))
 
     ex_out = torch.empty_like(plain_ex)
     bufs = fm.InexactBuffers(idx, BATCH, BATCH * LENGTH, flags, ZMAX, cap, "cuda")

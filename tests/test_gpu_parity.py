@@ -304,6 +304,38 @@ def test_claim_order_changes_nothing(small):
         say(hex(flags), "hits", g1[0].size, "nodes", n1)
 
 
+def test_subtree_transfers(small):
+    """With one lane per read-strand and zmax >= 2, idle lanes of the batched DFS take
+    subtrees over from busy lanes at the end of the launch (FM_STATS counts them). Hits,
+    statuses and node counts equal the oracle's and the plain kernel's, for substitutions
+    with and without the D bound and for the gapped search; two lanes per read-strand and
+    z = 1 launches take none."""
+    R, x, xr, idx = small
+    rd = synth.simulate_reads(R, 1500, 41, length=(60, 120), sub=(0.0, 0.03), z=(2, 2))
+    r1 = synth.simulate_reads(R, 1500, 42, length=(60, 120), sub=(0.0, 0.03), z=(1, 1))
+    cases = ((fm.FM_BOTH | fm.FM_DARRAY, "listing2_darray"), (fm.FM_BOTH, "listing2"),
+             (fm.FM_BOTH | fm.FM_DARRAY | fm.FM_GAPS, "listing2_gaps_darray"))
+    for flags, method in cases:
+        for reads, zmax in ((rd, 2), (r1, 1)):
+            cd, od, zd = fm.reads_to_device(reads.codes, reads.offs, reads.z)
+            wh, wo, wn = x.inexact(reads.codes, reads.offs, reads.z, oracle.BOTH, method, rev=xr, return_nodes=True)
+            for lanes in (1, 2):
+                idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=64, lanes=lanes)
+                try:
+                    bufs = fm.fm_search_inexact(idx, cd, od, zd, flags | fm.FM_STATS, zmax, 1 << 22)
+                    got = fm.hits_to_numpy(bufs, reads.count)
+                    st = bufs.stats()
+                finally:
+                    idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=128, lanes=1)
+                assert_same_hits(got, wh, wo, (flags, zmax, lanes))
+                assert st["occ8"] == int(wn.sum()), (flags, zmax, lanes)
+                if lanes == 1 and zmax == 2:
+                    assert st["subtrees"] > 0, flags
+                else:
+                    assert st["subtrees"] == 0, (flags, zmax, lanes)
+                say(hex(flags), "zmax", zmax, "lanes", lanes, "nodes", st["occ8"], "subtrees", st["subtrees"])
+
+
 def test_search_both_where_the_dfs_stops_early(small):
     """fm_search_both takes exact intervals from the DFS. Read-strands whose DFS ends
     before reaching the match-only leaf still get theirs: budgets above zmax (FM_EINVAL),
