@@ -50,6 +50,48 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def search_trace(fm, torch, idx, rd, count: int, dev):
+    """(k, l) of every node that Listing 2's substitution search (both strands, D bound)
+    expands for the first `count` reads of the step, level by level: the queries of the
+    search, to be replayed as independent Occ8 queries. Each level's children come from
+    fm_occ8 (k_b = C[b] + Occ(b, k-1) + 1, l_b = C[b] + Occ(b, l), kept when non-empty and
+    within the budget and the D bound from fm_darray), so the trace holds the queries as the
+    kernels issue them (at k = 0 the k-1 side reads row 0). Returns the (n, 2) uint32
+    queries and the same reads on the device, for checking the count against the DFS's."""
+    sub = rd.subset(np.arange(count))
+    m = int(sub.offs[1] - sub.offs[0])
+    assert (np.diff(sub.offs.astype(np.int64)) == m).all()
+    codes, offs, z = fm.reads_to_device(sub.codes, sub.offs, sub.z, dev)
+    D = fm.fm_darray(idx, codes, offs, m * count, fm.FM_BOTH).cpu().numpy()
+    W = sub.codes.reshape(count, m)
+    comp = np.where(W < 4, 3 - W, W)[:, ::-1]             # the strand-1 pattern
+    P = np.stack([W, comp], 1).reshape(2 * count, m)       # read-strand 2r + s
+    DD = np.stack([D[0].reshape(count, m), D[1].reshape(count, m)], 1).reshape(2 * count, m).astype(np.int16)
+    info = idx.info()
+    C = np.array(info["C"][:4], np.int64)
+    zz = np.repeat(sub.z.astype(np.int16), 2)
+    rs = np.nonzero(zz >= DD[:, m - 1])[0]                 # the root is pruned when z < D(m-1)
+    zr, k, l = zz[rs], np.zeros(rs.size, np.int64), np.full(rs.size, info["n"], np.int64)
+    out = []
+    for i in range(m - 1, -1, -1):
+        if rs.size == 0:
+            break
+        q = np.stack([np.maximum(k, 1), l], 1).astype(np.uint32)
+        out.append(q)
+        if i == 0:
+            break
+        o = fm.fm_occ8(idx, torch.from_numpy(q.view(np.int32)).to(dev)).cpu().numpy().view(np.uint32).astype(np.int64)
+        nxt = []
+        for b in range(4):
+            kb = C[b] + np.where(k == 0, 0, o[:, b]) + 1
+            lb = C[b] + o[:, 4 + b]
+            z2 = zr - (P[rs, i] != b)
+            ok = (kb <= lb) & (z2 >= 0) & (z2 >= DD[rs, i - 1])
+            nxt.append((kb[ok], lb[ok], rs[ok], z2[ok]))
+        k, l, rs, zr = (np.concatenate([x[j] for x in nxt]) for j in range(4))
+    return np.concatenate(out), (codes, offs, z, int(sub.offs[-1]))
+
+
 def dfs_kernel_name(tcfg: dict, zmax: int) -> str:
     """The compiled DFS of fm_search_both: kind 1 takes the exact intervals from the DFS; the
     last argument says whether its lanes split trees at the end of the launch (one lane
@@ -260,13 +302,31 @@ def main():
             np.array_equal(a, b) for a, b in zip(in_plain, in_batched))
         log("plain: %.3f ms/step, identical to batched: %s" % (plain_ms, plain_equal))
 
-    # Occ8 micro-benchmark: independent uniform (k, l) pairs (two buckets each) and narrow
-    # ones, l uniform and k = l + 1 - w with w in [0, 8] (mostly one bucket)
+    # Occ8 micro-benchmark: independent uniform (k, l) pairs (two buckets each), narrow ones,
+    # l uniform and k = l + 1 - w with w in [0, 8] (mostly one bucket), and the queries the
+    # inexact search itself makes (its trace on the step's first reads, replayed independently)
     occ8_rate = {}
+    trace_info = None
     if args.occ8_queries:
-        for kind in ("uniform", "narrow"):
-            q = torch.from_numpy(synth.occ8_queries(R.size, args.occ8_queries, 4242, kind).view(np.int32)).to(dev)
-            qo = torch.empty((args.occ8_queries, 8), dtype=torch.int32, device=dev)
+        t0 = time.time()
+        count = min(nreads, max(1000, args.occ8_queries // 160))
+        trace, (tc, to, tz, tlen) = search_trace(fm, torch, idx, rd, count, dev)
+        tb = fm.InexactBuffers(idx, count, tlen, INEXACT, ZMAX, 4 * count, dev)
+        fm.fm_search_inexact(idx, tc, to, tz, INEXACT | fm.FM_STATS, ZMAX, 4 * count, bufs=tb)
+        torch.cuda.synchronize()
+        trace_info = {"reads": count, "queries": int(trace.shape[0]),
+                      "equals_dfs_node_count": int(trace.shape[0]) == tb.stats()["occ8"]}
+        log("search trace of %d reads: %d queries in %.1fs, DFS node count equal: %s" % (
+            count, trace.shape[0], time.time() - t0, trace_info["equals_dfs_node_count"]))
+        del tb, tc, to, tz
+        for kind in ("uniform", "narrow", "search_trace"):
+            if kind == "search_trace":
+                qh = trace
+            else:
+                qh = synth.occ8_queries(R.size, args.occ8_queries, 4242, kind)
+            q = torch.from_numpy(qh.view(np.int32)).to(dev)
+            nq = qh.shape[0]
+            qo = torch.empty((nq, 8), dtype=torch.int32, device=dev)
             fm.fm_occ8(idx, q, out=qo)
             torch.cuda.synchronize()
             q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -275,7 +335,7 @@ def main():
                 fm.fm_occ8(idx, q, out=qo)
             q1.record()
             torch.cuda.synchronize()
-            occ8_rate[kind] = args.occ8_queries / (q0.elapsed_time(q1) / 3 / 1e3)
+            occ8_rate[kind] = nq / (q0.elapsed_time(q1) / 3 / 1e3)
             del q, qo
 
     # roofline of the dominant kernel: algorithmic bytes per launch / its event-timed duration
@@ -348,6 +408,7 @@ def main():
         "graph_equals_eager": graph_equal,
         "occ8_queries_per_s": {**{"fm_occ8_" + k: round(v, 1) for k, v in occ8_rate.items()},
                                "dfs_in_separate_call": round(in_stats["occ8"] / (sep_phase["dfs"] / 1e3), 1)},
+        "occ8_search_trace": trace_info,
         "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
         "separate_calls": {"ms_per_step": round(sep_ms, 4), "phase_ms": {k: round(v, 4) for k, v in sep_phase.items()},
                            "equal_to_one_pass": fused_equal},
