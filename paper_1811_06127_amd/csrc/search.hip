@@ -1201,8 +1201,8 @@ static hipError_t dfs_by_lanes(const fm_index *idx, const fm_tuning &t, const Df
 // only decides which lane searches which read-strand and when: results are unchanged.
 // Weights are bucketed into kOrderBins classes (exact below 64, then 16 per octave);
 // read-strands of one class are claimed in no particular order. The gapped search keeps
-// read order: there the heaviest class (patterns that occur, D zero throughout) spans
-// ten-fold node counts, so the weight cannot rank the trees that decide the tail.
+// read order: there the heaviest class (patterns that occur, D zero throughout) holds
+// most of the work in trees of 2.5-fold different sizes, which the weight cannot rank.
 
 struct OrderArgs {
     const uint64_t *offs;
