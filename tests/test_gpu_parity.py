@@ -302,6 +302,25 @@ def test_claim_order_changes_nothing(small):
         for u, v in zip(plain, g1):
             assert np.array_equal(u, v), flags
         say(hex(flags), "hits", g1[0].size, "nodes", n1)
+    # batches of one and three reads: one counting workgroup, mostly idle lanes
+    for count in (1, 3):
+        sub = rd.subset(np.arange(count))
+        cd, od, zd = fm.reads_to_device(sub.codes, sub.offs, sub.z)
+        flags = fm.FM_BOTH | fm.FM_DARRAY
+        want = x.inexact(sub.codes, sub.offs, sub.z, oracle.BOTH, "listing2_darray", rev=xr)
+        idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=64, lanes=1, order=1)
+        try:
+            got = fm.hits_to_numpy(fm.fm_search_inexact(idx, cd, od, zd, flags, 2, 1 << 12), count)
+        finally:
+            idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=128, lanes=1, order=1)
+        ok = got[2] == fm.FM_OK
+        assert ((got[2] == fm.FM_EINVAL) == (sub.z > 2)).all() and ok.any() == (sub.z <= 2).any()
+        for r in np.nonzero(ok)[0]:
+            a = got[0][int(got[1][r]):int(got[1][r + 1])]
+            w = want[0][int(want[1][r]):int(want[1][r + 1])]
+            for f in ("k", "l", "strand"):
+                assert np.array_equal(a[f], w[f]), (count, r, f)
+            assert np.array_equal(a["nmm"], w["d"]), (count, r)
 
 
 def test_subtree_transfers(small):
