@@ -634,7 +634,7 @@ def serve_bench(args):
     log("serving requests drawn in %.1fs: %d requests, %d reads" % (time.time() - t0, nreq, int(sizes.sum())))
     mixed = mixed_batch(idx, pool)
     opts = dict(lanes=args.serve_lanes, flags=fm.FM_BOTH | fm.FM_DARRAY, zmax=2, hit_reserve=4,
-                arena_bytes=2 << 30, ring_bytes=1 << 30)
+                arena_bytes=4 << 30, ring_bytes=1 << 30)
     mean_size = float(sizes.mean())
 
     srv = fm.Server(idx, **opts)
@@ -651,30 +651,48 @@ def serve_bench(args):
         last = max(last, srv.wait(t).t_done)
         srv.release(t)
     capacity = float(sizes[:m].sum()) / (last - c0)
-    rate = args.serve_load * capacity / mean_size            # requests per second
-    log("serving capacity %.3g reads/s; arrival rate %.1f requests/s" % (capacity, rate))
+    log("serving capacity %.3g reads/s; arrival rate %.1f requests/s" % (
+        capacity, args.serve_load * capacity / mean_size))
 
-    arrivals = np.cumsum(gaps / rate)
-    results = [None] * nreq
-    tickets = [None] * nreq
-    ready = threading.Semaphore(0)
+    def run_load(load):
+        """Every request once, Poisson arrivals at `load` times the capacity; returns the
+        results in submission order."""
+        arrivals = np.cumsum(gaps / (load * capacity / mean_size))
+        results = [None] * nreq
+        tickets = [None] * nreq
+        ready = threading.Semaphore(0)
 
-    def producer():
-        base = time.perf_counter()
-        for i, r in enumerate(reqs):
-            d = base + arrivals[i] - time.perf_counter()
-            if d > 0:
-                time.sleep(d)
-            tickets[i] = srv.submit(*r)
-            ready.release()
+        def producer():
+            base = time.perf_counter()
+            for i, r in enumerate(reqs):
+                d = base + arrivals[i] - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(*r)
+                ready.release()
 
-    th = threading.Thread(target=producer)
-    th.start()
-    for i in range(nreq):
-        ready.acquire()
-        results[i] = srv.wait(tickets[i])
-        srv.release(tickets[i])
-    th.join()
+        th = threading.Thread(target=producer)
+        th.start()
+        for i in range(nreq):
+            ready.acquire()
+            results[i] = srv.wait(tickets[i])
+            srv.release(tickets[i])
+        th.join()
+        return results
+
+    def summary(results):
+        lat = np.array([r.latency for r in results]) * 1e3
+        span = max(r.t_done for r in results) - min(r.t_submit for r in results)
+        return {"reads_per_s": round(int(sizes.sum()) / span, 1), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3),
+                "requests_per_batch": round(nreq / max(1, len({r.batch for r in results})), 2),
+                "all_ok": all(r.error == fm.FM_OK for r in results)}
+
+    other = {}
+    for load in (0.5, 0.95):
+        if abs(load - args.serve_load) > 1e-9:
+            other["%.2f" % load] = summary(run_load(load))
+    results = run_load(args.serve_load)
     st = srv.stats()
     # a few requests again, alone: their results must not depend on the batch
     same = True
@@ -687,20 +705,12 @@ def serve_bench(args):
                      and a.hits.tobytes() == b.hits.tobytes())
     srv.close()
     idx.free()
-    lat = np.array([r.latency for r in results]) * 1e3
-    t_first = min(r.t_submit for r in results)
-    t_last = max(r.t_done for r in results)
-    reads = int(sizes.sum())
-    ok = all(r.error == fm.FM_OK for r in results)
-    per_batch = nreq / max(1, len({r.batch for r in results}))
     out = {"workload": "2^28-base reference (5%% copies, 1%% tandem repeats); Poisson arrivals at %.2f of "
                        "capacity; requests of U{1..20000} reads, length U[50,250], 0.5-3%% substitutions, z in "
                        "{0,1,2}; both strands, D bound" % args.serve_load,
-           "requests": nreq, "reads": reads, "lanes": args.serve_lanes,
-           "capacity_reads_per_s": round(capacity, 1), "reads_per_s": round(reads / (t_last - t_first), 1),
-           "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-           "mean_ms": round(float(lat.mean()), 3), "requests_per_batch": round(per_batch, 2),
-           "retries": st["retries"], "all_ok": ok, "alone_equals_mixed": same, "mixed_batch": mixed}
+           "requests": nreq, "reads": int(sizes.sum()), "lanes": args.serve_lanes,
+           "capacity_reads_per_s": round(capacity, 1), **summary(results),
+           "retries": st["retries"], "alone_equals_mixed": same, "other_loads": other, "mixed_batch": mixed}
     log("serving:", out)
     return out
 
