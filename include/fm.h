@@ -132,7 +132,9 @@ typedef struct {
                                        FM_GAPS). Results are the same either way. */
 } fm_tuning;
 
-enum { FM_OP_EXACT = 0, FM_OP_DARRAY = 1, FM_OP_INEXACT = 2 };
+/* Operations with launch settings of their own. FM_OP_LOCATE (fm_locate: layout and
+ * waves_per_cu; lanes and depth are unused) is set by hand, not by fm_autotune. */
+enum { FM_OP_EXACT = 0, FM_OP_DARRAY = 1, FM_OP_INEXACT = 2, FM_OP_LOCATE = 3 };
 
 /* ----------------------------------------------------------------- general */
 
@@ -331,7 +333,7 @@ int fm_locate_workspace(const fm_index *idx, uint64_t niv, size_t *bytes);
  *      rows are located; call with pos_cap = 0 to size pos from offs[niv] first.
  *   flags: FM_STATS counts the Psi^-1 steps into the uint64 at byte offset 80 of ws.
  *   ws: device workspace of fm_locate_workspace bytes.
- * Uses the forward layout and launch settings of FM_OP_EXACT. Asynchronous on stream. */
+ * Uses the forward layout and launch settings of FM_OP_LOCATE. Asynchronous on stream. */
 int fm_locate(const fm_index *idx, const uint32_t *kl, uint64_t niv, uint32_t stride, uint64_t *offs,
               uint32_t *pos, uint64_t pos_cap, uint32_t flags, void *ws, size_t ws_bytes, void *stream);
 

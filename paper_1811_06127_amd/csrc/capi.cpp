@@ -83,14 +83,19 @@ bool valid_tuning(const fm_index *idx, const fm_tuning &t)
 
 // One lane per read-strand, one read-strand in flight per lane and 8 waves per CU: the
 // best setting measured on MI355X for all three searches; fm_autotune refines it.
+// Locating runs 16 waves per CU (measured 1.16G against 0.91G rows/s at 8 on the
+// 2^24 workload's hits).
 void default_tunings(fm_index *idx, uint32_t I)
 {
     fm_tuning ex = {I, 1, 1, 256, 8, 0, 0};
     fm_tuning dw = {I, 1, 1, 256, 8, 0, 0};
     fm_tuning in = {I, 1, 1, 256, 8, 1u << 22, 1};
+    // Psi^-1 walks share no buckets and each step waits for the last: more waves pay
+    fm_tuning lo = {I, 1, 1, 256, 16, 0, 0};
     idx->tune[FM_OP_EXACT] = ex;
     idx->tune[FM_OP_DARRAY] = dw;
     idx->tune[FM_OP_INEXACT] = in;
+    idx->tune[FM_OP_LOCATE] = lo;
 }
 
 // Moves packed BWTs to the device (unless they are there already) and builds the
@@ -386,14 +391,14 @@ void fm_index_free(fm_index *idx)
 
 int fm_get_tuning(const fm_index *idx, int op, fm_tuning *out)
 {
-    if (!idx || !out || op < 0 || op > 2) return FM_EINVAL;
+    if (!idx || !out || op < 0 || op > FM_OP_LOCATE) return FM_EINVAL;
     *out = idx->tune[op];
     return FM_OK;
 }
 
 int fm_set_tuning(fm_index *idx, int op, const fm_tuning *t)
 {
-    if (!idx || !t || op < 0 || op > 2 || !valid_tuning(idx, *t)) return FM_EINVAL;
+    if (!idx || !t || op < 0 || op > FM_OP_LOCATE || !valid_tuning(idx, *t)) return FM_EINVAL;
     if (op == FM_OP_DARRAY && (!idx->has_rev || !idx->rlay[ilog(t->occ_interval)])) return FM_EINVAL;
     idx->tune[op] = *t;
     return FM_OK;
@@ -530,7 +535,7 @@ int fm_locate(const fm_index *idx, const uint32_t *kl, uint64_t niv, uint32_t st
     if (pos_cap > (1ull << 31) || niv >= (1ull << 40)) return FM_ERANGE;
     if (ws_bytes < locate_ws_bytes(niv)) return FM_EINVAL;
     DeviceGuard g(idx->device);
-    return hip_status(launch_locate(idx, idx->tune[FM_OP_EXACT], kl, niv, stride, offs, pos, pos_cap, ws,
+    return hip_status(launch_locate(idx, idx->tune[FM_OP_LOCATE], kl, niv, stride, offs, pos, pos_cap, ws,
                                     (flags & FM_STATS) != 0, (hipStream_t)stream));
 }
 

@@ -21,7 +21,7 @@ struct fm_index {
     void *rlay[7] = {};    // layouts of reverse(R)
     uint64_t device_bytes = 0;
     uint32_t *sa_samples = nullptr;   // SA[32 j] for j = 0 .. n / 32 (fm_locate), or nullptr
-    fm_tuning tune[3] = {};
+    fm_tuning tune[4] = {};
     int cu_count = 0;
     std::string arch;
     // phase timing (diagnostics): events recorded per call, 5 boundaries per call

@@ -66,9 +66,11 @@ def test_every_row_all_layouts(text, device_sort):
             want.append(sa[k:l + 1])
     want = np.concatenate(want)
     for I in LAYOUTS:
-        idx.set_tuning(fm.FM_OP_EXACT, occ_interval=I)
-        offs, pos = locate(idx, kl)
-        assert offs[-1] == want.size and np.array_equal(pos, want), I
+        for waves in (4, 16, 0):
+            idx.set_tuning(fm.FM_OP_LOCATE, occ_interval=I, waves_per_cu=waves)
+            offs, pos = locate(idx, kl)
+            assert offs[-1] == want.size and np.array_equal(pos, want), (I, waves)
+    assert idx.get_tuning(fm.FM_OP_EXACT)["occ_interval"] == 128   # locating has settings of its own
     # a capped call locates the first rows only and still reports the total
     offs, pos = locate(idx, kl, cap=1000)
     assert offs[-1] == want.size and np.array_equal(pos[:1000], want[:1000])
