@@ -305,7 +305,7 @@ def main():
     # Occ8 micro-benchmark: independent uniform (k, l) pairs (two buckets each), narrow ones,
     # l uniform and k = l + 1 - w with w in [0, 8] (mostly one bucket), and the queries the
     # inexact search itself makes (its trace on the step's first reads, replayed independently)
-    occ8_rate = {}
+    occ8_rate, occ8_lanes = {}, {}
     trace_info = None
     if args.occ8_queries:
         t0 = time.time()
@@ -327,15 +327,23 @@ def main():
             q = torch.from_numpy(qh.view(np.int32)).to(dev)
             nq = qh.shape[0]
             qo = torch.empty((nq, 8), dtype=torch.int32, device=dev)
-            fm.fm_occ8(idx, q, out=qo)
-            torch.cuda.synchronize()
-            q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            q0.record()
-            for _ in range(3):
+            # fm_occ8 runs with the exact search's layout and lanes per query; the best of
+            # one and two lanes per query is reported for each query set
+            ex_cfg = idx.get_tuning(fm.FM_OP_EXACT)
+            for lanes in (1, 2):
+                idx.set_tuning(fm.FM_OP_EXACT, lanes=lanes)
                 fm.fm_occ8(idx, q, out=qo)
-            q1.record()
-            torch.cuda.synchronize()
-            occ8_rate[kind] = nq / (q0.elapsed_time(q1) / 3 / 1e3)
+                torch.cuda.synchronize()
+                q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                q0.record()
+                for _ in range(3):
+                    fm.fm_occ8(idx, q, out=qo)
+                q1.record()
+                torch.cuda.synchronize()
+                rate = nq / (q0.elapsed_time(q1) / 3 / 1e3)
+                if rate > occ8_rate.get(kind, 0.0):
+                    occ8_rate[kind], occ8_lanes[kind] = rate, lanes
+            idx.set_tuning(fm.FM_OP_EXACT, **ex_cfg)
             del q, qo
 
     # roofline of the dominant kernel: algorithmic bytes per launch / its event-timed duration
@@ -409,6 +417,7 @@ def main():
         "occ8_queries_per_s": {**{"fm_occ8_" + k: round(v, 1) for k, v in occ8_rate.items()},
                                "dfs_in_separate_call": round(in_stats["occ8"] / (sep_phase["dfs"] / 1e3), 1)},
         "occ8_search_trace": trace_info,
+        "occ8_lanes_per_query": occ8_lanes,
         "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
         "separate_calls": {"ms_per_step": round(sep_ms, 4), "phase_ms": {k: round(v, 4) for k, v in sep_phase.items()},
                            "equal_to_one_pass": fused_equal},
@@ -503,18 +512,22 @@ def genome_bench(args):
     # fetches the memory system sustains when nothing depends on a previous fetch
     occ8 = {}
     nq = 1 << 26
+    ex_cfg = idx.get_tuning(fm.FM_OP_EXACT)
     for kind in ("uniform", "narrow"):
         q = torch.from_numpy(synth.occ8_queries(R.size, nq, 4343, kind).view(np.int32)).cuda()
         qo = torch.empty((nq, 8), dtype=torch.int32, device="cuda")
-        fm.fm_occ8(idx, q, out=qo)
-        torch.cuda.synchronize()
-        ev[0].record()
-        for _ in range(3):
+        for lanes in (1, 2):                       # the best of one and two lanes per query
+            idx.set_tuning(fm.FM_OP_EXACT, lanes=lanes)
             fm.fm_occ8(idx, q, out=qo)
-        ev[1].record()
-        torch.cuda.synchronize()
-        occ8[kind] = nq / (ev[0].elapsed_time(ev[1]) / 3 / 1e3)
+            torch.cuda.synchronize()
+            ev[0].record()
+            for _ in range(3):
+                fm.fm_occ8(idx, q, out=qo)
+            ev[1].record()
+            torch.cuda.synchronize()
+            occ8[kind] = max(occ8.get(kind, 0.0), nq / (ev[0].elapsed_time(ev[1]) / 3 / 1e3))
         del q, qo
+    idx.set_tuning(fm.FM_OP_EXACT, **ex_cfg)
     reads = args.genome_batches * B
     nrs = 2 * B
     alg = st["buckets"] * 32 + 2 * B * LEN + 32 * nrs + 16 * int(eager[1][1][-1])
