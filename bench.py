@@ -284,6 +284,37 @@ def main():
         p.free()
     log("graph replay: %.3f ms/step, identical: %s" % (graph_ms, graph_equal))
 
+    # the step end to end over PCIe: reads uploaded from pinned host memory, then the exact
+    # intervals, hit offsets, statuses and the listed hits read back (their count is the
+    # same on every step of this batch, so no extra round trip reads it first)
+    n_listed = int(in_batched[1][-1])
+    h_in = [torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+            for a in (rd.codes, rd.offs.view(np.int64), rd.z)]
+    h_out = [torch.empty(t.shape, dtype=t.dtype).pin_memory()
+             for t in (ex_out, bufs.hit_offs, bufs.status, bufs.hits[:n_listed])]
+
+    def end_to_end():
+        for d, h in zip((codes, offs, z), h_in):
+            d.copy_(h, non_blocking=True)
+        step()
+        for h, d in zip(h_out, (ex_out, bufs.hit_offs, bufs.status, bufs.hits[:n_listed])):
+            h.copy_(d, non_blocking=True)
+
+    end_to_end()
+    torch.cuda.synchronize()
+    x0, x1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    x0.record()
+    for _ in range(args.steps):
+        end_to_end()
+    x1.record()
+    torch.cuda.synchronize()
+    e2e_ms = x0.elapsed_time(x1) / args.steps
+    e2e_equal = bool(torch.equal(h_out[0], ex_batched.cpu())) and bool(
+        np.array_equal(h_out[3].numpy().view(np.uint32).reshape(-1), in_batched[0].view(np.uint32).reshape(-1)))
+    e2e_bytes = sum(t.numel() * t.element_size() for t in h_in + h_out)
+    log("end to end over PCIe: %.3f ms/step (%.1f MB moved), identical: %s" % (e2e_ms, e2e_bytes / 1e6, e2e_equal))
+    del h_in, h_out
+
     # the plain kernels on the same step, and their agreement with the batched ones
     plain_ms = None
     plain_equal = None
@@ -413,6 +444,8 @@ def main():
         "batched_vs_plain": round(plain_ms / ms_step, 3) if plain_ms else None,
         "batched_equals_plain": plain_equal,
         "graph_ms_per_step": round(graph_ms, 4),
+        "pcie_inclusive": {"ms_per_step": round(e2e_ms, 4), "reads_per_s": round(nreads / (e2e_ms / 1e3), 1),
+                           "bytes_moved": int(e2e_bytes), "equals_device_resident": e2e_equal},
         "graph_equals_eager": graph_equal,
         "occ8_queries_per_s": {**{"fm_occ8_" + k: round(v, 1) for k, v in occ8_rate.items()},
                                "dfs_in_separate_call": round(in_stats["occ8"] / (sep_phase["dfs"] / 1e3), 1)},
