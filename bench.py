@@ -141,7 +141,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests in the serving run on the 2^28-base index (0 skips it)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of capacity")
-    ap.add_argument("--serve-lanes", type=int, default=2)
+    ap.add_argument("--serve-lanes", type=int, default=3)
     ap.add_argument("--serve-pool", type=int, default=2_000_000, help="reads the requests are drawn from")
     ap.add_argument("--genome-batches", type=int, default=16,
                     help="batches of 1M reads in the genome-scale run on the 3.1e9-base index (0 skips it)")
