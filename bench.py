@@ -313,7 +313,42 @@ def main():
         np.array_equal(h_out[3].numpy().view(np.uint32).reshape(-1), in_batched[0].view(np.uint32).reshape(-1)))
     e2e_bytes = sum(t.numel() * t.element_size() for t in h_in + h_out)
     log("end to end over PCIe: %.3f ms/step (%.1f MB moved), identical: %s" % (e2e_ms, e2e_bytes / 1e6, e2e_equal))
-    del h_in, h_out
+    del h_out
+
+    # the same with two buffer sets on two streams (default priority), so that one batch's
+    # copies overlap the other's search, as the server's lanes do
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    sets = []
+    for st_ in streams:
+        with torch.cuda.stream(st_):
+            c2, o2, z2, e2 = (torch.empty_like(t) for t in (codes, offs, z, ex_out))
+            b2 = fm.InexactBuffers(idx, nreads, total_len, INEXACT, ZMAX, hit_cap, dev)
+            ho = [torch.empty(t.shape, dtype=t.dtype).pin_memory()
+                  for t in (e2, b2.hit_offs, b2.status, b2.hits[:n_listed])]
+        sets.append((st_, c2, o2, z2, e2, b2, ho))
+
+    def overlapped(i):
+        st_, c2, o2, z2, e2, b2, ho = sets[i % 2]
+        with torch.cuda.stream(st_):
+            for d, h in zip((c2, o2, z2), h_in):
+                d.copy_(h, non_blocking=True)
+            fm.fm_search_both(idx, c2, o2, z2, EXACT, INEXACT, ZMAX, hit_cap, out=e2, bufs=b2, stream=st_)
+            for h, d in zip(ho, (e2, b2.hit_offs, b2.status, b2.hits[:n_listed])):
+                h.copy_(d, non_blocking=True)
+
+    for i in range(2):
+        overlapped(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        overlapped(i)
+    torch.cuda.synchronize()
+    ovl_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ovl_equal = all(bool(torch.equal(ho[0], ex_batched.cpu())) and bool(np.array_equal(
+        ho[3].numpy().view(np.uint32).reshape(-1), in_batched[0].view(np.uint32).reshape(-1)))
+        for (_, _, _, _, _, _, ho) in sets)
+    log("end to end over PCIe, two streams: %.3f ms/step, identical: %s" % (ovl_ms, ovl_equal))
+    del sets, h_in
 
     # the plain kernels on the same step, and their agreement with the batched ones
     plain_ms = None
@@ -445,7 +480,10 @@ def main():
         "batched_equals_plain": plain_equal,
         "graph_ms_per_step": round(graph_ms, 4),
         "pcie_inclusive": {"ms_per_step": round(e2e_ms, 4), "reads_per_s": round(nreads / (e2e_ms / 1e3), 1),
-                           "bytes_moved": int(e2e_bytes), "equals_device_resident": e2e_equal},
+                           "bytes_moved": int(e2e_bytes), "equals_device_resident": e2e_equal,
+                           "two_streams": {"ms_per_step": round(ovl_ms, 4),
+                                           "reads_per_s": round(nreads / (ovl_ms / 1e3), 1),
+                                           "equals_device_resident": ovl_equal}},
         "graph_equals_eager": graph_equal,
         "occ8_queries_per_s": {**{"fm_occ8_" + k: round(v, 1) for k, v in occ8_rate.items()},
                                "dfs_in_separate_call": round(in_stats["occ8"] / (sep_phase["dfs"] / 1e3), 1)},
