@@ -145,6 +145,8 @@ def parse():
     ap.add_argument("--serve-pool", type=int, default=2_000_000, help="reads the requests are drawn from")
     ap.add_argument("--genome-batches", type=int, default=16,
                     help="batches of 1M reads in the genome-scale run on the 3.1e9-base index (0 skips it)")
+    ap.add_argument("--pcie-two-streams", action="store_true",
+                    help="also time the step end to end on two streams, copies overlapping the other batch's search")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain device-to-device copy of this many MiB (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -315,40 +317,44 @@ def main():
     log("end to end over PCIe: %.3f ms/step (%.1f MB moved), identical: %s" % (e2e_ms, e2e_bytes / 1e6, e2e_equal))
     del h_out
 
-    # the same with two buffer sets on two streams (default priority), so that one batch's
-    # copies overlap the other's search, as the server's lanes do
-    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
-    sets = []
-    for st_ in streams:
-        with torch.cuda.stream(st_):
-            c2, o2, z2, e2 = (torch.empty_like(t) for t in (codes, offs, z, ex_out))
-            b2 = fm.InexactBuffers(idx, nreads, total_len, INEXACT, ZMAX, hit_cap, dev)
-            ho = [torch.empty(t.shape, dtype=t.dtype).pin_memory()
-                  for t in (e2, b2.hit_offs, b2.status, b2.hits[:n_listed])]
-        sets.append((st_, c2, o2, z2, e2, b2, ho))
+    def two_stream_e2e():
+        # the same with two buffer sets on two streams (default priority), so that one batch's
+        # copies overlap the other's search, as the server's lanes do. Off by default: streams
+        # made here share the GPU's few hardware queues with the serving leg's and were seen to
+        # slow both (the serving leg measures overlapped copies under load anyway).
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        sets = []
+        for st_ in streams:
+            with torch.cuda.stream(st_):
+                c2, o2, z2, e2 = (torch.empty_like(t) for t in (codes, offs, z, ex_out))
+                b2 = fm.InexactBuffers(idx, nreads, total_len, INEXACT, ZMAX, hit_cap, dev)
+                ho = [torch.empty(t.shape, dtype=t.dtype).pin_memory()
+                      for t in (e2, b2.hit_offs, b2.status, b2.hits[:n_listed])]
+            sets.append((st_, c2, o2, z2, e2, b2, ho))
 
-    def overlapped(i):
-        st_, c2, o2, z2, e2, b2, ho = sets[i % 2]
-        with torch.cuda.stream(st_):
-            for d, h in zip((c2, o2, z2), h_in):
-                d.copy_(h, non_blocking=True)
-            fm.fm_search_both(idx, c2, o2, z2, EXACT, INEXACT, ZMAX, hit_cap, out=e2, bufs=b2, stream=st_)
-            for h, d in zip(ho, (e2, b2.hit_offs, b2.status, b2.hits[:n_listed])):
-                h.copy_(d, non_blocking=True)
+        def overlapped(i):
+            st_, c2, o2, z2, e2, b2, ho = sets[i % 2]
+            with torch.cuda.stream(st_):
+                for d, h in zip((c2, o2, z2), h_in):
+                    d.copy_(h, non_blocking=True)
+                fm.fm_search_both(idx, c2, o2, z2, EXACT, INEXACT, ZMAX, hit_cap, out=e2, bufs=b2, stream=st_)
+                for h, d in zip(ho, (e2, b2.hit_offs, b2.status, b2.hits[:n_listed])):
+                    h.copy_(d, non_blocking=True)
 
-    for i in range(2):
-        overlapped(i)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        overlapped(i)
-    torch.cuda.synchronize()
-    ovl_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    ovl_equal = all(bool(torch.equal(ho[0], ex_batched.cpu())) and bool(np.array_equal(
-        ho[3].numpy().view(np.uint32).reshape(-1), in_batched[0].view(np.uint32).reshape(-1)))
-        for (_, _, _, _, _, _, ho) in sets)
-    log("end to end over PCIe, two streams: %.3f ms/step, identical: %s" % (ovl_ms, ovl_equal))
-    del sets, h_in
+        for i in range(2):
+            overlapped(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            overlapped(i)
+        torch.cuda.synchronize()
+        ovl_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ovl_equal = all(bool(torch.equal(ho[0], ex_batched.cpu())) and bool(np.array_equal(
+            ho[3].numpy().view(np.uint32).reshape(-1), in_batched[0].view(np.uint32).reshape(-1)))
+            for (_, _, _, _, _, _, ho) in sets)
+        log("end to end over PCIe, two streams: %.3f ms/step, identical: %s" % (ovl_ms, ovl_equal))
+        del sets
+        return ovl_ms, ovl_equal
 
     # the plain kernels on the same step, and their agreement with the batched ones
     plain_ms = None
@@ -446,12 +452,14 @@ def main():
         cpu, parity = cpu_baseline(R, rd, min(args.cpu_sample, nreads), ex_batched, in_batched, args.cpu_threads)
 
     serve = genome = None
-    if args.serve_requests > 0 or args.genome_batches > 0:
-        del codes, offs, z, ex_out, ex_ws, bufs
-        idx.free()
-        torch.cuda.empty_cache()
     if args.serve_requests > 0:
         serve = serve_bench(args)
+        torch.cuda.empty_cache()
+    ovl = two_stream_e2e() if args.pcie_two_streams else None
+    del h_in
+    if args.genome_batches > 0:
+        del codes, offs, z, ex_out, ex_ws, bufs
+        idx.free()
         torch.cuda.empty_cache()
     if args.genome_batches > 0:
         genome = genome_bench(args)
@@ -481,9 +489,9 @@ def main():
         "graph_ms_per_step": round(graph_ms, 4),
         "pcie_inclusive": {"ms_per_step": round(e2e_ms, 4), "reads_per_s": round(nreads / (e2e_ms / 1e3), 1),
                            "bytes_moved": int(e2e_bytes), "equals_device_resident": e2e_equal,
-                           "two_streams": {"ms_per_step": round(ovl_ms, 4),
-                                           "reads_per_s": round(nreads / (ovl_ms / 1e3), 1),
-                                           "equals_device_resident": ovl_equal}},
+                           "two_streams": None if ovl is None else {
+                               "ms_per_step": round(ovl[0], 4), "reads_per_s": round(nreads / (ovl[0] / 1e3), 1),
+                               "equals_device_resident": ovl[1]}},
         "graph_equals_eager": graph_equal,
         "occ8_queries_per_s": {**{"fm_occ8_" + k: round(v, 1) for k, v in occ8_rate.items()},
                                "dfs_in_separate_call": round(in_stats["occ8"] / (sep_phase["dfs"] / 1e3), 1)},
