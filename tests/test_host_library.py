@@ -35,6 +35,21 @@ def test_library_exports_every_declared_symbol():
         getattr(lib, n)
 
 
+def test_header_is_plain_c(tmp_path):
+    """include/fm.h compiles as C99 and as C++17 with warnings as errors: the boundary
+    holds plain types only."""
+    import shutil
+    import subprocess
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    src = tmp_path / "use_fm.c"
+    src.write_text('#include "fm.h"\nint main(void) { fm_tuning t; t.order = 1; return (int)t.order + FM_OP_LOCATE; }\n')
+    for cc, std, lang in (("gcc", "-std=c99", "c"), ("g++", "-std=c++17", "c++")):
+        if shutil.which(cc) is None:
+            pytest.skip("no %s" % cc)
+        subprocess.run([cc, std, "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-I", inc, "-x", lang, str(src)],
+                       check=True)
+
+
 def test_strerror_and_version():
     assert fm.strerror(fm.FM_OK) == "ok"
     assert fm.strerror(fm.FM_EOVERFLOW) == "hit capacity exceeded"
