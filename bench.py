@@ -885,9 +885,24 @@ def cpu_baseline(R, rd, sample, ex_batched, in_batched, threads):
     ok_in = bool(np.array_equal(go[:sample + 1], hoffs) and (gs[:sample] == 0).all()
                  and all(np.array_equal(g[f], hits[f]) for f in ("read", "k", "l", "strand"))
                  and np.array_equal(g["nmm"], hits["d"]))
+    # one host thread on the first reads of the sample, for the per-core rate
+    one = min(sample, 20_000)
+    t0 = time.time()
+    p1 = s.subset(np.arange(one))
+    x.exact(p1.codes, p1.offs, oracle.BOTH, "listing1")
+    x.inexact(p1.codes, p1.offs, p1.z, oracle.BOTH, "listing2_darray", rev=xr)
+    dt1 = time.time() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     cpu = {"value": round(sample / dt, 1), "unit": "reads/s", "cores": threads, "kind": "oracle",
            "sample": "first %d of the step's reads; exact (Listing 1) + z=1 inexact (Listing 2, D bound), "
-                     "both strands, %d host threads, index prebuilt" % (sample, threads)}
+                     "both strands, %d host threads, index prebuilt" % (sample, threads),
+           "single_thread": {"reads_per_s": round(one / dt1, 1), "sample": "first %d reads" % one},
+           "host": {"cpu_model": model, "nproc": os.cpu_count()}}
     parity = {"reads": sample, "exact_bit_exact": ok_ex, "inexact_bit_exact": ok_in}
     return cpu, parity
 
