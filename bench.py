@@ -266,6 +266,8 @@ def main():
     # Listing 2 with all its branches (z=1 edits) on the same reads
     gap = gapped_rate(fm, torch, idx, codes, offs, z, nreads, total_len, args)
     log("gapped:", gap)
+    frank = full_rank_rate(fm, torch, idx, codes, offs, nreads, ex_ws, args)
+    log("full rank:", frank)
 
     # the same step replayed from a launch graph captured for this batch shape
     plans = [fm.Plan.both(idx, codes, offs, z, EXACT, INEXACT, ZMAX, ex_out, bufs)]
@@ -495,6 +497,7 @@ def main():
         "graph_equals_eager": graph_equal,
         "occ8_queries_per_s": {**{"fm_occ8_" + k: round(v, 1) for k, v in occ8_rate.items()},
                                "dfs_in_separate_call": round(in_stats["occ8"] / (sep_phase["dfs"] / 1e3), 1)},
+        "full_rank_exact": frank,
         "occ8_search_trace": trace_info,
         "occ8_lanes_per_query": occ8_lanes,
         "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
@@ -646,6 +649,33 @@ def genome_bench(args):
     del codes, offs, z, ex_out, bufs
     idx.free()
     return out
+
+
+def full_rank_rate(fm, torch, idx, codes, offs, nreads, ws, args) -> dict:
+    """Full-rank exact search (FM_FULL_RANK: Listing 1 takes every step and a miss reports
+    its rank) of the step's reads on both strands: batched and plain, bit-identical."""
+    flags = fm.FM_BOTH | fm.FM_FULL_RANK
+    out = torch.empty((2 * nreads, 2), dtype=torch.int32, device=codes.device)
+    fm.fm_search_exact(idx, codes, offs, flags | fm.FM_STATS, out=out, ws=ws)
+    torch.cuda.synchronize()
+    steps = fm.exact_stats(ws)["steps"]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    res = {}
+    for name, extra, reps in (("batched", 0, args.steps), ("plain", fm.FM_PLAIN, max(args.plain_steps, 1))):
+        fm.fm_search_exact(idx, codes, offs, flags | extra, out=out, ws=ws)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            fm.fm_search_exact(idx, codes, offs, flags | extra, out=out, ws=ws)
+        ev[1].record()
+        torch.cuda.synchronize()
+        res[name] = (ev[0].elapsed_time(ev[1]) / reps, out.clone())
+    ms, pms = res["batched"][0], res["plain"][0]
+    return {"workload": "the step's 1M reads x 100 bp, both strands; every step taken, misses report their rank",
+            "ms": round(ms, 4), "reads_per_s": round(nreads / (ms / 1e3), 1),
+            "plain_reads_per_s": round(nreads / (pms / 1e3), 1), "batched_vs_plain": round(pms / ms, 3),
+            "batched_equals_plain": bool(torch.equal(res["batched"][1], res["plain"][1])),
+            "steps": steps, "steps_per_s": round(steps / (ms / 1e3), 1)}
 
 
 def gapped_rate(fm, torch, idx, codes, offs, z, nreads, total_len, args) -> dict:
