@@ -268,6 +268,8 @@ def main():
     log("gapped:", gap)
     frank = full_rank_rate(fm, torch, idx, codes, offs, nreads, ex_ws, args)
     log("full rank:", frank)
+    layouts = layout_rates(fm, torch, idx, step, ex_out, bufs, nreads, (ex_batched, in_batched))
+    log("layouts:", layouts)
 
     # the same step replayed from a launch graph captured for this batch shape
     plans = [fm.Plan.both(idx, codes, offs, z, EXACT, INEXACT, ZMAX, ex_out, bufs)]
@@ -498,6 +500,7 @@ def main():
         "occ8_queries_per_s": {**{"fm_occ8_" + k: round(v, 1) for k, v in occ8_rate.items()},
                                "dfs_in_separate_call": round(in_stats["occ8"] / (sep_phase["dfs"] / 1e3), 1)},
         "full_rank_exact": frank,
+        "step_by_layout": layouts,
         "occ8_search_trace": trace_info,
         "occ8_lanes_per_query": occ8_lanes,
         "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
@@ -648,6 +651,34 @@ def genome_bench(args):
     log("genome scale:", out)
     del codes, offs, z, ex_out, bufs
     idx.free()
+    return out
+
+
+def layout_rates(fm, torch, idx, step, ex_out, bufs, nreads, ref) -> dict:
+    """The step at every bucket layout of the index (one lane per read-strand, D walk at the
+    same layout): ms and reads/s, and agreement with the tuned run's output."""
+    ops = (fm.FM_OP_INEXACT, fm.FM_OP_DARRAY)
+    saved = [idx.get_tuning(op) for op in ops]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    out = {}
+    try:
+        for I in (64, 96, 128, 192, 224, 256, 448):
+            for op in ops:
+                idx.set_tuning(op, occ_interval=I, lanes=1)
+            step()
+            torch.cuda.synchronize()
+            ev[0].record()
+            for _ in range(3):
+                step()
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / 3
+            same = bool(torch.equal(ex_out, ref[0])) and all(
+                np.array_equal(a, b) for a, b in zip(fm.hits_to_numpy(bufs, nreads), ref[1]))
+            out[str(I)] = {"ms": round(ms, 4), "reads_per_s": round(nreads / (ms / 1e3), 1), "identical": same}
+    finally:
+        for op, t in zip(ops, saved):
+            idx.set_tuning(op, **t)
     return out
 
 
