@@ -97,6 +97,15 @@ typedef struct {
     uint32_t occ_interval;          /* checkpoint interval I: 64, 96, 128, 192, 224, 256, 448;
                                        0 for 128 */
     uint32_t flags;                 /* FM_LOAD_* */
+    void *dev_buf;                  /* NULL: the index allocates its device memory and frees it
+                                       in fm_index_free. Otherwise caller-owned device memory
+                                       on `device`, 256-byte aligned, of dev_buf_bytes bytes
+                                       (at least fm_index_bytes / fm_index_required_bytes),
+                                       into which the index places everything it keeps (its
+                                       layouts and SA samples); the caller frees it, and it
+                                       must outlive the index. Construction still allocates
+                                       transient working memory, freed before it returns. */
+    size_t dev_buf_bytes;
 } fm_load_opts;
 
 typedef struct {
@@ -110,7 +119,10 @@ typedef struct {
                                        256, 448 */
     uint32_t has_reverse;
     uint32_t sa_sample;             /* 32 when SA samples are kept (fm_locate), else 0 */
-    uint64_t device_bytes;          /* device memory owned by the index */
+    uint64_t device_bytes;          /* device memory the index keeps (in its own allocation, or
+                                       in the caller's dev_buf) */
+    uint32_t caller_memory;         /* 1 when that memory is the caller's dev_buf */
+    uint32_t pad;
 } fm_info;
 
 /* Launch configuration of one operation (see fm_get_tuning). */
@@ -179,9 +191,30 @@ int fm_index_from_text(const uint8_t *text, uint64_t n, const fm_load_opts *opts
 int fm_index_from_codes(const uint8_t *bwt, uint64_t rows, const uint8_t *rev_bwt,
                         const fm_load_opts *opts, fm_index **out);
 
-/* Loads an index file written by fm_index_build_file. FM_EIO, FM_EFORMAT (bad magic,
- * sizes, C or checksum), FM_EINVAL (FM_LOAD_REVERSE asked of a file without one). */
+/* Loads an index file written by fm_index_build_file: the packed BWT of R$ (Eq. 2) and,
+ * if the file has it, of reverse(R)$, with n, C (Background, Fig. 1) and the '$' rows.
+ * The file is read and checked on the host before any device work: FM_EIO when it
+ * cannot be opened, FM_EFORMAT for a bad magic or version, a truncated or oversized body,
+ * sizes that disagree, a checksum (over header and body) that does not match, or C or a
+ * '$' row that disagrees with the symbol counts of the packed BWT; FM_EINVAL when
+ * FM_LOAD_REVERSE is asked of a file without a reverse index, or dev_buf is given but
+ * misaligned, on another device or smaller than fm_index_required_bytes. Files hold no
+ * SA samples, so FM_LOAD_LOCATE has no effect here. */
 int fm_index_load(const char *path, const fm_load_opts *opts, fm_index **out);
+
+/* Device bytes an index over n symbols keeps when built with opts (fm_index_from_text,
+ * _codes or _load): the layouts (the one named by occ_interval, or all of them with
+ * FM_LOAD_ALL_LAYOUTS) of R and, with FM_LOAD_REVERSE, of reverse(R), plus with
+ * FM_LOAD_LOCATE the SA samples of fm_index_from_text (4 bytes per 32 rows); each piece
+ * is 256-byte aligned. This is the smallest dev_buf_bytes accepted. Host only; FM_EINVAL
+ * for an unsupported occ_interval, FM_ERANGE when n + 1 >= 2^32. */
+int fm_index_bytes(uint64_t n, const fm_load_opts *opts, size_t *bytes);
+
+/* fm_index_bytes for the index fm_index_load(path, opts) would create, with n and the
+ * presence of a reverse index read from the file's header (FM_LOAD_LOCATE ignored).
+ * Reads only the header: FM_EIO, FM_EFORMAT (bad magic or sizes), FM_EINVAL as for
+ * fm_index_load. Host only. */
+int fm_index_required_bytes(const char *path, const fm_load_opts *opts, size_t *bytes);
 
 int fm_index_info(const fm_index *idx, fm_info *out);
 

@@ -146,12 +146,60 @@ uint64_t fnv1a(const void *p, size_t bytes, uint64_t h)
     return h;
 }
 
-constexpr char kMagic[8] = {'F', 'M', 'O', 'C', 'C', '0', '0', '1'};
+constexpr char kMagic[8] = {'F', 'M', 'O', 'C', 'C', '0', '0', '2'};
 
 struct FileHeader {
     char magic[8];
     uint64_t n, flags, dollar, C[5], rev_dollar, rev_C[5], words, checksum;
 };
+
+// FNV-1a over the header (checksum field zero) and then the packed words of each side.
+uint64_t file_checksum(const FileHeader &h, const uint32_t *fwd, const uint32_t *rev)
+{
+    FileHeader z = h;
+    z.checksum = 0;
+    uint64_t sum = fnv1a(&z, sizeof z, 0xcbf29ce484222325ull);
+    sum = fnv1a(fwd, h.words * 4, sum);
+    if (rev) sum = fnv1a(rev, h.words * 4, sum);
+    return sum;
+}
+
+// The header's C and '$' row agree with the packed words of rows 0..n: C[c+1] - C[c] is
+// the number of rows holding code c, less the '$' row for code 0 (it is stored as 0),
+// and the word at the '$' row holds 0 there.
+bool side_consistent(const uint32_t *words, uint64_t n, uint64_t dollar, const uint64_t C[5])
+{
+    if (dollar > n || C[0] != 0 || C[4] != n) return false;
+    if ((words[dollar / 16] >> (2 * (dollar % 16))) & 3u) return false;
+    uint64_t cnt[4] = {0, 0, 0, 0};
+    const uint64_t rows = n + 1, full = rows / 16;
+    for (uint64_t w = 0; w < full; ++w) {
+        const uint32_t x = words[w], lo = x & 0x55555555u, hi = (x >> 1) & 0x55555555u;
+        const uint32_t t = (uint32_t)__builtin_popcount(lo & hi);
+        cnt[3] += t;
+        cnt[2] += (uint32_t)__builtin_popcount(hi) - t;
+        cnt[1] += (uint32_t)__builtin_popcount(lo) - t;
+    }
+    for (uint64_t r = full * 16; r < rows; ++r) {
+        const uint32_t c = (words[r / 16] >> (2 * (r % 16))) & 3u;
+        if (c) cnt[c]++;
+    }
+    if (rows % 16 && (words[full] >> (2 * (rows % 16))) != 0) return false;   // unused bits stay 0
+    cnt[0] = rows - cnt[1] - cnt[2] - cnt[3] - 1;
+    for (int c = 0; c < 4; ++c)
+        if (C[c] > C[c + 1] || C[c + 1] - C[c] != cnt[c]) return false;
+    return true;
+}
+
+// Reads and checks the header: magic, sizes, flags.
+int read_header(FILE *f, FileHeader &h)
+{
+    if (fread(&h, sizeof h, 1, f) != 1) return FM_EFORMAT;
+    if (memcmp(h.magic, kMagic, 8) != 0) return FM_EFORMAT;
+    if (h.n + 1 >= (1ull << 32) || h.words != (h.n + 1 + 15) / 16 || (h.flags & ~(uint64_t)FM_LOAD_REVERSE))
+        return FM_EFORMAT;
+    return FM_OK;
+}
 
 }  // namespace
 
@@ -235,9 +283,7 @@ int write_index_file(const char *path, uint64_t n, const HostSide &fwd, const Ho
         memcpy(h.rev_C, rev->C, sizeof h.rev_C);
     }
     h.words = fwd.words.size();
-    uint64_t sum = fnv1a(fwd.words.data(), fwd.words.size() * 4, 0xcbf29ce484222325ull);
-    if (rev) sum = fnv1a(rev->words.data(), rev->words.size() * 4, sum);
-    h.checksum = sum;
+    h.checksum = file_checksum(h, fwd.words.data(), rev ? rev->words.data() : nullptr);
     FILE *f = fopen(path, "wb");
     if (!f) return FM_EIO;
     bool ok = fwrite(&h, sizeof h, 1, f) == 1;
@@ -247,18 +293,26 @@ int write_index_file(const char *path, uint64_t n, const HostSide &fwd, const Ho
     return ok ? FM_OK : FM_EIO;
 }
 
+int read_index_header(const char *path, uint64_t *n, bool *has_rev)
+{
+    FILE *f = fopen(path, "rb");
+    if (!f) return FM_EIO;
+    FileHeader h;
+    const int st = read_header(f, h);
+    fclose(f);
+    if (st) return st;
+    *n = h.n;
+    *has_rev = (h.flags & FM_LOAD_REVERSE) != 0;
+    return FM_OK;
+}
+
 int read_index_file(const char *path, bool want_rev, uint64_t *n, HostSide &fwd, HostSide &rev, bool *has_rev)
 {
     FILE *f = fopen(path, "rb");
     if (!f) return FM_EIO;
     FileHeader h;
-    int st = FM_OK;
-    if (fread(&h, sizeof h, 1, f) != 1) st = FM_EFORMAT;
-    if (!st && memcmp(h.magic, kMagic, 8) != 0) st = FM_EFORMAT;
-    if (!st && (h.n + 1 >= (1ull << 32) || h.words != (h.n + 1 + 15) / 16 || h.dollar > h.n || h.C[4] != h.n))
-        st = FM_EFORMAT;
+    int st = read_header(f, h);
     const bool file_rev = !st && (h.flags & FM_LOAD_REVERSE);
-    if (!st && file_rev && (h.rev_dollar > h.n || h.rev_C[4] != h.n)) st = FM_EFORMAT;
     if (!st && want_rev && !file_rev) st = FM_EINVAL;
     if (!st) {
         try {
@@ -270,13 +324,12 @@ int read_index_file(const char *path, bool want_rev, uint64_t *n, HostSide &fwd,
     }
     if (!st && fread(fwd.words.data(), 4, h.words, f) != h.words) st = FM_EFORMAT;
     if (!st && file_rev && fread(rev.words.data(), 4, h.words, f) != h.words) st = FM_EFORMAT;
+    if (!st && fgetc(f) != EOF) st = FM_EFORMAT;                  // nothing may follow the body
     fclose(f);
     if (st) return st;
-    uint64_t sum = fnv1a(fwd.words.data(), fwd.words.size() * 4, 0xcbf29ce484222325ull);
-    if (file_rev) sum = fnv1a(rev.words.data(), rev.words.size() * 4, sum);
-    if (sum != h.checksum) return FM_EFORMAT;
-    for (int c = 0; c < 4; ++c)
-        if (h.C[c] > h.C[c + 1] || (file_rev && h.rev_C[c] > h.rev_C[c + 1])) return FM_EFORMAT;
+    if (file_checksum(h, fwd.words.data(), file_rev ? rev.words.data() : nullptr) != h.checksum) return FM_EFORMAT;
+    if (!side_consistent(fwd.words.data(), h.n, h.dollar, h.C)) return FM_EFORMAT;
+    if (file_rev && !side_consistent(rev.words.data(), h.n, h.rev_dollar, h.rev_C)) return FM_EFORMAT;
     *n = h.n;
     fwd.dollar = h.dollar;
     memcpy(fwd.C, h.C, sizeof h.C);

@@ -98,18 +98,59 @@ void default_tunings(fm_index *idx, uint32_t I)
     idx->tune[FM_OP_LOCATE] = lo;
 }
 
+// Where an index's pieces go: byte offsets of the forward and reverse layouts (~0: not
+// built) and of the SA samples, each 256-byte aligned, and the total.
+struct IndexPlan {
+    uint64_t lay[kLayouts], rlay[kLayouts], samples, total;
+};
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
+
+int plan_index(uint64_t n, const fm_load_opts *opts, bool rev, bool samples, IndexPlan &p)
+{
+    if (n + 1 >= (1ull << 32)) return FM_ERANGE;
+    const uint32_t I = opts && opts->occ_interval ? opts->occ_interval : 128;
+    if (ilog(I) < 0) return FM_EINVAL;
+    const bool all = opts && (opts->flags & FM_LOAD_ALL_LAYOUTS);
+    uint64_t at = 0;
+    for (int side = 0; side < 2; ++side)
+        for (int li = 0; li < kLayouts; ++li) {
+            uint64_t &slot = side ? p.rlay[li] : p.lay[li];
+            slot = ~0ull;
+            if ((side && !rev) || (!all && kIntervals[li] != I)) continue;
+            slot = at;
+            at = align256(at + layout_bytes(n, kIntervals[li]));
+        }
+    p.samples = ~0ull;
+    if (samples) {
+        p.samples = at;
+        at = align256(at + ((n + 1 + kSaSample - 1) / kSaSample) * 4);
+    }
+    p.total = at;
+    return FM_OK;
+}
+
 // Moves packed BWTs to the device (unless they are there already) and builds the
-// requested layouts.
+// requested layouts, in one allocation of the index's own or in the caller's dev_buf.
 int create_index(const fm_load_opts *opts, uint64_t n, const HostSide &fwd, const HostSide *rev, fm_index **out)
 {
     *out = nullptr;
     const int dev = opts ? opts->device : 0;
     uint32_t I = opts && opts->occ_interval ? opts->occ_interval : 128;
-    if (ilog(I) < 0) return FM_EINVAL;
-    const bool all = opts && (opts->flags & FM_LOAD_ALL_LAYOUTS);
+    const bool want_samples = !fwd.samples.empty() || fwd.dev_samples;
+    IndexPlan plan;
+    if (int st = plan_index(n, opts, rev != nullptr, want_samples, plan)) return st;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || dev < 0 || dev >= ndev) return FM_EDEVICE;
     DeviceGuard g(dev);
+    void *caller = opts ? opts->dev_buf : nullptr;
+    if (caller) {
+        hipPointerAttribute_t attr;
+        if ((uintptr_t)caller % 256 || opts->dev_buf_bytes < plan.total ||
+            hipPointerGetAttributes(&attr, caller) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+            attr.device != dev)
+            return FM_EINVAL;
+    }
     fm_index *idx = new (std::nothrow) fm_index();
     if (!idx) return FM_ENOMEM;
     idx->device = dev;
@@ -128,6 +169,16 @@ int create_index(const fm_load_opts *opts, uint64_t n, const HostSide &fwd, cons
     }
     idx->cu_count = prop.multiProcessorCount;
     idx->arch = prop.gcnArchName;
+    if (caller) {
+        idx->mem = caller;
+        idx->owns_mem = false;
+    } else if (hipMalloc(&idx->mem, plan.total ? plan.total : 256) != hipSuccess) {
+        idx->mem = nullptr;
+        fm_index_free(idx);
+        return FM_ENOMEM;
+    }
+    idx->device_bytes = plan.total;
+    char *base = (char *)idx->mem;
 
     const size_t pbytes = fwd.words.size() * 4;
     size_t sbytes = 0;
@@ -147,17 +198,12 @@ int create_index(const fm_load_opts *opts, uint64_t n, const HostSide &fwd, cons
             }
             src = (const uint32_t *)packed;
         }
-        for (uint32_t J : kIntervals) {
-            if (!all && J != I) continue;
-            void *buf = nullptr;
-            const size_t lb = layout_bytes(n, J);
-            if (hipMalloc(&buf, lb) != hipSuccess) {
-                st = FM_ENOMEM;
-                break;
-            }
-            (side ? idx->rlay : idx->lay)[ilog(J)] = buf;
-            idx->device_bytes += lb;
-            if (hipError_t e = build_layout(src, n, J, buf, scratch, nullptr)) {
+        for (int li = 0; li < kLayouts; ++li) {
+            const uint64_t off = side ? plan.rlay[li] : plan.lay[li];
+            if (off == ~0ull) continue;
+            void *buf = base + off;
+            (side ? idx->rlay : idx->lay)[li] = buf;
+            if (hipError_t e = build_layout(src, n, kIntervals[li], buf, scratch, nullptr)) {
                 st = hip_status(e);
                 break;
             }
@@ -168,11 +214,10 @@ int create_index(const fm_load_opts *opts, uint64_t n, const HostSide &fwd, cons
     if (scratch) (void)hipFree(scratch);
     // SA samples for fm_locate
     const uint64_t ns = (n + 1 + kSaSample - 1) / kSaSample;
-    if (!st && (!fwd.samples.empty() || fwd.dev_samples)) {
+    if (!st && want_samples) {
         if (!fwd.dev_samples && fwd.samples.size() != ns) st = FM_EINVAL;
-        else if (hipMalloc(&idx->sa_samples, ns * 4) != hipSuccess) st = FM_ENOMEM;
         else {
-            idx->device_bytes += ns * 4;
+            idx->sa_samples = (uint32_t *)(base + plan.samples);
             const hipError_t e = fwd.dev_samples
                                      ? hipMemcpy(idx->sa_samples, fwd.dev_samples, ns * 4, hipMemcpyDeviceToDevice)
                                      : hipMemcpy(idx->sa_samples, fwd.samples.data(), ns * 4, hipMemcpyHostToDevice);
@@ -209,7 +254,7 @@ const char *fm_strerror(int s)
     }
 }
 
-int fm_version(void) { return 1; }
+int fm_version(void) { return 2; }
 
 // The BWTs of text$ and (want_rev) reverse(text)$ sorted on the device, as device words.
 static int device_sides(const uint8_t *text, uint64_t n, int dev, bool want_rev, bool want_samples, HostSide &fwd,
@@ -358,6 +403,30 @@ int fm_index_load(const char *path, const fm_load_opts *opts, fm_index **out)
     return create_index(opts, n, fwd, (want_rev && has_rev) ? &rev : nullptr, out);
 }
 
+int fm_index_bytes(uint64_t n, const fm_load_opts *opts, size_t *bytes)
+{
+    if (!bytes) return FM_EINVAL;
+    IndexPlan p;
+    const bool rev = opts && (opts->flags & FM_LOAD_REVERSE), samples = opts && (opts->flags & FM_LOAD_LOCATE);
+    if (int st = plan_index(n, opts, rev, samples, p)) return st;
+    *bytes = p.total;
+    return FM_OK;
+}
+
+int fm_index_required_bytes(const char *path, const fm_load_opts *opts, size_t *bytes)
+{
+    if (!path || !bytes) return FM_EINVAL;
+    uint64_t n = 0;
+    bool has_rev = false;
+    if (int st = read_index_header(path, &n, &has_rev)) return st;
+    const bool want_rev = opts && (opts->flags & FM_LOAD_REVERSE);
+    if (want_rev && !has_rev) return FM_EINVAL;
+    IndexPlan p;
+    if (int st = plan_index(n, opts, want_rev, false, p)) return st;
+    *bytes = p.total;
+    return FM_OK;
+}
+
 int fm_index_info(const fm_index *idx, fm_info *out)
 {
     if (!idx || !out) return FM_EINVAL;
@@ -373,6 +442,7 @@ int fm_index_info(const fm_index *idx, fm_info *out)
     out->has_reverse = idx->has_rev ? 1u : 0u;
     out->sa_sample = idx->sa_samples ? kSaSample : 0u;
     out->device_bytes = idx->device_bytes;
+    out->caller_memory = idx->owns_mem ? 0u : 1u;
     return FM_OK;
 }
 
@@ -381,11 +451,7 @@ void fm_index_free(fm_index *idx)
     if (!idx) return;
     DeviceGuard g(idx->device);
     release_events(idx);
-    for (int i = 0; i < kLayouts; ++i) {
-        if (idx->lay[i]) (void)hipFree(idx->lay[i]);
-        if (idx->rlay[i]) (void)hipFree(idx->rlay[i]);
-    }
-    if (idx->sa_samples) (void)hipFree(idx->sa_samples);
+    if (idx->mem && idx->owns_mem) (void)hipFree(idx->mem);
     delete idx;
 }
 

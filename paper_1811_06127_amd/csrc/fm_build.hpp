@@ -27,5 +27,7 @@ int bwt_stats(const uint8_t *bwt, uint64_t rows, uint64_t *dollar_row, uint64_t 
 int build_side(const uint8_t *text, uint64_t n, bool reverse, HostSide &out, bool want_samples = false);
 int write_index_file(const char *path, uint64_t n, const HostSide &fwd, const HostSide *rev);
 int read_index_file(const char *path, bool want_rev, uint64_t *n, HostSide &fwd, HostSide &rev, bool *has_rev);
+// n and whether a reverse index is present, from the header alone (checked as by read_index_file).
+int read_index_header(const char *path, uint64_t *n, bool *has_rev);
 
 }  // namespace fm

@@ -17,7 +17,9 @@ struct fm_index {
     uint64_t dollar = 0, rev_dollar = 0;
     uint64_t C[5] = {0, 0, 0, 0, 0}, rev_C[5] = {0, 0, 0, 0, 0};
     bool has_rev = false;
-    void *lay[7] = {};     // forward layouts for I = 64, 96, 128, 192, 224, 256, 448
+    void *mem = nullptr;   // one device block holding the layouts and SA samples
+    bool owns_mem = true;  // false: mem is the caller's dev_buf (never freed here)
+    void *lay[7] = {};     // forward layouts for I = 64, 96, 128, 192, 224, 256, 448 (inside mem)
     void *rlay[7] = {};    // layouts of reverse(R)
     uint64_t device_bytes = 0;
     uint32_t *sa_samples = nullptr;   // SA[32 j] for j = 0 .. n / 32 (fm_locate), or nullptr

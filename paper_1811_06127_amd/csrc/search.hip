@@ -591,12 +591,13 @@ struct Dfs {
         }
     }
 
-    // Pattern symbol i of the strand (complemented on strand 1).
+    // Pattern symbol i of the strand (complemented on strand 1). Every code above 3 is
+    // returned as 4: such a symbol matches no base, and the frames keep it in 4 bits.
     __device__ uint32_t sym(const DfsArgs &a) const
     {
         const uint32_t o = (uint32_t)((uintptr_t)code_ptr(a) & 15u);
         const uint32_t c = (sel4(o >> 2, win.x, win.y, win.z, win.w) >> (8 * (o & 3))) & 0xFFu;
-        return strand_sym(c, strand);
+        return strand_sym(c < 4u ? c : 4u, strand);
     }
 
     // Header of a new read-strand (offsets, budget, D record): loaded into registers of

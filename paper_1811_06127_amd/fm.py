@@ -36,14 +36,15 @@ class Interval(C.Structure):
 
 
 class LoadOpts(C.Structure):
-    _fields_ = [("device", C.c_int), ("occ_interval", C.c_uint32), ("flags", C.c_uint32)]
+    _fields_ = [("device", C.c_int), ("occ_interval", C.c_uint32), ("flags", C.c_uint32),
+                ("dev_buf", C.c_void_p), ("dev_buf_bytes", C.c_size_t)]
 
 
 class Info(C.Structure):
     _fields_ = [("n", C.c_uint64), ("dollar_row", C.c_uint64), ("C", C.c_uint64 * 5),
                 ("rev_dollar_row", C.c_uint64), ("rev_C", C.c_uint64 * 5), ("occ_interval", C.c_uint32),
                 ("layouts", C.c_uint32), ("has_reverse", C.c_uint32), ("sa_sample", C.c_uint32),
-                ("device_bytes", C.c_uint64)]
+                ("device_bytes", C.c_uint64), ("caller_memory", C.c_uint32), ("pad", C.c_uint32)]
 
 
 class Tuning(C.Structure):
@@ -97,6 +98,8 @@ def lib() -> C.CDLL:
         "fm_index_from_text": (i32, [vp, u64, C.POINTER(LoadOpts), C.POINTER(vp)]),
         "fm_index_from_codes": (i32, [vp, u64, vp, C.POINTER(LoadOpts), C.POINTER(vp)]),
         "fm_index_load": (i32, [C.c_char_p, C.POINTER(LoadOpts), C.POINTER(vp)]),
+        "fm_index_bytes": (i32, [u64, C.POINTER(LoadOpts), C.POINTER(C.c_size_t)]),
+        "fm_index_required_bytes": (i32, [C.c_char_p, C.POINTER(LoadOpts), C.POINTER(C.c_size_t)]),
         "fm_index_info": (i32, [vp, C.POINTER(Info)]),
         "fm_index_free": (None, [vp]),
         "fm_get_tuning": (i32, [vp, i32, C.POINTER(Tuning)]),
@@ -206,41 +209,65 @@ def fm_index_build_file(text: np.ndarray, path: str, flags: int = 0):
 
 # ---------------------------------------------------------------- index
 
-class Index:
-    """An FM-index resident in device memory (owner of an fm_index handle)."""
+def fm_index_bytes(n: int, occ_interval: int = 128, flags: int = 0) -> int:
+    """Device bytes an index over n symbols keeps when built with these options."""
+    b = C.c_size_t(0)
+    o = LoadOpts(0, occ_interval, flags, None, 0)
+    _check(lib().fm_index_bytes(n, C.byref(o), C.byref(b)), "fm_index_bytes")
+    return int(b.value)
 
-    def __init__(self, handle: int):
+
+def fm_index_required_bytes(path: str, occ_interval: int = 128, flags: int = 0) -> int:
+    """Device bytes Index.load(path, ...) keeps, from the file's header alone."""
+    b = C.c_size_t(0)
+    o = LoadOpts(0, occ_interval, flags, None, 0)
+    _check(lib().fm_index_required_bytes(path.encode(), C.byref(o), C.byref(b)), "fm_index_required_bytes")
+    return int(b.value)
+
+
+class Index:
+    """An FM-index resident in device memory (owner of an fm_index handle). With dev_buf
+    (a contiguous uint8 device tensor of at least fm_index_bytes / fm_index_required_bytes bytes) the
+    index keeps its layouts in that tensor, which this object holds on to until free()."""
+
+    def __init__(self, handle: int, dev_buf: torch.Tensor | None = None):
         self._h = C.c_void_p(handle)
+        self._buf = dev_buf
 
     @staticmethod
-    def _opts(device, occ_interval, flags):
-        return LoadOpts(device, occ_interval, flags)
+    def _opts(device, occ_interval, flags, dev_buf=None):
+        if dev_buf is None:
+            return LoadOpts(device, occ_interval, flags, None, 0)
+        _dev(dev_buf, torch.uint8, "dev_buf")
+        return LoadOpts(device, occ_interval, flags, _ptr(dev_buf), dev_buf.numel())
 
     @classmethod
-    def from_text(cls, text: np.ndarray, device: int = 0, occ_interval: int = 128, flags: int = 0) -> "Index":
+    def from_text(cls, text: np.ndarray, device: int = 0, occ_interval: int = 128, flags: int = 0,
+                  dev_buf: torch.Tensor | None = None) -> "Index":
         text = np.ascontiguousarray(text, dtype=np.uint8)
         h = C.c_void_p()
-        o = cls._opts(device, occ_interval, flags)
+        o = cls._opts(device, occ_interval, flags, dev_buf)
         _check(lib().fm_index_from_text(_ptr(text), text.size, C.byref(o), C.byref(h)), "fm_index_from_text")
-        return cls(h.value)
+        return cls(h.value, dev_buf)
 
     @classmethod
     def from_codes(cls, bwt: np.ndarray, rev_bwt: np.ndarray | None = None, device: int = 0,
-                   occ_interval: int = 128, flags: int = 0) -> "Index":
+                   occ_interval: int = 128, flags: int = 0, dev_buf: torch.Tensor | None = None) -> "Index":
         bwt = np.ascontiguousarray(bwt, dtype=np.uint8)
         rb = None if rev_bwt is None else np.ascontiguousarray(rev_bwt, dtype=np.uint8)
         h = C.c_void_p()
-        o = cls._opts(device, occ_interval, flags)
+        o = cls._opts(device, occ_interval, flags, dev_buf)
         _check(lib().fm_index_from_codes(_ptr(bwt), bwt.size, _ptr(rb), C.byref(o), C.byref(h)),
                "fm_index_from_codes")
-        return cls(h.value)
+        return cls(h.value, dev_buf)
 
     @classmethod
-    def load(cls, path: str, device: int = 0, occ_interval: int = 128, flags: int = 0) -> "Index":
+    def load(cls, path: str, device: int = 0, occ_interval: int = 128, flags: int = 0,
+             dev_buf: torch.Tensor | None = None) -> "Index":
         h = C.c_void_p()
-        o = cls._opts(device, occ_interval, flags)
+        o = cls._opts(device, occ_interval, flags, dev_buf)
         _check(lib().fm_index_load(path.encode(), C.byref(o), C.byref(h)), "fm_index_load")
-        return cls(h.value)
+        return cls(h.value, dev_buf)
 
     @property
     def handle(self) -> C.c_void_p:
@@ -253,7 +280,8 @@ class Index:
         _check(lib().fm_index_info(self.handle, C.byref(i)), "fm_index_info")
         return {"n": i.n, "dollar_row": i.dollar_row, "C": list(i.C), "rev_dollar_row": i.rev_dollar_row,
                 "rev_C": list(i.rev_C), "occ_interval": i.occ_interval, "layouts": i.layouts,
-                "has_reverse": bool(i.has_reverse), "sa_sample": i.sa_sample, "device_bytes": i.device_bytes}
+                "has_reverse": bool(i.has_reverse), "sa_sample": i.sa_sample, "device_bytes": i.device_bytes,
+                "caller_memory": bool(i.caller_memory)}
 
     def get_tuning(self, op: int) -> dict:
         t = Tuning()
@@ -279,6 +307,7 @@ class Index:
         if self._h:
             lib().fm_index_free(self._h)
             self._h = C.c_void_p()
+        self._buf = None
 
     def __del__(self):
         try:

@@ -490,3 +490,38 @@ def test_determinism_and_batch_independence(small):
         ha = a[0][int(a[1][r]):int(a[1][r + 1])]
         hc = c[0][int(c[1][j]):int(c[1][j + 1])]
         assert np.array_equal(ha[["k", "l", "strand", "nmm"]], hc[["k", "l", "strand", "nmm"]])
+
+
+def test_non_base_codes_above_4(small):
+    """Any read code above 3 matches no base (fm.h): reads holding codes 5, 16, 78 and 255
+    give the oracle's hits (which treats every such code alike) and the same results as
+    with code 4 in their place, for substitutions and the gapped search, plain and batched,
+    with subtree transfers on (one lane per read-strand, z = 2)."""
+    R, x, xr, idx = small
+    rd = synth.simulate_reads(R, 800, 57, length=(40, 100), sub=(0.0, 0.03), z=(0, 2))
+    odd = rd.codes.copy()
+    pos = np.arange(5, odd.size, 61)
+    odd[pos] = np.resize(np.array([5, 16, 78, 255], np.uint8), pos.size)
+    n4 = odd.copy()
+    n4[pos] = 4
+    cases = ((fm.FM_BOTH | fm.FM_DARRAY, "listing2_darray"), (fm.FM_BOTH, "listing2"),
+             (fm.FM_BOTH | fm.FM_DARRAY | fm.FM_GAPS, "listing2_gaps_darray"))
+    for flags, method in cases:
+        wh, wo = x.inexact(odd, rd.offs, rd.z, oracle.BOTH, method, rev=xr)
+        w4 = x.inexact(n4, rd.offs, rd.z, oracle.BOTH, method, rev=xr)
+        assert np.array_equal(wo, w4[1]) and np.array_equal(wh, w4[0])
+        assert_same_hits(run_inexact(idx, odd, rd.offs, rd.z, flags | fm.FM_PLAIN, 2)[0], wh, wo, ("plain", flags))
+        for lanes in (1, 2):
+            idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=64, lanes=lanes)
+            try:
+                got = run_inexact(idx, odd, rd.offs, rd.z, flags, 2)[0]
+            finally:
+                idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=128, lanes=1)
+            assert_same_hits(got, wh, wo, (flags, lanes))
+    want_ex = x.exact(n4, rd.offs, oracle.BOTH, "listing1")
+    cd, od, zd = fm.reads_to_device(odd, rd.offs, rd.z)
+    assert np.array_equal(to_u32(fm.fm_search_exact(idx, cd, od, fm.FM_BOTH)), want_ex)
+    ex, bufs = fm.fm_search_both(idx, cd, od, zd, fm.FM_BOTH, fm.FM_BOTH | fm.FM_DARRAY, 2, 1 << 16)
+    assert np.array_equal(to_u32(ex), want_ex)
+    wh, wo = x.inexact(odd, rd.offs, rd.z, oracle.BOTH, "listing2_darray", rev=xr)
+    assert_same_hits(fm.hits_to_numpy(bufs, rd.count), wh, wo, "both")

@@ -53,7 +53,7 @@ def test_header_is_plain_c(tmp_path):
 def test_strerror_and_version():
     assert fm.strerror(fm.FM_OK) == "ok"
     assert fm.strerror(fm.FM_EOVERFLOW) == "hit capacity exceeded"
-    assert fm.lib().fm_version() == 1
+    assert fm.lib().fm_version() == 2
 
 
 def read_golden(name):
@@ -120,7 +120,7 @@ def test_index_file_roundtrip_header(tmp_path):
     p = str(tmp_path / "x.fmi")
     fm.fm_index_build_file(R, p, fm.FM_LOAD_REVERSE)
     raw = open(p, "rb").read()
-    assert raw[:8] == b"FMOCC001"
+    assert raw[:8] == b"FMOCC002"
     hdr = np.frombuffer(raw[8:8 + 8 * 16], np.uint64)
     x = oracle.OracleIndex(R)
     assert hdr[0] == 5000 and hdr[2] == x.dollar_row
@@ -128,3 +128,130 @@ def test_index_file_roundtrip_header(tmp_path):
     words = int(hdr[14])
     assert words == (5001 + 15) // 16
     assert len(raw) == 8 + 8 * 16 + 2 * 4 * words
+
+
+HEADER = 8 + 16 * 8       # magic, then n, flags, dollar, C[5], rev_dollar, rev_C[5], words, checksum
+
+
+def fnv1a(data: bytes, h: int = 0xcbf29ce484222325) -> int:
+    for b in data:
+        h = ((h ^ b) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def with_checksum(raw: bytearray) -> bytearray:
+    """The file's checksum recomputed (FNV-1a over the header with a zero checksum field,
+    then the body), so that a test can change a header field and still pass the checksum."""
+    z = bytearray(raw)
+    z[HEADER - 8:HEADER] = bytes(8)
+    raw[HEADER - 8:HEADER] = np.uint64(fnv1a(bytes(z))).tobytes()
+    return raw
+
+
+def load_status(path, flags=0):
+    try:
+        idx = fm.Index.load(path, flags=flags)
+    except fm.FmError as e:
+        return e.status
+    idx.free()
+    return fm.FM_OK
+
+
+def test_index_file_damage_is_rejected_before_device_work(tmp_path):
+    """fm_index_load checks the file on the host: a missing file is FM_EIO; a bad magic, a
+    truncated or extended body, a flipped body or header byte (checksum), and a C or '$'
+    row that disagrees with the packed words (checksum recomputed) are FM_EFORMAT; asking a
+    file without a reverse index for one is FM_EINVAL. None of them reaches the device."""
+    R = synth.reference_with_repeats(9000, 31, copy_frac=0.1, copy_len=(100, 500))
+    good = str(tmp_path / "good.fmi")
+    fm.fm_index_build_file(R, good, fm.FM_LOAD_REVERSE)
+    raw = bytearray(open(good, "rb").read())
+    x = oracle.OracleIndex(R)
+    hdr = np.frombuffer(bytes(raw[8:HEADER]), np.uint64)
+    assert hdr[2] == x.dollar_row and hdr[3:8].tolist() == x.C.tolist()
+    assert bytes(with_checksum(bytearray(raw))) == bytes(raw)      # the test's checksum is the file's
+
+    def status_of(data, name, flags=fm.FM_LOAD_REVERSE):
+        p = str(tmp_path / name)
+        open(p, "wb").write(bytes(data))
+        return load_status(p, flags)
+
+    assert load_status(str(tmp_path / "absent.fmi")) == fm.FM_EIO
+    bad = bytearray(raw)
+    bad[:8] = b"FMOCC001"
+    assert status_of(bad, "magic") == fm.FM_EFORMAT
+    assert status_of(raw[:-4], "short") == fm.FM_EFORMAT
+    assert status_of(raw[:HEADER - 3], "header_only") == fm.FM_EFORMAT
+    assert status_of(raw + b"\0", "long") == fm.FM_EFORMAT
+    for off in (HEADER + 17, len(raw) - 1, HEADER + (len(raw) - HEADER) // 2):
+        bad = bytearray(raw)
+        bad[off] ^= 0x10
+        assert status_of(bad, "body%d" % off) == fm.FM_EFORMAT, off
+    for field in (2, 4, 9, 12):                      # dollar, C[1], rev_dollar, rev_C[3]
+        bad = bytearray(raw)
+        bad[8 + 8 * field] ^= 0x01
+        assert status_of(bad, "hdr%d" % field) == fm.FM_EFORMAT, field
+    # header fields changed consistently with the checksum: caught by the recount of the words
+    bad = bytearray(raw)
+    C = hdr[3:8].copy()
+    C[1] += 1
+    C[2] -= 1 if C[2] > C[1] else 0
+    bad[8 + 3 * 8:8 + 8 * 8] = C.tobytes()
+    assert status_of(with_checksum(bad), "recount_C") == fm.FM_EFORMAT
+    bwt = x.bwt
+    other = int(np.nonzero(bwt != 0)[0][3])           # a row whose BWT symbol is not A
+    bad = bytearray(raw)
+    bad[8 + 2 * 8:8 + 3 * 8] = np.uint64(other).tobytes()
+    assert status_of(with_checksum(bad), "recount_dollar") == fm.FM_EFORMAT
+    bad = bytearray(raw)
+    bad[8 + 8:8 + 16] = np.uint64(7).tobytes()       # unknown flags
+    assert status_of(with_checksum(bad), "flags") == fm.FM_EFORMAT
+    fwd_only = str(tmp_path / "fwd.fmi")
+    fm.fm_index_build_file(R, fwd_only, 0)
+    assert load_status(fwd_only, fm.FM_LOAD_REVERSE) == fm.FM_EINVAL
+    import torch
+    if not torch.cuda.is_available():
+        # the intact file passes every check and fails only for want of a device
+        assert load_status(good, fm.FM_LOAD_REVERSE) == fm.FM_EDEVICE
+        assert load_status(fwd_only) == fm.FM_EDEVICE
+
+
+def layout_bytes(n, I):
+    nb = n // I + 1
+    bb = 32 if I <= 96 else (64 if I <= 224 else 128)
+    extra = ((nb + (682 if I == 96 else 292) - 1) // (682 if I == 96 else 292)) * 16 if I in (96, 224) else 0
+    return nb * bb + extra
+
+
+def test_index_bytes_and_required_bytes(tmp_path):
+    """fm_index_bytes adds up the layouts kept (the one asked for, or all seven; both
+    directions with FM_LOAD_REVERSE) and the SA samples (4 bytes per 32 rows), each piece
+    256-byte aligned; fm_index_required_bytes gives the same from a file's header."""
+    a = lambda x: (x + 255) // 256 * 256
+    for n in (0, 1, 1000, 70_001, 3_100_000_000):
+        for I in (64, 96, 128, 192, 224, 256, 448):
+            assert fm.fm_index_bytes(n, I) == a(layout_bytes(n, I))
+            assert fm.fm_index_bytes(n, I, fm.FM_LOAD_REVERSE) == 2 * a(layout_bytes(n, I))
+        every = sum(a(layout_bytes(n, I)) for I in (64, 96, 128, 192, 224, 256, 448))
+        assert fm.fm_index_bytes(n, 128, fm.FM_LOAD_ALL_LAYOUTS | fm.FM_LOAD_REVERSE) == 2 * every
+        assert fm.fm_index_bytes(n, 64, fm.FM_LOAD_LOCATE) == a(layout_bytes(n, 64)) + a((n + 1 + 31) // 32 * 4)
+    with pytest.raises(fm.FmError):
+        fm.fm_index_bytes(1000, 100)
+    with pytest.raises(fm.FmError):
+        fm.fm_index_bytes(1 << 32, 64)
+    R = synth.iid_reference(12_345, 5)
+    p = str(tmp_path / "r.fmi")
+    fm.fm_index_build_file(R, p, fm.FM_LOAD_REVERSE)
+    for I in (64, 128, 448):
+        for fl in (0, fm.FM_LOAD_REVERSE, fm.FM_LOAD_ALL_LAYOUTS):
+            assert fm.fm_index_required_bytes(p, I, fl) == fm.fm_index_bytes(R.size, I, fl)
+        # SA samples are never in a file
+        assert fm.fm_index_required_bytes(p, I, fm.FM_LOAD_LOCATE) == fm.fm_index_bytes(R.size, I)
+    q = str(tmp_path / "f.fmi")
+    fm.fm_index_build_file(R, q, 0)
+    with pytest.raises(fm.FmError) as e:
+        fm.fm_index_required_bytes(q, 64, fm.FM_LOAD_REVERSE)
+    assert e.value.status == fm.FM_EINVAL
+    with pytest.raises(fm.FmError) as e:
+        fm.fm_index_required_bytes(str(tmp_path / "absent"), 64)
+    assert e.value.status == fm.FM_EIO
