@@ -329,6 +329,25 @@ int fm_search_inexact(const fm_index *idx, const uint8_t *codes, const uint64_t 
                       fm_hit *hits, uint64_t hit_cap, uint64_t *hit_offs, uint32_t *status,
                       void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): fm_search_inexact with its workspace in
+ * a static device array of FM_NOALLOC_WS_BYTES bytes that the library keeps on each device
+ * it runs on until the process ends, so the call takes no ws argument and allocates
+ * nothing. Arguments, results and errors are fm_search_inexact's, except: FM_ERANGE when
+ * the batch's workspace (fm_search_inexact_workspace) exceeds FM_NOALLOC_WS_BYTES (about
+ * 140 bytes per read-strand plus 16 per read and 16 per hit_cap entry); FM_EINVAL with
+ * FM_STATS (the counts would stay in the array). required (nullable, device, one uint64)
+ * receives the total hit count every read would need, as fm_search_inexact leaves it at
+ * byte offset 8 of ws. Every call on a device uses that device's one array, which keeps
+ * the last call's contents (each call clears what it needs), so calls that overlap on one
+ * device -- on different streams, or from different host threads -- race and must not be
+ * made; calls on one stream are ordered and safe. */
+#define FM_NOALLOC_WS_BYTES (64u << 20)
+int fm_search_inexact_noalloc(const fm_index *idx, const uint8_t *codes, const uint64_t *offs,
+                              const uint8_t *z, uint64_t nreads, uint32_t flags, uint32_t zmax,
+                              fm_hit *hits, uint64_t hit_cap, uint64_t *hit_offs, uint32_t *status,
+                              uint64_t *required, void *stream);
+
 /* Both searches of one batch: exactly the results of fm_search_exact(codes, offs, nreads,
  * exact_flags, intervals) and of fm_search_inexact(codes, offs, z, nreads, flags, zmax,
  * hits, hit_cap, hit_offs, status, ws, ws_bytes), bit for bit. When every strand of

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfmocc.so")
-SOURCES = ["sa_build.hip", "layout.hip", "search.hip", "capi.cpp", "build.cpp", "runtime.cpp", "server.cpp"]
+SOURCES = ["sa_build.hip", "layout.hip", "search.hip", "capi.cpp", "build.cpp", "runtime.cpp", "server.cpp",
+           "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

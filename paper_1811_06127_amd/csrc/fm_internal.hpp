@@ -40,6 +40,8 @@ constexpr uint32_t kHitSlots = 4;      // hits stored per read-strand without an
 constexpr uint32_t kOrderBins = 256;   // weight classes of the DFS claim order
 constexpr uint32_t kOrderBlocks = 1024; // workgroups that count and place the claim order
 
+inline uint32_t nstrands_of(uint32_t flags) { return ((flags & FM_FWD) ? 1u : 0u) + ((flags & FM_REVCOMP) ? 1u : 0u); }
+
 constexpr int kLayouts = 7;
 constexpr uint32_t kIntervals[kLayouts] = {64, 96, 128, 192, 224, 256, 448};
 // slot of a checkpoint interval in the index's layout arrays, -1 when unsupported

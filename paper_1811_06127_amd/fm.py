@@ -118,6 +118,7 @@ def lib() -> C.CDLL:
         "fm_phase_timing": (i32, [vp, u32]),
         "fm_phase_times": (i32, [vp, C.POINTER(C.c_float), C.POINTER(C.c_uint32)]),
         "fm_plan_free": (None, [vp]),
+        "fm_search_inexact_noalloc": (i32, [vp, vp, vp, vp, u64, u32, u32, vp, u64, vp, vp, vp, vp]),
         "fm_search_both": (i32, [vp, vp, vp, vp, u64, u32, u32, u32, vp, vp, u64, vp, vp, vp, C.c_size_t, vp]),
         "fm_locate_workspace": (i32, [vp, u64, C.POINTER(C.c_size_t)]),
         "fm_locate": (i32, [vp, vp, u64, u32, vp, vp, u64, u32, vp, C.c_size_t, vp]),
@@ -411,6 +412,29 @@ def fm_search_inexact(idx: Index, codes: torch.Tensor, offs: torch.Tensor, z: to
                                    _ptr(bufs.hits), bufs.hit_cap, _ptr(bufs.hit_offs), _ptr(bufs.status),
                                    _ptr(bufs.ws), bufs.ws.numel(), _stream(stream)), "fm_search_inexact")
     return bufs
+
+
+FM_NOALLOC_WS_BYTES = 64 << 20
+
+
+def fm_search_inexact_noalloc(idx: Index, codes: torch.Tensor, offs: torch.Tensor, z: torch.Tensor, flags: int,
+                              zmax: int, hits: torch.Tensor, hit_offs: torch.Tensor, status: torch.Tensor,
+                              required: torch.Tensor | None = None, stream=None):
+    """fm_search_inexact_noalloc: the inexact search with the library's static per-device
+    workspace. The caller passes the outputs: hits (hit_cap, 4) int32, hit_offs (nreads+1)
+    int64, status (>= nreads) int32, and optionally required (1) int64."""
+    _dev(codes, torch.uint8, "codes")
+    _dev(offs, torch.int64, "offs")
+    _dev(z, torch.uint8, "z")
+    _dev(hits, torch.int32, "hits")
+    _dev(hit_offs, torch.int64, "hit_offs")
+    _dev(status, torch.int32, "status")
+    if required is not None:
+        _dev(required, torch.int64, "required")
+    nreads = offs.numel() - 1
+    _check(lib().fm_search_inexact_noalloc(idx.handle, _ptr(codes), _ptr(offs), _ptr(z), nreads, flags, zmax,
+                                           _ptr(hits), hits.shape[0], _ptr(hit_offs), _ptr(status), _ptr(required),
+                                           _stream(stream)), "fm_search_inexact_noalloc")
 
 
 def fm_search_both(idx: Index, codes: torch.Tensor, offs: torch.Tensor, z: torch.Tensor, exact_flags: int,
