@@ -1,15 +1,20 @@
 #!/usr/bin/env python3
 """Throughput of the FM-index hot path on one MI355X.
 
-Workload (one step): a 2^24-base reference (95% i.i.d. bases plus 500-5,000 bp copies
-with 2% substitutions), 1,000,000 reads of 100 bp sampled from either strand with 1%
-substitutions; the exact backward search of every read on both strands, then the
-z=1 substitution search on both strands pruned by the D lower bound. Inputs are
-resident in device memory before timing starts; the index is built once, untimed.
+Headline workload: batching at genome scale. A 3.1e9-base reference (55% i.i.d. bases,
+45% copies of 500 repeat families with 5-15% divergence) and 16M reads of 150 bp from
+either strand with 1% substitutions, all resident in device memory; every read gets the
+exact backward search (Listing 1) and the z=2 substitution search (Listing 2) on both
+strands, pruned by the D lower bound, in one pass, in batches of 1M reads, each replayed
+from a launch graph captured for it. A step is one batch. The index is built once,
+untimed (suffixes sorted on the device).
 
 Prints one JSON line: reads/s of the batched persistent kernels (value), the plain
-one-thread-per-read-strand kernels on the same step, Occ8 rates, the roofline of the
-dominant kernel and the CPU oracle's rate on a bounded sample of the same workload.
+one-thread-per-read-strand kernels on the same batch, the roofline of the dominant kernel
+(the DFS) with its duration measured by the graphs' own events on every timed replay,
+and the oracle's rate on a sample of the same reads. Further keys hold the other
+workloads: the 2^24 step, the small exact workload, the mixed-budget batch and serving
+on the 2^28 index, Occ8 micro-benchmarks, locate, the gapped and full-rank searches.
 """
 from __future__ import annotations
 
@@ -127,8 +132,19 @@ def locate_rate(fm, torch, idx, hits, nh: int, reps: int = 3) -> dict:
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=16,
+                    help="timed steps of the headline; a step is one batch of 1M reads, cycling through the batches")
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="run the genome-scale headline alone (no 2^24 step, small workload or serving legs)")
+    ap.add_argument("--genome-cpu-sample", type=int, default=2000,
+                    help="reads of the genome-scale workload the oracle's text-only checkers search")
+    ap.add_argument("--genome-trace-reads", type=int, default=10_000,
+                    help="reads whose search trace is replayed as independent Occ8 queries at genome scale")
+    ap.add_argument("--batch-reads", type=int, default=4_000_000,
+                    help="reads of the mixed-budget batch on the 2^28-base index")
+    ap.add_argument("--tune-sample", type=int, default=250_000,
+                    help="reads of the mixed-budget batch the autotuner times")
     ap.add_argument("--reads", type=int, default=1_000_000)
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--occ8-queries", type=int, default=1 << 26)
@@ -144,7 +160,7 @@ def parse():
     ap.add_argument("--serve-lanes", type=int, default=3)
     ap.add_argument("--serve-pool", type=int, default=2_000_000, help="reads the requests are drawn from")
     ap.add_argument("--genome-batches", type=int, default=16,
-                    help="batches of 1M reads in the genome-scale run on the 3.1e9-base index (0 skips it)")
+                    help="batches of 1M reads in the genome-scale run on the 3.1e9-base index")
     ap.add_argument("--pcie-two-streams", action="store_true",
                     help="also time the step end to end on two streams, copies overlapping the other batch's search")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -153,30 +169,18 @@ def parse():
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the search shards by replicating the index and splitting the "
-              "reads, and this build runs and reports the single-GPU share only (--gpus 1).", file=sys.stderr)
-        sys.exit(2)
-
+def step_2e24(args):
+    """The 2^24 step: a 2^24-base reference (95% i.i.d. bases plus 500-5,000 bp copies with 2%
+    substitutions), 1,000,000 reads of 100 bp sampled from either strand with 1%
+    substitutions; the exact backward search of every read on both strands and the z=1
+    substitution search on both strands pruned by the D lower bound, in one pass
+    (fm_search_both). Its 8.4 MB index lives in the caches, not HBM."""
     import torch
 
     import synth
     from paper_1811_06127_amd import fm
 
-    torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-    if args.copy_calibration:
-        n = args.copy_calibration << 20
-        src = torch.ones(n, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        torch.add(src, 1, out=dst)           # one elementwise kernel: n bytes in, n bytes out
-        torch.cuda.synchronize()
-        log("copy calibration: %d bytes read, %d bytes written" % (n, n))
-        del src, dst
     t0 = time.time()
     R = synth.repeats_2e24_reference()
     rd = synth.reads_2e24(R, args.reads)
@@ -266,6 +270,8 @@ def main():
     # Listing 2 with all its branches (z=1 edits) on the same reads
     gap = gapped_rate(fm, torch, idx, codes, offs, z, nreads, total_len, args)
     log("gapped:", gap)
+    gap["z2"] = gapped_z2_rate(fm, torch, idx, rd, args)
+    log("gapped z=2:", gap["z2"])
     frank = full_rank_rate(fm, torch, idx, codes, offs, nreads, ex_ws, args)
     log("full rank:", frank)
     layouts = layout_rates(fm, torch, idx, step, ex_out, bufs, nreads, (ex_batched, in_batched))
@@ -442,7 +448,7 @@ def main():
              "walk_batched<%d, %d, %d, 1>" % (tcfg["occ_interval"], tcfg["lanes"], tcfg["depth"]))
     key = (kernel_source_hash(), kname, tuple(tcfg[f] for f in TRAFFIC_KEY_FIELDS), "2^24")
     traffic = MEASURED_TRAFFIC.get(key)
-    roofline = {"bound": "hbm", "kernel": kname,
+    roofline = {"bound": residency_bound(idx.info()["device_bytes"]), "kernel": kname,
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": int(sum(traffic)) if traffic else None,
@@ -455,38 +461,20 @@ def main():
     if args.cpu_sample > 0:
         cpu, parity = cpu_baseline(R, rd, min(args.cpu_sample, nreads), ex_batched, in_batched, args.cpu_threads)
 
-    serve = genome = None
-    if args.serve_requests > 0:
-        serve = serve_bench(args)
-        torch.cuda.empty_cache()
     ovl = two_stream_e2e() if args.pcie_two_streams else None
     del h_in
-    if args.genome_batches > 0:
-        del codes, offs, z, ex_out, ex_ws, bufs
-        idx.free()
-        torch.cuda.empty_cache()
-    if args.genome_batches > 0:
-        genome = genome_bench(args)
-
+    index_bytes = idx.info()["device_bytes"]
+    del codes, offs, z, ex_out, ex_ws, bufs
+    idx.free()
+    torch.cuda.empty_cache()
     reads_s = nreads / (ms_step / 1e3)
     out = {
-        "metric": METRIC,
-        "value": round(reads_s, 1),
-        "unit": "reads/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "workload": "2^24-base reference with 5% copies (2% divergence); 1M reads x 100 bp, 1% substitutions, "
+                    "either strand; exact + z=1 substitution search, both strands, D-array pruning",
+        "n": int(R.size), "reads": nreads, "read_len": 100, "z": ZMAX, "strands": 2, "hit_cap": hit_cap,
+        "index_bytes_all_layouts": int(index_bytes),
+        "reads_per_s": round(reads_s, 1),
         "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic (seeded SplitMix64 reference and reads)",
-        "config": {"workload": "2^24-base reference with 5% copies (2% divergence); 1M reads x 100 bp, 1% "
-                               "substitutions, either strand; exact + z=1 substitution search, both strands, "
-                               "D-array pruning",
-                   "n": int(R.size), "reads": nreads, "read_len": 100, "z": ZMAX, "strands": 2,
-                   "hit_cap": hit_cap},
         "plain_reads_per_s": round(nreads / (plain_ms / 1e3), 1) if plain_ms else None,
         "batched_vs_plain": round(plain_ms / ms_step, 3) if plain_ms else None,
         "batched_equals_plain": plain_equal,
@@ -515,92 +503,241 @@ def main():
         "parity_sample": parity,
         "locate": loc,
         "gapped": gap,
-        "serving": serve,
-        "genome_scale": genome,
-        "p99_latency_ms": serve["p99_ms"] if serve else None,
+    }
+    log("2^24 step:", {k: out[k] for k in ("reads_per_s", "ms_per_step", "batched_vs_plain", "roofline")})
+    return out
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the search shards by replicating the index and splitting the "
+              "reads, and this build runs and reports the single-GPU share only (--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.add(src, 1, out=dst)           # one elementwise kernel: n bytes in, n bytes out
+        torch.cuda.synchronize()
+        log("copy calibration: %d bytes read, %d bytes written" % (n, n))
+        del src, dst
+
+    head = genome_headline(args)
+    extra = dict(head["extra"])
+    extra["parity_sample"] = head["parity_sample"]
+    if not args.headline_only:
+        extra["small_exact"] = small_exact(args)
+        extra["step_2e24"] = step_2e24(args)
+        torch.cuda.empty_cache()
+        if args.serve_requests > 0:
+            extra["serving"] = serve_bench(args)
+            extra["p99_latency_ms"] = extra["serving"]["p99_ms"]
+            torch.cuda.empty_cache()
+    out = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "reads/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded SplitMix64 reference and reads)",
+        "config": head["config"],
+        "roofline": head["roofline"],
+        "cpu_baseline": head["cpu_baseline"],
+        **extra,
     }
     print(json.dumps(out), flush=True)
 
 
-def genome_bench(args):
-    """Batching at genome scale: the 3.1e9-base text (55% i.i.d., 45% copies of 500 repeat
-    families with 5-15% divergence), reads of 150 bp with 1% substitutions, z=2 with the D
-    bound on both strands, in batches of 1M replayed from one launch graph captured for the
-    batch shape. Each batch's reads are copied into the captured buffers before its replay;
-    the timed region is the replays."""
+def genome_headline(args):
+    """The headline: batching at genome scale. A 3.1e9-base text (55% i.i.d., 45% copies
+    of 500 repeat families with 5-15% divergence) and 16M reads of 150 bp with 1%
+    substitutions, all resident in device memory; z=2 with the D bound on both strands,
+    in batches of 1M reads, each replayed from a launch graph captured for it (one per
+    batch, outputs per batch). A step is one batch; steps cycle through the batches.
+    The graphs record phase events of their own, so the DFS kernel's duration is measured
+    on every replay of the timed region."""
     import torch
 
     import synth
     from paper_1811_06127_amd import fm
 
     B, LEN, Z = 1_000_000, 150, 2
+    NB = args.genome_batches
     flags = fm.FM_BOTH | fm.FM_DARRAY
+    cap = 16 * B
     t0 = time.time()
     R = synth.genome_like_reference()
+    t1 = time.time()
     idx = fm.Index.from_text(R, occ_interval=64,
                              flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_DEVICE_SORT | fm.FM_LOAD_LOCATE)
-    build_s = time.time() - t0
-    rd = synth.genome_reads(R, args.genome_batches * B)
-    log("genome-scale inputs in %.1fs (index %.1fs, suffixes sorted on the device)" % (time.time() - t0, build_s))
-    first = rd.subset(np.arange(B))
-    codes, offs, z = fm.reads_to_device(first.codes, first.offs, first.z)
-    ex_out = torch.empty((2 * B, 2), dtype=torch.int32, device="cuda")
-    bufs = fm.InexactBuffers(idx, B, B * LEN, flags | fm.FM_PLAIN, Z, 16 * B, "cuda")
+    build_s = time.time() - t1
+    rd = synth.genome_reads(R, NB * B)
+    assert (np.diff(rd.offs) == LEN).all()
+    log("genome-scale inputs in %.1fs (index %.1fs, suffixes sorted on the device): %s" % (
+        time.time() - t0, build_s, idx.info()))
+    codes_all = torch.from_numpy(rd.codes).cuda()
+    z_all = torch.from_numpy(rd.z).cuda()
+    offs = torch.from_numpy(rd.offs[:B + 1].view(np.int64)).cuda()      # every batch has the same offsets
+    batches = []
+    for b in range(NB):
+        codes = codes_all[b * B * LEN:(b + 1) * B * LEN]
+        z = z_all[b * B:(b + 1) * B]
+        ex = torch.empty((2 * B, 2), dtype=torch.int32, device="cuda")
+        bufs = fm.InexactBuffers(idx, B, B * LEN, flags, Z, cap, "cuda")
+        batches.append((codes, z, ex, bufs))
     # the index's default launch settings: at this scale the tuner's choice varies between runs
     # within timing noise, and fixed settings keep runs and their profiles comparable
     tuning = {"inexact": idx.get_tuning(fm.FM_OP_INEXACT), "d_walk": idx.get_tuning(fm.FM_OP_DARRAY)}
 
-    def call(extra=0):
-        fm.fm_search_both(idx, codes, offs, z, fm.FM_BOTH, flags | extra, Z, 16 * B, out=ex_out, bufs=bufs)
-
-    # work counters and kernel phases of the first batch (eager calls)
-    call(fm.FM_STATS)
+    # eager calls with work counters: nodes, buckets and hits per batch, and each batch's outputs
+    work = {"occ8": 0, "buckets": 0, "walk_steps": 0, "walk_buckets": 0, "subtrees": 0}
+    hits_per_batch, eager = [], []
+    for codes, z, ex, bufs in batches:
+        fm.fm_search_both(idx, codes, offs, z, fm.FM_BOTH, flags | fm.FM_STATS, Z, cap, out=ex, bufs=bufs)
+        torch.cuda.synchronize()
+        st = bufs.stats()
+        for k in work:
+            work[k] += st[k]
+        n = int(bufs.hit_offs[-1].item())
+        hits_per_batch.append(n)
+        eager.append((ex.clone(), bufs.hit_offs.clone(), bufs.status[:B].clone(), bufs.hits[:n].clone()))
+    all_ok = all(bool((e[2] == fm.FM_OK).all()) for e in eager)
+    # the plain one-thread-per-read-strand kernels on the first batch
+    codes, z, ex, bufs = batches[0]
+    pex = torch.empty_like(ex)
+    pbufs = fm.InexactBuffers(idx, B, B * LEN, flags | fm.FM_PLAIN, Z, cap, "cuda")
     torch.cuda.synchronize()
-    st = bufs.stats()
-    call()
-    idx.phase_timing(3)
-    for _ in range(3):
-        call()
-    torch.cuda.synchronize()
-    ph, _ = idx.phase_times()
-    idx.phase_timing(0)
-    phase = {"d_walk": ph["d_walk"] / 3, "dfs": ph["dfs"] / 3, "compaction": ph["compaction"] / 3}
-    eager = (ex_out.clone(), fm.hits_to_numpy(bufs, B))
     t = time.time()
-    call(fm.FM_PLAIN)
+    fm.fm_search_both(idx, codes, offs, z, fm.FM_BOTH, flags | fm.FM_PLAIN, Z, cap, out=pex, bufs=pbufs)
     torch.cuda.synchronize()
     plain_s = time.time() - t
-    plain_equal = bool(torch.equal(ex_out, eager[0])) and all(
-        np.array_equal(a, b) for a, b in zip(fm.hits_to_numpy(bufs, B), eager[1]))
+    n0 = hits_per_batch[0]
+    plain_equal = bool(torch.equal(pex, eager[0][0]) and torch.equal(pbufs.hit_offs, eager[0][1])
+                       and torch.equal(pbufs.status[:B], eager[0][2]) and torch.equal(pbufs.hits[:n0], eager[0][3]))
+    del pex, pbufs
+    log("genome scale: eager pass with counters done; plain kernels %.1f ms, identical: %s" % (
+        plain_s * 1e3, plain_equal))
 
-    plan = fm.Plan.both(idx, codes, offs, z, fm.FM_BOTH, flags, Z, ex_out, bufs)
+    # one graph per batch, captured while phase timing is on so that every replay records
+    # the boundaries of its D walk, DFS and compaction on the replay stream
+    idx.phase_timing(1)
+    try:
+        plans = [fm.Plan.both(idx, codes, offs, z, fm.FM_BOTH, flags, Z, ex, bufs) for codes, z, ex, bufs in batches]
+        timed_events = True
+    except fm.FmError as e:
+        log("graphs with phase events could not be captured (%s); capturing them without" % e)
+        idx.phase_timing(0)
+        plans = [fm.Plan.both(idx, codes, offs, z, fm.FM_BOTH, flags, Z, ex, bufs) for codes, z, ex, bufs in batches]
+        timed_events = False
+    idx.phase_timing(0)
+    phase_sum = {"d_walk": 0.0, "dfs": 0.0, "compaction": 0.0}
+    phase_n = 0
+
+    def collect(b):
+        nonlocal phase_n, timed_events
+        if not timed_events:
+            return
+        try:
+            ph = plans[b].phase_times()
+        except fm.FmError as e:
+            log("phase events of the replays could not be read (%s)" % e)
+            timed_events = False
+            return
+        for k in phase_sum:
+            phase_sum[k] += ph[k]
+        phase_n += 1
+
+    for s in range(args.warmup):
+        plans[s % NB].launch()
+    torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ms = 0.0
-    hits = 0
-    replay_equal = True
-    for b in range(args.genome_batches):
-        codes.copy_(torch.from_numpy(rd.codes[b * B * LEN:(b + 1) * B * LEN]))
-        z.copy_(torch.from_numpy(rd.z[b * B:(b + 1) * B]))
+    K = args.steps
+    ev[0].record()
+    for s in range(K):
+        b = s % NB
+        if s >= NB:
+            collect(b)           # the replay NB steps back has been queued long before: no idle gap
+        plans[b].launch()
+    ev[1].record()
+    torch.cuda.synchronize()
+    total_ms = ev[0].elapsed_time(ev[1])
+    for s in range(max(0, K - NB), K):
+        collect(s % NB)
+    phase_source = "the graphs' own phase events on every timed replay"
+    if not timed_events or phase_n != K:
+        # the DFS duration from eager calls of the same batches with the index's phase events
+        phase_source = "eager calls of the same batches after the timed region (index phase events)"
+        idx.phase_timing(NB)
+        for codes, z, ex, bufs in batches:
+            fm.fm_search_both(idx, codes, offs, z, fm.FM_BOTH, flags, Z, cap, out=ex, bufs=bufs)
         torch.cuda.synchronize()
-        ev[0].record()
-        plan.launch()
-        ev[1].record()
-        torch.cuda.synchronize()
-        ms += ev[0].elapsed_time(ev[1])
-        h = fm.hits_to_numpy(bufs, B)
-        hits += int(h[1][-1])
-        if b == 0:
-            replay_equal = bool(torch.equal(ex_out, eager[0])) and all(np.array_equal(a, c) for a, c in zip(h, eager[1]))
-            gloc = locate_rate(fm, torch, idx, bufs.hits, int(h[1][-1]))
-    plan.free()
-    # the same index under independent random Occ8 queries: the rate of random bucket
-    # fetches the memory system sustains when nothing depends on a previous fetch
+        ph, _ = idx.phase_times()
+        idx.phase_timing(0)
+        phase_sum = {k: ph[k] / NB * K for k in phase_sum}
+    replay_equal = all(bool(torch.equal(ex, e[0]) and torch.equal(bufs.hit_offs, e[1])
+                            and torch.equal(bufs.status[:B], e[2]) and torch.equal(bufs.hits[:e[3].shape[0]], e[3]))
+                       for (codes, z, ex, bufs), e in zip(batches, eager))
+    ms_step = total_ms / K
+    phase = {k: v / K for k, v in phase_sum.items()}
+    log("genome scale: %d steps of 1M reads in %.1f ms (%.3f ms/step), phases %s, replays identical: %s" % (
+        K, total_ms, ms_step, phase, replay_equal))
+    for p in plans:
+        p.free()
+
+    # roofline of the DFS: algorithmic bytes per launch (its bucket fetches at 32 B, the
+    # patterns read twice, 32 B per read-strand of records, 16 B per hit), averaged over the
+    # batches, over its average duration in the timed region
+    nrs = 2 * B
+    alg = (work["buckets"] * 32 + NB * (2 * B * LEN + 32 * nrs) + 16 * sum(hits_per_batch)) / NB
+    achieved = alg / (phase["dfs"] / 1e3) / 1e9
+    tcfg = tuning["inexact"]
+    key = (kernel_source_hash(), dfs_kernel_name(tcfg, Z), tuple(tcfg[f] for f in TRAFFIC_KEY_FIELDS), "3.1e9")
+    traffic = MEASURED_TRAFFIC.get(key)
+    index_bytes = idx.info()["device_bytes"]
+    roofline = {"bound": residency_bound(index_bytes), "kernel": key[1], "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": int(sum(traffic)) if traffic else None,
+                "traffic_gb_per_s": round(sum(traffic) / (phase["dfs"] / 1e3) / 1e9, 1) if traffic else None,
+                "bytes_per_launch": int(alg), "avg_launch_ms": round(phase["dfs"], 3),
+                "kernel_source_hash": key[0], "index_bytes": int(index_bytes), "duration_from": phase_source}
+
+    # text positions of the first batch's hits (Eq. 4-5)
+    codes, z, ex, bufs = batches[0]
+    gloc = locate_rate(fm, torch, idx, bufs.hits, hits_per_batch[0])
+    # the same index under independent random Occ8 queries, and the search's own queries
     occ8 = {}
     nq = 1 << 26
     ex_cfg = idx.get_tuning(fm.FM_OP_EXACT)
-    for kind in ("uniform", "narrow"):
-        q = torch.from_numpy(synth.occ8_queries(R.size, nq, 4343, kind).view(np.int32)).cuda()
-        qo = torch.empty((nq, 8), dtype=torch.int32, device="cuda")
+    qsets = {"uniform": synth.occ8_queries(R.size, nq, 4343, "uniform"),
+             "narrow": synth.occ8_queries(R.size, nq, 4343, "narrow")}
+    trace_info = None
+    if args.occ8_queries:
+        tcount = min(B, max(1000, args.genome_trace_reads))
+        trace, (tc, to, tz, tlen) = search_trace(fm, torch, idx, rd, tcount, "cuda")
+        tb = fm.InexactBuffers(idx, tcount, tlen, flags, Z, 16 * tcount, "cuda")
+        fm.fm_search_inexact(idx, tc, to, tz, flags | fm.FM_STATS, Z, 16 * tcount, bufs=tb)
+        torch.cuda.synchronize()
+        trace_info = {"reads": tcount, "queries": int(trace.shape[0]),
+                      "equals_dfs_node_count": int(trace.shape[0]) == tb.stats()["occ8"]}
+        qsets["search_trace"] = trace
+        del tb, tc, to, tz
+    for kind, qh in qsets.items():
+        q = torch.from_numpy(qh.view(np.int32)).cuda()
+        qo = torch.empty((qh.shape[0], 8), dtype=torch.int32, device="cuda")
         for lanes in (1, 2):                       # the best of one and two lanes per query
             idx.set_tuning(fm.FM_OP_EXACT, lanes=lanes)
             fm.fm_occ8(idx, q, out=qo)
@@ -610,48 +747,118 @@ def genome_bench(args):
                 fm.fm_occ8(idx, q, out=qo)
             ev[1].record()
             torch.cuda.synchronize()
-            occ8[kind] = max(occ8.get(kind, 0.0), nq / (ev[0].elapsed_time(ev[1]) / 3 / 1e3))
+            occ8[kind] = max(occ8.get(kind, 0.0), qh.shape[0] / (ev[0].elapsed_time(ev[1]) / 3 / 1e3))
         del q, qo
     idx.set_tuning(fm.FM_OP_EXACT, **ex_cfg)
-    reads = args.genome_batches * B
-    nrs = 2 * B
-    alg = st["buckets"] * 32 + 2 * B * LEN + 32 * nrs + 16 * int(eager[1][1][-1])
-    achieved = alg / (phase["dfs"] / 1e3) / 1e9
-    tcfg = tuning["inexact"]
-    key = (kernel_source_hash(), dfs_kernel_name(tcfg, Z),
-           tuple(tcfg[f] for f in TRAFFIC_KEY_FIELDS), "3.1e9")
-    traffic = MEASURED_TRAFFIC.get(key)
-    out = {
-        "workload": "3.1e9-base reference (55%% i.i.d., 45%% copies of 500 families, 5-15%% divergence); %d batches of "
-                    "1M reads x 150 bp, 1%% substitutions, either strand; exact + z=2 substitution search, both "
-                    "strands, D bound; one launch graph replayed per batch" % args.genome_batches,
-        "reads": reads,
-        "reads_per_s": round(reads / (ms / 1e3), 1),
-        "ms_per_batch": round(ms / args.genome_batches, 3),
-        "plain_reads_per_s": round(B / plain_s, 1),
-        "batched_vs_plain": round(plain_s * 1e3 / (ms / args.genome_batches), 3),
-        "batched_equals_plain": plain_equal,
-        "replay_equals_eager": replay_equal,
-        "hits": hits,
-        "index_build_s": round(build_s, 2),
-        "phase_ms_per_batch": {k: round(v, 3) for k, v in phase.items()},
-        "work_per_batch": {"dfs_nodes": st["occ8"], "dfs_buckets": st["buckets"], "d_walk_steps": st["walk_steps"],
-                           "d_walk_buckets": st["walk_buckets"], "dfs_subtrees_taken_over": st["subtrees"]},
-        "dfs_buckets_per_s": round(st["buckets"] / (phase["dfs"] / 1e3), 1),
-        "occ8_queries_per_s": {"fm_occ8_" + k: round(v, 1) for k, v in occ8.items()},
-        "locate_first_batch": gloc,
-        "tuning": tuning,
-        "roofline": {"bound": "hbm", "kernel": key[1], "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": int(sum(traffic)) if traffic else None,
-                     "traffic_gb_per_s": round(sum(traffic) / (phase["dfs"] / 1e3) / 1e9, 1) if traffic else None,
-                     "bytes_per_launch": int(alg), "avg_launch_ms": round(phase["dfs"], 3),
-                     "kernel_source_hash": key[0]},
-    }
-    log("genome scale:", out)
-    del codes, offs, z, ex_out, bufs
+    del qsets
+
+    # the oracle's text-only checkers on a sample (the first 1,000 reads and 1,000 spread
+    # over the set), timed on the host, and the GPU's results for those reads checked
+    cpu = parity = None
+    if args.cpu_sample > 0:
+        sample = np.unique(np.concatenate([np.arange(args.genome_cpu_sample // 2),
+                                           np.linspace(args.genome_cpu_sample // 2, NB * B - 1,
+                                                       args.genome_cpu_sample // 2).astype(np.int64)]))
+        got_ex = np.zeros((sample.size * 2, 2), np.uint32)
+        got = []
+        host = [None] * NB
+        for j, r in enumerate(sample):
+            b, i = divmod(int(r), B)
+            if host[b] is None:
+                e = eager[b]
+                h = e[3].cpu().numpy().view(np.uint32).reshape(-1, 4).copy().view(fm.HIT_DTYPE).reshape(-1)
+                host[b] = (e[0].cpu().numpy().view(np.uint32), e[1].cpu().numpy().view(np.uint64), h)
+            exb, ob, hb = host[b]
+            got_ex[2 * j:2 * j + 2] = exb[2 * i:2 * i + 2]
+            got.append(hb[int(ob[i]):int(ob[i + 1])])
+        cpu, parity = genome_cpu_baseline(R, rd.subset(sample), got_ex, got, args.cpu_threads)
+    del eager, batches, codes_all, z_all, offs
     idx.free()
-    return out
+    torch.cuda.empty_cache()
+    reads_s = B / (ms_step / 1e3)
+    return {
+        "value": round(reads_s, 1),
+        "ms_per_step": round(ms_step, 4),
+        "config": {"workload": "3.1e9-base reference (55%% i.i.d., 45%% copies of 500 repeat families, 5-15%% "
+                               "divergence); %d batches of 1M reads x 150 bp, 1%% substitutions, either strand, all "
+                               "resident in HBM; exact + z=2 substitution search, both strands, D-array pruning; "
+                               "one launch graph per batch, replayed; a step is one batch" % NB,
+                   "n": int(R.size), "reads": NB * B, "batch_reads": B, "read_len": LEN, "z": Z, "strands": 2,
+                   "d_bound": True, "hit_cap_per_batch": cap, "graph_replay": True},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity_sample": parity,
+        "extra": {
+            "plain_reads_per_s": round(B / plain_s, 1),
+            "batched_vs_plain": round(plain_s * 1e3 / ms_step, 3),
+            "batched_equals_plain": plain_equal,
+            "replay_equals_eager": replay_equal,
+            "all_status_ok": all_ok,
+            "hits": int(sum(hits_per_batch)),
+            "index_build_s": round(build_s, 2),
+            "phase_ms_per_step": {k: round(v, 3) for k, v in phase.items()},
+            "work_per_batch": {"dfs_nodes": work["occ8"] // NB, "dfs_buckets": work["buckets"] // NB,
+                               "d_walk_steps": work["walk_steps"] // NB, "d_walk_buckets": work["walk_buckets"] // NB,
+                               "dfs_subtrees_taken_over": work["subtrees"] // NB},
+            "dfs_occ8_per_s": round(work["occ8"] / NB / (phase["dfs"] / 1e3), 1),
+            "dfs_buckets_per_s": round(work["buckets"] / NB / (phase["dfs"] / 1e3), 1),
+            "occ8_queries_per_s": {"fm_occ8_" + k: round(v, 1) for k, v in occ8.items()},
+            "occ8_search_trace": trace_info,
+            "locate_first_batch": gloc,
+            "tuning": tuning,
+        },
+    }
+
+
+def genome_cpu_baseline(R, srd, got_ex, got_hits, threads):
+    """The oracle at genome scale: its text-only checkers (exact intervals
+    by a batched rank scan over the text, z-substitution hit sets by a pigeonhole seed pass
+    and the rank scan), which need no suffix array, on `threads` host threads; also checks
+    the GPU's results for the sampled reads bit for bit."""
+    import oracle
+    t0 = time.time()
+    want_ex = oracle.exact_by_rank_scan_batch(R, srd.codes, srd.offs, oracle.BOTH, threads=threads)
+    t1 = time.time()
+    wh, wo = oracle.pigeonhole_hits_batch(R, srd.codes, srd.offs, srd.z, oracle.BOTH, threads=threads)
+    t2 = time.time()
+    ok_ex = bool(np.array_equal(got_ex, want_ex))
+    ok_in = True
+    for j in range(srd.count):
+        a = got_hits[j]
+        w = wh[int(wo[j]):int(wo[j + 1])]
+        ok_in &= bool(np.array_equal(a["k"], w["k"]) and np.array_equal(a["l"], w["l"]) and
+                      np.array_equal(a["strand"], w["strand"]) and np.array_equal(a["nmm"], w["d"]))
+    dt = t2 - t0
+    log("oracle text-only checkers: %d reads in %.1fs (rank scan %.1fs, pigeonhole %.1fs) on %d threads; "
+        "exact equal %s, hits equal %s" % (srd.count, dt, t1 - t0, t2 - t1, threads, ok_ex, ok_in))
+    cpu = {"value": round(srd.count / dt, 1), "unit": "reads/s", "cores": threads, "kind": "oracle",
+           "sample": "%d reads of the 16M (the first %d and %d spread over the set); the oracle's text-only "
+                     "checkers, which need no index: exact intervals of both strands by a batched rank scan "
+                     "over the 3.1e9-base text, z=2 hit sets by a pigeonhole seed pass plus rank scans; both "
+                     "passes cost about one sweep of the text whatever the sample, so this rate grows with "
+                     "the sample" % (srd.count, srd.count // 2, srd.count - srd.count // 2),
+           "seconds": {"rank_scan": round(t1 - t0, 2), "pigeonhole": round(t2 - t1, 2)},
+           "host": host_info()}
+    parity = {"reads": srd.count, "exact_bit_exact": ok_ex, "inexact_bit_exact": ok_in,
+              "exact_hits": int((want_ex[:, 0] <= want_ex[:, 1]).sum()), "hits": int(wh.size)}
+    return cpu, parity
+
+
+def host_info() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def residency_bound(index_bytes: int) -> str:
+    """'hbm' when the index (both directions) is far larger than the last-level caches
+    (8 x 4 MB of L2 and 256 MB of MALL), so that random bucket fetches are served from HBM;
+    'cache' when it fits in them and the HBM fraction measures cache-served bytes."""
+    return "hbm" if index_bytes > 4 * (256 << 20) else "cache"
 
 
 def layout_rates(fm, torch, idx, step, ex_out, bufs, nreads, ref) -> dict:
@@ -707,6 +914,54 @@ def full_rank_rate(fm, torch, idx, codes, offs, nreads, ws, args) -> dict:
             "plain_reads_per_s": round(nreads / (pms / 1e3), 1), "batched_vs_plain": round(pms / ms, 3),
             "batched_equals_plain": bool(torch.equal(res["batched"][1], res["plain"][1])),
             "steps": steps, "steps_per_s": round(steps / (ms / 1e3), 1)}
+
+
+def gapped_z2_rate(fm, torch, idx, rd, args, count: int = 200_000) -> dict:
+    """Listing 2 with all its branches at z=2 edits on the step's first 200K reads, both
+    strands, D bound: the hit capacity is sized from the first call's required count (a
+    call whose hits overflow reports the total every read needs), then batched and plain
+    are timed and compared."""
+    flags = fm.FM_BOTH | fm.FM_DARRAY | fm.FM_GAPS
+    sub = rd.subset(np.arange(min(count, rd.count)))
+    n = sub.count
+    codes, offs, _ = fm.reads_to_device(sub.codes, sub.offs, sub.z)
+    z = torch.full((n,), 2, dtype=torch.uint8, device="cuda")
+    cap = 16 * n
+    gb = fm.InexactBuffers(idx, n, int(sub.offs[-1]), flags, 2, cap, "cuda")
+    fm.fm_search_inexact(idx, codes, offs, z, flags, 2, cap, bufs=gb)
+    torch.cuda.synchronize()
+    first_cap, need = cap, gb.required()
+    if need > cap:
+        cap = need
+    gb = fm.InexactBuffers(idx, n, int(sub.offs[-1]), flags | fm.FM_PLAIN, 2, cap, "cuda")
+    fm.fm_search_inexact(idx, codes, offs, z, flags | fm.FM_STATS, 2, cap, bufs=gb)
+    torch.cuda.synchronize()
+    st = gb.stats()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    res = {}
+    for name, extra, reps in (("batched", 0, 3), ("plain", fm.FM_PLAIN, 1)):
+        fm.fm_search_inexact(idx, codes, offs, z, flags | extra, 2, cap, bufs=gb)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            fm.fm_search_inexact(idx, codes, offs, z, flags | extra, 2, cap, bufs=gb)
+        ev[1].record()
+        torch.cuda.synchronize()
+        res[name] = (ev[0].elapsed_time(ev[1]) / reps, fm.hits_to_numpy(gb, n))
+    hits, _, status = res["batched"][1]
+    out = {"workload": "the step's first %d reads x 100 bp; z=2 edits, both strands, D bound; one hit per interval"
+                       % n,
+           "reads": n, "ms": round(res["batched"][0], 3), "reads_per_s": round(n / res["batched"][0] * 1e3, 1),
+           "plain_reads_per_s": round(n / res["plain"][0] * 1e3, 1),
+           "batched_vs_plain": round(res["plain"][0] / res["batched"][0], 3),
+           "batched_equals_plain": all(np.array_equal(a, b) for a, b in zip(res["batched"][1], res["plain"][1])),
+           "hits": int(hits.size), "all_ok": bool((status == fm.FM_OK).all()),
+           "hit_capacity": {"first_call": first_cap, "required_before_merging": int(need), "used": cap,
+                            "required_per_read": round(need / n, 2)},
+           "dfs_nodes": st["occ8"], "dfs_buckets": st["buckets"]}
+    del gb, codes, offs, z
+    torch.cuda.empty_cache()
+    return out
 
 
 def gapped_rate(fm, torch, idx, codes, offs, z, nreads, total_len, args) -> dict:
@@ -771,7 +1026,8 @@ def serve_bench(args):
 
     t0 = time.time()
     R = synth.repeats_2e28_reference()
-    idx = fm.Index.from_text(R, occ_interval=64, flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_DEVICE_SORT)
+    idx = fm.Index.from_text(R, occ_interval=64,
+                             flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_DEVICE_SORT | fm.FM_LOAD_ALL_LAYOUTS)
     log("serving index (n=%d) built in %.1fs (suffixes sorted on the device)" % (R.size, time.time() - t0))
     t0 = time.time()
     pool = synth.mixed_reads_2e28(R, args.serve_pool, seed=3005)
@@ -785,7 +1041,7 @@ def serve_bench(args):
         lo, hi = int(pool.offs[s0]), int(pool.offs[s0 + n])
         reqs.append((pool.codes[lo:hi], pool.offs[s0:s0 + n + 1] - np.uint64(lo), pool.z[s0:s0 + n]))
     log("serving requests drawn in %.1fs: %d requests, %d reads" % (time.time() - t0, nreq, int(sizes.sum())))
-    mixed = mixed_batch(idx, pool)
+    mixed = batch_2e28(idx, R, args)
     opts = dict(lanes=args.serve_lanes, flags=fm.FM_BOTH | fm.FM_DARRAY, zmax=2, hit_reserve=4,
                 arena_bytes=4 << 30, ring_bytes=1 << 30)
     mean_size = float(sizes.mean())
@@ -870,17 +1126,38 @@ def serve_bench(args):
     return out
 
 
-def mixed_batch(idx, pool):
-    """The whole read pool (budgets 0-2, lengths 50-250) in one persistent launch of the
-    inexact search, both strands with the D bound, against the plain kernels."""
+def batch_2e28(idx, R, args):
+    """The mixed-budget batch: 4M reads of the 2^28-base reference (lengths U[50, 250],
+    0.5-3% substitutions, z in {0, 1, 2}) in one persistent launch of the inexact search,
+    both strands with the D bound, with the layout, lanes, occupancy and claim order chosen
+    by the autotuner on a sample of the same reads; against the plain kernels. Also Occ8
+    rates on this index."""
     import torch
 
+    import synth
     from paper_1811_06127_amd import fm
 
+    t0 = time.time()
+    pool = synth.mixed_reads_2e28(R, args.batch_reads)
     n = pool.count
-    codes, offs, z = fm.reads_to_device(pool.codes, pool.offs, pool.z)
+    log("mixed-budget reads drawn in %.1fs: %d reads, %d bases" % (time.time() - t0, n, int(pool.offs[-1])))
     flags = fm.FM_BOTH | fm.FM_DARRAY
     cap = 6 * n
+    saved = {op: idx.get_tuning(op) for op in (fm.FM_OP_INEXACT, fm.FM_OP_DARRAY)}
+    tuning = {}
+    if not args.no_tune:
+        t0 = time.time()
+        ts = pool.subset(np.arange(min(n, args.tune_sample)))
+        tc, to, tz = fm.reads_to_device(ts.codes, ts.offs, ts.z)
+        tb = fm.InexactBuffers(idx, ts.count, int(ts.offs[-1]), flags | fm.FM_PLAIN, 2, 6 * ts.count, "cuda")
+        for name, op in (("inexact", fm.FM_OP_INEXACT), ("d_walk", fm.FM_OP_DARRAY)):
+            cfg, ms = fm.fm_autotune(idx, op, tc, to, tz, flags, 2, bufs=tb, cache_path=args.tune_cache)
+            tuning[name] = {"config": cfg, "ms_on_sample": ms}
+        tuning["sample_reads"] = ts.count
+        tuning["seconds"] = round(time.time() - t0, 1)
+        log("mixed-budget batch autotuned on %d reads in %.1fs: %s" % (ts.count, time.time() - t0, tuning))
+        del tb, tc, to, tz
+    codes, offs, z = fm.reads_to_device(pool.codes, pool.offs, pool.z)
     bufs = fm.InexactBuffers(idx, n, int(pool.offs[-1]), flags | fm.FM_PLAIN, 2, cap, "cuda")
 
     def timed(extra, reps):
@@ -894,15 +1171,82 @@ def mixed_batch(idx, pool):
         torch.cuda.synchronize()
         return t0.elapsed_time(t1) / reps, fm.hits_to_numpy(bufs, n)
 
+    fm.fm_search_inexact(idx, codes, offs, z, flags | fm.FM_STATS, 2, cap, bufs=bufs)
+    torch.cuda.synchronize()
+    st = bufs.stats()
     ms, hb = timed(0, 3)
     pms, hp = timed(fm.FM_PLAIN, 1)
-    out = {"reads": n, "total_bases": int(pool.offs[-1]), "ms": round(ms, 3), "reads_per_s": round(n / ms * 1e3, 1),
-           "plain_reads_per_s": round(n / pms * 1e3, 1), "batched_equals_plain": all(
-               np.array_equal(a, b) for a, b in zip(hb, hp)), "hits": int(hb[1][-1]),
-           "tuning": idx.get_tuning(fm.FM_OP_INEXACT)}
+    occ8 = {}
+    nq = 1 << 26
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for kind in ("uniform", "narrow"):
+        q = torch.from_numpy(synth.occ8_queries(R.size, nq, 4444, kind).view(np.int32)).cuda()
+        qo = torch.empty((nq, 8), dtype=torch.int32, device="cuda")
+        fm.fm_occ8(idx, q, out=qo)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(3):
+            fm.fm_occ8(idx, q, out=qo)
+        ev[1].record()
+        torch.cuda.synchronize()
+        occ8["fm_occ8_" + kind] = round(nq / (ev[0].elapsed_time(ev[1]) / 3 / 1e3), 1)
+        del q, qo
+    out = {"workload": "2^28-base reference (5%% copies, 1%% tandem repeats); %d reads, length U[50,250], "
+                       "0.5-3%% substitutions, z in {0,1,2} mixed in one persistent launch; both strands, D bound"
+                       % n,
+           "reads": n, "total_bases": int(pool.offs[-1]), "ms": round(ms, 3), "reads_per_s": round(n / ms * 1e3, 1),
+           "plain_reads_per_s": round(n / pms * 1e3, 1), "batched_vs_plain": round(pms / ms, 3),
+           "batched_equals_plain": all(np.array_equal(a, b) for a, b in zip(hb, hp)), "hits": int(hb[1][-1]),
+           "all_ok": bool((hb[2] == fm.FM_OK).all()), "dfs_nodes": st["occ8"], "dfs_buckets": st["buckets"],
+           "tuning": tuning or {"inexact": {"config": idx.get_tuning(fm.FM_OP_INEXACT)}},
+           "occ8_queries_per_s": occ8}
     log("mixed-budget batch on the 2^28 index:", out)
+    for op, t in saved.items():
+        idx.set_tuning(op, **t)
     del bufs, codes, offs, z
     torch.cuda.empty_cache()
+    return out
+
+
+def small_exact(args):
+    """The small workload: a 65,536-base i.i.d. reference and 10,000 exact queries of 32
+    symbols (half copied from the reference, half random), forward strand, I=128: batched
+    and plain rates, and the intervals against the oracle's (binary search over its suffix
+    array)."""
+    import torch
+
+    import oracle
+    import synth
+    from paper_1811_06127_amd import fm
+
+    w = synth.small_exact_workload()
+    idx = fm.Index.from_text(w.ref, occ_interval=128)
+    cd, od, _ = fm.reads_to_device(w.reads.codes, w.reads.offs)
+    n = w.reads.count
+    ws = torch.zeros(fm.fm_search_exact_workspace(idx, n, fm.FM_FWD), dtype=torch.uint8, device="cuda")
+    out = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    res = {}
+    reps = 200
+    for name, extra in (("batched", 0), ("plain", fm.FM_PLAIN)):
+        for _ in range(3):
+            fm.fm_search_exact(idx, cd, od, fm.FM_FWD | extra, out=out, ws=ws)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            fm.fm_search_exact(idx, cd, od, fm.FM_FWD | extra, out=out, ws=ws)
+        ev[1].record()
+        torch.cuda.synchronize()
+        res[name] = (ev[0].elapsed_time(ev[1]) / reps, out.cpu().numpy().view(np.uint32).copy())
+    want = oracle.OracleIndex(w.ref).exact(w.reads.codes, w.reads.offs, oracle.FWD, "definition")
+    idx.free()
+    out = {"workload": "65,536-base i.i.d. reference; 10,000 exact queries of 32 (half copied, half random), "
+                       "forward strand, I=128; the queries are too few to fill the chip, so this rate is launch-bound",
+           "reads": n, "ms": round(res["batched"][0], 4), "reads_per_s": round(n / res["batched"][0] * 1e3, 1),
+           "plain_reads_per_s": round(n / res["plain"][0] * 1e3, 1),
+           "equals_oracle": bool(np.array_equal(res["batched"][1], want) and np.array_equal(res["plain"][1], want)),
+           "hits": int((want[:, 0] <= want[:, 1]).sum())}
+    log("small exact workload:", out)
     return out
 
 

@@ -393,7 +393,8 @@ int fm_locate(const fm_index *idx, const uint32_t *kl, uint64_t niv, uint32_t st
 
 /* Diagnostics. With capacity > 0, every later search call on idx records HIP events on
  * its stream at its phase boundaries (the first `capacity` calls are kept); capacity 0
- * turns this off. Not for concurrent use, and off while a plan is captured. */
+ * turns this off. Not for concurrent use. A plan captured meanwhile records events of its
+ * own instead (fm_plan_phase_times); its replays are not recorded here. */
 int fm_phase_timing(fm_index *idx, uint32_t capacity);
 
 /* Waits for the recorded events and writes the milliseconds spent per phase, summed
@@ -422,6 +423,15 @@ int fm_plan_create_both(const fm_index *idx, const uint8_t *codes, const uint64_
 
 /* Enqueues one replay of the plan on stream. */
 int fm_plan_launch(fm_plan *plan, void *stream);
+
+/* A plan created while the index's phase timing (fm_phase_timing) is on records HIP events
+ * of its own at the phase boundaries of every replay, on the stream it is replayed on.
+ * This waits for the last replay's events and writes its milliseconds per phase as
+ * fm_phase_times does (ms[0] exact walk, ms[1] D walk and claim order, ms[2] DFS kernel,
+ * ms[3] compaction; 0 for phases the plan does not have). FM_EINVAL for a plan created
+ * without phase timing. A replay still queued when this is called is waited for; the
+ * events of earlier replays are overwritten by later ones. */
+int fm_plan_phase_times(fm_plan *plan, float ms[4]);
 
 void fm_plan_free(fm_plan *plan);
 

@@ -14,6 +14,8 @@ using namespace fm;
 
 namespace fm {
 
+thread_local const PhaseEvents *g_plan_events = nullptr;
+
 DevLayout dev_layout(const fm_index *idx, uint32_t I, bool rev)
 {
     DevLayout d;
@@ -505,7 +507,7 @@ int fm_search_exact(const fm_index *idx, const uint8_t *codes, const uint64_t *o
         if (hipError_t e = launch_fill(ws, 0, kWsHeader / 4, s)) return hip_status(e);
     }
     WalkCall c{codes, offs, nullptr, nreads, flags, 0, out, ws};
-    const PhaseEvents pe = take_events(idx, 0);
+    const PhaseEvents pe = g_plan_events ? *g_plan_events : take_events(idx, 0);
     pe.mark(0, s);
     const hipError_t e = launch_walk(idx, idx->tune[FM_OP_EXACT], WALK_EXACT, plain, c, s);
     pe.mark(1, s);
@@ -546,7 +548,7 @@ int fm_search_inexact(const fm_index *idx, const uint8_t *codes, const uint64_t 
     if (ws_bytes < inexact_ws_layout(nreads, nstrands(flags), zmax, hit_cap).total) return FM_EINVAL;
     DeviceGuard g(idx->device);
     DfsCall c{codes, offs, z, nreads, flags, zmax, hits, hit_cap, hit_offs, status, ws};
-    const PhaseEvents pe = take_events(idx, 1);
+    const PhaseEvents pe = g_plan_events ? *g_plan_events : take_events(idx, 1);
     return hip_status(launch_inexact(idx, idx->tune[FM_OP_INEXACT], idx->tune[FM_OP_DARRAY], plain, c,
                                      (hipStream_t)stream, &pe));
 }
@@ -579,7 +581,7 @@ int fm_search_both(const fm_index *idx, const uint8_t *codes, const uint64_t *of
     DfsCall c{codes, offs, z, nreads, flags, zmax, hits, hit_cap, hit_offs, status, ws};
     c.ex_out = intervals;
     c.ex_flags = exact_flags & FM_BOTH;
-    const PhaseEvents pe = take_events(idx, 1);
+    const PhaseEvents pe = g_plan_events ? *g_plan_events : take_events(idx, 1);
     return hip_status(launch_inexact(idx, idx->tune[FM_OP_INEXACT], idx->tune[FM_OP_DARRAY], false, c,
                                      (hipStream_t)stream, &pe));
 }

@@ -155,6 +155,10 @@ struct PhaseEvents {
 hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuning &tw, bool plain,
                           const DfsCall &c, hipStream_t s, const PhaseEvents *pe);
 
+// Phase events of the plan being captured on this thread (see fm_plan_create), or
+// nullptr: search calls then record the index's own phase events, if any.
+extern thread_local const PhaseEvents *g_plan_events;
+
 int max_blocks_per_cu(const void *kernel, int block, size_t lds);
 
 }  // namespace fm

@@ -14,6 +14,8 @@ struct fm_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int device = 0;
+    int kind = 1;                  // 0: exact search, 1: inexact or both
+    PhaseEvents ev;                // recorded by the graph at the phase boundaries, if timed
 };
 
 namespace {
@@ -90,6 +92,21 @@ void cache_store(const char *path, const std::string &key, const fm_tuning &t, f
     fclose(f);
 }
 
+// A plan created while the index's phase timing is on records events of its own at the
+// phase boundaries of each replay (see fm_plan_phase_times).
+int plan_events(const fm_index *idx, fm_plan *p)
+{
+    if (!idx->timing_cap) return FM_OK;
+    for (int i = 0; i < 5; ++i) {
+        if (p->kind == 0 && i > 1) break;
+        if (hipEventCreate(&p->ev.ev[i]) != hipSuccess) {
+            p->ev.ev[i] = nullptr;
+            return FM_EDEVICE;
+        }
+    }
+    return FM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -107,13 +124,14 @@ int fm_plan_create(const fm_index *idx, int op, const uint8_t *codes, const uint
     p->device = idx->device;
     hipStream_t s = nullptr;
     int st = hs(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    p->kind = op == FM_OP_EXACT ? 0 : 1;
+    if (!st) st = plan_events(idx, p);
     if (!st) st = hs(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
     if (!st) {
-        const uint32_t cap = idx->timing_cap;   // no phase events inside a graph
-        idx->timing_cap = 0;
+        g_plan_events = &p->ev;       // the index's own phase events stay out of the graph
         const int cs = run_op(idx, op, codes, offs, z, nreads, flags, zmax, out_buf, hit_cap, hit_offs, status, ws,
                               ws_bytes, s);
-        idx->timing_cap = cap;
+        g_plan_events = nullptr;
         const int es = hs(hipStreamEndCapture(s, &p->graph));
         st = cs ? cs : es;
     }
@@ -142,13 +160,13 @@ int fm_plan_create_both(const fm_index *idx, const uint8_t *codes, const uint64_
     p->device = idx->device;
     hipStream_t s = nullptr;
     int st = hs(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    if (!st) st = plan_events(idx, p);
     if (!st) st = hs(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
     if (!st) {
-        const uint32_t cap = idx->timing_cap;   // no phase events inside a graph
-        idx->timing_cap = 0;
+        g_plan_events = &p->ev;
         const int cs = fm_search_both(idx, codes, offs, z, nreads, exact_flags, flags, zmax, intervals, hits, hit_cap,
                                       hit_offs, status, ws, ws_bytes, s);
-        idx->timing_cap = cap;
+        g_plan_events = nullptr;
         const int es = hs(hipStreamEndCapture(s, &p->graph));
         st = cs ? cs : es;
     }
@@ -169,11 +187,38 @@ int fm_plan_launch(fm_plan *plan, void *stream)
     return hs(hipGraphLaunch(plan->exec, (hipStream_t)stream));
 }
 
+int fm_plan_phase_times(fm_plan *plan, float ms[4])
+{
+    if (!plan || !ms || !plan->ev.ev[0]) return FM_EINVAL;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(plan->device);
+    int st = FM_OK;
+    auto span = [&](hipEvent_t a, hipEvent_t b) {
+        float m = 0.f;
+        if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&m, a, b) != hipSuccess) st = FM_EDEVICE;
+        return m;
+    };
+    for (int i = 0; i < 4; ++i) ms[i] = 0.f;
+    const hipEvent_t *e = plan->ev.ev;
+    if (plan->kind == 0) {
+        ms[0] = span(e[0], e[1]);
+    } else {
+        ms[1] = span(e[1], e[2]);
+        ms[2] = span(e[2], e[3]);
+        ms[3] = span(e[3], e[4]);
+    }
+    (void)hipSetDevice(prev);
+    return st;
+}
+
 void fm_plan_free(fm_plan *plan)
 {
     if (!plan) return;
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    for (hipEvent_t e : plan->ev.ev)
+        if (e) (void)hipEventDestroy(e);
     delete plan;
 }
 

@@ -115,6 +115,7 @@ def lib() -> C.CDLL:
         "fm_plan_create": (i32, [vp, i32, vp, vp, vp, u64, u32, u32, vp, u64, vp, vp, vp, C.c_size_t,
                                  C.POINTER(vp)]),
         "fm_plan_launch": (i32, [vp, vp]),
+        "fm_plan_phase_times": (i32, [vp, C.POINTER(C.c_float)]),
         "fm_phase_timing": (i32, [vp, u32]),
         "fm_phase_times": (i32, [vp, C.POINTER(C.c_float), C.POINTER(C.c_uint32)]),
         "fm_plan_free": (None, [vp]),
@@ -556,6 +557,13 @@ class Plan:
 
     def launch(self, stream=None):
         _check(lib().fm_plan_launch(self._h, _stream(stream)), "fm_plan_launch")
+
+    def phase_times(self) -> dict:
+        """Milliseconds per phase of the last replay (fm_plan_phase_times); the plan must have
+        been created while the index's phase timing was on."""
+        ms = (C.c_float * 4)()
+        _check(lib().fm_plan_phase_times(self._h, ms), "fm_plan_phase_times")
+        return {"exact_walk": ms[0], "d_walk": ms[1], "dfs": ms[2], "compaction": ms[3]}
 
     def free(self):
         if self._h:
