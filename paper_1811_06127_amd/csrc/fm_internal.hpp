@@ -144,18 +144,22 @@ struct DfsCall {
     fm_interval *ex_out = nullptr;   // non-null: exact intervals of the ex_flags strands, taken from the DFS
     uint32_t ex_flags = 0;
 };
-// Phase boundary events of one call (nullptr entries: not recorded).
+// Phase boundaries of one call: HIP events recorded there (nullptr entries: not recorded),
+// or, while a plan is captured, a cut of the capture into a new graph segment.
 struct PhaseEvents {
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    void (*cut)(void *ctx, int i, hipStream_t s) = nullptr;
+    void *ctx = nullptr;
     void mark(int i, hipStream_t s) const
     {
-        if (ev[i]) (void)hipEventRecord(ev[i], s);
+        if (cut) cut(ctx, i, s);
+        else if (ev[i]) (void)hipEventRecord(ev[i], s);
     }
 };
 hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuning &tw, bool plain,
                           const DfsCall &c, hipStream_t s, const PhaseEvents *pe);
 
-// Phase events of the plan being captured on this thread (see fm_plan_create), or
+// Phase boundaries of the plan being captured on this thread (see fm_plan_create), or
 // nullptr: search calls then record the index's own phase events, if any.
 extern thread_local const PhaseEvents *g_plan_events;
 

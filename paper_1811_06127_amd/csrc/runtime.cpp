@@ -10,12 +10,20 @@
 
 using namespace fm;
 
-struct fm_plan {
+// A plan is one captured graph, or, when created under phase timing, one graph per phase
+// (segment) with HIP events recorded on the replay stream between them.
+struct PlanSegment {
+    int mark = -1;                 // phase boundary the segment starts at (-1: the call's start)
     hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraphExec_t exec = nullptr; // nullptr when nothing was captured in the segment
+};
+
+struct fm_plan {
+    std::vector<PlanSegment> seg;
     int device = 0;
     int kind = 1;                  // 0: exact search, 1: inexact or both
-    PhaseEvents ev;                // recorded by the graph at the phase boundaries, if timed
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // timed plans: one per boundary
+    hipError_t cut_error = hipSuccess;
 };
 
 namespace {
@@ -92,19 +100,51 @@ void cache_store(const char *path, const std::string &key, const fm_tuning &t, f
     fclose(f);
 }
 
-// A plan created while the index's phase timing is on records events of its own at the
-// phase boundaries of each replay (see fm_plan_phase_times).
-int plan_events(const fm_index *idx, fm_plan *p)
+// Ends the capture of the current segment at phase boundary i and starts the next one.
+void plan_cut(void *ctx, int i, hipStream_t s)
 {
-    if (!idx->timing_cap) return FM_OK;
-    for (int i = 0; i < 5; ++i) {
-        if (p->kind == 0 && i > 1) break;
-        if (hipEventCreate(&p->ev.ev[i]) != hipSuccess) {
-            p->ev.ev[i] = nullptr;
-            return FM_EDEVICE;
-        }
+    fm_plan *p = (fm_plan *)ctx;
+    PlanSegment &cur = p->seg.back();
+    hipError_t e = hipStreamEndCapture(s, &cur.graph);
+    PlanSegment next;
+    next.mark = i;
+    p->seg.push_back(next);
+    if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess && p->cut_error == hipSuccess) p->cut_error = e;
+}
+
+// Captures one call (run) on stream s into the plan: a single graph, or, when the index's
+// phase timing is on, one graph per phase and an event per boundary.
+template <typename F>
+int capture(const fm_index *idx, fm_plan *p, hipStream_t s, F run)
+{
+    const bool timed = idx->timing_cap > 0;
+    if (timed)
+        for (int i = 0; i < 5; ++i)
+            if (hipEventCreate(&p->ev[i]) != hipSuccess) {
+                p->ev[i] = nullptr;
+                return FM_EDEVICE;
+            }
+    p->seg.assign(1, PlanSegment());
+    int st = hs(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    if (st) return st;
+    PhaseEvents pe;                    // no index events inside a graph; cuts when timed
+    if (timed) {
+        pe.cut = plan_cut;
+        pe.ctx = p;
     }
-    return FM_OK;
+    g_plan_events = &pe;
+    const int cs = run();
+    g_plan_events = nullptr;
+    const int es = hs(hipStreamEndCapture(s, &p->seg.back().graph));
+    st = cs ? cs : (p->cut_error != hipSuccess ? hs(p->cut_error) : es);
+    for (PlanSegment &g : p->seg) {
+        if (st || !g.graph) continue;
+        size_t nodes = 0;
+        if (hipGraphGetNodes(g.graph, nullptr, &nodes) != hipSuccess) st = FM_EDEVICE;
+        else if (nodes) st = hs(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+    }
+    return st;
 }
 
 }  // namespace
@@ -125,17 +165,11 @@ int fm_plan_create(const fm_index *idx, int op, const uint8_t *codes, const uint
     hipStream_t s = nullptr;
     int st = hs(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     p->kind = op == FM_OP_EXACT ? 0 : 1;
-    if (!st) st = plan_events(idx, p);
-    if (!st) st = hs(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-    if (!st) {
-        g_plan_events = &p->ev;       // the index's own phase events stay out of the graph
-        const int cs = run_op(idx, op, codes, offs, z, nreads, flags, zmax, out_buf, hit_cap, hit_offs, status, ws,
-                              ws_bytes, s);
-        g_plan_events = nullptr;
-        const int es = hs(hipStreamEndCapture(s, &p->graph));
-        st = cs ? cs : es;
-    }
-    if (!st) st = hs(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    if (!st)
+        st = capture(idx, p, s, [&] {
+            return run_op(idx, op, codes, offs, z, nreads, flags, zmax, out_buf, hit_cap, hit_offs, status, ws,
+                          ws_bytes, s);
+        });
     if (s) (void)hipStreamDestroy(s);
     (void)hipSetDevice(prev);
     if (st) {
@@ -160,17 +194,11 @@ int fm_plan_create_both(const fm_index *idx, const uint8_t *codes, const uint64_
     p->device = idx->device;
     hipStream_t s = nullptr;
     int st = hs(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    if (!st) st = plan_events(idx, p);
-    if (!st) st = hs(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-    if (!st) {
-        g_plan_events = &p->ev;
-        const int cs = fm_search_both(idx, codes, offs, z, nreads, exact_flags, flags, zmax, intervals, hits, hit_cap,
-                                      hit_offs, status, ws, ws_bytes, s);
-        g_plan_events = nullptr;
-        const int es = hs(hipStreamEndCapture(s, &p->graph));
-        st = cs ? cs : es;
-    }
-    if (!st) st = hs(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    if (!st)
+        st = capture(idx, p, s, [&] {
+            return fm_search_both(idx, codes, offs, z, nreads, exact_flags, flags, zmax, intervals, hits, hit_cap,
+                                  hit_offs, status, ws, ws_bytes, s);
+        });
     if (s) (void)hipStreamDestroy(s);
     (void)hipSetDevice(prev);
     if (st) {
@@ -183,13 +211,18 @@ int fm_plan_create_both(const fm_index *idx, const uint8_t *codes, const uint64_
 
 int fm_plan_launch(fm_plan *plan, void *stream)
 {
-    if (!plan || !plan->exec) return FM_EINVAL;
-    return hs(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+    if (!plan || plan->seg.empty()) return FM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    for (const PlanSegment &g : plan->seg) {
+        if (g.mark >= 0 && plan->ev[g.mark] && hipEventRecord(plan->ev[g.mark], s) != hipSuccess) return FM_EDEVICE;
+        if (g.exec && hipGraphLaunch(g.exec, s) != hipSuccess) return FM_EDEVICE;
+    }
+    return FM_OK;
 }
 
 int fm_plan_phase_times(fm_plan *plan, float ms[4])
 {
-    if (!plan || !ms || !plan->ev.ev[0]) return FM_EINVAL;
+    if (!plan || !ms || !plan->ev[0]) return FM_EINVAL;
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(plan->device);
@@ -200,7 +233,7 @@ int fm_plan_phase_times(fm_plan *plan, float ms[4])
         return m;
     };
     for (int i = 0; i < 4; ++i) ms[i] = 0.f;
-    const hipEvent_t *e = plan->ev.ev;
+    const hipEvent_t *e = plan->ev;
     if (plan->kind == 0) {
         ms[0] = span(e[0], e[1]);
     } else {
@@ -208,6 +241,7 @@ int fm_plan_phase_times(fm_plan *plan, float ms[4])
         ms[2] = span(e[2], e[3]);
         ms[3] = span(e[3], e[4]);
     }
+    if (st) (void)hipGetLastError();     // leave no error behind for later calls to pick up
     (void)hipSetDevice(prev);
     return st;
 }
@@ -215,9 +249,11 @@ int fm_plan_phase_times(fm_plan *plan, float ms[4])
 void fm_plan_free(fm_plan *plan)
 {
     if (!plan) return;
-    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
-    if (plan->graph) (void)hipGraphDestroy(plan->graph);
-    for (hipEvent_t e : plan->ev.ev)
+    for (PlanSegment &g : plan->seg) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    for (hipEvent_t e : plan->ev)
         if (e) (void)hipEventDestroy(e);
     delete plan;
 }
