@@ -122,7 +122,7 @@ typedef struct {
     uint64_t device_bytes;          /* device memory the index keeps (in its own allocation, or
                                        in the caller's dev_buf) */
     uint32_t caller_memory;         /* 1 when that memory is the caller's dev_buf */
-    uint32_t pad;
+    uint32_t table_depth;           /* longest strings in the prefix table (see fm_tuning) */
 } fm_info;
 
 /* Launch configuration of one operation (see fm_get_tuning). */
@@ -142,6 +142,13 @@ typedef struct {
                                        weighing each by its D bound's slack, sum over i of
                                        max(0, z - D(i)); 0 = in read order (always so with
                                        FM_GAPS). Results are the same either way. */
+    uint32_t table_depth;           /* substitution search, one lane per read-strand: a DFS node
+                                       whose matched pattern suffix S is shorter than this takes
+                                       the intervals of its four children bS from the index's
+                                       prefix table (the Listing 1 interval of every string of
+                                       length 1..fm_info.table_depth, kept at load time) instead
+                                       of an Occ8 over the BWT; 0 = never. At most
+                                       fm_info.table_depth. Results are the same either way. */
 } fm_tuning;
 
 /* Operations with launch settings of their own. FM_OP_LOCATE (fm_locate: layout and
@@ -204,9 +211,11 @@ int fm_index_load(const char *path, const fm_load_opts *opts, fm_index **out);
 
 /* Device bytes an index over n symbols keeps when built with opts (fm_index_from_text,
  * _codes or _load): the layouts (the one named by occ_interval, or all of them with
- * FM_LOAD_ALL_LAYOUTS) of R and, with FM_LOAD_REVERSE, of reverse(R), plus with
- * FM_LOAD_LOCATE the SA samples of fm_index_from_text (4 bytes per 32 rows); each piece
- * is 256-byte aligned. This is the smallest dev_buf_bytes accepted. Host only; FM_EINVAL
+ * FM_LOAD_ALL_LAYOUTS) of R and, with FM_LOAD_REVERSE, of reverse(R); the prefix table
+ * of R: for t = 1..T the Listing 1 interval (k, l) of every string of length t over ACGT,
+ * 8 bytes each, with T = min(12, floor(log4(n + 1)) - 3) (none when that is below 1); and
+ * with FM_LOAD_LOCATE the SA samples of fm_index_from_text (4 bytes per 32 rows); each
+ * piece is 256-byte aligned. This is the smallest dev_buf_bytes accepted. Host only; FM_EINVAL
  * for an unsupported occ_interval, FM_ERANGE when n + 1 >= 2^32. */
 int fm_index_bytes(uint64_t n, const fm_load_opts *opts, size_t *bytes);
 
@@ -317,8 +326,10 @@ int fm_search_inexact_workspace(const fm_index *idx, uint64_t nreads, uint64_t t
  *      offsets 64 (expanded DFS nodes, each one Occ8 step), 72 (buckets fetched by
  *      them; a node whose interval is still (0, n) takes its children from C and
  *      fetches none), 80 (D-walk steps that fetched) and 88 (buckets they fetched)
- *      count the work done, and 96 the subtrees that idle lanes of the batched DFS took
- *      over from busy ones at the end of the launch (one lane per read-strand, zmax >= 2).
+ *      count the work done, 96 the subtrees that idle lanes of the batched DFS took
+ *      over from busy ones at the end of the launch (one lane per read-strand, zmax >= 2),
+ *      and 104 the expanded nodes whose children came from the prefix table (they fetch
+ *      no bucket; see fm_tuning.table_depth).
  * Output is deterministic (independent of scheduling, batch order and launch tuning)
  * whenever hit_cap suffices. When it does not, hits beyond the per-read-strand slots
  * compete for hit_cap places in arrival order, so which reads end FM_EOVERFLOW can vary

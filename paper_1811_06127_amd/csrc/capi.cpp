@@ -80,6 +80,7 @@ bool valid_tuning(const fm_index *idx, const fm_tuning &t)
     if (t.depth != 1 && t.depth != 2) return false;
     if (t.block < 64 || t.block > 256 || t.block % 64) return false;
     if (t.order > 1) return false;
+    if (t.table_depth > idx->table_levels) return false;
     return true;
 }
 
@@ -89,11 +90,11 @@ bool valid_tuning(const fm_index *idx, const fm_tuning &t)
 // 2^24 workload's hits).
 void default_tunings(fm_index *idx, uint32_t I)
 {
-    fm_tuning ex = {I, 1, 1, 256, 8, 0, 0};
-    fm_tuning dw = {I, 1, 1, 256, 8, 0, 0};
-    fm_tuning in = {I, 1, 1, 256, 8, 1u << 22, 1};
+    fm_tuning ex = {I, 1, 1, 256, 8, 0, 0, 0};
+    fm_tuning dw = {I, 1, 1, 256, 8, 0, 0, 0};
+    fm_tuning in = {I, 1, 1, 256, 8, 1u << 22, 1, idx->table_levels};
     // Psi^-1 walks share no buckets and each step waits for the last: more waves pay
-    fm_tuning lo = {I, 1, 1, 256, 16, 0, 0};
+    fm_tuning lo = {I, 1, 1, 256, 16, 0, 0, 0};
     idx->tune[FM_OP_EXACT] = ex;
     idx->tune[FM_OP_DARRAY] = dw;
     idx->tune[FM_OP_INEXACT] = in;
@@ -103,7 +104,8 @@ void default_tunings(fm_index *idx, uint32_t I)
 // Where an index's pieces go: byte offsets of the forward and reverse layouts (~0: not
 // built) and of the SA samples, each 256-byte aligned, and the total.
 struct IndexPlan {
-    uint64_t lay[kLayouts], rlay[kLayouts], samples, total;
+    uint64_t lay[kLayouts], rlay[kLayouts], table, samples, total;
+    uint32_t table_levels;
 };
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
@@ -123,6 +125,12 @@ int plan_index(uint64_t n, const fm_load_opts *opts, bool rev, bool samples, Ind
             slot = at;
             at = align256(at + layout_bytes(n, kIntervals[li]));
         }
+    p.table_levels = prefix_table_levels(n);
+    p.table = ~0ull;
+    if (p.table_levels) {
+        p.table = at;
+        at = align256(at + prefix_table_entries(p.table_levels) * 8);
+    }
     p.samples = ~0ull;
     if (samples) {
         p.samples = at;
@@ -214,6 +222,13 @@ int create_index(const fm_load_opts *opts, uint64_t n, const HostSide &fwd, cons
     }
     if (packed) (void)hipFree(packed);
     if (scratch) (void)hipFree(scratch);
+    // prefix table of R, computed with the index's own Occ8
+    if (!st && plan.table_levels) {
+        idx->ptab = (uint2 *)(base + plan.table);
+        idx->table_levels = plan.table_levels;
+        if (hipError_t e = build_prefix_table(idx, I, nullptr)) st = hip_status(e);
+        else if (hipDeviceSynchronize() != hipSuccess) st = FM_EDEVICE;
+    }
     // SA samples for fm_locate
     const uint64_t ns = (n + 1 + kSaSample - 1) / kSaSample;
     if (!st && want_samples) {
@@ -445,6 +460,7 @@ int fm_index_info(const fm_index *idx, fm_info *out)
     out->sa_sample = idx->sa_samples ? kSaSample : 0u;
     out->device_bytes = idx->device_bytes;
     out->caller_memory = idx->owns_mem ? 0u : 1u;
+    out->table_depth = idx->table_levels;
     return FM_OK;
 }
 

@@ -23,6 +23,8 @@ struct fm_index {
     void *rlay[7] = {};    // layouts of reverse(R)
     uint64_t device_bytes = 0;
     uint32_t *sa_samples = nullptr;   // SA[32 j] for j = 0 .. n / 32 (fm_locate), or nullptr
+    uint2 *ptab = nullptr;            // prefix table of R (see prefix_table_levels), or nullptr
+    uint32_t table_levels = 0;
     fm_tuning tune[4] = {};
     int cu_count = 0;
     std::string arch;
@@ -65,6 +67,22 @@ inline uint64_t layout_bytes(uint64_t n, uint32_t I)
 
 DevLayout dev_layout(const fm_index *idx, uint32_t I, bool rev);
 
+// Prefix table of R: for t = 1..T, the interval that Listing 1 gives the string
+// s_0 .. s_{t-1} from (0, n) (empty ones as Listing 1 leaves them, k > l), at entry
+// table_level_base(t) + sum_j s_j 4^j, so that the four children b.S of a string S of
+// length t - 1 are four consecutive entries (32 bytes) at 4 * code(S). T grows with n
+// (strings much shorter than log4(n) are the ones many DFS nodes share).
+inline uint32_t prefix_table_levels(uint64_t n)
+{
+    int t = 0;
+    while (t < 16 && ((n + 1) >> (2 * (t + 1))) > 0) ++t;    // t = floor(log4(n + 1))
+    t -= 3;
+    return t < 1 ? 0u : (t > 12 ? 12u : (uint32_t)t);
+}
+__host__ __device__ inline uint64_t table_level_base(uint32_t t) { return ((1ull << (2 * t)) - 4) / 3; }
+inline uint64_t prefix_table_entries(uint32_t T) { return T ? table_level_base(T + 1) : 0; }
+hipError_t build_prefix_table(const fm_index *idx, uint32_t I, hipStream_t s);
+
 // Workspace header (byte offsets); the rest of the workspace follows at kWsHeader.
 enum : size_t {
     kWsQueue = 0,        // uint32 work-queue counter (exact / D walk)
@@ -77,6 +95,7 @@ enum : size_t {
     kWsStatWalk = 80,    // uint64 walk steps that fetched
     kWsStatWalkBk = 88,  // uint64 buckets those steps fetched
     kWsStatSteal = 96,   // uint64 subtrees idle DFS lanes took over (dfs_steal)
+    kWsStatTable = 104,  // uint64 DFS nodes whose children came from the prefix table
     kWsHeader = 256
 };
 

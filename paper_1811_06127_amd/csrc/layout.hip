@@ -315,6 +315,60 @@ hipError_t launch_occ8(const fm_index *idx, const fm_tuning &t, const fm_interva
     }
 }
 
+// ------------------------------------------------------------------ prefix table
+
+// Level t of the prefix table from level t - 1: each parent string S (level 0: the empty
+// string, interval (0, n)) gives its four children b.S by one Occ8 at (k - 1, l), Listing
+// 1's update k_b = C[b] + Occ(b, k - 1) + 1, l_b = C[b] + Occ(b, l), with Occ(b, -1) = 0.
+// An empty parent (k > l) gives empty children, as Listing 1 keeps them. Children are
+// written as 32 bytes at 4 * (parent entry).
+template <int I>
+__global__ void __launch_bounds__(256) prefix_level(DevLayout lay, const uint2 *parent, uint64_t np, uint4 *child)
+{
+    const uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const uint2 kl = parent ? parent[p] : make_uint2(0u, lay.n);
+    const uint32_t k = kl.x ? kl.x : 1u, l = kl.y;
+    Pair<I, 1> pr;
+    pr.load(lay, 0, k, l);
+    Occ4 a, b;
+    occ8<I, 1>(lay, pr, 0, k, l, a, b);
+    if (!kl.x) a = Occ4{0, 0, 0, 0};
+    const uint32_t C0 = lay.C[0], C1 = lay.C[1], C2 = lay.C[2], C3 = lay.C[3];
+    child[2 * p] = make_uint4(C0 + a.a + 1, C0 + b.a, C1 + a.c + 1, C1 + b.c);
+    child[2 * p + 1] = make_uint4(C2 + a.g + 1, C2 + b.g, C3 + a.t + 1, C3 + b.t);
+}
+
+template <int I>
+static hipError_t prefix_table_t(DevLayout lay, uint2 *tab, uint32_t T, hipStream_t s)
+{
+    for (uint32_t t = 1; t <= T; ++t) {
+        const uint64_t np = 1ull << (2 * (t - 1));
+        const uint2 *parent = t == 1 ? nullptr : tab + table_level_base(t - 1);
+        uint4 *child = (uint4 *)(tab + table_level_base(t));
+        hipLaunchKernelGGL(prefix_level<I>, dim3((uint32_t)((np + 255) / 256)), dim3(256), 0, s, lay, parent, np,
+                           child);
+        if (hipError_t e = hipGetLastError()) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t build_prefix_table(const fm_index *idx, uint32_t I, hipStream_t s)
+{
+    if (!idx->ptab || !idx->table_levels) return hipSuccess;
+    const DevLayout lay = dev_layout(idx, I, false);
+    switch (I) {
+    case 64: return prefix_table_t<64>(lay, idx->ptab, idx->table_levels, s);
+    case 96: return prefix_table_t<96>(lay, idx->ptab, idx->table_levels, s);
+    case 128: return prefix_table_t<128>(lay, idx->ptab, idx->table_levels, s);
+    case 192: return prefix_table_t<192>(lay, idx->ptab, idx->table_levels, s);
+    case 224: return prefix_table_t<224>(lay, idx->ptab, idx->table_levels, s);
+    case 256: return prefix_table_t<256>(lay, idx->ptab, idx->table_levels, s);
+    case 448: return prefix_table_t<448>(lay, idx->ptab, idx->table_levels, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 // Resident workgroups per CU for a kernel; the runtime query is slow, so each
 // (device, kernel, block, LDS) answer is computed once and kept.
 int max_blocks_per_cu(const void *kernel, int block, size_t lds)

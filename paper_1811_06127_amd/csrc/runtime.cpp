@@ -80,8 +80,8 @@ bool cache_lookup(const char *path, const std::string &key, fm_tuning *t, float 
         char k[300];
         fm_tuning v = {};
         float m = 0;
-        if (sscanf(line, "%299s %u %u %u %u %u %u %u %f", k, &v.occ_interval, &v.lanes, &v.depth, &v.block,
-                   &v.waves_per_cu, &v.node_budget, &v.order, &m) == 9 && key == k) {
+        if (sscanf(line, "%299s %u %u %u %u %u %u %u %u %f", k, &v.occ_interval, &v.lanes, &v.depth, &v.block,
+                   &v.waves_per_cu, &v.node_budget, &v.order, &v.table_depth, &m) == 10 && key == k) {
             *t = v;
             *ms = m;
             found = true;   // last entry wins
@@ -95,8 +95,8 @@ void cache_store(const char *path, const std::string &key, const fm_tuning &t, f
 {
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %u %u %u %u %u %u %u %.6f\n", key.c_str(), t.occ_interval, t.lanes, t.depth, t.block,
-            t.waves_per_cu, t.node_budget, t.order, ms);
+    fprintf(f, "%s %u %u %u %u %u %u %u %u %.6f\n", key.c_str(), t.occ_interval, t.lanes, t.depth, t.block,
+            t.waves_per_cu, t.node_budget, t.order, t.table_depth, ms);
     fclose(f);
 }
 

@@ -536,11 +536,17 @@ struct DfsArgs {
     // slots per read, for the strands in ex_strands (bit s: strand s)
     uint2 *ex_out;
     uint32_t ex_nstr, ex_strands;
+    // prefix table (see table_level_base): substitution nodes whose matched suffix is
+    // shorter than tdepth read their children from it (tdepth = 0: never)
+    const uint4 *tab;
+    uint32_t tdepth;
+    unsigned long long *stat_tbl;
 };
 
 // Stack frame (48 bytes in LDS): the intervals of a node's four children and, in
-// meta, the node's pattern position less one (bits 0-15), its remaining budget (16-19),
-// its pattern symbol (20-23) and the children still to visit (24-27).
+// meta.x, the node's pattern position less one (bits 0-15), its remaining budget (16-19),
+// its pattern symbol (20-23) and the children still to visit (24-27); in meta.y the code
+// of the node's matched suffix (see Dfs::code).
 struct Frame {
     uint4 k, l;
     uint4 meta;
@@ -553,6 +559,9 @@ struct Dfs {
     uint64_t bp03;                  // D breakpoints 0..3, 16 bits each (0xFFFF: none)
     uint32_t bp4;                   // D breakpoint 4
     uint32_t i, zr, k, l;           // current node: pattern symbol i (>= 0) still to match
+    // substitution search: code of the node's matched suffix S = W'[i+1 .. m-1], sum_j
+    // S[j] 4^j (exact while S is shorter than the prefix table's depth, unused after)
+    uint32_t code;
     uint32_t sp;                    // frames on the stack
     uint32_t hits, status, nodes;
     bool done;
@@ -645,6 +654,7 @@ struct Dfs {
         l = a.lay.n;
         i = m - 1;
         zr = z0;
+        code = 0;
         wtag = ~0ull;
         uint32_t nbp = 0;
         bp03 = ~0ull;
@@ -670,24 +680,36 @@ struct Dfs {
 };
 
 // Loads of one expansion, issued before anything waits on them: the symbol, the buckets
-// and the frame on top of the stack, which is the one a pop takes (a node pops only
-// when it pushes nothing).
+// (or, for a node whose matched suffix is shorter than the prefix table's depth, its
+// children's 32 bytes of the table instead) and the frame on top of the stack, which is
+// the one a pop takes (a node pops only when it pushes nothing).
 template <int I, int L>
 struct NodeLoads {
     Pair<I, L> pr;
+    uint4 t0, t1;          // table: (k, l) of children 0, 1 and of children 2, 3
+    bool tbl;
     uint4 tk, tl;
-    uint32_t tmeta;
+    uint2 tmeta;
 };
 
 template <int I, int L>
 __device__ __forceinline__ void dfs_load(const DfsArgs &a, Dfs &d, uint32_t q, const Frame *fr, NodeLoads<I, L> &nl)
 {
     d.fetch_code(a);
-    nl.pr.load(a.lay, q, d.k ? d.k : 1u, d.l);
+    const uint32_t depth = d.m - 1 - d.i;            // length of the matched suffix
+    nl.tbl = L == 1 && d.k != 0 && depth < a.tdepth;
+    if (nl.tbl) {
+        const uint4 *t = a.tab + (table_level_base(depth + 1) / 2 + 2 * (uint64_t)d.code);
+        nl.t0 = t[0];
+        nl.t1 = t[1];
+        nl.pr.same = true;
+    } else {
+        nl.pr.load(a.lay, q, d.k ? d.k : 1u, d.l);
+    }
     const Frame *ft = fr + (d.sp ? d.sp - 1 : a.fcap - 1);
     nl.tk = ft->k;
     nl.tl = ft->l;
-    nl.tmeta = ft->meta.x;
+    nl.tmeta = make_uint2(ft->meta.x, ft->meta.y);
 }
 
 // Expands the current node: one Occ8 at (k-1, l) gives the intervals of all four
@@ -702,27 +724,40 @@ __device__ __forceinline__ void dfs_load(const DfsArgs &a, Dfs &d, uint32_t q, c
 // update free of branches.
 template <int I, int L>
 __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeLoads<I, L> &nl, uint32_t q,
-                                           Frame *fr, bool lead, uint64_t &n_occ, uint64_t &n_bk)
+                                           Frame *fr, bool lead, uint64_t &n_occ, uint64_t &n_bk, uint64_t &n_tb)
 {
     const uint32_t kk = d.k ? d.k : 1u;
     const uint32_t wi = d.sym(a);
-    Occ4 o1, o2;
-    occ8<I, L>(a.lay, nl.pr, q, kk, d.l, o1, o2);
-    // children; at the root (0, n) Occ(., -1) is zero and Occ(., n) is every symbol's total
     const bool root = d.k == 0;
     const uint32_t C0 = a.lay.C[0], C1 = a.lay.C[1], C2 = a.lay.C[2], C3 = a.lay.C[3];
     uint32_t kb[4], lb[4];
-    kb[0] = C0 + 1 + (root ? 0u : o1.a);
-    kb[1] = C1 + 1 + (root ? 0u : o1.c);
-    kb[2] = C2 + 1 + (root ? 0u : o1.g);
-    kb[3] = C3 + 1 + (root ? 0u : o1.t);
-    lb[0] = C0 + o2.a;
-    lb[1] = C1 + o2.c;
-    lb[2] = C2 + o2.g;
-    lb[3] = C3 + o2.t;
+    if (nl.tbl) {
+        // the children's intervals as the table holds them (Listing 1 from (0, n))
+        kb[0] = nl.t0.x;
+        lb[0] = nl.t0.y;
+        kb[1] = nl.t0.z;
+        lb[1] = nl.t0.w;
+        kb[2] = nl.t1.x;
+        lb[2] = nl.t1.y;
+        kb[3] = nl.t1.z;
+        lb[3] = nl.t1.w;
+    } else {
+        Occ4 o1, o2;
+        occ8<I, L>(a.lay, nl.pr, q, kk, d.l, o1, o2);
+        // children; at the root (0, n) Occ(., -1) is zero and Occ(., n) is every symbol's total
+        kb[0] = C0 + 1 + (root ? 0u : o1.a);
+        kb[1] = C1 + 1 + (root ? 0u : o1.c);
+        kb[2] = C2 + 1 + (root ? 0u : o1.g);
+        kb[3] = C3 + 1 + (root ? 0u : o1.t);
+        lb[0] = C0 + o2.a;
+        lb[1] = C1 + o2.c;
+        lb[2] = C2 + o2.g;
+        lb[3] = C3 + o2.t;
+    }
     if (a.stat_occ && lead) {
         n_occ += 1;
-        n_bk += root ? 0 : (nl.pr.same ? 1 : 2);
+        n_bk += (root || nl.tbl) ? 0 : (nl.pr.same ? 1 : 2);
+        n_tb += nl.tbl ? 1 : 0;
     }
     // surviving children
     const int cpos = (int)d.i - 1;
@@ -756,6 +791,7 @@ __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeL
         fw->k = make_uint4(kb[0], kb[1], kb[2], kb[3]);
         fw->l = make_uint4(lb[0], lb[1], lb[2], lb[3]);
         fw->meta.x = (ci & 0xFFFFu) | (d.zr << 16) | (wi << 20) | (rest << 24);
+        fw->meta.y = d.code;
     }
     const uint32_t nsp = d.sp + (rest ? 1u : 0u);
     // otherwise the next node comes from the top frame: a mismatch child while there is
@@ -763,7 +799,7 @@ __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeL
     const bool pop = !advance && nsp > 0;
     Frame *ft = fr + (pop ? nsp - 1 : spare);
     const uint4 tk = nl.tk, tl = nl.tl;
-    const uint32_t meta = nl.tmeta;
+    const uint32_t meta = nl.tmeta.x;
     const uint32_t trest = (meta >> 24) & 0xFu, twi = (meta >> 20) & 0xFu;
     const uint32_t tmm = trest & ~(twi < 4 ? 1u << twi : 0u);
     const uint32_t bt = (uint32_t)__builtin_ctz((tmm ? tmm : trest) | 0x10u) & 3u;
@@ -772,6 +808,7 @@ __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeL
     d.k = advance ? sel4(cont, kb[0], kb[1], kb[2], kb[3]) : sel4(bt, tk.x, tk.y, tk.z, tk.w);
     d.l = advance ? sel4(cont, lb[0], lb[1], lb[2], lb[3]) : sel4(bt, tl.x, tl.y, tl.z, tl.w);
     d.i = advance ? ci : (meta & 0xFFFFu);
+    d.code = advance ? (d.code << 2) | cont : (nl.tmeta.y << 2) | bt;
     d.zr = advance ? d.zr - (cont != wi ? 1u : 0u) : ((meta >> 16) & 0xFu) - (bt != twi ? 1u : 0u);
     d.sp = pop && !left ? nsp - 1 : nsp;
     d.done = !advance && !pop;
@@ -1008,7 +1045,7 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
         d.request(a, item);
         d.begin(a);
     }
-    uint64_t n_occ = 0, n_bk = 0;
+    uint64_t n_occ = 0, n_bk = 0, n_tb = 0;
     for (;;) {
         const bool active = d.rs != kEmpty;
         if (!__any(active)) break;
@@ -1020,13 +1057,14 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
             } else {
                 NodeLoads<I, 1> nl;
                 dfs_load<I, 1>(a, d, 0, fr, nl);
-                dfs_expand<I, 1>(a, d, nl, 0, fr, true, n_occ, n_bk);
+                dfs_expand<I, 1>(a, d, nl, 0, fr, true, n_occ, n_bk, n_tb);
             }
         }
         dfs_emit<1, K, false>(a, d, active, true);
     }
     wave_add(a.stat_occ, n_occ);
     wave_add(a.stat_bk, n_bk);
+    wave_add(a.stat_tbl, n_tb);
 }
 
 // Each round: idle groups (refilled in batches) take read-strands and issue their
@@ -1085,6 +1123,7 @@ __device__ __forceinline__ void dfs_steal(const DfsArgs &a, Dfs &d, Frame *frame
         d.k = sel4(c, kk.x, kk.y, kk.z, kk.w);
         d.l = sel4(c, ll.x, ll.y, ll.z, ll.w);
         d.i = vmx & 0xFFFFu;
+        d.code = (vmy << 2) | c;
         d.zr = vzr - 1u;
     }
     d.rs = vrs;
@@ -1121,7 +1160,7 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
     d.done = false;
     WaveQueue wq;
     wq.start(a.queue);
-    uint64_t n_occ = 0, n_bk = 0;
+    uint64_t n_occ = 0, n_bk = 0, n_tb = 0;
     for (;;) {
         if constexpr (S) {
             if (wq.exhausted) dfs_steal<K>(a, d, lds_frames, fr);
@@ -1143,7 +1182,7 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
             } else {
                 NodeLoads<I, L> nl;
                 dfs_load<I, L>(a, d, q, fr, nl);
-                dfs_expand<I, L>(a, d, nl, q, fr, lead, n_occ, n_bk);
+                dfs_expand<I, L>(a, d, nl, q, fr, lead, n_occ, n_bk, n_tb);
             }
         }
         if (fresh) d.begin(a);
@@ -1157,6 +1196,7 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
     }
     wave_add(a.stat_occ, n_occ);
     wave_add(a.stat_bk, n_bk);
+    wave_add(a.stat_tbl, n_tb);
 }
 
 template <int I, int L, int K, bool S>
@@ -1673,6 +1713,12 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     a.stat_occ = (c.flags & FM_STATS) ? (unsigned long long *)(ws + kWsStatOcc) : nullptr;
     a.stat_bk = (c.flags & FM_STATS) ? (unsigned long long *)(ws + kWsStatBuckets) : nullptr;
     a.stat_steal = (c.flags & FM_STATS) ? (unsigned long long *)(ws + kWsStatSteal) : nullptr;
+    a.stat_tbl = (c.flags & FM_STATS) ? (unsigned long long *)(ws + kWsStatTable) : nullptr;
+    // the prefix table serves substitution nodes (the gapped search consumes pattern and
+    // string at different rates, so a node's depth is not m - 1 - i there)
+    a.tab = (const uint4 *)idx->ptab;
+    a.tdepth = (c.flags & FM_GAPS) || !idx->ptab ? 0u : (t.table_depth < idx->table_levels ? t.table_depth
+                                                                                            : idx->table_levels);
     const bool ex = c.ex_out != nullptr;
     a.ex_out = (uint2 *)c.ex_out;
     a.ex_nstr = strand_count(c.ex_flags);

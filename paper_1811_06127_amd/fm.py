@@ -22,7 +22,8 @@ FM_OP_EXACT, FM_OP_DARRAY, FM_OP_INEXACT, FM_OP_LOCATE = 0, 1, 2, 3
 FM_ZMAX = 4
 
 # byte offsets inside the inexact workspace (see fm_search_inexact in fm.h)
-WS_REQUIRED, WS_STAT_OCC, WS_STAT_BUCKETS, WS_STAT_WALK, WS_STAT_WALK_BK, WS_STAT_STEAL = 8, 64, 72, 80, 88, 96
+WS_REQUIRED, WS_STAT_OCC, WS_STAT_BUCKETS, WS_STAT_WALK, WS_STAT_WALK_BK, WS_STAT_STEAL, WS_STAT_TABLE = \
+    8, 64, 72, 80, 88, 96, 104
 
 
 class FmError(RuntimeError):
@@ -44,13 +45,13 @@ class Info(C.Structure):
     _fields_ = [("n", C.c_uint64), ("dollar_row", C.c_uint64), ("C", C.c_uint64 * 5),
                 ("rev_dollar_row", C.c_uint64), ("rev_C", C.c_uint64 * 5), ("occ_interval", C.c_uint32),
                 ("layouts", C.c_uint32), ("has_reverse", C.c_uint32), ("sa_sample", C.c_uint32),
-                ("device_bytes", C.c_uint64), ("caller_memory", C.c_uint32), ("pad", C.c_uint32)]
+                ("device_bytes", C.c_uint64), ("caller_memory", C.c_uint32), ("table_depth", C.c_uint32)]
 
 
 class Tuning(C.Structure):
     _fields_ = [("occ_interval", C.c_uint32), ("lanes", C.c_uint32), ("depth", C.c_uint32),
                 ("block", C.c_uint32), ("waves_per_cu", C.c_uint32), ("node_budget", C.c_uint32),
-                ("order", C.c_uint32)]
+                ("order", C.c_uint32), ("table_depth", C.c_uint32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -283,7 +284,7 @@ class Index:
         return {"n": i.n, "dollar_row": i.dollar_row, "C": list(i.C), "rev_dollar_row": i.rev_dollar_row,
                 "rev_C": list(i.rev_C), "occ_interval": i.occ_interval, "layouts": i.layouts,
                 "has_reverse": bool(i.has_reverse), "sa_sample": i.sa_sample, "device_bytes": i.device_bytes,
-                "caller_memory": bool(i.caller_memory)}
+                "caller_memory": bool(i.caller_memory), "table_depth": i.table_depth}
 
     def get_tuning(self, op: int) -> dict:
         t = Tuning()
@@ -395,9 +396,9 @@ class InexactBuffers:
         return int(self.ws[WS_REQUIRED:WS_REQUIRED + 8].cpu().numpy().view(np.uint64)[0])
 
     def stats(self) -> dict:
-        v = self.ws[WS_STAT_OCC:WS_STAT_OCC + 40].cpu().numpy().view(np.uint64)
+        v = self.ws[WS_STAT_OCC:WS_STAT_OCC + 48].cpu().numpy().view(np.uint64)
         return {"occ8": int(v[0]), "buckets": int(v[1]), "walk_steps": int(v[2]), "walk_buckets": int(v[3]),
-                "subtrees": int(v[4])}
+                "subtrees": int(v[4]), "table": int(v[5])}
 
 
 def fm_search_inexact(idx: Index, codes: torch.Tensor, offs: torch.Tensor, z: torch.Tensor, flags: int,

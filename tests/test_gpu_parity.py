@@ -525,3 +525,49 @@ def test_non_base_codes_above_4(small):
     assert np.array_equal(to_u32(ex), want_ex)
     wh, wo = x.inexact(odd, rd.offs, rd.z, oracle.BOTH, "listing2_darray", rev=xr)
     assert_same_hits(fm.hits_to_numpy(bufs, rd.count), wh, wo, "both")
+
+
+def test_prefix_table_depths():
+    """The prefix table (children of nodes whose matched suffix is shorter than
+    table_depth come from the table, not from an Occ8) changes nothing: at every depth
+    0..T, hits and node counts equal the oracle's (Listing 2 with and without the D bound,
+    z up to 2 with subtree transfers), exact intervals from fm_search_both equal Listing
+    1's, for the plain and batched kernels and several layouts; FM_STATS counts the table
+    nodes (none at depth 0, none with two lanes per read-strand, and they fetch no
+    bucket)."""
+    R = synth.reference_with_repeats(1 << 20, 4343, copy_frac=0.08, copy_len=(300, 3000), copy_sub=0.02,
+                                     tandem_frac=0.01, tandem_unit=(2, 30), tandem_len=(100, 600))
+    x = oracle.OracleIndex(R)
+    xr = oracle.OracleIndex(oracle.reverse_text(R))
+    idx = fm.Index.from_text(R, occ_interval=64, flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_ALL_LAYOUTS)
+    T = idx.info()["table_depth"]
+    assert T == 7 and idx.get_tuning(fm.FM_OP_INEXACT)["table_depth"] == T
+    with pytest.raises(fm.FmError):
+        idx.set_tuning(fm.FM_OP_INEXACT, table_depth=T + 1)
+    rd = synth.simulate_reads(R, 1200, 77, length=(40, 120), sub=(0.0, 0.03), z=(0, 2))
+    cd, od, zd = fm.reads_to_device(rd.codes, rd.offs, rd.z)
+    want_ex = x.exact(rd.codes, rd.offs, oracle.BOTH, "listing1")
+    for flags, method in ((fm.FM_BOTH | fm.FM_DARRAY, "listing2_darray"), (fm.FM_BOTH, "listing2")):
+        wh, wo, wn = x.inexact(rd.codes, rd.offs, rd.z, oracle.BOTH, method, rev=xr, return_nodes=True)
+        for depth in (0, 1, 3, 5, T):
+            for I, lanes, extra in ((64, 1, 0), (64, 1, fm.FM_PLAIN), (128, 1, 0), (448, 1, 0), (64, 2, 0)):
+                idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=I, lanes=lanes, table_depth=depth)
+                try:
+                    bufs = fm.fm_search_inexact(idx, cd, od, zd, flags | fm.FM_STATS | extra, 2, 1 << 16)
+                    got = fm.hits_to_numpy(bufs, rd.count)
+                    st = bufs.stats()
+                    ex, b2 = fm.fm_search_both(idx, cd, od, zd, fm.FM_BOTH, flags | extra, 2, 1 << 16)
+                    got2 = fm.hits_to_numpy(b2, rd.count)
+                finally:
+                    idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=64, lanes=1, table_depth=T)
+                tag = (hex(flags), depth, I, lanes, extra)
+                assert_same_hits(got, wh, wo, tag)
+                assert_same_hits(got2, wh, wo, tag)
+                assert np.array_equal(to_u32(ex), want_ex), tag
+                assert st["occ8"] == int(wn.sum()), tag
+                if depth == 0 or lanes > 1:
+                    assert st["table"] == 0, tag
+                else:
+                    assert st["table"] > 0, tag
+                say(tag, "nodes", st["occ8"], "table nodes", st["table"], "buckets", st["buckets"])
+    idx.free()

@@ -225,16 +225,21 @@ def layout_bytes(n, I):
 
 def test_index_bytes_and_required_bytes(tmp_path):
     """fm_index_bytes adds up the layouts kept (the one asked for, or all seven; both
-    directions with FM_LOAD_REVERSE) and the SA samples (4 bytes per 32 rows), each piece
-    256-byte aligned; fm_index_required_bytes gives the same from a file's header."""
+    directions with FM_LOAD_REVERSE), the prefix table (8 bytes per string of length 1..T)
+    and the SA samples (4 bytes per 32 rows), each piece 256-byte aligned;
+    fm_index_required_bytes gives the same from a file's header."""
     a = lambda x: (x + 255) // 256 * 256
-    for n in (0, 1, 1000, 70_001, 3_100_000_000):
+    depths = {0: 0, 1: 0, 1000: 1, 70_001: 5, 1 << 20: 7, 1 << 28: 11, 3_100_000_000: 12}
+    for n, T in depths.items():
+        # prefix table: 8 bytes for every string of length 1..T, T = floor(log4(n + 1)) - 3 in [0, 12]
+        assert T == max(0, min(12, int(np.floor(np.log(n + 1) / np.log(4) + 1e-12)) - 3)) or n + 1 < 4
+        tab = a(8 * sum(4 ** t for t in range(1, T + 1)))
         for I in (64, 96, 128, 192, 224, 256, 448):
-            assert fm.fm_index_bytes(n, I) == a(layout_bytes(n, I))
-            assert fm.fm_index_bytes(n, I, fm.FM_LOAD_REVERSE) == 2 * a(layout_bytes(n, I))
+            assert fm.fm_index_bytes(n, I) == a(layout_bytes(n, I)) + tab
+            assert fm.fm_index_bytes(n, I, fm.FM_LOAD_REVERSE) == 2 * a(layout_bytes(n, I)) + tab
         every = sum(a(layout_bytes(n, I)) for I in (64, 96, 128, 192, 224, 256, 448))
-        assert fm.fm_index_bytes(n, 128, fm.FM_LOAD_ALL_LAYOUTS | fm.FM_LOAD_REVERSE) == 2 * every
-        assert fm.fm_index_bytes(n, 64, fm.FM_LOAD_LOCATE) == a(layout_bytes(n, 64)) + a((n + 1 + 31) // 32 * 4)
+        assert fm.fm_index_bytes(n, 128, fm.FM_LOAD_ALL_LAYOUTS | fm.FM_LOAD_REVERSE) == 2 * every + tab
+        assert fm.fm_index_bytes(n, 64, fm.FM_LOAD_LOCATE) == a(layout_bytes(n, 64)) + tab + a((n + 1 + 31) // 32 * 4)
     with pytest.raises(fm.FmError):
         fm.fm_index_bytes(1000, 100)
     with pytest.raises(fm.FmError):
