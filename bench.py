@@ -42,7 +42,7 @@ MEASURED_TRAFFIC = {
     ("c77bb245ef765e06", "dfs_batched<64, 1, 1, false>", (64, 1, 1, 256, 8, 1), "2^24"): (12_445_370_940, 140_566_474),
     ("c77bb245ef765e06", "dfs_batched<64, 1, 1, true>", (64, 1, 1, 256, 8, 1), "3.1e9"): (339_978_555_080, 298_035_042),
 }
-TRAFFIC_KEY_FIELDS = ("occ_interval", "lanes", "depth", "block", "waves_per_cu", "order")
+TRAFFIC_KEY_FIELDS = ("occ_interval", "lanes", "depth", "block", "waves_per_cu", "order", "table_depth")
 KERNEL_SOURCES = ("search.hip", "fm_device.hpp", "fm_internal.hpp")
 
 
@@ -438,7 +438,8 @@ def step_2e24(args):
     # interval (8 bytes), plus 16 bytes per hit
     alg = {
         "d_walk": both_stats["walk_buckets"] * (16 + Iw // 4) + 2 * total_len + 16 * nrs,
-        "dfs": both_stats["buckets"] * (16 + I // 4) + 2 * total_len + 32 * nrs + 16 * n_hits,
+        "dfs": both_stats["buckets"] * (16 + I // 4) + 32 * both_stats["table"] + 2 * total_len + 32 * nrs
+        + 16 * n_hits,
     }
     dom = max(("d_walk", "dfs"), key=lambda k: phase_ms[k])
     achieved = alg[dom] / (phase_ms[dom] / 1e3) / 1e9
@@ -496,7 +497,8 @@ def step_2e24(args):
                            "equal_to_one_pass": fused_equal},
         "work_per_step": {"exact_steps": ex_stats["steps"], "exact_buckets": ex_stats["buckets"],
                           "d_walk_steps": in_stats["walk_steps"], "d_walk_buckets": in_stats["walk_buckets"],
-                          "dfs_nodes": both_stats["occ8"], "dfs_buckets": both_stats["buckets"], "hits": n_hits},
+                          "dfs_nodes": both_stats["occ8"], "dfs_buckets": both_stats["buckets"],
+                          "dfs_table_nodes": both_stats["table"], "hits": n_hits},
         "tuning": tuning,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -604,7 +606,7 @@ def genome_headline(args):
     tuning = {"inexact": idx.get_tuning(fm.FM_OP_INEXACT), "d_walk": idx.get_tuning(fm.FM_OP_DARRAY)}
 
     # eager calls with work counters: nodes, buckets and hits per batch, and each batch's outputs
-    work = {"occ8": 0, "buckets": 0, "walk_steps": 0, "walk_buckets": 0, "subtrees": 0}
+    work = {"occ8": 0, "buckets": 0, "walk_steps": 0, "walk_buckets": 0, "subtrees": 0, "table": 0}
     hits_per_batch, eager = [], []
     for codes, z, ex, bufs in batches:
         fm.fm_search_both(idx, codes, offs, z, fm.FM_BOTH, flags | fm.FM_STATS, Z, cap, out=ex, bufs=bufs)
@@ -698,11 +700,11 @@ def genome_headline(args):
     for p in plans:
         p.free()
 
-    # roofline of the DFS: algorithmic bytes per launch (its bucket fetches at 32 B, the
-    # patterns read twice, 32 B per read-strand of records, 16 B per hit), averaged over the
-    # batches, over its average duration in the timed region
+    # roofline of the DFS: algorithmic bytes per launch (its bucket fetches at 32 B, its
+    # prefix-table reads at 32 B, the patterns read twice, 32 B per read-strand of records,
+    # 16 B per hit), averaged over the batches, over its average duration in the timed region
     nrs = 2 * B
-    alg = (work["buckets"] * 32 + NB * (2 * B * LEN + 32 * nrs) + 16 * sum(hits_per_batch)) / NB
+    alg = ((work["buckets"] + work["table"]) * 32 + NB * (2 * B * LEN + 32 * nrs) + 16 * sum(hits_per_batch)) / NB
     achieved = alg / (phase["dfs"] / 1e3) / 1e9
     tcfg = tuning["inexact"]
     key = (kernel_source_hash(), dfs_kernel_name(tcfg, Z), tuple(tcfg[f] for f in TRAFFIC_KEY_FIELDS), "3.1e9")
@@ -798,6 +800,7 @@ def genome_headline(args):
             "index_build_s": round(build_s, 2),
             "phase_ms_per_step": {k: round(v, 3) for k, v in phase.items()},
             "work_per_batch": {"dfs_nodes": work["occ8"] // NB, "dfs_buckets": work["buckets"] // NB,
+                               "dfs_table_nodes": work["table"] // NB,
                                "d_walk_steps": work["walk_steps"] // NB, "d_walk_buckets": work["walk_buckets"] // NB,
                                "dfs_subtrees_taken_over": work["subtrees"] // NB},
             "dfs_occ8_per_s": round(work["occ8"] / NB / (phase["dfs"] / 1e3), 1),

@@ -534,7 +534,7 @@ def test_prefix_table_depths():
     z up to 2 with subtree transfers), exact intervals from fm_search_both equal Listing
     1's, for the plain and batched kernels and several layouts; FM_STATS counts the table
     nodes (none at depth 0, none with two lanes per read-strand, and they fetch no
-    bucket)."""
+    bucket; the root takes its children from C at any depth)."""
     R = synth.reference_with_repeats(1 << 20, 4343, copy_frac=0.08, copy_len=(300, 3000), copy_sub=0.02,
                                      tandem_frac=0.01, tandem_unit=(2, 30), tandem_len=(100, 600))
     x = oracle.OracleIndex(R)
@@ -565,7 +565,7 @@ def test_prefix_table_depths():
                 assert_same_hits(got2, wh, wo, tag)
                 assert np.array_equal(to_u32(ex), want_ex), tag
                 assert st["occ8"] == int(wn.sum()), tag
-                if depth == 0 or lanes > 1:
+                if depth <= 1 or lanes > 1:             # depth 1 would serve the root alone, which reads C
                     assert st["table"] == 0, tag
                 else:
                     assert st["table"] > 0, tag
