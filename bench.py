@@ -33,14 +33,14 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "reads/s & Occ8 queries/s, batched vs plain kernel, bit-exact; p99 latency"
 
-# Bytes per launch of the dominant kernel measured with rocprofv3 (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by
-# the same counters on a plain 1 GiB copy kernel; profiles/search_kernels_2e24_counters.md and
-# profiles/genome_dfs_3e9_counters.md). They hold only for the kernel sources, launch settings and workload they
-# were measured with: the key is a hash of the kernel sources, the kernel, its tuning and the workload; any other
-# combination reports traffic as null.
+# Bytes per launch of the dominant kernel measured with rocprofv3 (read requests and WRITE_SIZE per dispatch, checked
+# against the same counters on a plain 1 GiB copy kernel; profiles/genome_dfs_3e9_counters.md). They hold only for
+# the kernel sources, launch settings and workload they were measured with: the key is a hash of the kernel sources,
+# the kernel, its tuning and the workload; any other combination reports traffic as null.
 MEASURED_TRAFFIC = {
-    ("c77bb245ef765e06", "dfs_batched<64, 1, 1, false>", (64, 1, 1, 256, 8, 1), "2^24"): (12_445_370_940, 140_566_474),
-    ("c77bb245ef765e06", "dfs_batched<64, 1, 1, true>", (64, 1, 1, 256, 8, 1), "3.1e9"): (339_978_555_080, 298_035_042),
+    # read = TCC_EA0_RDREQ x 128 B (each EA read request moves a 128 B line on gfx950), write = WRITE_SIZE
+    ("05410cc082ae1806", "dfs_batched<64, 1, 1, true>", (64, 1, 1, 256, 8, 1, 12), "3.1e9"):
+        (276_670_730_208, 315_871_636),
 }
 TRAFFIC_KEY_FIELDS = ("occ_interval", "lanes", "depth", "block", "waves_per_cu", "order", "table_depth")
 KERNEL_SOURCES = ("search.hip", "fm_device.hpp", "fm_internal.hpp")
