@@ -111,22 +111,38 @@ def log(*a):
 
 def locate_rate(fm, torch, idx, hits, nh: int, reps: int = 3) -> dict:
     """fm_locate over the rows of the first nh hit records (Eq. 4-5): rows located per
-    second and Psi^-1 steps per row, event-timed on the current stream."""
-    offs, pos, steps = fm.fm_locate(idx, hits[:nh], stats=True)
+    second and Psi^-1 steps per row, event-timed on the current stream, at 1, 2 and 4 rows
+    in flight per lane and 8 or 16 waves per CU; the fastest is kept as the index's locate
+    setting, and every setting must give the same positions."""
+    offs, ref, steps = fm.fm_locate(idx, hits[:nh], stats=True)
     rows = int(offs[-1].item())
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ev[0].record()
-    for _ in range(reps):
-        fm.fm_locate(idx, hits[:nh], cap=rows)
-    ev[1].record()
-    torch.cuda.synchronize()
-    ms = ev[0].elapsed_time(ev[1]) / reps
+    base = idx.get_tuning(fm.FM_OP_LOCATE)
+    sweep, best, same = {}, None, True
+    for depth in (1, 2, 4):
+        for waves in (8, 16):
+            idx.set_tuning(fm.FM_OP_LOCATE, depth=depth, waves_per_cu=waves)
+            _, pos = fm.fm_locate(idx, hits[:nh], cap=rows)
+            same &= bool(torch.equal(pos, ref))
+            ev[0].record()
+            for _ in range(reps):
+                fm.fm_locate(idx, hits[:nh], cap=rows)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / reps
+            sweep["depth%d_waves%d" % (depth, waves)] = round(rows / (ms / 1e3), 1)
+            if best is None or ms < best[0]:
+                best = (ms, depth, waves)
+    idx.set_tuning(fm.FM_OP_LOCATE, **{**base, "depth": best[1], "waves_per_cu": best[2]})
+    ms = best[0]
     # algorithmic bytes: a 32 B bucket per Psi^-1 step (I=64), a sample and a position per row,
     # an interval and an offset per hit
     alg = steps * 32 + rows * 8 + nh * 16
     return {"hits": nh, "rows": rows, "ms": round(ms, 4), "rows_per_s": round(rows / (ms / 1e3), 1),
             "steps_per_row": round(steps / max(rows, 1), 2), "steps_per_s": round(steps / (ms / 1e3), 1),
-            "algorithmic_gb_per_s": round(alg / (ms / 1e3) / 1e9, 1)}
+            "algorithmic_gb_per_s": round(alg / (ms / 1e3) / 1e9, 1),
+            "rows_in_flight_per_lane": best[1], "waves_per_cu": best[2], "rows_per_s_by_setting": sweep,
+            "same_positions_every_setting": same}
 
 
 def parse():

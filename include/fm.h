@@ -132,7 +132,8 @@ typedef struct {
                                        16-byte chunks (2 for I = 64/96, 4 for 128/192/224,
                                        8 for 256/448) */
     uint32_t depth;                 /* walks: read-strands in flight per lane group, 1 or 2
-                                       (the DFS keeps one) */
+                                       (the DFS keeps one); FM_OP_LOCATE: rows in flight per
+                                       lane, 1, 2 or 4 */
     uint32_t block;                 /* threads per workgroup: 64, 128, 192 or 256 */
     uint32_t waves_per_cu;          /* persistent grid = CUs * waves_per_cu * 64 / block;
                                        0 = as many as fit */
@@ -151,8 +152,8 @@ typedef struct {
                                        fm_info.table_depth. Results are the same either way. */
 } fm_tuning;
 
-/* Operations with launch settings of their own. FM_OP_LOCATE (fm_locate: layout and
- * waves_per_cu; lanes and depth are unused) is set by hand, not by fm_autotune. */
+/* Operations with launch settings of their own. FM_OP_LOCATE (fm_locate: layout, depth
+ * and waves_per_cu; lanes are unused) is set by hand, not by fm_autotune. */
 enum { FM_OP_EXACT = 0, FM_OP_DARRAY = 1, FM_OP_INEXACT = 2, FM_OP_LOCATE = 3 };
 
 /* ----------------------------------------------------------------- general */

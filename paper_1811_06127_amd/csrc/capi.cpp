@@ -71,13 +71,13 @@ void release_events(const fm_index *idx)
 
 uint32_t nstrands(uint32_t flags) { return ((flags & FM_FWD) ? 1u : 0u) + ((flags & FM_REVCOMP) ? 1u : 0u); }
 
-bool valid_tuning(const fm_index *idx, const fm_tuning &t)
+bool valid_tuning(const fm_index *idx, int op, const fm_tuning &t)
 {
     const int li = ilog(t.occ_interval);
     if (li < 0 || !idx->lay[li]) return false;
     if (t.lanes != 1 && t.lanes != 2 && t.lanes != 4 && t.lanes != 8) return false;
     if (t.lanes > max_lanes(t.occ_interval)) return false;
-    if (t.depth != 1 && t.depth != 2) return false;
+    if (t.depth != 1 && t.depth != 2 && !(op == FM_OP_LOCATE && t.depth == 4)) return false;
     if (t.block < 64 || t.block > 256 || t.block % 64) return false;
     if (t.order > 1) return false;
     if (t.table_depth > idx->table_levels) return false;
@@ -482,7 +482,7 @@ int fm_get_tuning(const fm_index *idx, int op, fm_tuning *out)
 
 int fm_set_tuning(fm_index *idx, int op, const fm_tuning *t)
 {
-    if (!idx || !t || op < 0 || op > FM_OP_LOCATE || !valid_tuning(idx, *t)) return FM_EINVAL;
+    if (!idx || !t || op < 0 || op > FM_OP_LOCATE || !valid_tuning(idx, op, *t)) return FM_EINVAL;
     if (op == FM_OP_DARRAY && (!idx->has_rev || !idx->rlay[ilog(t->occ_interval)])) return FM_EINVAL;
     idx->tune[op] = *t;
     return FM_OK;

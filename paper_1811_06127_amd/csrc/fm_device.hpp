@@ -235,6 +235,35 @@ __device__ __forceinline__ void part2(const Bucket<I, L> &a, const Bucket<I, L> 
     o2 = s2;
 }
 
+// Occ(sym, p) before the '$' correction for the position at offset r of a bucket held
+// whole by one lane (L = 1): the bucket's count of sym plus the symbols equal to sym at
+// offsets 0..r (sbc: the superblock counts of compact layouts).
+template <int I>
+__device__ __forceinline__ uint32_t part1(const Bucket<I, 1> &bk, uint32_t r, uint32_t sym, uint4 sbc)
+{
+    const uint32_t pat = sym * EVEN;
+    uint32_t s = 0;
+#pragma unroll
+    for (int c = 0; c < Geo<I>::USED; ++c) {
+        const uint4 v = bk.v[c];
+        if constexpr (Geo<I>::COMPACT) {
+            if (c == 0) s += u16_count(v, sym) + sel4(sym, sbc.x, sbc.y, sbc.z, sbc.w);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int gw = compact_gw(c, i);
+                if (gw < 0) continue;
+                const uint32_t x = w[i] ^ pat;
+                s = __popc(~(x | (x >> 1)) & EVEN & gword_mask(gw, r)) + s;
+            }
+        } else {
+            if (c == 0) s += sel4(sym, v.x, v.y, v.z, v.w);
+            else s += eq_count_chunk(v, pat, chunk_rel(r, c));
+        }
+    }
+    return s;
+}
+
 // The BWT symbol at offset r of a bucket held whole by one lane (L = 1): 2 bits of the
 // symbol word r / 16. Compact layouts keep symbol words 0-1 in chunk 0 (after the
 // counts) and four per chunk after it; the others keep four per chunk from chunk 1.

@@ -1867,67 +1867,124 @@ __device__ __forceinline__ uint64_t locate_interval(const LocateArgs &a, uint64_
 // Eq. 4-5: from row k, apply Psi^-1(i) = C[BWT[i]] + Occ(BWT[i], i) until the row is a
 // multiple of kSaSample (its SA value is stored) or is the '$' row (SA = 0); SA[k] is
 // that value plus the number of steps. One bucket fetch per step gives both BWT[i] and
-// Occ(BWT[i], i). Persistent, with the work queue and round order of walk_batched.
-template <int I>
+// Occ(BWT[i], i); only the stepped symbol's occurrences are counted. Each lane keeps P
+// rows in flight (independent chains, each step waiting only for its own bucket), so a
+// lane has P bucket loads outstanding per round. Persistent, with the work queue and
+// round order of walk_batched.
+template <int I, int P>
 __global__ void __launch_bounds__(256) locate_batched(LocateArgs a)
 {
     const uint64_t all = a.offs[a.niv];
     const uint32_t total = (uint32_t)(all < a.cap ? all : a.cap);
-    uint32_t item = kEmpty, row = 0, steps = 0, sv = 0;
+    uint32_t item[P], row[P], steps[P], sv[P];
+    bool fin[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        item[p] = kEmpty;
+        row[p] = steps[p] = sv[p] = 0;
+        fin[p] = false;
+    }
     uint64_t jprev = 0, nsteps = 0;
-    bool fin = false;
     WaveQueue wq;
     wq.start(a.queue);
     for (;;) {
         // 1. the bucket of every running row
-        const bool act = item != kEmpty && !fin;
-        const uint32_t j = (act ? row : 0u) / I;
-        Bucket<I, 1> bk;
-        fetch<I, 1>(a.lay, j, 0, bk);
-        uint4 sbc = make_uint4(0, 0, 0, 0);
-        if constexpr (Geo<I>::COMPACT) sbc = a.lay.sb[j / Geo<I>::SB];
-        // 2. positions of the rows that finished last round (their sample loads are in)
-        if (fin) {
-            a.pos[item] = sv + steps;
-            item = kEmpty;
-            fin = false;
+        bool act[P];
+        Bucket<I, 1> bk[P];
+        uint4 sbc[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            act[p] = item[p] != kEmpty && !fin[p];
+            const uint32_t j = (act[p] ? row[p] : 0u) / I;
+            fetch<I, 1>(a.lay, j, 0, bk[p]);
+            sbc[p] = make_uint4(0, 0, 0, 0);
+            if constexpr (Geo<I>::COMPACT) sbc[p] = a.lay.sb[j / Geo<I>::SB];
         }
-        // 3. idle lanes take an item and find its row
-        bool fresh = false;
-        if (refill_now<1>(item == kEmpty)) {
-            const uint32_t it = wave_take<1>(wq, item == kEmpty, a.queue, total);
-            if (it != kEmpty) {
-                item = it;
-                fresh = true;
+        // 2. positions of the rows that finished last round (their sample loads are in)
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            if (fin[p]) {
+                a.pos[item[p]] = sv[p] + steps[p];
+                item[p] = kEmpty;
+                fin[p] = false;
             }
         }
-        const bool quit = !__any(item != kEmpty);
-        // 4. one step of the running rows; new rows begin
-        if (fresh) {
-            jprev = locate_interval(a, item, jprev);
-            row = a.kl[jprev * a.stride] + (uint32_t)(item - a.offs[jprev]);
-            steps = 0;
-        } else if (act) {
-            const uint32_t r = row % I;
-            const uint32_t c = symbol_at<I>(bk, r);
-            const Occ4 o = part4<I, 1>(bk, 0, r, sbc);
-            // '$' is stored as A: rows past it hold one A too many (row is never the '$' row here)
-            const uint32_t occ = sel4(c, o.a - (row > a.lay.dollar ? 1u : 0u), o.c, o.g, o.t);
-            row = c_of(a.lay, c) + occ;
-            steps += 1;
-            nsteps += 1;
+        // 3. idle slots take an item (items a lane takes only increase, across slots too)
+        bool fresh[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            fresh[p] = false;
+            if (refill_now<1>(item[p] == kEmpty)) {
+                const uint32_t it = wave_take<1>(wq, item[p] == kEmpty, a.queue, total);
+                if (it != kEmpty) {
+                    item[p] = it;
+                    fresh[p] = true;
+                }
+            }
         }
-        if (fresh || act) {
-            fin = row % kSaSample == 0 || row == a.lay.dollar;
-            if (fin) sv = row == a.lay.dollar ? 0u : a.samples[row / kSaSample];
+        bool any = false;
+#pragma unroll
+        for (int p = 0; p < P; ++p) any |= item[p] != kEmpty;
+        const bool quit = !__any(any);
+        // 4. one step of the running rows; new rows begin
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            if (fresh[p]) {
+                jprev = locate_interval(a, item[p], jprev);
+                row[p] = a.kl[jprev * a.stride] + (uint32_t)(item[p] - a.offs[jprev]);
+                steps[p] = 0;
+            } else if (act[p]) {
+                const uint32_t r = row[p] % I;
+                const uint32_t c = symbol_at<I>(bk[p], r);
+                // '$' is stored as A: rows past it hold one A too many (row is never the '$' row here)
+                const uint32_t occ = part1<I>(bk[p], r, c, sbc[p]) - ((c == 0 && row[p] > a.lay.dollar) ? 1u : 0u);
+                row[p] = c_of(a.lay, c) + occ;
+                steps[p] += 1;
+                nsteps += 1;
+            }
+            if (fresh[p] || act[p]) {
+                fin[p] = row[p] % kSaSample == 0 || row[p] == a.lay.dollar;
+                if (fin[p]) sv[p] = row[p] == a.lay.dollar ? 0u : a.samples[row[p] / kSaSample];
+            }
         }
 #pragma unroll
-        for (int t = 0; t < Bucket<I, 1>::NPL; ++t)
-            asm volatile("" ::"v"(bk.v[t].x), "v"(bk.v[t].y), "v"(bk.v[t].z), "v"(bk.v[t].w));
-        asm volatile("" ::"v"(sbc.x), "v"(sbc.y), "v"(sbc.z), "v"(sbc.w));
+        for (int p = 0; p < P; ++p) {
+#pragma unroll
+            for (int t = 0; t < Bucket<I, 1>::NPL; ++t)
+                asm volatile("" ::"v"(bk[p].v[t].x), "v"(bk[p].v[t].y), "v"(bk[p].v[t].z), "v"(bk[p].v[t].w));
+            asm volatile("" ::"v"(sbc[p].x), "v"(sbc[p].y), "v"(sbc[p].z), "v"(sbc[p].w));
+        }
         if (quit) break;
     }
     wave_add(a.stat_steps, nsteps);
+}
+
+template <int I, int P>
+static hipError_t locate_launch(const fm_index *idx, const fm_tuning &t, const LocateArgs &a, hipStream_t s)
+{
+    const int block = 256;
+    int per = max_blocks_per_cu((const void *)locate_batched<I, P>, block, 0);
+    if (t.waves_per_cu) {
+        const int want = (int)(t.waves_per_cu * 64 / block);
+        if (want >= 1 && want < per) per = want;
+    }
+    uint64_t grid = (uint64_t)idx->cu_count * per;
+    const uint64_t need = (a.cap + (uint64_t)block * P - 1) / ((uint64_t)block * P);
+    if (need < grid) grid = need;
+    if (grid == 0) grid = 1;
+    hipLaunchKernelGGL((locate_batched<I, P>), dim3((uint32_t)grid), dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int I>
+static hipError_t locate_by_depth(const fm_index *idx, const fm_tuning &t, const LocateArgs &a, hipStream_t s)
+{
+    switch (t.depth) {
+    case 1: return locate_launch<I, 1>(idx, t, a, s);
+    case 2: return locate_launch<I, 2>(idx, t, a, s);
+    case 4: return locate_launch<I, 4>(idx, t, a, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 size_t locate_ws_bytes(uint64_t niv)
@@ -1965,37 +2022,16 @@ hipError_t launch_locate(const fm_index *idx, const fm_tuning &t, const uint32_t
     a.cap = cap;
     a.queue = (uint32_t *)(w + kWsQueue);
     a.stat_steps = stats ? (unsigned long long *)(w + kWsStatWalk) : nullptr;
-    const int block = 256;
-    const void *kern = nullptr;
     switch (t.occ_interval) {
-    case 64: kern = (const void *)locate_batched<64>; break;
-    case 96: kern = (const void *)locate_batched<96>; break;
-    case 128: kern = (const void *)locate_batched<128>; break;
-    case 192: kern = (const void *)locate_batched<192>; break;
-    case 224: kern = (const void *)locate_batched<224>; break;
-    case 256: kern = (const void *)locate_batched<256>; break;
-    case 448: kern = (const void *)locate_batched<448>; break;
+    case 64: return locate_by_depth<64>(idx, t, a, s);
+    case 96: return locate_by_depth<96>(idx, t, a, s);
+    case 128: return locate_by_depth<128>(idx, t, a, s);
+    case 192: return locate_by_depth<192>(idx, t, a, s);
+    case 224: return locate_by_depth<224>(idx, t, a, s);
+    case 256: return locate_by_depth<256>(idx, t, a, s);
+    case 448: return locate_by_depth<448>(idx, t, a, s);
     default: return hipErrorInvalidValue;
     }
-    int per = max_blocks_per_cu(kern, block, 0);
-    if (t.waves_per_cu) {
-        const int want = (int)(t.waves_per_cu * 64 / block);
-        if (want >= 1 && want < per) per = want;
-    }
-    uint64_t grid = (uint64_t)idx->cu_count * per;
-    const uint64_t need = (cap + block - 1) / block;
-    if (need < grid) grid = need;
-    switch (t.occ_interval) {
-    case 64: hipLaunchKernelGGL(locate_batched<64>, dim3((uint32_t)grid), dim3(block), 0, s, a); break;
-    case 96: hipLaunchKernelGGL(locate_batched<96>, dim3((uint32_t)grid), dim3(block), 0, s, a); break;
-    case 128: hipLaunchKernelGGL(locate_batched<128>, dim3((uint32_t)grid), dim3(block), 0, s, a); break;
-    case 192: hipLaunchKernelGGL(locate_batched<192>, dim3((uint32_t)grid), dim3(block), 0, s, a); break;
-    case 224: hipLaunchKernelGGL(locate_batched<224>, dim3((uint32_t)grid), dim3(block), 0, s, a); break;
-    case 256: hipLaunchKernelGGL(locate_batched<256>, dim3((uint32_t)grid), dim3(block), 0, s, a); break;
-    case 448: hipLaunchKernelGGL(locate_batched<448>, dim3((uint32_t)grid), dim3(block), 0, s, a); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
 }
 
 }  // namespace fm

@@ -66,14 +66,23 @@ def test_every_row_all_layouts(text, device_sort):
             want.append(sa[k:l + 1])
     want = np.concatenate(want)
     for I in LAYOUTS:
-        for waves in (4, 16, 0):
-            idx.set_tuning(fm.FM_OP_LOCATE, occ_interval=I, waves_per_cu=waves)
+        for waves, depth in ((4, 1), (16, 1), (0, 1), (8, 2), (16, 4), (4, 4)):
+            idx.set_tuning(fm.FM_OP_LOCATE, occ_interval=I, waves_per_cu=waves, depth=depth)
             offs, pos = locate(idx, kl)
-            assert offs[-1] == want.size and np.array_equal(pos, want), (I, waves)
+            assert offs[-1] == want.size and np.array_equal(pos, want), (I, waves, depth)
     assert idx.get_tuning(fm.FM_OP_EXACT)["occ_interval"] == 128   # locating has settings of its own
-    # a capped call locates the first rows only and still reports the total
-    offs, pos = locate(idx, kl, cap=1000)
-    assert offs[-1] == want.size and np.array_equal(pos[:1000], want[:1000])
+    with pytest.raises(fm.FmError):
+        idx.set_tuning(fm.FM_OP_LOCATE, depth=3)
+    with pytest.raises(fm.FmError):
+        idx.set_tuning(fm.FM_OP_EXACT, depth=4)                     # four rows in flight: locating only
+    # a capped call locates the first rows only and still reports the total, at every depth
+    for depth in (1, 2, 4):
+        idx.set_tuning(fm.FM_OP_LOCATE, occ_interval=128, waves_per_cu=16, depth=depth)
+        offs, pos = locate(idx, kl, cap=1000)
+        assert offs[-1] == want.size and np.array_equal(pos[:1000], want[:1000]), depth
+        # fewer rows than lanes in flight
+        offs, pos = locate(idx, kl, cap=7)
+        assert np.array_equal(pos[:7], want[:7]), depth
     idx.free()
 
 
