@@ -266,23 +266,26 @@ __device__ __forceinline__ uint32_t part1(const Bucket<I, 1> &bk, uint32_t r, ui
 
 // The BWT symbol at offset r of a bucket held whole by one lane (L = 1): 2 bits of the
 // symbol word r / 16. Compact layouts keep symbol words 0-1 in chunk 0 (after the
-// counts) and four per chunk after it; the others keep four per chunk from chunk 1.
+// counts) and four per chunk after it; the others keep four per chunk from chunk 1. The
+// word is picked by masks rather than selects: a select between two of the bucket's
+// loaded words lets the compiler turn it into one load at a computed offset, which moves
+// the bucket to scratch memory.
 template <int I>
 __device__ __forceinline__ uint32_t symbol_at(const Bucket<I, 1> &bk, uint32_t r)
 {
-    const uint32_t g = r / 16;
-    uint32_t ch, wi;
-    if constexpr (Geo<I>::COMPACT) {
-        ch = g < 2 ? 0u : 1u + (g - 2) / 4;
-        wi = g < 2 ? 2u + g : (g - 2) % 4;
-    } else {
-        ch = 1u + g / 4;
-        wi = g % 4;
-    }
-    uint4 v = bk.v[0];
+    const int g = (int)(r / 16);
+    uint32_t word = 0;
 #pragma unroll
-    for (int t = 1; t < Bucket<I, 1>::NPL; ++t) v = ch == (uint32_t)t ? bk.v[t] : v;
-    return (sel4(wi, v.x, v.y, v.z, v.w) >> (2 * (r % 16))) & 3u;
+    for (int t = 0; t < Bucket<I, 1>::NPL; ++t) {
+        const uint32_t w[4] = {bk.v[t].x, bk.v[t].y, bk.v[t].z, bk.v[t].w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int gw = Geo<I>::COMPACT ? compact_gw(t, i) : (t == 0 ? -1 : 4 * (t - 1) + i);
+            if (gw < 0) continue;
+            word |= w[i] & (0u - (uint32_t)(g == gw));
+        }
+    }
+    return (word >> (2 * (r % 16))) & 3u;
 }
 
 // This lane's share of Occ(., p) for all four symbols at offset r of a bucket (sbc:
