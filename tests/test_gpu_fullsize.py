@@ -122,20 +122,124 @@ def test_mixed_budget_workload_full_size():
     fm.fm_search_exact(idx, codes, offs, fm.FM_BOTH | fm.FM_PLAIN, out=ex_out, ws=ex_ws)
     assert np.array_equal(ex_out.cpu().numpy().view(np.uint32), ex_b)
     say("batched == plain over %d reads" % n)
-    # sampled outputs against the text-only checkers: reads of every budget, most of them
-    # among reads the GPU reports hits for, so that the hit sets compared are not empty
-    rng = synth.Rng(78)
-    has = np.diff(in_b[1]) > 0
+    # sampled outputs against the oracle's batched text-only checkers (rank scan for the
+    # exact intervals, pigeonhole windows for the hit sets): every budget and read-length
+    # quartile, random reads, reads with hits and repeat-rich reads (several hits or an
+    # exact interval of several rows), 2,000 and more in all
+    ex_rows = ex_b.reshape(n, 2, 2)
+    exact_rows = np.where(ex_rows[:, :, 0] <= ex_rows[:, :, 1], ex_rows[:, :, 1] - ex_rows[:, :, 0] + 1, 0).max(1)
+    sample = stratified_sample(rd, in_b[1], exact_rows, seed=78)
+    check_against_text(R, rd, sample, ex_rows, in_b, "2^28")
+
+
+def stratified_sample(rd, hit_offs, exact_rows, seed):
+    """Reads of every budget and length quartile: 100 random, 50 with hits and 20
+    repeat-rich ones (5 hits or more, or an exact interval of 2 rows or more) per stratum."""
+    rng = synth.Rng(seed)
+    lens = np.diff(rd.offs.astype(np.int64))
+    nh = np.diff(hit_offs.astype(np.int64))
+    edges = np.quantile(lens, [0.25, 0.5, 0.75])
+    qb = np.searchsorted(edges, lens, side="right")
     pick = []
-    for v, k_any, k_hit in ((0, 1, 1), (1, 1, 2), (2, 1, 2)):
-        any_v = np.nonzero(rd.z == v)[0]
-        hit_v = np.nonzero((rd.z == v) & has)[0]
-        pick += [any_v[rng.integers(0, any_v.size - 1, k_any)], hit_v[rng.integers(0, hit_v.size - 1, k_hit)]]
+    for zv in (0, 1, 2):
+        for q in range(4):
+            inside = (rd.z == zv) & (qb == q)
+            for cond, k in ((inside, 100), (inside & (nh > 0), 50), (inside & ((nh >= 5) | (exact_rows >= 2)), 20)):
+                ids = np.nonzero(cond)[0]
+                pick.append(ids[np.argsort(rng.uniform(ids.size), kind="stable")[:k]])   # without replacement
     sample = np.unique(np.concatenate(pick))
+    assert sample.size >= 2000, sample.size
+    return sample
+
+
+def check_against_text(R, rd, sample, ex_rows, got, tag):
     s = rd.subset(sample)
     t0 = time.time()
-    want = oracle.exact_by_rank_scan(R, s.codes, s.offs, oracle.BOTH)
-    assert np.array_equal(ex_b.reshape(n, 2, 2)[sample].reshape(-1, 2), want)
-    wh, wo = oracle.pigeonhole_hits(R, s.codes, s.offs, s.z, oracle.BOTH)
-    say("text-only checks of %d reads in %.1fs: %d hits" % (sample.size, time.time() - t0, wh.size))
-    check_sampled_hits(in_b, wh, wo, sample, "2^28")
+    want = oracle.exact_by_rank_scan_batch(R, s.codes, s.offs, oracle.BOTH, threads=16)
+    assert np.array_equal(ex_rows[sample].reshape(-1, 2), want), tag
+    wh, wo = oracle.pigeonhole_hits_batch(R, s.codes, s.offs, s.z, oracle.BOTH, threads=16)
+    check_sampled_hits(got, wh, wo, sample, tag)
+    nh = np.diff(wo.astype(np.int64))
+    say("%s: %d sampled reads checked by the text-only checkers in %.1fs: budgets %s, %d with hits, %d hits, "
+        "%d exact hits, most hits in one read %d" % (
+            tag, sample.size, time.time() - t0, np.bincount(s.z, minlength=3).tolist(), int((nh > 0).sum()), wh.size,
+            int((want[:, 0] <= want[:, 1]).sum()), int(nh.max())))
+    assert (nh > 0).sum() >= sample.size // 3          # the hit sets compared are not mostly empty
+
+
+@pytest.mark.timeout(1200)
+def test_serving_on_the_2e28_index():
+    """The server on the 2^28-base index: 120 requests of 1..20,000 mixed reads (budgets
+    0-2, lengths 50-250) submitted while earlier ones run on three lanes; 2,000 and more
+    reads sampled across the served requests equal the oracle's text-only checkers, and
+    requests served again alone are byte-identical to their results in the mix."""
+    import threading
+
+    t0 = time.time()
+    R = synth.repeats_2e28_reference()
+    idx = fm.Index.from_text(R, occ_interval=64, flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_DEVICE_SORT)
+    pool = synth.mixed_reads_2e28(R, 600_000, seed=3005)
+    rng = synth.Rng(3106)
+    nreq = 120
+    sizes = rng.integers(1, 20_000, nreq)
+    starts = rng.integers(0, pool.count - 20_001, nreq)
+    reqs = []
+    for s0, k in zip(starts, sizes):
+        lo, hi = int(pool.offs[s0]), int(pool.offs[s0 + k])
+        reqs.append((pool.codes[lo:hi], pool.offs[s0:s0 + k + 1] - np.uint64(lo), pool.z[s0:s0 + k]))
+    say("2^28 index and %d requests (%d reads) in %.1fs" % (nreq, int(sizes.sum()), time.time() - t0))
+    flags = fm.FM_BOTH | fm.FM_DARRAY
+    with fm.Server(idx, lanes=3, flags=flags, zmax=2, arena_bytes=2 << 30) as srv:
+        tickets = []
+
+        def producer():
+            for r in reqs:
+                tickets.append(srv.submit(*r))
+                time.sleep(0.001)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        results = []
+        for t in tickets:
+            results.append(srv.wait(t, timeout=120.0))
+            srv.release(t)
+        st = srv.stats()
+        # a few requests again, alone
+        alone = []
+        for i in range(0, nreq, 15):
+            t = srv.submit(*reqs[i])
+            alone.append((i, srv.wait(t, timeout=60.0)))
+            srv.release(t)
+    assert st["error"] == 0 and st["requests_done"] == nreq + len(alone)
+    assert len({r.batch for r in results}) < nreq                  # requests shared batches
+    for i, a in alone:
+        b = results[i]
+        assert np.array_equal(a.status, b.status) and np.array_equal(a.hit_offs, b.hit_offs), i
+        assert a.hits.tobytes() == b.hits.tobytes(), i
+    say("served: %s; %d requests again alone, identical" % (st, len(alone)))
+    # the served reads as one batch: its reads, hits and statuses in request order
+    codes = np.concatenate([r[0] for r in reqs])
+    lens = np.concatenate([np.diff(r[1].astype(np.int64)) for r in reqs])
+    offs = np.zeros(lens.size + 1, np.uint64)
+    np.cumsum(lens, out=offs[1:])
+    z = np.concatenate([r[2] for r in reqs])
+    rd = synth.Reads(codes, offs, z, np.full(z.size, -1), np.zeros(z.size, np.uint8))
+    hits = np.concatenate([r.hits for r in results])
+    per = np.concatenate([np.diff(r.hit_offs.astype(np.int64)) for r in results])
+    hoffs = np.zeros(per.size + 1, np.uint64)
+    np.cumsum(per, out=hoffs[1:])
+    status = np.concatenate([r.status for r in results])
+    assert (status == fm.FM_OK).all()
+    # exact intervals are not served: the sample is stratified by budget and length only
+    sample = stratified_sample(rd, hoffs, np.zeros(rd.count, np.int64), seed=79)
+    s = rd.subset(sample)
+    t0 = time.time()
+    wh, wo = oracle.pigeonhole_hits_batch(R, s.codes, s.offs, s.z, oracle.BOTH, threads=16)
+    check_sampled_hits((hits, hoffs, status), wh, wo, sample, "served 2^28")
+    nh = np.diff(wo.astype(np.int64))
+    say("served 2^28: %d sampled reads checked in %.1fs: budgets %s, %d with hits, %d hits, most in one read %d" % (
+        sample.size, time.time() - t0, np.bincount(s.z, minlength=3).tolist(), int((nh > 0).sum()), wh.size,
+        int(nh.max())))
+    assert (nh > 0).sum() >= sample.size // 3
+    idx.free()
