@@ -132,9 +132,9 @@ def test_mixed_budget_workload_full_size():
     check_against_text(R, rd, sample, ex_rows, in_b, "2^28")
 
 
-def stratified_sample(rd, hit_offs, exact_rows, seed):
-    """Reads of every budget and length quartile: 100 random, 50 with hits and 20
-    repeat-rich ones (5 hits or more, or an exact interval of 2 rows or more) per stratum."""
+def stratified_sample(rd, hit_offs, exact_rows, seed, counts=(100, 50, 20)):
+    """Reads of every budget and length quartile: (by default) 100 random, 50 with hits and
+    20 repeat-rich ones (5 hits or more, or an exact interval of 2 rows or more) per stratum."""
     rng = synth.Rng(seed)
     lens = np.diff(rd.offs.astype(np.int64))
     nh = np.diff(hit_offs.astype(np.int64))
@@ -144,7 +144,8 @@ def stratified_sample(rd, hit_offs, exact_rows, seed):
     for zv in (0, 1, 2):
         for q in range(4):
             inside = (rd.z == zv) & (qb == q)
-            for cond, k in ((inside, 100), (inside & (nh > 0), 50), (inside & ((nh >= 5) | (exact_rows >= 2)), 20)):
+            rich = inside & ((nh >= 5) | (exact_rows >= 2))
+            for cond, k in zip((inside, inside & (nh > 0), rich), counts):
                 ids = np.nonzero(cond)[0]
                 pick.append(ids[np.argsort(rng.uniform(ids.size), kind="stable")[:k]])   # without replacement
     sample = np.unique(np.concatenate(pick))
@@ -204,13 +205,13 @@ def test_serving_on_the_2e28_index():
         for t in tickets:
             results.append(srv.wait(t, timeout=120.0))
             srv.release(t)
-        st = srv.stats()
         # a few requests again, alone
         alone = []
         for i in range(0, nreq, 15):
             t = srv.submit(*reqs[i])
             alone.append((i, srv.wait(t, timeout=60.0)))
             srv.release(t)
+        st = srv.stats()
     assert st["error"] == 0 and st["requests_done"] == nreq + len(alone)
     assert len({r.batch for r in results}) < nreq                  # requests shared batches
     for i, a in alone:
@@ -232,7 +233,7 @@ def test_serving_on_the_2e28_index():
     status = np.concatenate([r.status for r in results])
     assert (status == fm.FM_OK).all()
     # exact intervals are not served: the sample is stratified by budget and length only
-    sample = stratified_sample(rd, hoffs, np.zeros(rd.count, np.int64), seed=79)
+    sample = stratified_sample(rd, hoffs, np.zeros(rd.count, np.int64), seed=79, counts=(120, 60, 25))
     s = rd.subset(sample)
     t0 = time.time()
     wh, wo = oracle.pigeonhole_hits_batch(R, s.codes, s.offs, s.z, oracle.BOTH, threads=16)
