@@ -25,9 +25,9 @@
  *     gives {C[c]+1, C[c+1]}, the +1 convention of Listing 1, rather than Eq. 3 taken
  *     literally);
  *   - an empty final interval is reported as the canonical miss (k, l) = (1, 0);
- *   - Listing 2: the per-character loop computes its (k, l) into fresh locals from the
- *     parent's interval, every branch is guarded by k <= l, and only the substitution
- *     branches are taken (gap branches are out of scope);
+ *   - Listing 2: every child interval is computed from its parent's (k, l), every branch
+ *     that extends the string needs a non-empty interval, and by default only the
+ *     substitution branches are taken (the deletion and insertion branches on request);
  *   - read symbols outside ACGT (code 4) occur nowhere in R and never equal a base;
  *   - the reverse-complement strand of a read W is W reversed with c -> 3 - c.
  *
@@ -372,49 +372,57 @@ typedef struct {
     uint64_t nodes;        /* calls that reached the per-character loop */
 } inex_ctx;
 
-/* InexRecur(W, i, z, k, l), substitution branches only. The bound test is the
- * listing's "z < 0", strengthened to "z < D(i)" when the D-array is used (D(-1) = 0). */
-static void inex_recur(inex_ctx *c, int64_t i, int z, int64_t k, int64_t l)
+/* One edge below a node of Listing 2's search tree: the pattern position still to
+ * match, the budget left after the edge's cost, and the interval of the string W' built
+ * so far (symbols are prepended: backward search). */
+typedef struct {
+    int64_t i;
+    int z;
+    int64_t k, l;
+} inex_child;
+
+/* A node whose budget is below what its pattern prefix still needs is not expanded: the
+ * listing's "z < 0", or "z < D(i)" with the D lower bound (D(-1) = 0). */
+static int inex_pruned(const inex_ctx *c, int64_t i, int z)
 {
-    int bound = (c->D && i >= 0) ? c->D[i] : 0;
-    if (z < bound) return;
-    if (i < 0) {
-        push_hit(c->hits, c->read, c->strand, k, l, c->z0 - z);
-        return;
-    }
-    c->nodes++;
-    for (int b = 0; b < 4; b++) {
-        int64_t kb = (int64_t)c->x->C[b] + occ_at(c->x, b, k - 1) + 1;
-        int64_t lb = (int64_t)c->x->C[b] + occ_at(c->x, b, l);
-        if (kb <= lb) {
-            if (b == c->W[i]) inex_recur(c, i - 1, z, kb, lb);
-            else inex_recur(c, i - 1, z - 1, kb, lb);
-        }
-    }
+    const int need = (c->D && i >= 0) ? c->D[i] : 0;
+    return z < need;
 }
 
-/* InexRecur(W, i, z, k, l) with every branch of Listing 2: W[i] skipped (a deletion:
- * i-1, z-1, same interval), a symbol b inserted before it (i, z-1, the interval of
- * bW'), and W[i] matched or substituted by b (i-1, z or z-1, the interval of bW'); each
- * b branch only for a non-empty interval. The bound test is as in inex_recur. */
-static void gap_recur(inex_ctx *c, int64_t i, int z, int64_t k, int64_t l)
+/* The edges below node (i, z, k, l). Each symbol b whose extension bW' occurs (its
+ * interval by the update of Listing 1 is non-empty) gives a step to position i-1, free
+ * when b is W[i] and one substitution otherwise; every child interval is computed from
+ * the node's own (k, l). With gaps the listing's two other branches are taken as well:
+ * W[i] deleted (position i-1, the node's interval, cost 1) and b inserted before W[i]
+ * (position i, the interval of bW', cost 1). Returns the number of edges (at most 9). */
+static int inex_children(const inex_ctx *c, int gaps, int64_t i, int z, int64_t k, int64_t l, inex_child *out)
 {
-    const int lower = (c->D && i >= 0) ? c->D[i] : 0;     /* the bound of inex_recur */
-    if (z < lower) return;
+    int n = 0;
+    if (gaps) out[n++] = (inex_child){i - 1, z - 1, k, l};
+    for (int b = 0; b < 4; b++) {
+        const int64_t kb = (int64_t)c->x->C[b] + occ_at(c->x, b, k - 1) + 1;
+        const int64_t lb = (int64_t)c->x->C[b] + occ_at(c->x, b, l);
+        if (kb > lb) continue;
+        if (gaps) out[n++] = (inex_child){i, z - 1, kb, lb};
+        out[n++] = (inex_child){i - 1, b == c->W[i] ? z : z - 1, kb, lb};
+    }
+    return n;
+}
+
+/* The search below node (i, z, k, l): a node past the pattern's first symbol (i < 0) is a
+ * hit of cost z0 - z; any other node not pruned is expanded (counted in c->nodes) and its
+ * edges searched. */
+static void inex_search(inex_ctx *c, int gaps, int64_t i, int z, int64_t k, int64_t l)
+{
+    if (inex_pruned(c, i, z)) return;
     if (i < 0) {
         push_hit(c->hits, c->read, c->strand, k, l, c->z0 - z);
         return;
     }
     c->nodes++;
-    gap_recur(c, i - 1, z - 1, k, l);                     /* W[i] deleted */
-    for (int b = 0; b < 4; b++) {
-        const int64_t ck = (int64_t)c->x->C[b] + occ_at(c->x, b, k - 1) + 1;
-        const int64_t cl = (int64_t)c->x->C[b] + occ_at(c->x, b, l);
-        if (ck <= cl) {
-            gap_recur(c, i, z - 1, ck, cl);               /* b inserted */
-            gap_recur(c, i - 1, b == c->W[i] ? z : z - 1, ck, cl);
-        }
-    }
+    inex_child ch[9];
+    const int n = inex_children(c, gaps, i, z, k, l, ch);
+    for (int j = 0; j < n; j++) inex_search(c, gaps, ch[j].i, ch[j].z, ch[j].k, ch[j].l);
 }
 
 /* ------------------------------------------------------------------ definition of the hit set */
@@ -556,8 +564,7 @@ int64_t oracle_inexact(const oracle_index *x, const oracle_index *rev, const uin
                     oracle_darray_one(rev, P, m, D);
                     c.D = D;
                 }
-                if (method >= 3) gap_recur(&c, m - 1, z[r], 0, x->n);
-                else inex_recur(&c, m - 1, z[r], 0, x->n);
+                inex_search(&c, method >= 3, m - 1, z[r], 0, x->n);
                 nodes += c.nodes;
             }
         }

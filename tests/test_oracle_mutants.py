@@ -24,12 +24,12 @@ MUTANTS = {
                          "k = (int64_t)x->C[b] + occ_at(x, b, k) + 1;\n        l = (int64_t)x->C[b] + occ_at(x, b, l);\n    }"),
     "listing1_drop_plus1": ("k = (int64_t)x->C[b] + occ_at(x, b, k - 1) + 1;\n        l = (int64_t)x->C[b] + occ_at(x, b, l);\n    }",
                             "k = (int64_t)x->C[b] + occ_at(x, b, k - 1);\n        l = (int64_t)x->C[b] + occ_at(x, b, l);\n    }"),
-    "listing2_swap_cost": ("if (b == c->W[i]) inex_recur(c, i - 1, z, kb, lb);\n            else inex_recur(c, i - 1, z - 1, kb, lb);",
-                           "if (b == c->W[i]) inex_recur(c, i - 1, z - 1, kb, lb);\n            else inex_recur(c, i - 1, z, kb, lb);"),
-    "listing2_strict_guard": ("if (kb <= lb) {", "if (kb < lb) {"),
-    "listing2_k_index": ("int64_t kb = (int64_t)c->x->C[b] + occ_at(c->x, b, k - 1) + 1;",
-                         "int64_t kb = (int64_t)c->x->C[b] + occ_at(c->x, b, k) + 1;"),
-    "dbound_too_strong": ("int bound = (c->D && i >= 0) ? c->D[i] : 0;", "int bound = (c->D && i >= 0) ? c->D[i] + 1 : 0;"),
+    "listing2_swap_cost": ("b == c->W[i] ? z : z - 1, kb, lb}", "b == c->W[i] ? z - 1 : z, kb, lb}"),
+    "listing2_strict_guard": ("if (kb > lb) continue;", "if (kb >= lb) continue;"),
+    "listing2_k_index": ("const int64_t kb = (int64_t)c->x->C[b] + occ_at(c->x, b, k - 1) + 1;",
+                         "const int64_t kb = (int64_t)c->x->C[b] + occ_at(c->x, b, k) + 1;"),
+    "dbound_too_strong": ("const int need = (c->D && i >= 0) ? c->D[i] : 0;",
+                          "const int need = (c->D && i >= 0) ? c->D[i] + 1 : 0;"),
     "darray_no_restart": ("k = 0;\n            l = rev->n;", "k = 0;\n            l = 0;"),
     "revcomp_no_complement": ("P[i] = c < 4 ? (uint8_t)(3 - c) : c;", "P[i] = c;"),
     "definition_dollar_high": ("if (s + j >= x->n) return -1;", "if (s + j >= x->n) return 1;"),
@@ -38,8 +38,8 @@ MUTANTS = {
     "rank_scan_prefix_not_smaller": ("if (r < 0 || (r == 0 && avail < m)) less++;", "if (r < 0) less++;"),
     "pigeonhole_strict_budget": ("if (hamming(R + s, P, m) > z) continue;", "if (hamming(R + s, P, m) >= z) continue;"),
     "pigeonhole_piece_offset": ("const int64_t s = p - a[i];", "const int64_t s = p;"),
-    "gap_insert_consumes": ("gap_recur(c, i, z - 1, ck, cl);", "gap_recur(c, i - 1, z - 1, ck, cl);"),
-    "gap_delete_free": ("gap_recur(c, i - 1, z - 1, k, l);", "gap_recur(c, i - 1, z, k, l);"),
+    "gap_insert_consumes": ("(inex_child){i, z - 1, kb, lb}", "(inex_child){i - 1, z - 1, kb, lb}"),
+    "gap_delete_free": ("(inex_child){i - 1, z - 1, k, l}", "(inex_child){i - 1, z, k, l}"),
     "gap_leading_insert_allowed": ("if (i == 0) v = j == 0 ? 0 : inf;", "if (i == 0) v = (int)j;"),
     "gap_keeps_largest_cost": ("return (a->d > b->d) - (a->d < b->d);", "return (a->d < b->d) - (a->d > b->d);"),
 }
