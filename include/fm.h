@@ -240,9 +240,11 @@ int fm_get_tuning(const fm_index *idx, int op, fm_tuning *out);
  * ones or the layout was not built. Not safe concurrently with searches on idx. */
 int fm_set_tuning(fm_index *idx, int op, const fm_tuning *t);
 
-/* Times every compiled launch configuration of op on a sample batch (same arguments
- * as the corresponding search, device buffers owned by the caller, ws sized with
- * the op's workspace call for the sample and hit_cap) and keeps the fastest that
+/* Times every compiled launch configuration of op (layout, lanes, depth, waves per CU;
+ * for the substitution DFS also the claim order and the prefix table on or off) on a
+ * sample batch (same arguments as the corresponding search, device buffers owned by the
+ * caller, ws sized with the op's workspace call for the sample and hit_cap) and keeps the
+ * fastest that
  * reproduces the plain kernel's output bit for bit (a candidate replaces the current
  * choice only when it is at least 1% faster, so settings within timing noise of each
  * other resolve to the one tried first). Synchronises `stream`. If

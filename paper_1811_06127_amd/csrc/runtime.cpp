@@ -307,16 +307,20 @@ int fm_autotune(fm_index *idx, int op, const uint8_t *codes, const uint64_t *off
         if (op == FM_OP_DARRAY && !idx->rlay[ilog(I)]) continue;
         for (uint32_t lanes = 1; lanes <= max_lanes(I); lanes *= 2) {
             for (uint32_t depth = 1; depth <= (op == FM_OP_INEXACT ? 1u : 2u); ++depth) {
-                // the claim order matters only to the substitution DFS with the D bound
+                // the claim order matters only to the substitution DFS with the D bound, and
+                // the prefix table only to the substitution DFS with one lane per read-strand
                 const bool orders = op == FM_OP_INEXACT && (flags & FM_DARRAY) && !(flags & FM_GAPS);
-                for (uint32_t cand = 0; cand < (orders ? 10u : 5u); ++cand) {
+                const bool tables = op == FM_OP_INEXACT && !(flags & FM_GAPS) && lanes == 1 && idx->table_levels;
+                const uint32_t ncand = (orders ? 10u : 5u) * (tables ? 2u : 1u);
+                for (uint32_t cand = 0; cand < ncand; ++cand) {
                     static const uint32_t kWaves[5] = {0u, 4u, 8u, 12u, 16u};
                     fm_tuning t = base;
                     t.occ_interval = I;
                     t.lanes = lanes;
                     t.depth = depth;
                     t.waves_per_cu = kWaves[cand % 5];
-                    if (orders) t.order = cand < 5 ? 1u : 0u;
+                    if (orders) t.order = (cand / 5) % 2 == 0 ? 1u : 0u;
+                    if (tables) t.table_depth = cand < ncand / 2 ? idx->table_levels : 0u;
                     if (fm_set_tuning(idx, op, &t) != FM_OK) continue;
                     st = run_op(idx, call_op, codes, offs, z, nreads, run_flags, zmax, out_buf, hit_cap, hit_offs,
                                 status, ws, ws_bytes, s);
