@@ -23,18 +23,29 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
 // Per-wave view of the global work queue: the current chunk [qb, qe) of read-strands and,
 // in lane 0, the start of the next chunk, claimed one chunk ahead so that taking work
-// never waits for the atomic.
+// never waits for the atomic. The first chunk of every wave is its own without an atomic
+// (wave w of the grid takes chunk w); the chunks after those are claimed from the queue
+// counter, and not at all when the first chunks already cover the work, so a small
+// launch makes no atomic on the shared counter.
 struct WaveQueue {
     uint32_t qb, qe;
     uint32_t nxt;          // lane 0: start of the next claimed chunk
+    uint32_t fixed;        // items handed out as the waves' first chunks
     bool exhausted;
 
-    __device__ void start(uint32_t *queue)
+    __device__ void start()
     {
+        const uint32_t wpb = blockDim.x / 64;
         qb = qe = 0;
         exhausted = false;
-        nxt = 0;
-        if (__lane_id() == 0) nxt = atomicAdd(queue, kQueueChunk);
+        fixed = gridDim.x * wpb * kQueueChunk;
+        nxt = (blockIdx.x * wpb + threadIdx.x / 64) * kQueueChunk;
+    }
+
+    // The chunk after the current one (lane 0): from the queue counter while work is left.
+    __device__ uint32_t claim(uint32_t *queue, uint32_t total) const
+    {
+        return fixed >= total ? total : fixed + atomicAdd(queue, kQueueChunk);
     }
 };
 
@@ -56,7 +67,7 @@ __device__ uint32_t wave_take(WaveQueue &wq, bool need, uint32_t *queue, uint32_
             }
             wq.qb = base;
             wq.qe = base + kQueueChunk < total ? base + kQueueChunk : total;
-            if (lane == 0) wq.nxt = atomicAdd(queue, kQueueChunk);
+            if (lane == 0) wq.nxt = wq.claim(queue, total);
         }
         const uint32_t avail = wq.qe - wq.qb;
         const uint32_t r = lanes_below(mask) - ((lane != lead && ((mask >> lead) & 1ull)) ? 1u : 0u);
@@ -318,7 +329,7 @@ __global__ void __launch_bounds__(256) walk_batched(WalkArgs a)
         pending[p] = false;
     }
     WaveQueue wq;
-    wq.start(a.queue);
+    wq.start();
     uint64_t steps = 0, bks = 0;
     for (;;) {
         // 1. the loads of every running slot
@@ -1159,7 +1170,7 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
     d.rs = kEmpty;
     d.done = false;
     WaveQueue wq;
-    wq.start(a.queue);
+    wq.start();
     uint64_t n_occ = 0, n_bk = 0, n_tb = 0;
     for (;;) {
         if constexpr (S) {
@@ -1886,7 +1897,7 @@ __global__ void __launch_bounds__(256) locate_batched(LocateArgs a)
     }
     uint64_t jprev = 0, nsteps = 0;
     WaveQueue wq;
-    wq.start(a.queue);
+    wq.start();
     for (;;) {
         // 1. the bucket of every running row
         bool act[P];
