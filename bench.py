@@ -153,6 +153,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--headline-only", action="store_true",
                     help="run the genome-scale headline alone (no 2^24 step, small workload or serving legs)")
+    ap.add_argument("--legs", default="headline,small,step,serving",
+                    help="comma-separated legs to run (a profiling run may take one); the JSON line's headline "
+                         "fields are null without the headline leg")
     ap.add_argument("--genome-cpu-sample", type=int, default=2000,
                     help="reads of the genome-scale workload the oracle's text-only checkers search")
     ap.add_argument("--genome-trace-reads", type=int, default=10_000,
@@ -548,17 +551,24 @@ def main():
         log("copy calibration: %d bytes read, %d bytes written" % (n, n))
         del src, dst
 
-    head = genome_headline(args)
+    legs = set(args.legs.split(","))
+    if args.headline_only:
+        legs = {"headline"}
+    head = {"value": None, "ms_per_step": None, "config": None, "roofline": None, "cpu_baseline": None,
+            "parity_sample": None, "extra": {}}
+    if "headline" in legs:
+        head = genome_headline(args)
     extra = dict(head["extra"])
     extra["parity_sample"] = head["parity_sample"]
-    if not args.headline_only:
+    if "small" in legs:
         extra["small_exact"] = small_exact(args)
+    if "step" in legs:
         extra["step_2e24"] = step_2e24(args)
         torch.cuda.empty_cache()
-        if args.serve_requests > 0:
-            extra["serving"] = serve_bench(args)
-            extra["p99_latency_ms"] = extra["serving"]["p99_ms"]
-            torch.cuda.empty_cache()
+    if "serving" in legs and args.serve_requests > 0:
+        extra["serving"] = serve_bench(args)
+        extra["p99_latency_ms"] = extra["serving"]["p99_ms"]
+        torch.cuda.empty_cache()
     out = {
         "metric": METRIC,
         "value": head["value"],
