@@ -703,24 +703,31 @@ struct NodeLoads {
     uint2 tmeta;
 };
 
-template <int I, int L>
+// TB: the launch uses the prefix table (one lane per read-strand, substitution search);
+// without it the kernel keeps no suffix codes at all.
+template <int I, int L, bool TB>
 __device__ __forceinline__ void dfs_load(const DfsArgs &a, Dfs &d, uint32_t q, const Frame *fr, NodeLoads<I, L> &nl)
 {
     d.fetch_code(a);
-    const uint32_t depth = d.m - 1 - d.i;            // length of the matched suffix
-    nl.tbl = L == 1 && d.k != 0 && depth < a.tdepth;
-    if (nl.tbl) {
-        const uint4 *t = a.tab + (table_level_base(depth + 1) / 2 + 2 * (uint64_t)d.code);
-        nl.t0 = t[0];
-        nl.t1 = t[1];
-        nl.pr.same = true;
+    nl.tbl = false;
+    if constexpr (TB) {
+        const uint32_t depth = d.m - 1 - d.i;        // length of the matched suffix
+        nl.tbl = d.k != 0 && depth < a.tdepth;
+        if (nl.tbl) {
+            const uint4 *t = a.tab + (table_level_base(depth + 1) / 2 + 2 * (uint64_t)d.code);
+            nl.t0 = t[0];
+            nl.t1 = t[1];
+            nl.pr.same = true;
+        } else {
+            nl.pr.load(a.lay, q, d.k ? d.k : 1u, d.l);
+        }
     } else {
         nl.pr.load(a.lay, q, d.k ? d.k : 1u, d.l);
     }
     const Frame *ft = fr + (d.sp ? d.sp - 1 : a.fcap - 1);
     nl.tk = ft->k;
     nl.tl = ft->l;
-    nl.tmeta = make_uint2(ft->meta.x, ft->meta.y);
+    nl.tmeta = make_uint2(ft->meta.x, TB ? ft->meta.y : 0u);
 }
 
 // Expands the current node: one Occ8 at (k-1, l) gives the intervals of all four
@@ -733,7 +740,7 @@ __device__ __forceinline__ void dfs_load(const DfsArgs &a, Dfs &d, uint32_t q, c
 // frame on the stack, and at most z frames are ever stacked. Frame `fcap - 1` is a spare
 // that absorbs the writes and reads of lanes that neither push nor pop, which keeps the
 // update free of branches.
-template <int I, int L>
+template <int I, int L, bool TB>
 __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeLoads<I, L> &nl, uint32_t q,
                                            Frame *fr, bool lead, uint64_t &n_occ, uint64_t &n_bk, uint64_t &n_tb)
 {
@@ -742,7 +749,7 @@ __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeL
     const bool root = d.k == 0;
     const uint32_t C0 = a.lay.C[0], C1 = a.lay.C[1], C2 = a.lay.C[2], C3 = a.lay.C[3];
     uint32_t kb[4], lb[4];
-    if (nl.tbl) {
+    if (TB && nl.tbl) {
         // the children's intervals as the table holds them (Listing 1 from (0, n))
         kb[0] = nl.t0.x;
         lb[0] = nl.t0.y;
@@ -802,7 +809,7 @@ __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeL
         fw->k = make_uint4(kb[0], kb[1], kb[2], kb[3]);
         fw->l = make_uint4(lb[0], lb[1], lb[2], lb[3]);
         fw->meta.x = (ci & 0xFFFFu) | (d.zr << 16) | (wi << 20) | (rest << 24);
-        fw->meta.y = d.code;
+        if constexpr (TB) fw->meta.y = d.code;
     }
     const uint32_t nsp = d.sp + (rest ? 1u : 0u);
     // otherwise the next node comes from the top frame: a mismatch child while there is
@@ -819,7 +826,7 @@ __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeL
     d.k = advance ? sel4(cont, kb[0], kb[1], kb[2], kb[3]) : sel4(bt, tk.x, tk.y, tk.z, tk.w);
     d.l = advance ? sel4(cont, lb[0], lb[1], lb[2], lb[3]) : sel4(bt, tl.x, tl.y, tl.z, tl.w);
     d.i = advance ? ci : (meta & 0xFFFFu);
-    d.code = advance ? (d.code << 2) | cont : (nl.tmeta.y << 2) | bt;
+    if constexpr (TB) d.code = advance ? (d.code << 2) | cont : (nl.tmeta.y << 2) | bt;
     d.zr = advance ? d.zr - (cont != wi ? 1u : 0u) : ((meta >> 16) & 0xFu) - (bt != twi ? 1u : 0u);
     d.sp = pop && !left ? nsp - 1 : nsp;
     d.done = !advance && !pop;
@@ -1043,7 +1050,7 @@ __device__ void dfs_emit(const DfsArgs &a, Dfs &d, bool active, bool lead)
     }
 }
 
-template <int I, int K>
+template <int I, int K, bool TB>
 __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
 {
     extern __shared__ Frame lds_frames[];
@@ -1067,8 +1074,8 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
                 gap_expand<I, 1>(a, d, nl, 0, fr, true, n_occ, n_bk);
             } else {
                 NodeLoads<I, 1> nl;
-                dfs_load<I, 1>(a, d, 0, fr, nl);
-                dfs_expand<I, 1>(a, d, nl, 0, fr, true, n_occ, n_bk, n_tb);
+                dfs_load<I, 1, TB>(a, d, 0, fr, nl);
+                dfs_expand<I, 1, TB>(a, d, nl, 0, fr, true, n_occ, n_bk, n_tb);
             }
         }
         dfs_emit<1, K, false>(a, d, active, true);
@@ -1158,8 +1165,9 @@ __device__ __forceinline__ void dfs_steal(const DfsArgs &a, Dfs &d, Frame *frame
     d.el = 0;
 }
 
-// S: lanes take subtrees from one another at the end of the launch (dfs_steal).
-template <int I, int L, int K, bool S>
+// S: lanes take subtrees from one another at the end of the launch (dfs_steal). TB: the
+// prefix table serves shallow nodes (dfs_load).
+template <int I, int L, int K, bool S, bool TB>
 __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
 {
     extern __shared__ Frame lds_frames[];
@@ -1192,8 +1200,8 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
                 gap_expand<I, L>(a, d, nl, q, fr, lead, n_occ, n_bk);
             } else {
                 NodeLoads<I, L> nl;
-                dfs_load<I, L>(a, d, q, fr, nl);
-                dfs_expand<I, L>(a, d, nl, q, fr, lead, n_occ, n_bk, n_tb);
+                dfs_load<I, L, TB>(a, d, q, fr, nl);
+                dfs_expand<I, L, TB>(a, d, nl, q, fr, lead, n_occ, n_bk, n_tb);
             }
         }
         if (fresh) d.begin(a);
@@ -1210,12 +1218,12 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
     wave_add(a.stat_tbl, n_tb);
 }
 
-template <int I, int L, int K, bool S>
+template <int I, int L, int K, bool S, bool TB = false>
 static hipError_t dfs_launch_batched(const fm_index *idx, const fm_tuning &t, const DfsArgs &a, hipStream_t s)
 {
     const int block = (int)t.block;
     const size_t lds = (size_t)(block / L) * a.fcap * sizeof(Frame);
-    int per = max_blocks_per_cu((const void *)dfs_batched<I, L, K, S>, block, lds);
+    int per = max_blocks_per_cu((const void *)dfs_batched<I, L, K, S, TB>, block, lds);
     if (t.waves_per_cu) {
         int want = (int)(t.waves_per_cu * 64 / block);
         if (want >= 1 && want < per) per = want;
@@ -1223,7 +1231,7 @@ static hipError_t dfs_launch_batched(const fm_index *idx, const fm_tuning &t, co
     uint64_t grid = (uint64_t)idx->cu_count * per;
     const uint64_t need = ((uint64_t)a.total * L + block - 1) / block;
     if (need < grid) grid = need ? need : 1;
-    hipLaunchKernelGGL((dfs_batched<I, L, K, S>), dim3((uint32_t)grid), dim3(block), lds, s, a);
+    hipLaunchKernelGGL((dfs_batched<I, L, K, S, TB>), dim3((uint32_t)grid), dim3(block), lds, s, a);
     return hipGetLastError();
 }
 
@@ -1232,6 +1240,11 @@ static hipError_t dfs_by_lanes(const fm_index *idx, const fm_tuning &t, const Df
 {
     switch (t.lanes) {
     case 1:
+        if constexpr (K != kDfsGap) {
+            if (a.tdepth)
+                return a.tf_count ? dfs_launch_batched<I, 1, K, true, true>(idx, t, a, s)
+                                  : dfs_launch_batched<I, 1, K, false, true>(idx, t, a, s);
+        }
         return a.tf_count ? dfs_launch_batched<I, 1, K, true>(idx, t, a, s)
                           : dfs_launch_batched<I, 1, K, false>(idx, t, a, s);
     case 2: return dfs_launch_batched<I, 2, K, false>(idx, t, a, s);
@@ -1646,19 +1659,19 @@ InexactWs inexact_ws_layout(uint64_t nreads, uint32_t nstr, uint32_t zmax, uint6
     return w;
 }
 
-template <int K>
+template <int K, bool TB>
 static hipError_t dfs_plain_launch(const fm_tuning &t, const DfsArgs &a, hipStream_t s)
 {
     const uint32_t grid = (a.total + 255) / 256;
     const size_t lds = (size_t)256 * a.fcap * sizeof(Frame);
     switch (t.occ_interval) {
-    case 64: hipLaunchKernelGGL((dfs_plain<64, K>), dim3(grid), dim3(256), lds, s, a); break;
-    case 96: hipLaunchKernelGGL((dfs_plain<96, K>), dim3(grid), dim3(256), lds, s, a); break;
-    case 128: hipLaunchKernelGGL((dfs_plain<128, K>), dim3(grid), dim3(256), lds, s, a); break;
-    case 192: hipLaunchKernelGGL((dfs_plain<192, K>), dim3(grid), dim3(256), lds, s, a); break;
-    case 224: hipLaunchKernelGGL((dfs_plain<224, K>), dim3(grid), dim3(256), lds, s, a); break;
-    case 256: hipLaunchKernelGGL((dfs_plain<256, K>), dim3(grid), dim3(256), lds, s, a); break;
-    case 448: hipLaunchKernelGGL((dfs_plain<448, K>), dim3(grid), dim3(256), lds, s, a); break;
+    case 64: hipLaunchKernelGGL((dfs_plain<64, K, TB>), dim3(grid), dim3(256), lds, s, a); break;
+    case 96: hipLaunchKernelGGL((dfs_plain<96, K, TB>), dim3(grid), dim3(256), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((dfs_plain<128, K, TB>), dim3(grid), dim3(256), lds, s, a); break;
+    case 192: hipLaunchKernelGGL((dfs_plain<192, K, TB>), dim3(grid), dim3(256), lds, s, a); break;
+    case 224: hipLaunchKernelGGL((dfs_plain<224, K, TB>), dim3(grid), dim3(256), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((dfs_plain<256, K, TB>), dim3(grid), dim3(256), lds, s, a); break;
+    case 448: hipLaunchKernelGGL((dfs_plain<448, K, TB>), dim3(grid), dim3(256), lds, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1751,7 +1764,8 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     }
     pe->mark(2, s);
     if (plain)
-        e = gap ? dfs_plain_launch<kDfsGap>(t, a, s) : dfs_plain_launch<kDfsSub>(t, a, s);
+        e = gap ? dfs_plain_launch<kDfsGap, false>(t, a, s)
+                : (a.tdepth ? dfs_plain_launch<kDfsSub, true>(t, a, s) : dfs_plain_launch<kDfsSub, false>(t, a, s));
     else if (gap)
         e = dfs_batched_launch<kDfsGap>(idx, t, a, s);
     else
