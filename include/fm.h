@@ -76,8 +76,10 @@ enum {
     FM_PLAIN = 16,                  /* use the plain one-thread-per-read-strand kernels */
     FM_STATS = 32,                  /* count Occ queries and bucket fetches into the workspace */
     FM_FULL_RANK = 64,              /* fm_search_exact: no early exit; misses report (rank, rank-1) */
-    FM_GAPS = 128                   /* fm_search_inexact: Listing 2 with its deletion and insertion
+    FM_GAPS = 128,                  /* fm_search_inexact: Listing 2 with its deletion and insertion
                                        branches too (edit differences, not only substitutions) */
+    FM_TUNE_KEEP_LAYOUT = 256       /* fm_autotune only: keep the current layout and lanes per
+                                       read-strand and time the other settings */
 };
 
 /* Load flags. */
@@ -250,6 +252,10 @@ int fm_set_tuning(fm_index *idx, int op, const fm_tuning *t);
  * other resolve to the one tried first). Synchronises `stream`. If
  * cache_path is non-NULL the choice is looked up there first (key: device
  * architecture, n, read count, total length, zmax, flags) and stored after tuning.
+ * With FM_TUNE_KEEP_LAYOUT in flags only the depth, waves per CU, claim order and prefix
+ * table are searched, at the current layout and lanes: a coarse tuning on a sample can
+ * then be refined on a batch of the real size, where the launch's tail weighs less and
+ * the best occupancy can differ.
  * best (nullable) receives the choice; ms (nullable) its time per call. */
 int fm_autotune(fm_index *idx, int op, const uint8_t *codes, const uint64_t *offs,
                 const uint8_t *z, uint64_t nreads, uint32_t flags, uint32_t zmax,

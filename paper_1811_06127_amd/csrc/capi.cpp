@@ -515,11 +515,15 @@ int fm_search_exact(const fm_index *idx, const uint8_t *codes, const uint64_t *o
     if (!nreads) return FM_OK;
     DeviceGuard g(idx->device);
     hipStream_t s = (hipStream_t)stream;
-    if (!plain) {
-        if (hipError_t e = launch_fill(ws, 0, kWsHeader / 4, s)) return hip_status(e);
-    }
     if ((flags & FM_STATS) && (!ws || ws_bytes < kWsHeader)) return FM_EINVAL;
-    if (plain && (flags & FM_STATS)) {
+    // The persistent walk gives every wave a first chunk of its own and goes to the queue
+    // counter only for the chunks after those. A launch of at most one workgroup per
+    // compute unit (its grid is then exactly the workgroups the read-strands need) covers
+    // every read-strand with first chunks, so the counter is never read and a small batch
+    // costs one launch, as the plain kernel does.
+    const fm_tuning &te = idx->tune[FM_OP_EXACT];
+    const bool queue_read = nreads * nstrands(flags) * te.lanes > (uint64_t)idx->cu_count * te.block;
+    if ((flags & FM_STATS) || (!plain && queue_read)) {
         if (hipError_t e = launch_fill(ws, 0, kWsHeader / 4, s)) return hip_status(e);
     }
     WalkCall c{codes, offs, nullptr, nreads, flags, 0, out, ws};

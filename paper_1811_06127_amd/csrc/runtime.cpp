@@ -268,7 +268,9 @@ int fm_autotune(fm_index *idx, int op, const uint8_t *codes, const uint64_t *off
     const int call_op = op == FM_OP_EXACT ? FM_OP_EXACT : FM_OP_INEXACT;
     uint64_t total_len = 0;
     if (hipMemcpy(&total_len, offs + nreads, 8, hipMemcpyDeviceToHost) != hipSuccess) return FM_EDEVICE;
-    const std::string key = cache_key(idx, op, nreads, total_len, zmax, flags);
+    std::string key = cache_key(idx, op, nreads, total_len, zmax, flags);
+    if (flags & FM_TUNE_KEEP_LAYOUT)   // the choice then depends on the layout and lanes kept
+        key += "|I" + std::to_string(idx->tune[op].occ_interval) + "|L" + std::to_string(idx->tune[op].lanes);
     if (cache_path) {
         fm_tuning t;
         float m;
@@ -279,6 +281,8 @@ int fm_autotune(fm_index *idx, int op, const uint8_t *codes, const uint64_t *off
         }
     }
     // reference output: the plain kernels
+    const bool keep_layout = (flags & FM_TUNE_KEEP_LAYOUT) != 0;
+    flags &= ~(uint32_t)FM_TUNE_KEEP_LAYOUT;
     const uint32_t plain_flags = (flags | FM_PLAIN) & ~(uint32_t)FM_STATS;
     size_t need = 0;
     if (call_op == FM_OP_INEXACT) fm_search_inexact_workspace(idx, nreads, total_len, plain_flags, zmax, hit_cap, &need);
@@ -305,7 +309,9 @@ int fm_autotune(fm_index *idx, int op, const uint8_t *codes, const uint64_t *off
     for (uint32_t I : kIntervals) {
         if (!idx->lay[ilog(I)]) continue;
         if (op == FM_OP_DARRAY && !idx->rlay[ilog(I)]) continue;
+        if (keep_layout && I != base.occ_interval) continue;
         for (uint32_t lanes = 1; lanes <= max_lanes(I); lanes *= 2) {
+            if (keep_layout && lanes != base.lanes) continue;
             for (uint32_t depth = 1; depth <= (op == FM_OP_INEXACT ? 1u : 2u); ++depth) {
                 // the claim order matters only to the substitution DFS with the D bound, and
                 // the prefix table only to the substitution DFS with one lane per read-strand

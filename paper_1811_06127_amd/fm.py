@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libfmocc.so")
 
 FM_OK, FM_EINVAL, FM_EIO, FM_EFORMAT, FM_ENOMEM, FM_EDEVICE, FM_EOVERFLOW, FM_EBUDGET, FM_ERANGE, FM_EAGAIN = range(10)
 FM_FWD, FM_REVCOMP, FM_BOTH, FM_DARRAY, FM_PLAIN, FM_STATS, FM_FULL_RANK, FM_GAPS = 1, 2, 3, 4, 16, 32, 64, 128
+FM_TUNE_KEEP_LAYOUT = 256
 FM_LOAD_REVERSE, FM_LOAD_ALL_LAYOUTS, FM_LOAD_DEVICE_SORT, FM_LOAD_LOCATE = 1, 2, 4, 8
 FM_OP_EXACT, FM_OP_DARRAY, FM_OP_INEXACT, FM_OP_LOCATE = 0, 1, 2, 3
 FM_ZMAX = 4

@@ -161,6 +161,37 @@ def test_exact_full_rank(small, flags):
     idx.set_tuning(fm.FM_OP_EXACT, occ_interval=128, lanes=1)
 
 
+def test_exact_work_queue_with_a_dirty_workspace(small):
+    """The exact search clears its work-queue counter only when some wave goes back to it,
+    i.e. when the read-strands need more than one workgroup per CU; a smaller batch is
+    covered by the waves' own first chunks and never reads the counter. With every
+    workspace byte set to garbage first, batches on both sides of that size, at several
+    occupancies and lanes, equal the oracle."""
+    R, x, xr, idx = small
+    cu = torch.cuda.get_device_properties(0).multi_processor_count
+    rng = np.random.default_rng(17)
+    m = 24
+    for nreads in (1000, 40 * cu * 2, 200 * cu):
+        pos = rng.integers(0, R.size - m, nreads)
+        pats = R[pos[:, None] + np.arange(m)].copy()
+        flip = rng.random(nreads) < 0.3
+        pats[flip, rng.integers(0, m, int(flip.sum()))] ^= 1
+        codes = pats.reshape(-1)
+        offs = (np.arange(nreads + 1, dtype=np.uint64) * m)
+        want = x.exact(codes, offs, fm.FM_BOTH, "definition")
+        cd, od, _ = fm.reads_to_device(codes, offs)
+        ws = torch.empty(fm.fm_search_exact_workspace(idx, nreads, fm.FM_BOTH), dtype=torch.uint8, device="cuda")
+        for I, L, waves in ((128, 1, 0), (128, 1, 4), (64, 2, 16), (256, 8, 8)):
+            idx.set_tuning(fm.FM_OP_EXACT, occ_interval=I, lanes=L, depth=1, waves_per_cu=waves)
+            ws.fill_(0xAB)
+            queue_read = nreads * 2 * L > cu * 256
+            say("dirty workspace:", nreads, "reads", (I, L, waves), "queue read:", queue_read)
+            got = to_u32(fm.fm_search_exact(idx, cd, od, fm.FM_BOTH, ws=ws))
+            bad = np.nonzero((got != want).any(axis=1))[0]
+            assert bad.size == 0, (nreads, I, L, waves, bad[:5])
+    idx.set_tuning(fm.FM_OP_EXACT, occ_interval=128, lanes=1, depth=1, waves_per_cu=0)
+
+
 def test_exact_small_workload():
     w = synth.small_exact_workload()
     x = oracle.OracleIndex(w.ref)
