@@ -100,8 +100,9 @@ def search_trace(fm, torch, idx, rd, count: int, dev):
 def dfs_kernel_name(tcfg: dict, zmax: int) -> str:
     """The compiled DFS of fm_search_both: kind 1 takes the exact intervals from the DFS; the
     fourth argument says whether its lanes split trees at the end of the launch (one lane
-    per read-strand and zmax >= 2), the fifth whether the prefix table serves shallow nodes
-    (one lane per read-strand and a table depth above zero)."""
+    per read-strand and zmax >= 2; at zmax 1 only batches below 512 read-strands per CU,
+    smaller than any the bench times), the fifth whether the prefix table serves shallow
+    nodes (one lane per read-strand and a table depth above zero)."""
     steal = tcfg["lanes"] == 1 and zmax >= 2
     table = tcfg["lanes"] == 1 and tcfg.get("table_depth", 0) > 0
     return "dfs_batched<%d, %d, 1, %s, %s>" % (tcfg["occ_interval"], tcfg["lanes"], "true" if steal else "false",

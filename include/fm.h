@@ -336,7 +336,8 @@ int fm_search_inexact_workspace(const fm_index *idx, uint64_t nreads, uint64_t t
  *      them; a node whose interval is still (0, n) takes its children from C and
  *      fetches none), 80 (D-walk steps that fetched) and 88 (buckets they fetched)
  *      count the work done, 96 the subtrees that idle lanes of the batched DFS took
- *      over from busy ones at the end of the launch (one lane per read-strand, zmax >= 2),
+ *      over from busy ones at the end of the launch (one lane per read-strand; zmax >= 2,
+ *      or zmax 1 in batches of fewer than 512 read-strands per compute unit),
  *      and 104 the expanded nodes whose children came from the prefix table (they fetch
  *      no bucket; see fm_tuning.table_depth).
  * Output is deterministic (independent of scheduling, batch order and launch tuning)

@@ -26,26 +26,40 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 // never waits for the atomic. The first chunk of every wave is its own without an atomic
 // (wave w of the grid takes chunk w); the chunks after those are claimed from the queue
 // counter, and not at all when the first chunks already cover the work, so a small
-// launch makes no atomic on the shared counter.
+// launch makes no atomic on the shared counter. Dealt (the DFS with subtree transfers):
+// the first chunks are dealt round-robin instead, wave w taking items w, w + W, w + 2W,
+// ... of the W waves' share, so that the heaviest read-strands of a claim order, which
+// come first, land in different waves, where each has lanes of its own to help with it.
 struct WaveQueue {
     uint32_t qb, qe;
     uint32_t nxt;          // lane 0: start of the next claimed chunk
     uint32_t fixed;        // items handed out as the waves' first chunks
+    uint32_t chunk;        // items per chunk
+    uint32_t wave, waves;  // this wave's index in the grid, and the grid's wave count
+    uint32_t first;        // dealt: items in this wave's first chunk (0 once taken)
+    bool dealt, strided;   // first chunks dealt; the current chunk is the dealt one
     bool exhausted;
 
-    __device__ void start()
+    __device__ void start(uint32_t items_per_chunk, uint32_t total, bool deal)
     {
         const uint32_t wpb = blockDim.x / 64;
         qb = qe = 0;
         exhausted = false;
-        fixed = gridDim.x * wpb * kQueueChunk;
-        nxt = (blockIdx.x * wpb + threadIdx.x / 64) * kQueueChunk;
+        chunk = items_per_chunk;
+        waves = gridDim.x * wpb;
+        wave = blockIdx.x * wpb + threadIdx.x / 64;
+        fixed = waves * chunk;
+        nxt = wave * chunk;
+        dealt = deal;
+        strided = false;
+        const uint32_t share = fixed < total ? fixed : total;
+        first = wave < share ? (share - wave + waves - 1) / waves : 0u;
     }
 
     // The chunk after the current one (lane 0): from the queue counter while work is left.
     __device__ uint32_t claim(uint32_t *queue, uint32_t total) const
     {
-        return fixed >= total ? total : fixed + atomicAdd(queue, kQueueChunk);
+        return fixed >= total ? total : fixed + atomicAdd(queue, chunk);
     }
 };
 
@@ -60,19 +74,29 @@ __device__ uint32_t wave_take(WaveQueue &wq, bool need, uint32_t *queue, uint32_
     while (mask) {
         if (wq.qb >= wq.qe) {
             if (wq.exhausted) break;
+            if (wq.dealt) {
+                // the dealt first chunk: positions 0 .. first - 1 stand for items wave + j * waves
+                wq.dealt = false;
+                wq.strided = true;
+                wq.qb = 0;
+                wq.qe = wq.first;
+                if (lane == 0) wq.nxt = wq.claim(queue, total);
+                continue;
+            }
             const uint32_t base = (uint32_t)__builtin_amdgcn_readfirstlane((int)wq.nxt);
             if (base >= total) {
                 wq.exhausted = true;
                 break;
             }
+            wq.strided = false;
             wq.qb = base;
-            wq.qe = base + kQueueChunk < total ? base + kQueueChunk : total;
+            wq.qe = base + wq.chunk < total ? base + wq.chunk : total;
             if (lane == 0) wq.nxt = wq.claim(queue, total);
         }
         const uint32_t avail = wq.qe - wq.qb;
         const uint32_t r = lanes_below(mask) - ((lane != lead && ((mask >> lead) & 1ull)) ? 1u : 0u);
         const bool mine = need && ((mask >> lead) & 1ull) && r < avail;
-        if (mine) got = wq.qb + r;
+        if (mine) got = wq.strided ? wq.wave + (wq.qb + r) * wq.waves : wq.qb + r;
         const uint32_t cnt = (uint32_t)__popcll(mask);
         wq.qb += cnt < avail ? cnt : avail;
         need = need && !mine;
@@ -329,7 +353,7 @@ __global__ void __launch_bounds__(256) walk_batched(WalkArgs a)
         pending[p] = false;
     }
     WaveQueue wq;
-    wq.start();
+    wq.start(kQueueChunk, a.total, false);
     uint64_t steps = 0, bks = 0;
     for (;;) {
         // 1. the loads of every running slot
@@ -530,8 +554,10 @@ struct DfsArgs {
     // whose header is rec[2j], rec[2j+1] (see order_place)
     const uint4 *rec;
     uint32_t total, nstr, strand0, zmax;
-    uint32_t fcap;         // stack frames per read-strand: zmax, plus one spare
+    uint32_t fcap;         // stack frames per read-strand: zmax (one more where lanes take
+                           // subtrees from one another), plus one spare
     uint32_t budget;       // expanded nodes per read-strand
+    uint32_t chunk;        // read-strands a wave takes from the work queue at once
     fm_hit *slots;         // kHitSlots hits per read-strand
     fm_hit *opool;         // hits beyond the slots
     uint64_t ocap;
@@ -737,12 +763,19 @@ __device__ __forceinline__ void dfs_load(const DfsArgs &a, Dfs &d, uint32_t q, c
 // Otherwise a mismatch child, if any, is continued and the node's other survivors are
 // pushed as one frame; frames hand out their mismatch children first and the match
 // child last, so the current node descends from a mismatch child of every node with a
-// frame on the stack, and at most z frames are ever stacked. Frame `fcap - 1` is a spare
+// frame on the stack, and at most z frames are stacked that way. In the tail of a
+// launch (sf: lanes are taking subtrees from one another, see dfs_steal) a node whose
+// stack is empty instead continues with its match child and leaves all its mismatch
+// children in the one frame, where idle lanes take them: the path that matches every
+// symbol, which no other lane can take, is then walked without waiting for those
+// subtrees. That frame is the bottom one, so the stack holds at most z + 1 frames. A
+// bottom frame whose children other lanes took is dropped. Frame `fcap - 1` is a spare
 // that absorbs the writes and reads of lanes that neither push nor pop, which keeps the
 // update free of branches.
 template <int I, int L, bool TB>
 __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeLoads<I, L> &nl, uint32_t q,
-                                           Frame *fr, bool lead, uint64_t &n_occ, uint64_t &n_bk, uint64_t &n_tb)
+                                           Frame *fr, bool lead, bool sf, uint64_t &n_occ, uint64_t &n_bk,
+                                           uint64_t &n_tb)
 {
     const uint32_t kk = d.k ? d.k : 1u;
     const uint32_t wi = d.sym(a);
@@ -795,23 +828,27 @@ __device__ __forceinline__ void dfs_expand(const DfsArgs &a, Dfs &d, const NodeL
         d.pl[b] = lb[b];
     }
     d.pd = (d.z0 - d.zr) | (wi << 8);
+    // a bottom frame emptied by other lanes is dropped (it is the top one only when alone)
+    const uint32_t sp = (d.sp == 1 && ((nl.tmeta.x >> 24) & 0xFu) == 0) ? 0u : d.sp;
     // continue with a mismatch child if there is one, else with the match child; the
-    // other survivors of a node that continues with a mismatch go into a frame
+    // other survivors of a node that continues with a mismatch go into a frame (in the
+    // tail, a node with an empty stack continues with the match child instead)
     const uint32_t go = leaf ? 0u : valid;
     const uint32_t mism = go & ~mbit;
     const bool advance = go != 0;
-    const uint32_t cont = mism ? (uint32_t)__builtin_ctz(mism) : (wi & 3u);
-    const uint32_t rest = mism ? (go & ~(1u << cont)) : 0u;
+    const bool spine = sf && sp == 0 && mism != 0 && (go & mbit) != 0;
+    const uint32_t cont = (mism && !spine) ? (uint32_t)__builtin_ctz(mism) : (wi & 3u);
+    const uint32_t rest = spine ? mism : (mism ? (go & ~(1u << cont)) : 0u);
     const uint32_t ci = d.i - 1;
     const uint32_t spare = a.fcap - 1;
-    Frame *fw = fr + (rest ? d.sp : spare);
+    Frame *fw = fr + (rest ? sp : spare);
     if (lead) {
         fw->k = make_uint4(kb[0], kb[1], kb[2], kb[3]);
         fw->l = make_uint4(lb[0], lb[1], lb[2], lb[3]);
         fw->meta.x = (ci & 0xFFFFu) | (d.zr << 16) | (wi << 20) | (rest << 24);
         if constexpr (TB) fw->meta.y = d.code;
     }
-    const uint32_t nsp = d.sp + (rest ? 1u : 0u);
+    const uint32_t nsp = sp + (rest ? 1u : 0u);
     // otherwise the next node comes from the top frame: a mismatch child while there is
     // one, then the match child, which retires the frame
     const bool pop = !advance && nsp > 0;
@@ -925,13 +962,15 @@ __device__ __forceinline__ void gap_expand(const DfsArgs &a, Dfs &d, const GapLo
     const uint32_t cont = (uint32_t)__builtin_ctz((costly ? costly : go) | 0x200u);
     const uint32_t rest = costly ? (go & ~(1u << cont)) : 0u;
     const uint32_t spare = a.fcap - 1;
-    Frame *fw = fr + (rest ? d.sp : spare);
+    // a bottom frame emptied by other lanes (dfs_steal) is dropped
+    const uint32_t sp = (d.sp == 1 && (nl.tmeta.w & 0x1FFu) == 0) ? 0u : d.sp;
+    Frame *fw = fr + (rest ? sp : spare);
     if (lead) {
         fw->k = kb;
         fw->l = lb;
         fw->meta = make_uint4((d.i & 0xFFFFu) | (d.zr << 16) | (wi << 20), d.k, d.l, rest);
     }
-    const uint32_t nsp = d.sp + (rest ? 1u : 0u);
+    const uint32_t nsp = sp + (rest ? 1u : 0u);
     // otherwise the next node comes from the top frame: a costly child while there is one,
     // then the matching step, which retires the frame
     const bool pop = !advance && nsp > 0;
@@ -1075,7 +1114,7 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
             } else {
                 NodeLoads<I, 1> nl;
                 dfs_load<I, 1, TB>(a, d, 0, fr, nl);
-                dfs_expand<I, 1, TB>(a, d, nl, 0, fr, true, n_occ, n_bk, n_tb);
+                dfs_expand<I, 1, TB>(a, d, nl, 0, fr, true, false, n_occ, n_bk, n_tb);
             }
         }
         dfs_emit<1, K, false>(a, d, active, true);
@@ -1091,53 +1130,88 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
 // and finished read-strands retired. K: the kind of search (kDfsSubExact: exact intervals
 // as well, see dfs_emit; kDfsGap: Listing 2 with all its branches).
 // The tail of a launch: once the work queue is exhausted, lanes fall idle while the
-// last trees are still being searched. An idle lane then takes a pending costly child
-// (a substitution, or in the gapped search also an insertion or the deletion) from the
-// bottom (shallowest, so largest) frame of a busy lane of its wave and searches that
-// subtree of the same read-strand; one transfer per wave and round, and only for children
-// left with a budget of one or more (so z >= 2). Only frames with two or more pending
-// children give one away, so a frame never empties under its owner, and the child that
-// matches is never taken, so the path that matches every symbol (and with it the exact
-// interval) stays with the owner. Hits of a stolen subtree go to the overflow pool; its
-// hit count, status and node count are summed per read-strand apart from the owner's
-// (tf_*), and the compaction adds the two. One lane per read-strand only (frames are
-// per lane).
+// last trees are still being searched. Idle lanes then take pending costly children (a
+// substitution, or in the gapped search also an insertion or the deletion) from the
+// bottom (shallowest, so largest) frames of busy lanes of their wave and search those
+// subtrees of the same read-strands. Every idle lane can take one child per round: the
+// costly children of the wave's bottom frames are numbered in lane order, the r-th idle
+// lane takes child r, and each donor clears the children it gave from its own frame. The
+// child that matches is never taken, so the path that matches every symbol (and with it
+// the exact interval) stays with the owner; a bottom frame left with no child is dropped
+// by its owner (dfs_expand, gap_expand). Hits of a stolen subtree go to the overflow
+// pool; its hit count, status and node count are summed per read-strand apart from the
+// owner's (tf_*), and the compaction adds the two. One lane per read-strand only (frames
+// are per lane).
 template <int K>
-__device__ __forceinline__ void dfs_steal(const DfsArgs &a, Dfs &d, Frame *frames, const Frame *fr)
+__device__ __forceinline__ void dfs_steal(const DfsArgs &a, Dfs &d, Frame *frames, Frame *fr)
 {
     constexpr bool G = K == kDfsGap;
     const uint32_t lane = __lane_id();
     const bool busy = d.rs != kEmpty;
+    const uint64_t idle = __ballot(!busy);
+    if (!idle) return;
     // this lane's bottom frame: its node's budget and symbol, and the children still to visit
     const uint4 m = (busy && d.sp >= 1) ? fr->meta : make_uint4(0u, 0u, 0u, 0u);
     const uint32_t pend = G ? (m.w & 0x1FFu) : ((m.x >> 24) & 0xFu);
     const uint32_t wi = (m.x >> 20) & 0xFu;
     const uint32_t costly = pend & ~(wi < 4 ? 1u << wi : 0u);
-    // a costly child keeps a budget of at least one (below that its subtree is a single
-    // exact walk, not worth a transfer)
-    const bool deep = ((m.x >> 16) & 0xFu) >= 2;
-    const uint64_t idle = __ballot(!busy);
-    const uint64_t rich = __ballot(busy && d.sp >= 1 && costly != 0 && __popc(pend) >= 2 && deep);
-    if (!idle || !rich) return;
-    const int t = __builtin_ctzll(idle), v = __builtin_ctzll(rich);
-    const uint32_t vmx = __shfl(m.x, v), vmy = __shfl(m.y, v), vmz = __shfl(m.z, v), vpend = __shfl(pend, v);
-    const uint32_t vrs = __shfl(d.rs, v), vread = __shfl(d.read, v);
-    const uint32_t vstrand = __shfl(d.strand, v), vm = __shfl(d.m, v), vz0 = __shfl(d.z0, v);
-    const uint32_t vb0 = __shfl((uint32_t)d.base, v), vb1 = __shfl((uint32_t)(d.base >> 32), v);
-    const uint32_t vp0 = __shfl((uint32_t)d.bp03, v), vp1 = __shfl((uint32_t)(d.bp03 >> 32), v);
-    const uint32_t vbp4 = __shfl(d.bp4, v);
-    if ((int)lane != t) return;
-    if (a.stat_steal) atomicAdd(a.stat_steal, 1ull);
-    Frame *df = frames + (size_t)(threadIdx.x - lane + (uint32_t)v) * a.fcap;
+    const uint32_t cnt = (uint32_t)__popc(costly);            // 0-3; 0-8 in the gapped search
+    // numbering: this lane's costly children start at pre; the wave has tot of them
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int bit = 0; bit < 4; ++bit) {
+        const uint64_t bb = __ballot((cnt >> bit) & 1u);
+        pre += lanes_below(bb) << bit;
+        tot += (uint32_t)__popcll(bb) << bit;
+    }
+    if (tot == 0) return;
+    const uint32_t nidle = (uint32_t)__popcll(idle);
+    // a donor gives its children numbered below the idle count, lowest first
+    const uint32_t given = pre >= nidle ? 0u : (cnt < nidle - pre ? cnt : nidle - pre);
+    if (given) {
+        uint32_t rem = costly, gone = 0;
+        for (uint32_t g = 0; g < given; ++g) {
+            const uint32_t lo = rem & (0u - rem);
+            gone |= lo;
+            rem ^= lo;
+        }
+        const uint32_t left = pend & ~gone;
+        if constexpr (G)
+            fr->meta.w = left;
+        else
+            fr->meta.x = (m.x & 0x00FFFFFFu) | (left << 24);
+    }
+    // an idle lane of rank r takes child r: its donor is the first lane whose numbering
+    // ends above r
+    const uint32_t r = lanes_below(idle);
+    const bool take = !busy && r < tot;
+    const uint32_t end = pre + cnt;
+    uint32_t v = 0;
+#pragma unroll
+    for (uint32_t step = 32; step >= 1; step >>= 1) {
+        const uint32_t e = __shfl(end, (int)(v + step - 1));
+        v += e <= r ? step : 0u;
+    }
+    const uint32_t vpre = __shfl(pre, (int)v), vcost = __shfl(costly, (int)v);
+    const uint32_t vmx = __shfl(m.x, (int)v), vmy = __shfl(m.y, (int)v), vmz = __shfl(m.z, (int)v);
+    const uint32_t vrs = __shfl(d.rs, (int)v), vread = __shfl(d.read, (int)v);
+    const uint32_t vstrand = __shfl(d.strand, (int)v), vm = __shfl(d.m, (int)v), vz0 = __shfl(d.z0, (int)v);
+    const uint32_t vb0 = __shfl((uint32_t)d.base, (int)v), vb1 = __shfl((uint32_t)(d.base >> 32), (int)v);
+    const uint32_t vp0 = __shfl((uint32_t)d.bp03, (int)v), vp1 = __shfl((uint32_t)(d.bp03 >> 32), (int)v);
+    const uint32_t vbp4 = __shfl(d.bp4, (int)v);
+    const uint64_t takers = __ballot(take);
+    if (a.stat_steal && lane == 0) atomicAdd(a.stat_steal, (unsigned long long)__popcll(takers));
+    if (!take) return;
+    // the (r - vpre)-th costly child of the donor's frame, counting from the lowest
+    uint32_t x = vcost;
+    for (uint32_t g = r - vpre; g > 0; --g) x &= x - 1;
+    const uint32_t c = (uint32_t)__builtin_ctz(x);
+    const Frame *df = frames + (size_t)(threadIdx.x - lane + v) * a.fcap;
     const uint32_t vwi = (vmx >> 20) & 0xFu, vzr = (vmx >> 16) & 0xFu;
-    const uint32_t c = (uint32_t)__builtin_ctz(vpend & ~(vwi < 4 ? 1u << vwi : 0u));
     const uint4 kk = df->k, ll = df->l;
-    const uint32_t left = vpend & ~(1u << c);
     if constexpr (G) {
-        df->meta.w = left;
         gap_child(c, vmx & 0xFFFFu, vzr, vwi, vmy, vmz, kk, ll, d.i, d.zr, d.k, d.l);
     } else {
-        df->meta.x = (vmx & 0x00FFFFFFu) | (left << 24);
         d.k = sel4(c, kk.x, kk.y, kk.z, kk.w);
         d.l = sel4(c, ll.x, ll.y, ll.z, ll.w);
         d.i = vmx & 0xFFFFu;
@@ -1178,7 +1252,7 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
     d.rs = kEmpty;
     d.done = false;
     WaveQueue wq;
-    wq.start();
+    wq.start(a.chunk, a.total, S);
     uint64_t n_occ = 0, n_bk = 0, n_tb = 0;
     for (;;) {
         if constexpr (S) {
@@ -1201,7 +1275,7 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
             } else {
                 NodeLoads<I, L> nl;
                 dfs_load<I, L, TB>(a, d, q, fr, nl);
-                dfs_expand<I, L, TB>(a, d, nl, q, fr, lead, n_occ, n_bk, n_tb);
+                dfs_expand<I, L, TB>(a, d, nl, q, fr, lead, S && wq.exhausted, n_occ, n_bk, n_tb);
             }
         }
         if (fresh) d.begin(a);
@@ -1218,19 +1292,32 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
     wave_add(a.stat_tbl, n_tb);
 }
 
+// A batch with fewer read-strands than the launch has lanes is spread over every wave
+// that fits (with subtree transfers, S): each wave then starts with fewer read-strands
+// than lanes, and its idle lanes share its trees from the first round. Otherwise waves
+// take kQueueChunk read-strands at a time.
 template <int I, int L, int K, bool S, bool TB = false>
-static hipError_t dfs_launch_batched(const fm_index *idx, const fm_tuning &t, const DfsArgs &a, hipStream_t s)
+static hipError_t dfs_launch_batched(const fm_index *idx, const fm_tuning &t, const DfsArgs &a0, hipStream_t s)
 {
     const int block = (int)t.block;
-    const size_t lds = (size_t)(block / L) * a.fcap * sizeof(Frame);
+    const size_t lds = (size_t)(block / L) * a0.fcap * sizeof(Frame);
     int per = max_blocks_per_cu((const void *)dfs_batched<I, L, K, S, TB>, block, lds);
     if (t.waves_per_cu) {
         int want = (int)(t.waves_per_cu * 64 / block);
         if (want >= 1 && want < per) per = want;
     }
-    uint64_t grid = (uint64_t)idx->cu_count * per;
-    const uint64_t need = ((uint64_t)a.total * L + block - 1) / block;
-    if (need < grid) grid = need ? need : 1;
+    const uint64_t wpb = (uint64_t)block / 64, cap = (uint64_t)idx->cu_count * per, waves = cap * wpb;
+    DfsArgs a = a0;
+    a.chunk = kQueueChunk;
+    uint64_t need;                        // workgroups the batch fills
+    if (S && (uint64_t)a.total < waves * kQueueChunk) {
+        const uint64_t c = ((uint64_t)a.total + waves - 1) / waves;
+        a.chunk = (uint32_t)(c ? c : 1);
+        need = (((uint64_t)a.total + a.chunk - 1) / a.chunk + wpb - 1) / wpb;
+    } else {
+        need = ((uint64_t)a.total * L + block - 1) / block;
+    }
+    const uint64_t grid = need < cap ? (need ? need : 1) : cap;
     hipLaunchKernelGGL((dfs_batched<I, L, K, S, TB>), dim3((uint32_t)grid), dim3(block), lds, s, a);
     return hipGetLastError();
 }
@@ -1724,6 +1811,7 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
     a.total = (uint32_t)(c.nreads * nstr);
     a.zmax = c.zmax;
     a.fcap = c.zmax + 1;
+    a.chunk = kQueueChunk;
     a.budget = t.node_budget ? t.node_budget : 0xFFFFFFFFu;
     a.slots = (fm_hit *)(ws + W.slots);
     a.opool = (fm_hit *)(ws + W.opool);
@@ -1754,8 +1842,14 @@ hipError_t launch_inexact(const fm_index *idx, const fm_tuning &t, const fm_tuni
         if (e != hipSuccess) return e;
         a.rec = (const uint4 *)(ws + W.rec);
     }
-    if (!plain && t.lanes == 1 && c.zmax >= 2) {
-        // lanes of the batched DFS take subtrees from one another at the end of the launch
+    // Lanes of the batched DFS take subtrees from one another at the end of the launch,
+    // with room for the frame a node leaves there when it walks its match child first. At
+    // z = 1 only in batches with fewer read-strands than an 8-wave-per-CU launch has lanes:
+    // in larger ones the trees are small next to the launch, and stolen hits, which go
+    // through the overflow pool, cost more than the shorter tail gains.
+    const bool small_batch = (uint64_t)a.total < (uint64_t)idx->cu_count * 8 * 64;
+    if (!plain && t.lanes == 1 && (c.zmax >= 2 || (c.zmax == 1 && small_batch))) {
+        a.fcap = c.zmax + 2;
         a.tf_count = (uint32_t *)(ws + W.tf_count);
         a.tf_status = (uint32_t *)(ws + W.tf_status);
         a.tf_nodes = (uint32_t *)(ws + W.tf_nodes);
@@ -1911,7 +2005,7 @@ __global__ void __launch_bounds__(256) locate_batched(LocateArgs a)
     }
     uint64_t jprev = 0, nsteps = 0;
     WaveQueue wq;
-    wq.start();
+    wq.start(kQueueChunk, total, false);
     for (;;) {
         // 1. the bucket of every running row
         bool act[P];

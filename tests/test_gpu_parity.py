@@ -355,18 +355,22 @@ def test_claim_order_changes_nothing(small):
 
 
 def test_subtree_transfers(small):
-    """With one lane per read-strand and zmax >= 2, idle lanes of the batched DFS take
-    subtrees over from busy lanes at the end of the launch (FM_STATS counts them). Hits,
-    statuses and node counts equal the oracle's and the plain kernel's, for substitutions
-    with and without the D bound and for the gapped search; two lanes per read-strand and
-    z = 1 launches take none."""
+    """With one lane per read-strand, idle lanes of the batched DFS take subtrees over from
+    busy lanes at the end of the launch (FM_STATS counts them), and there a node with an
+    empty stack walks its match child first and leaves its mismatch children to them.
+    Hits, statuses and node counts equal the oracle's, for substitutions with and without
+    the D bound and for the gapped search, at z = 1 and 2, in a full batch and in batches
+    of a few reads (where the work queue is empty from the start and a few trees are
+    spread over the whole wave); two lanes per read-strand take none."""
     R, x, xr, idx = small
     rd = synth.simulate_reads(R, 1500, 41, length=(60, 120), sub=(0.0, 0.03), z=(2, 2))
     r1 = synth.simulate_reads(R, 1500, 42, length=(60, 120), sub=(0.0, 0.03), z=(1, 1))
+    tiny2 = rd.subset(np.arange(6))
+    tiny1 = r1.subset(np.arange(3))
     cases = ((fm.FM_BOTH | fm.FM_DARRAY, "listing2_darray"), (fm.FM_BOTH, "listing2"),
              (fm.FM_BOTH | fm.FM_DARRAY | fm.FM_GAPS, "listing2_gaps_darray"))
     for flags, method in cases:
-        for reads, zmax in ((rd, 2), (r1, 1)):
+        for reads, zmax in ((rd, 2), (r1, 1), (tiny2, 2), (tiny1, 1)):
             cd, od, zd = fm.reads_to_device(reads.codes, reads.offs, reads.z)
             wh, wo, wn = x.inexact(reads.codes, reads.offs, reads.z, oracle.BOTH, method, rev=xr, return_nodes=True)
             for lanes in (1, 2):
@@ -377,13 +381,14 @@ def test_subtree_transfers(small):
                     st = bufs.stats()
                 finally:
                     idx.set_tuning(fm.FM_OP_INEXACT, occ_interval=128, lanes=1)
-                assert_same_hits(got, wh, wo, (flags, zmax, lanes))
-                assert st["occ8"] == int(wn.sum()), (flags, zmax, lanes)
-                if lanes == 1 and zmax == 2:
-                    assert st["subtrees"] > 0, flags
+                assert_same_hits(got, wh, wo, (flags, zmax, lanes, reads.count))
+                assert st["occ8"] == int(wn.sum()), (flags, zmax, lanes, reads.count)
+                if lanes == 1:
+                    assert st["subtrees"] > 0, (flags, zmax, reads.count)
                 else:
                     assert st["subtrees"] == 0, (flags, zmax, lanes)
-                say(hex(flags), "zmax", zmax, "lanes", lanes, "nodes", st["occ8"], "subtrees", st["subtrees"])
+                say(hex(flags), "zmax", zmax, "reads", reads.count, "lanes", lanes, "nodes", st["occ8"],
+                    "subtrees", st["subtrees"])
 
 
 def test_search_both_where_the_dfs_stops_early(small):
