@@ -26,10 +26,11 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 // never waits for the atomic. The first chunk of every wave is its own without an atomic
 // (wave w of the grid takes chunk w); the chunks after those are claimed from the queue
 // counter, and not at all when the first chunks already cover the work, so a small
-// launch makes no atomic on the shared counter. Dealt (the DFS with subtree transfers):
-// the first chunks are dealt round-robin instead, wave w taking items w, w + W, w + 2W,
-// ... of the W waves' share, so that the heaviest read-strands of a claim order, which
-// come first, land in different waves, where each has lanes of its own to help with it.
+// launch makes no atomic on the shared counter. Dealt (the DFS with subtree transfers
+// and a claim order): the first chunks are dealt round-robin instead, wave w taking
+// items w, w + W, w + 2W, ... of the W waves' share, so that the heaviest read-strands,
+// which the claim order puts first, land in different waves, where each has lanes of its
+// own to help with it.
 struct WaveQueue {
     uint32_t qb, qe;
     uint32_t nxt;          // lane 0: start of the next claimed chunk
@@ -1135,7 +1136,8 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
 // bottom (shallowest, so largest) frames of busy lanes of their wave and search those
 // subtrees of the same read-strands. Every idle lane can take one child per round: the
 // costly children of the wave's bottom frames are numbered in lane order, the r-th idle
-// lane takes child r, and each donor clears the children it gave from its own frame. The
+// lane takes child r, and each donor clears the children it gave from its own frame (the
+// gapped search gives only children left with a budget of one or more). The
 // child that matches is never taken, so the path that matches every symbol (and with it
 // the exact interval) stays with the owner; a bottom frame left with no child is dropped
 // by its owner (dfs_expand, gap_expand). Hits of a stolen subtree go to the overflow
@@ -1154,7 +1156,10 @@ __device__ __forceinline__ void dfs_steal(const DfsArgs &a, Dfs &d, Frame *frame
     const uint4 m = (busy && d.sp >= 1) ? fr->meta : make_uint4(0u, 0u, 0u, 0u);
     const uint32_t pend = G ? (m.w & 0x1FFu) : ((m.x >> 24) & 0xFu);
     const uint32_t wi = (m.x >> 20) & 0xFu;
-    const uint32_t costly = pend & ~(wi < 4 ? 1u << wi : 0u);
+    // the gapped search gives away only children left with a budget of one or more (its
+    // zero-budget subtrees are short and many: measured no faster to share)
+    const bool give = !G || ((m.x >> 16) & 0xFu) >= 2;
+    const uint32_t costly = give ? pend & ~(wi < 4 ? 1u << wi : 0u) : 0u;
     const uint32_t cnt = (uint32_t)__popc(costly);            // 0-3; 0-8 in the gapped search
     // numbering: this lane's costly children start at pre; the wave has tot of them
     uint32_t pre = 0, tot = 0;
@@ -1252,7 +1257,7 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
     d.rs = kEmpty;
     d.done = false;
     WaveQueue wq;
-    wq.start(a.chunk, a.total, S);
+    wq.start(a.chunk, a.total, S && a.rec != nullptr);
     uint64_t n_occ = 0, n_bk = 0, n_tb = 0;
     for (;;) {
         if constexpr (S) {
