@@ -1145,7 +1145,7 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
 // owner's (tf_*), and the compaction adds the two. One lane per read-strand only (frames
 // are per lane).
 template <int K>
-__device__ __forceinline__ void dfs_steal(const DfsArgs &a, Dfs &d, Frame *frames, Frame *fr)
+__device__ __forceinline__ void dfs_steal(const DfsArgs &a, Dfs &d, Frame *frames, Frame *fr, uint64_t &n_steal)
 {
     constexpr bool G = K == kDfsGap;
     const uint32_t lane = __lane_id();
@@ -1204,9 +1204,8 @@ __device__ __forceinline__ void dfs_steal(const DfsArgs &a, Dfs &d, Frame *frame
     const uint32_t vb0 = __shfl((uint32_t)d.base, (int)v), vb1 = __shfl((uint32_t)(d.base >> 32), (int)v);
     const uint32_t vp0 = __shfl((uint32_t)d.bp03, (int)v), vp1 = __shfl((uint32_t)(d.bp03 >> 32), (int)v);
     const uint32_t vbp4 = __shfl(d.bp4, (int)v);
-    const uint64_t takers = __ballot(take);
-    if (a.stat_steal && lane == 0) atomicAdd(a.stat_steal, (unsigned long long)__popcll(takers));
     if (!take) return;
+    if (a.stat_steal) n_steal += 1;
     // the (r - vpre)-th costly child of the donor's frame, counting from the lowest
     uint32_t x = vcost;
     for (uint32_t g = r - vpre; g > 0; --g) x &= x - 1;
@@ -1258,10 +1257,10 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
     d.done = false;
     WaveQueue wq;
     wq.start(a.chunk, a.total, S && a.rec != nullptr);
-    uint64_t n_occ = 0, n_bk = 0, n_tb = 0;
+    uint64_t n_occ = 0, n_bk = 0, n_tb = 0, n_steal = 0;
     for (;;) {
         if constexpr (S) {
-            if (wq.exhausted) dfs_steal<K>(a, d, lds_frames, fr);
+            if (wq.exhausted) dfs_steal<K>(a, d, lds_frames, fr, n_steal);
         }
         const bool running = d.rs != kEmpty;
         bool fresh = false;
@@ -1295,6 +1294,7 @@ __global__ void __launch_bounds__(256) dfs_batched(DfsArgs a)
     wave_add(a.stat_occ, n_occ);
     wave_add(a.stat_bk, n_bk);
     wave_add(a.stat_tbl, n_tb);
+    wave_add(a.stat_steal, n_steal);
 }
 
 // A batch with fewer read-strands than the launch has lanes is spread over every wave
