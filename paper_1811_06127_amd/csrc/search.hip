@@ -1133,14 +1133,14 @@ __global__ void __launch_bounds__(256) dfs_plain(DfsArgs a)
 // The tail of a launch: once the work queue is exhausted, lanes fall idle while the
 // last trees are still being searched. Idle lanes then take pending costly children (a
 // substitution, or in the gapped search also an insertion or the deletion) from the
-// bottom (shallowest, so largest) frames of busy lanes of their wave and search those
-// subtrees of the same read-strands. Every idle lane can take one child per round: the
-// costly children of the wave's bottom frames are numbered in lane order, the r-th idle
-// lane takes child r, and each donor clears the children it gave from its own frame (the
-// gapped search gives only children left with a budget of one or more). The
-// child that matches is never taken, so the path that matches every symbol (and with it
-// the exact interval) stays with the owner; a bottom frame left with no child is dropped
-// by its owner (dfs_expand, gap_expand). Hits of a stolen subtree go to the overflow
+// lowest (shallowest, so largest) frames that have them in busy lanes of their wave and
+// search those subtrees of the same read-strands. Every idle lane can take one child per
+// round: the children on offer are numbered in lane order, the r-th idle lane takes
+// child r, and each donor clears the children it gave from its own frame (the gapped
+// search gives only children left with a budget of one or more). The child that matches
+// is never taken, so the path that matches every symbol (and with it the exact interval)
+// stays with the owner; a bottom frame left with no child is dropped by its owner
+// (dfs_expand, gap_expand), and a frame above it always keeps one. Hits of a stolen subtree go to the overflow
 // pool; its hit count, status and node count are summed per read-strand apart from the
 // owner's (tf_*), and the compaction adds the two. One lane per read-strand only (frames
 // are per lane).
@@ -1152,15 +1152,33 @@ __device__ __forceinline__ void dfs_steal(const DfsArgs &a, Dfs &d, Frame *frame
     const bool busy = d.rs != kEmpty;
     const uint64_t idle = __ballot(!busy);
     if (!idle) return;
-    // this lane's bottom frame: its node's budget and symbol, and the children still to visit
-    const uint4 m = (busy && d.sp >= 1) ? fr->meta : make_uint4(0u, 0u, 0u, 0u);
-    const uint32_t pend = G ? (m.w & 0x1FFu) : ((m.x >> 24) & 0xFu);
+    // The lowest frame of this lane with children to give (its node's budget and symbol, and
+    // the children still to visit): a costly child can leave the bottom frame whatever else
+    // stays (an emptied bottom frame is dropped by its owner), a frame above it only while
+    // another child stays, so those frames never empty. The gapped search gives away only
+    // children left with a budget of one or more (its zero-budget subtrees are short and
+    // many: measured no faster to share).
+    uint4 m = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t fsel = 0, pend = 0, costly = 0, cnt = 0;
+    if (busy) {
+        for (uint32_t f = 0; f < d.sp && cnt == 0; ++f) {
+            const uint4 mf = fr[f].meta;
+            const uint32_t pf = G ? (mf.w & 0x1FFu) : ((mf.x >> 24) & 0xFu);
+            const uint32_t wf = (mf.x >> 20) & 0xFu;
+            const bool ok = !G || ((mf.x >> 16) & 0xFu) >= 2;
+            const uint32_t cf = ok ? pf & ~(wf < 4 ? 1u << wf : 0u) : 0u;
+            const uint32_t nc = (uint32_t)__popc(cf), np = (uint32_t)__popc(pf);
+            const uint32_t can = (f == 0 || nc < np) ? nc : np - 1;
+            if (can) {
+                fsel = f;
+                m = mf;
+                pend = pf;
+                costly = cf;
+                cnt = can;
+            }
+        }
+    }
     const uint32_t wi = (m.x >> 20) & 0xFu;
-    // the gapped search gives away only children left with a budget of one or more (its
-    // zero-budget subtrees are short and many: measured no faster to share)
-    const bool give = !G || ((m.x >> 16) & 0xFu) >= 2;
-    const uint32_t costly = give ? pend & ~(wi < 4 ? 1u << wi : 0u) : 0u;
-    const uint32_t cnt = (uint32_t)__popc(costly);            // 0-3; 0-8 in the gapped search
     // numbering: this lane's costly children start at pre; the wave has tot of them
     uint32_t pre = 0, tot = 0;
 #pragma unroll
@@ -1182,9 +1200,9 @@ __device__ __forceinline__ void dfs_steal(const DfsArgs &a, Dfs &d, Frame *frame
         }
         const uint32_t left = pend & ~gone;
         if constexpr (G)
-            fr->meta.w = left;
+            fr[fsel].meta.w = left;
         else
-            fr->meta.x = (m.x & 0x00FFFFFFu) | (left << 24);
+            fr[fsel].meta.x = (m.x & 0x00FFFFFFu) | (left << 24);
     }
     // an idle lane of rank r takes child r: its donor is the first lane whose numbering
     // ends above r
@@ -1197,7 +1215,7 @@ __device__ __forceinline__ void dfs_steal(const DfsArgs &a, Dfs &d, Frame *frame
         const uint32_t e = __shfl(end, (int)(v + step - 1));
         v += e <= r ? step : 0u;
     }
-    const uint32_t vpre = __shfl(pre, (int)v), vcost = __shfl(costly, (int)v);
+    const uint32_t vpre = __shfl(pre, (int)v), vcost = __shfl(costly, (int)v), vf = __shfl(fsel, (int)v);
     const uint32_t vmx = __shfl(m.x, (int)v), vmy = __shfl(m.y, (int)v), vmz = __shfl(m.z, (int)v);
     const uint32_t vrs = __shfl(d.rs, (int)v), vread = __shfl(d.read, (int)v);
     const uint32_t vstrand = __shfl(d.strand, (int)v), vm = __shfl(d.m, (int)v), vz0 = __shfl(d.z0, (int)v);
@@ -1210,7 +1228,7 @@ __device__ __forceinline__ void dfs_steal(const DfsArgs &a, Dfs &d, Frame *frame
     uint32_t x = vcost;
     for (uint32_t g = r - vpre; g > 0; --g) x &= x - 1;
     const uint32_t c = (uint32_t)__builtin_ctz(x);
-    const Frame *df = frames + (size_t)(threadIdx.x - lane + v) * a.fcap;
+    const Frame *df = frames + (size_t)(threadIdx.x - lane + v) * a.fcap + vf;
     const uint32_t vwi = (vmx >> 20) & 0xFu, vzr = (vmx >> 16) & 0xFu;
     const uint4 kk = df->k, ll = df->l;
     if constexpr (G) {
