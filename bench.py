@@ -885,6 +885,20 @@ def genome_cpu_baseline(R, srd, got_ex, got_hits, threads):
     dt = t2 - t0
     log("oracle text-only checkers: %d reads in %.1fs (rank scan %.1fs, pigeonhole %.1fs) on %d threads; "
         "exact equal %s, hits equal %s" % (srd.count, dt, t1 - t0, t2 - t1, threads, ok_ex, ok_in))
+    # the same checkers on one thread (each pass is about one sweep of the text)
+    one = None
+    if threads > 1:
+        u0 = time.time()
+        one_ex = oracle.exact_by_rank_scan_batch(R, srd.codes, srd.offs, oracle.BOTH, threads=1)
+        u1 = time.time()
+        one_h, one_o = oracle.pigeonhole_hits_batch(R, srd.codes, srd.offs, srd.z, oracle.BOTH, threads=1)
+        u2 = time.time()
+        one = {"reads_per_s": round(srd.count / (u2 - u0), 1),
+               "seconds": {"rank_scan": round(u1 - u0, 2), "pigeonhole": round(u2 - u1, 2)},
+               "same_results": bool(np.array_equal(one_ex, want_ex) and np.array_equal(one_h, wh)
+                                    and np.array_equal(one_o, wo))}
+        log("oracle text-only checkers on one thread: %.1fs (rank scan %.1fs, pigeonhole %.1fs)" % (
+            u2 - u0, u1 - u0, u2 - u1))
     cpu = {"value": round(srd.count / dt, 1), "unit": "reads/s", "cores": threads, "kind": "oracle",
            "sample": "%d reads of the 16M (the first %d and %d spread over the set); the oracle's text-only "
                      "checkers, which need no index: exact intervals of both strands by a batched rank scan "
@@ -892,7 +906,7 @@ def genome_cpu_baseline(R, srd, got_ex, got_hits, threads):
                      "passes cost about one sweep of the text whatever the sample, so this rate grows with "
                      "the sample" % (srd.count, srd.count // 2, srd.count - srd.count // 2),
            "seconds": {"rank_scan": round(t1 - t0, 2), "pigeonhole": round(t2 - t1, 2)},
-           "host": host_info()}
+           "single_thread": one, "host": host_info()}
     parity = {"reads": srd.count, "exact_bit_exact": ok_ex, "inexact_bit_exact": ok_in,
               "exact_hits": int((want_ex[:, 0] <= want_ex[:, 1]).sum()), "hits": int(wh.size)}
     return cpu, parity
