@@ -5,7 +5,7 @@ Headline workload: batching at genome scale. A 3.1e9-base reference (55% i.i.d. 
 45% copies of 500 repeat families with 5-15% divergence) and 16M reads of 150 bp from
 either strand with 1% substitutions, all resident in device memory; every read gets the
 exact backward search (Listing 1) and the z=2 substitution search (Listing 2) on both
-strands, pruned by the D lower bound, in one pass, in batches of 1M reads, each replayed
+strands, pruned by the D lower bound, in one pass, in batches of 4M reads, each replayed
 from a launch graph captured for it. A step is one batch. The index is built once,
 untimed (suffixes sorted on the device).
 
@@ -19,6 +19,7 @@ on the 2^28 index, Occ8 micro-benchmarks, locate, the gapped and full-rank searc
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -36,10 +37,13 @@ METRIC = "reads/s & Occ8 queries/s, batched vs plain kernel, bit-exact; p99 late
 # Bytes per launch of the dominant kernel measured with rocprofv3 (read requests and WRITE_SIZE per dispatch, checked
 # against the same counters on a plain 1 GiB copy kernel; profiles/genome_dfs_3e9_counters.md). They hold only for
 # the kernel sources, launch settings and workload they were measured with: the key is a hash of the kernel sources,
-# the kernel, its tuning and the workload; any other combination reports traffic as null.
+# the kernel, its tuning and the workload (index size / reads per launch); any other combination reports traffic
+# as null.
 MEASURED_TRAFFIC = {
     # read = TCC_EA0_RDREQ x 128 B (each EA read request moves a 128 B line on gfx950), write = WRITE_SIZE
-    ("d1e91b2f1de5addc", "dfs_batched<64, 1, 1, true, true>", (64, 1, 1, 256, 8, 1, 12), "3.1e9"):
+    ("d1e91b2f1de5addc", "dfs_batched<64, 1, 1, true, true>", (64, 1, 1, 256, 8, 1, 12), "3.1e9/4000000"):
+        (1_121_612_261_717, 967_993_275),
+    ("d1e91b2f1de5addc", "dfs_batched<64, 1, 1, true, true>", (64, 1, 1, 256, 8, 1, 12), "3.1e9/1000000"):
         (275_877_930_464, 1_067_345_276),
 }
 TRAFFIC_KEY_FIELDS = ("occ_interval", "lanes", "depth", "block", "waves_per_cu", "order", "table_depth")
@@ -153,7 +157,8 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=16,
-                    help="timed steps of the headline; a step is one batch of 1M reads, cycling through the batches")
+                    help="timed steps of the headline; a step is one batch of the genome-scale run, cycling through "
+                         "the batches")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--headline-only", action="store_true",
                     help="run the genome-scale headline alone (no 2^24 step, small workload or serving legs)")
@@ -182,8 +187,14 @@ def parse():
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate as a fraction of capacity")
     ap.add_argument("--serve-lanes", type=int, default=3)
     ap.add_argument("--serve-pool", type=int, default=2_000_000, help="reads the requests are drawn from")
-    ap.add_argument("--genome-batches", type=int, default=16,
-                    help="batches of 1M reads in the genome-scale run on the 3.1e9-base index")
+    ap.add_argument("--genome-batches", type=int, default=4,
+                    help="batches in the genome-scale run on the 3.1e9-base index")
+    ap.add_argument("--genome-batch-reads", type=int, default=4_000_000,
+                    help="reads per batch (one launch graph each) in the genome-scale run: each DFS launch "
+                         "ends with a tail of about 8 ms in which its last trees keep part of the chip busy, "
+                         "so larger batches spend less of their time there")
+    ap.add_argument("--skip-two-stream", action="store_true",
+                    help="skip the genome-scale replays on two streams")
     ap.add_argument("--pcie-two-streams", action="store_true",
                     help="also time the step end to end on two streams, copies overlapping the other batch's search")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -598,8 +609,8 @@ def genome_headline(args):
     """The headline: batching at genome scale. A 3.1e9-base text (55% i.i.d., 45% copies
     of 500 repeat families with 5-15% divergence) and 16M reads of 150 bp with 1%
     substitutions, all resident in device memory; z=2 with the D bound on both strands,
-    in batches of 1M reads, each replayed from a launch graph captured for it (one per
-    batch, outputs per batch). A step is one batch; steps cycle through the batches.
+    in batches of `--genome-batch-reads` (4M), each replayed from a launch graph captured for
+    it (one per batch, outputs per batch). A step is one batch; steps cycle through the batches.
     The graphs record phase events of their own, so the DFS kernel's duration is measured
     on every replay of the timed region."""
     import torch
@@ -607,7 +618,7 @@ def genome_headline(args):
     import synth
     from paper_1811_06127_amd import fm
 
-    B, LEN, Z = 1_000_000, 150, 2
+    B, LEN, Z = args.genome_batch_reads, 150, 2
     NB = args.genome_batches
     flags = fm.FM_BOTH | fm.FM_DARRAY
     cap = 16 * B
@@ -723,11 +734,19 @@ def genome_headline(args):
     # The same replays on two streams, batch b on stream b % 2 (a plan's replays stay in order
     # on one stream; consecutive batches share no buffer): one batch's search then runs in
     # the capacity the other's tail leaves idle. Reported beside the headline, which keeps one
-    # stream so that each DFS launch's duration (the roofline's) is its own.
+    # stream so that each DFS launch's duration (the roofline's) is its own. The two streams
+    # come from the HIP runtime and are destroyed afterwards: a process has few hardware
+    # queues (4 by default), streams that torch creates hold theirs until the process ends,
+    # and streams created later (the serving leg's) then share queues and lose their overlap.
     two_stream = None
-    if NB % 2 == 0:
+    if NB % 2 == 0 and not args.skip_two_stream:
         main = torch.cuda.current_stream()
-        pair = [torch.cuda.Stream(), torch.cuda.Stream()]
+        hip = ctypes.CDLL("libamdhip64.so.7")
+        raw = [ctypes.c_void_p() for _ in range(2)]
+        for r in raw:
+            if hip.hipStreamCreateWithFlags(ctypes.byref(r), ctypes.c_uint(1)) != 0:   # hipStreamNonBlocking
+                raise RuntimeError("hipStreamCreateWithFlags failed")
+        pair = [torch.cuda.ExternalStream(r.value) for r in raw]
         ev[0].record()
         for st in pair:
             st.wait_stream(main)
@@ -738,6 +757,10 @@ def genome_headline(args):
         ev[1].record()
         torch.cuda.synchronize()
         t2 = ev[0].elapsed_time(ev[1])
+        del pair
+        for r in raw:
+            if hip.hipStreamDestroy(r) != 0:
+                raise RuntimeError("hipStreamDestroy failed")
         two_stream = {"ms_per_step": round(t2 / K, 4), "reads_per_s": round(K * B / (t2 / 1e3), 1)}
         log("genome scale on two streams: %d steps in %.1f ms (%.3f ms/step)" % (K, t2, t2 / K))
     replay_equal = all(bool(torch.equal(ex, e[0]) and torch.equal(bufs.hit_offs, e[1])
@@ -745,8 +768,8 @@ def genome_headline(args):
                        for (codes, z, ex, bufs), e in zip(batches, eager))
     ms_step = total_ms / K
     phase = {k: v / K for k, v in phase_sum.items()}
-    log("genome scale: %d steps of 1M reads in %.1f ms (%.3f ms/step), phases %s, replays identical: %s" % (
-        K, total_ms, ms_step, phase, replay_equal))
+    log("genome scale: %d steps of %d reads in %.1f ms (%.3f ms/step), phases %s, replays identical: %s" % (
+        K, B, total_ms, ms_step, phase, replay_equal))
     for p in plans:
         p.free()
 
@@ -757,7 +780,7 @@ def genome_headline(args):
     alg = ((work["buckets"] + work["table"]) * 32 + NB * (2 * B * LEN + 32 * nrs) + 16 * sum(hits_per_batch)) / NB
     achieved = alg / (phase["dfs"] / 1e3) / 1e9
     tcfg = tuning["inexact"]
-    key = (kernel_source_hash(), dfs_kernel_name(tcfg, Z), tuple(tcfg[f] for f in TRAFFIC_KEY_FIELDS), "3.1e9")
+    key = (kernel_source_hash(), dfs_kernel_name(tcfg, Z), tuple(tcfg[f] for f in TRAFFIC_KEY_FIELDS), "3.1e9/%d" % B)
     traffic = MEASURED_TRAFFIC.get(key)
     index_bytes = idx.info()["device_bytes"]
     roofline = {"bound": residency_bound(index_bytes), "kernel": key[1], "achieved": round(achieved, 1),
@@ -832,9 +855,9 @@ def genome_headline(args):
         "value": round(reads_s, 1),
         "ms_per_step": round(ms_step, 4),
         "config": {"workload": "3.1e9-base reference (55%% i.i.d., 45%% copies of 500 repeat families, 5-15%% "
-                               "divergence); %d batches of 1M reads x 150 bp, 1%% substitutions, either strand, all "
-                               "resident in HBM; exact + z=2 substitution search, both strands, D-array pruning; "
-                               "one launch graph per batch, replayed; a step is one batch" % NB,
+                               "divergence); %d batches of %d reads x 150 bp, 1%% substitutions, either strand, "
+                               "all resident in HBM; exact + z=2 substitution search, both strands, D-array "
+                               "pruning; one launch graph per batch, replayed; a step is one batch" % (NB, B),
                    "n": int(R.size), "reads": NB * B, "batch_reads": B, "read_len": LEN, "z": Z, "strands": 2,
                    "d_bound": True, "hit_cap_per_batch": cap, "graph_replay": True},
         "roofline": roofline,
