@@ -508,7 +508,10 @@ int fm_server_bytes(const fm_server_opts *opts, uint64_t nreads, uint64_t total_
 
 /* Creates the server and starts its worker. FM_EINVAL for options outside the listed
  * ranges (or FM_DARRAY without a reverse index), FM_ENOMEM when the arena or its
- * pinned mirror cannot be allocated. */
+ * pinned mirror cannot be allocated. Each lane runs on a stream of its own; a process
+ * has few hardware queues (4 by default), and lanes whose streams share a queue with
+ * other streams no longer overlap, so create the server before other streams that
+ * stay alive. */
 int fm_server_create(const fm_index *idx, const fm_server_opts *opts, fm_server **out);
 
 /* Queues a request: codes (host) with nreads+1 nondecreasing offsets (host, codes of
