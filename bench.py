@@ -605,6 +605,28 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def random_read_ceiling(fm, torch, idx, spans=(1 << 30, 2 << 30, 4 << 30), rounds=64):
+    """Independent reads of random 32-byte blocks over each span of device memory
+    (fm_probe_random_reads, the median of 3 timed launches after one untimed): the rate at
+    which the device serves the searches' bucket fetches over an index of that size."""
+    buf = torch.zeros(max(spans), dtype=torch.uint8, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    rates = {}
+    for span in spans:
+        fm.probe_random_reads(idx, buf, span, rounds, sink)
+        ms = []
+        for _ in range(3):
+            ev[0].record()
+            n = fm.probe_random_reads(idx, buf, span, rounds, sink)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms.append(ev[0].elapsed_time(ev[1]))
+        rates["%d GiB" % (span >> 30)] = round(n / (sorted(ms)[1] / 1e3), 1)
+    del buf, sink
+    return rates
+
+
 def genome_headline(args):
     """The headline: batching at genome scale. A 3.1e9-base text (55% i.i.d., 45% copies
     of 500 repeat families with 5-15% divergence) and 16M reads of 150 bp with 1%
@@ -768,6 +790,8 @@ def genome_headline(args):
                        for (codes, z, ex, bufs), e in zip(batches, eager))
     ms_step = total_ms / K
     phase = {k: v / K for k, v in phase_sum.items()}
+    ceiling = random_read_ceiling(fm, torch, idx)
+    log("random 32-byte reads: %s per second" % ceiling)
     log("genome scale: %d steps of %d reads in %.1f ms (%.3f ms/step), phases %s, replays identical: %s" % (
         K, B, total_ms, ms_step, phase, replay_equal))
     for p in plans:
@@ -789,6 +813,16 @@ def genome_headline(args):
                 "traffic_gb_per_s": round(sum(traffic) / (phase["dfs"] / 1e3) / 1e9, 1) if traffic else None,
                 "bytes_per_launch": int(alg), "avg_launch_ms": round(phase["dfs"], 3),
                 "kernel_source_hash": key[0], "index_bytes": int(index_bytes), "duration_from": phase_source}
+    # The DFS's fetches against the rate the device serves independent random 32-byte reads
+    # over a span like the one it reads (the 1.55 GB forward layout and the prefix table)
+    fetch_rate = (work["buckets"] + work["table"]) / NB / (phase["dfs"] / 1e3)
+    roofline["random_read_ceiling"] = {
+        "reads_per_s_by_span": ceiling,
+        "dfs_fetches_per_s": round(fetch_rate, 1),
+        "dfs_line_requests_per_s": round(traffic[0] / 128 / (phase["dfs"] / 1e3), 1) if traffic else None,
+        "dfs_fetches_vs_2_GiB": round(fetch_rate / ceiling["2 GiB"], 3),
+        "probe": "fm_probe_random_reads: 16 waves per CU, 4 reads of one random 32-byte block in flight per lane",
+    }
 
     # text positions of the first batch's hits (Eq. 4-5)
     codes, z, ex, bufs = batches[0]

@@ -272,6 +272,20 @@ int fm_autotune(fm_index *idx, int op, const uint8_t *codes, const uint64_t *off
  * (no Occ value can be that large). */
 int fm_occ8(const fm_index *idx, const fm_interval *q, uint64_t nq, uint32_t *out, void *stream);
 
+/* Diagnostic: the memory system's ceiling for the searches' access pattern. One launch on
+ * idx's device (16 waves per compute unit, 4 reads in flight per lane, `rounds` rounds)
+ * in which every lane reads random 32-byte blocks of buf[0 .. span): one 32-byte bucket
+ * is what an Occ8 reads at I=64 (Background), and a bucket fetch is a read of a random
+ * block of the index. Timing the call over a span about the size of the index gives the
+ * rate of independent bucket fetches the device can serve there. buf: device, at least
+ * span bytes, 16-byte aligned, read only. span: a power of two, at least 4096. rounds:
+ * 1..4096. sink: device, one uint32, written only if a lane's sum of the words it read
+ * equals a fixed constant (it keeps the loads live). *reads (host) receives the number of
+ * 32-byte reads the launch makes. FM_EINVAL for other arguments, FM_EDEVICE if the launch
+ * fails. */
+int fm_probe_random_reads(const fm_index *idx, const void *buf, uint64_t span, uint32_t rounds,
+                          uint32_t *sink, uint64_t *reads, void *stream);
+
 /* ----------------------------------------------------------------- exact search */
 
 /* Workspace bytes fm_search_exact needs (256; also with FM_PLAIN, where ws may be NULL

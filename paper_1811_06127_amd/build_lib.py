@@ -11,7 +11,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfmocc.so")
 SOURCES = ["sa_build.hip", "layout.hip", "search.hip", "capi.cpp", "build.cpp", "runtime.cpp", "server.cpp",
-           "noalloc.hip"]
+           "noalloc.hip", "probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

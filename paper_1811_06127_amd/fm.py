@@ -109,6 +109,7 @@ def lib() -> C.CDLL:
         "fm_autotune": (i32, [vp, i32, vp, vp, vp, u64, u32, u32, vp, u64, vp, vp, vp, C.c_size_t, C.c_char_p,
                               vp, C.POINTER(Tuning), C.POINTER(C.c_float)]),
         "fm_occ8": (i32, [vp, vp, u64, vp, vp]),
+        "fm_probe_random_reads": (i32, [vp, vp, u64, u32, vp, C.POINTER(C.c_uint64), vp]),
         "fm_search_exact_workspace": (i32, [vp, u64, u32, C.POINTER(C.c_size_t)]),
         "fm_search_exact": (i32, [vp, vp, vp, u64, u32, vp, vp, C.c_size_t, vp]),
         "fm_darray": (i32, [vp, vp, vp, u64, u64, u32, vp, vp]),
@@ -331,6 +332,19 @@ def fm_occ8(idx: Index, q: torch.Tensor, out: torch.Tensor | None = None, stream
     _dev(out, torch.int32, "out")
     _check(lib().fm_occ8(idx.handle, _ptr(q), nq, _ptr(out), _stream(stream)), "fm_occ8")
     return out
+
+
+def probe_random_reads(idx: Index, buf: torch.Tensor, span: int, rounds: int, sink: torch.Tensor,
+                       stream=None) -> int:
+    """One launch of random 32-byte reads over buf[:span] (device tensor of at least span
+    bytes) on idx's device; sink: one-word int32 device tensor. Returns the reads made."""
+    if not buf.is_cuda or buf.numel() * buf.element_size() < span:
+        raise ValueError("buf must be a device tensor of at least span bytes")
+    _dev(sink, torch.int32, "sink")
+    n = C.c_uint64(0)
+    _check(lib().fm_probe_random_reads(idx.handle, _ptr(buf), span, rounds, _ptr(sink), C.byref(n),
+                                       _stream(stream)), "fm_probe_random_reads")
+    return int(n.value)
 
 
 def fm_search_exact_workspace(idx: Index, nreads: int, flags: int) -> int:

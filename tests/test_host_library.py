@@ -50,6 +50,15 @@ def test_header_is_plain_c(tmp_path):
                        check=True)
 
 
+def test_probe_rejects_arguments_without_a_device():
+    """fm_probe_random_reads checks its arguments before it touches a device."""
+    import ctypes
+    n = ctypes.c_uint64(0)
+    L = fm.lib()
+    assert L.fm_probe_random_reads(None, None, 4096, 1, None, ctypes.byref(n), None) == fm.FM_EINVAL
+    assert n.value == 0
+
+
 def test_strerror_and_version():
     assert fm.strerror(fm.FM_OK) == "ok"
     assert fm.strerror(fm.FM_EOVERFLOW) == "hit capacity exceeded"
