@@ -367,9 +367,8 @@ def fm_search_exact(idx: Index, codes: torch.Tensor, offs: torch.Tensor, flags: 
     nreads = offs.numel() - 1
     if out is None:
         out = torch.empty((nreads * nstrands(flags), 2), dtype=torch.int32, device=codes.device)
-    need = fm_search_exact_workspace(idx, nreads, flags) if not (flags & FM_PLAIN and not flags & FM_STATS) else 0
-    if ws is None and need:
-        ws = torch.empty(need, dtype=torch.uint8, device=codes.device)
+    if ws is None and not (flags & FM_PLAIN and not flags & FM_STATS):
+        ws = torch.empty(fm_search_exact_workspace(idx, nreads, flags), dtype=torch.uint8, device=codes.device)
     wsb = ws.numel() if ws is not None else 0
     _check(lib().fm_search_exact(idx.handle, _ptr(codes), _ptr(offs), nreads, flags, _ptr(out), _ptr(ws), wsb,
                                  _stream(stream)), "fm_search_exact")
