@@ -41,10 +41,8 @@ METRIC = "reads/s & Occ8 queries/s, batched vs plain kernel, bit-exact; p99 late
 # as null.
 MEASURED_TRAFFIC = {
     # read = TCC_EA0_RDREQ x 128 B (each EA read request moves a 128 B line on gfx950), write = WRITE_SIZE
-    ("d1e91b2f1de5addc", "dfs_batched<64, 1, 1, true, true>", (64, 1, 1, 256, 8, 1, 12), "3.1e9/4000000"):
-        (1_121_612_261_717, 967_993_275),
-    ("d1e91b2f1de5addc", "dfs_batched<64, 1, 1, true, true>", (64, 1, 1, 256, 8, 1, 12), "3.1e9/1000000"):
-        (275_877_930_464, 1_067_345_276),
+    ("1ad2b605713d0b55", "dfs_batched<64, 1, 1, true, true>", (64, 1, 1, 256, 8, 1, 14), "3.1e9/4000000"):
+        (1_047_402_509_952, 969_603_605),
 }
 TRAFFIC_KEY_FIELDS = ("occ_interval", "lanes", "depth", "block", "waves_per_cu", "order", "table_depth")
 KERNEL_SOURCES = ("search.hip", "fm_device.hpp", "fm_internal.hpp")

@@ -216,7 +216,7 @@ int fm_index_load(const char *path, const fm_load_opts *opts, fm_index **out);
  * _codes or _load): the layouts (the one named by occ_interval, or all of them with
  * FM_LOAD_ALL_LAYOUTS) of R and, with FM_LOAD_REVERSE, of reverse(R); the prefix table
  * of R: for t = 1..T the Listing 1 interval (k, l) of every string of length t over ACGT,
- * 8 bytes each, with T = min(12, floor(log4(n + 1)) - 3) (none when that is below 1); and
+ * 8 bytes each, with T = min(14, floor(log4(n + 1)) - 1) (none when that is below 1); and
  * with FM_LOAD_LOCATE the SA samples of fm_index_from_text (4 bytes per 32 rows); each
  * piece is 256-byte aligned. This is the smallest dev_buf_bytes accepted. Host only; FM_EINVAL
  * for an unsupported occ_interval, FM_ERANGE when n + 1 >= 2^32. */

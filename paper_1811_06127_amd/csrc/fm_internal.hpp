@@ -70,14 +70,17 @@ DevLayout dev_layout(const fm_index *idx, uint32_t I, bool rev);
 // Prefix table of R: for t = 1..T, the interval that Listing 1 gives the string
 // s_0 .. s_{t-1} from (0, n) (empty ones as Listing 1 leaves them, k > l), at entry
 // table_level_base(t) + sum_j s_j 4^j, so that the four children b.S of a string S of
-// length t - 1 are four consecutive entries (32 bytes) at 4 * code(S). T grows with n
-// (strings much shorter than log4(n) are the ones many DFS nodes share).
+// length t - 1 are four consecutive entries (32 bytes) at 4 * code(S). T grows with n up
+// to one level short of log4(n), where a string still occurs a few times on average, and
+// stops at 14 (2.86 GB): a node shallower than T reads one table entry instead of the one
+// or two buckets of an Occ8, and every level added moved the genome-scale DFS closer to
+// one read per node.
 inline uint32_t prefix_table_levels(uint64_t n)
 {
     int t = 0;
     while (t < 16 && ((n + 1) >> (2 * (t + 1))) > 0) ++t;    // t = floor(log4(n + 1))
-    t -= 3;
-    return t < 1 ? 0u : (t > 12 ? 12u : (uint32_t)t);
+    t -= 1;
+    return t < 1 ? 0u : (t > 14 ? 14u : (uint32_t)t);
 }
 __host__ __device__ inline uint64_t table_level_base(uint32_t t) { return ((1ull << (2 * t)) - 4) / 3; }
 inline uint64_t prefix_table_entries(uint32_t T) { return T ? table_level_base(T + 1) : 0; }

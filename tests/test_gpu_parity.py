@@ -579,7 +579,7 @@ def test_prefix_table_depths():
     xr = oracle.OracleIndex(oracle.reverse_text(R))
     idx = fm.Index.from_text(R, occ_interval=64, flags=fm.FM_LOAD_REVERSE | fm.FM_LOAD_ALL_LAYOUTS)
     T = idx.info()["table_depth"]
-    assert T == 7 and idx.get_tuning(fm.FM_OP_INEXACT)["table_depth"] == T
+    assert T == 9 and idx.get_tuning(fm.FM_OP_INEXACT)["table_depth"] == T
     with pytest.raises(fm.FmError):
         idx.set_tuning(fm.FM_OP_INEXACT, table_depth=T + 1)
     rd = synth.simulate_reads(R, 1200, 77, length=(40, 120), sub=(0.0, 0.03), z=(0, 2))

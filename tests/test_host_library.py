@@ -238,10 +238,10 @@ def test_index_bytes_and_required_bytes(tmp_path):
     and the SA samples (4 bytes per 32 rows), each piece 256-byte aligned;
     fm_index_required_bytes gives the same from a file's header."""
     a = lambda x: (x + 255) // 256 * 256
-    depths = {0: 0, 1: 0, 1000: 1, 70_001: 5, 1 << 20: 7, 1 << 28: 11, 3_100_000_000: 12}
+    depths = {0: 0, 1: 0, 14: 0, 15: 1, 1000: 3, 70_001: 7, 1 << 20: 9, 1 << 28: 13, 3_100_000_000: 14}
     for n, T in depths.items():
-        # prefix table: 8 bytes for every string of length 1..T, T = floor(log4(n + 1)) - 3 in [0, 12]
-        assert T == max(0, min(12, int(np.floor(np.log(n + 1) / np.log(4) + 1e-12)) - 3)) or n + 1 < 4
+        # prefix table: 8 bytes for every string of length 1..T, T = floor(log4(n + 1)) - 1 in [0, 14]
+        assert T == max(0, min(14, int(np.floor(np.log(n + 1) / np.log(4) + 1e-12)) - 1)) or n + 1 < 4
         tab = a(8 * sum(4 ** t for t in range(1, T + 1)))
         for I in (64, 96, 128, 192, 224, 256, 448):
             assert fm.fm_index_bytes(n, I) == a(layout_bytes(n, I)) + tab
